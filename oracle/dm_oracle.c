@@ -1,0 +1,145 @@
+/*
+ * dm_oracle.c - CPU oracle for the distance-matrix matrix-vector product.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg do.  It shares no code with the HIP library.
+ *
+ * What it computes is the plain definition of the query (Section 1, the
+ * matrix-vector query model; Theorem for p = 1 in Section 2):
+ *
+ *     (A z)_i = sum_j z_j * f(x_i, x_j)
+ *
+ * with f(x, y) = sum_k |x(k) - y(k)|          (l1, Section 2)
+ *  and f(x, y) = sum_k (x(k) - y(k))^2        (l2 squared, Appendix A, p = 2)
+ *
+ * Each requested row of A is formed explicitly, entry by entry (a difference,
+ * then an absolute value or a square, summed over k), and then multiplied by
+ * Z with j ascending.  No prefix sums, no sorting and no norm expansion are
+ * used, so the oracle shares neither the l1 method's scan nor the l2-squared
+ * low-rank form's cancellation.
+ *
+ * Floating point: every quantity is FP64, compiled with -ffp-contract=off.
+ * Integer variant: int64 inputs, entries and products in __int128, so the
+ * result is exact; a flag reports any output that does not fit in int64.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <math.h>
+
+#define DM_ORACLE_L1 1
+#define DM_ORACLE_L2SQ 2
+
+/* One entry of A in FP64: f(x_i, x_j). */
+static double entry_f64(const double* xi, const double* xj, int32_t d, int metric)
+{
+    double a = 0.0;
+    for (int32_t k = 0; k < d; ++k) {
+        double diff = xi[k] - xj[k];
+        if (metric == DM_ORACLE_L1)
+            a += fabs(diff);
+        else
+            a += diff * diff;
+    }
+    return a;
+}
+
+/* One entry of A exactly, from int64 coordinates. */
+static __int128 entry_i128(const int64_t* xi, const int64_t* xj, int32_t d, int metric)
+{
+    __int128 a = 0;
+    for (int32_t k = 0; k < d; ++k) {
+        __int128 diff = (__int128)xi[k] - (__int128)xj[k];
+        if (metric == DM_ORACLE_L1)
+            a += diff < 0 ? -diff : diff;
+        else
+            a += diff * diff;
+    }
+    return a;
+}
+
+/*
+ * Rows `rows[0..m)` of the explicit distance matrix, A_out is m x n row-major.
+ * X is n x d row-major.
+ */
+void oracle_rows_f64(const double* X, int64_t n, int32_t d, int metric,
+                     const int64_t* rows, int64_t m, double* A_out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < m; ++t) {
+        const double* xi = X + rows[t] * (int64_t)d;
+        for (int64_t j = 0; j < n; ++j)
+            A_out[t * n + j] = entry_f64(xi, X + j * (int64_t)d, d, metric);
+    }
+}
+
+/*
+ * Y[t, c] = sum_j A[rows[t], j] * Z[j, c]   (Z is n x b row-major, Y is m x b)
+ * rownorm2[t]  = sum_j A[rows[t], j]^2                 (may be NULL)
+ * absdot[t, c] = sum_j |A[rows[t], j]| * |Z[j, c]|     (may be NULL)
+ */
+void oracle_matvec_f64(const double* X, int64_t n, int32_t d, int metric,
+                       const double* Z, int32_t b, const int64_t* rows, int64_t m,
+                       double* Y, double* rownorm2, double* absdot)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < m; ++t) {
+        const double* xi = X + rows[t] * (int64_t)d;
+        double* y = Y + t * (int64_t)b;
+        double* ad = absdot ? absdot + t * (int64_t)b : NULL;
+        double rn = 0.0;
+        for (int32_t c = 0; c < b; ++c) {
+            y[c] = 0.0;
+            if (ad) ad[c] = 0.0;
+        }
+        for (int64_t j = 0; j < n; ++j) {
+            double a = entry_f64(xi, X + j * (int64_t)d, d, metric);
+            const double* zj = Z + j * (int64_t)b;
+            for (int32_t c = 0; c < b; ++c) {
+                y[c] += a * zj[c];
+                if (ad) ad[c] += fabs(a) * fabs(zj[c]);
+            }
+            rn += a * a;
+        }
+        if (rownorm2) rownorm2[t] = rn;
+    }
+}
+
+/*
+ * Exact integer variant.  Returns the number of outputs whose exact value does
+ * not fit in int64 (those outputs hold the low 64 bits of the exact value).
+ */
+int64_t oracle_matvec_i64(const int64_t* X, int64_t n, int32_t d, int metric,
+                          const int64_t* Z, int32_t b, const int64_t* rows, int64_t m,
+                          int64_t* Y)
+{
+    int64_t overflow = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : overflow)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t* xi = X + rows[t] * (int64_t)d;
+        __int128* acc = (__int128*)calloc((size_t)b, sizeof(__int128));
+        for (int64_t j = 0; j < n; ++j) {
+            __int128 a = entry_i128(xi, X + j * (int64_t)d, d, metric);
+            const int64_t* zj = Z + j * (int64_t)b;
+            for (int32_t c = 0; c < b; ++c)
+                acc[c] += a * (__int128)zj[c];
+        }
+        for (int32_t c = 0; c < b; ++c) {
+            if (acc[c] > (__int128)INT64_MAX || acc[c] < (__int128)INT64_MIN) overflow += 1;
+            Y[t * (int64_t)b + c] = (int64_t)(uint64_t)(unsigned __int128)acc[c];
+        }
+        free(acc);
+    }
+    return overflow;
+}
+
+/* Number of OpenMP threads the oracle runs on (1 without OpenMP). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
