@@ -1,0 +1,143 @@
+/*
+ * dm.h - implicit distance-matrix matrix-vector products on MI355X (gfx950).
+ *
+ * For points x_1..x_n in R^d and a distance f, the n x n matrix
+ * A_ij = f(x_i, x_j) is never formed; the library answers queries z -> A z
+ * (the matrix-vector query model of Section 1 of Indyk & Silwal, "Faster
+ * Linear Algebra for Distance Matrices").
+ *
+ *   DM_L1    f(x, y) = sum_k |x(k) - y(k)|       Algorithms 1 and 2, Section 2
+ *   DM_L2SQ  f(x, y) = sum_k (x(k) - y(k))^2     Algorithm 3, Appendix A
+ *
+ * l1: dm_prepare sorts the n values of every coordinate once (Algorithm 1;
+ * stable, ties by ascending point index) and keeps the permutations, their
+ * inverses (ranks) and the sorted values.  Each query then walks every
+ * coordinate in sorted order with prefix sums P0 = sum z_j and
+ * P1 = sum x_j(k) z_j and adds x_ik (2 P0 - T0) - (2 P1 - T1) to row i
+ * (Algorithm 2 and the proof of its exactness theorem, Section 2).
+ * l2 squared: A z = ||x_i||^2 sum_j z_j + sum_j ||x_j||^2 z_j - 2 X (X^T z)
+ * (the decomposition of Section 1.2 and Algorithm 3).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments named X, Z, Out, U, workspace are DEVICE pointers
+ *    (memory on the current HIP device); every other pointer is host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *  - X is n x d row-major.  Z and Out are n x b row-major (a point's b
+ *    right-hand-side values are contiguous).
+ *  - Float data (DM_F32, DM_F64): Z is DM_F32, Out is float.  DM_F64 points
+ *    are rounded once to FP32 at preparation.  Integer data (DM_I32, DM_I64,
+ *    |x| < 2^31): Z is DM_I32 or DM_I64, Out is int64 and exact.
+ *  - Argument errors are reported synchronously and before any device work.
+ *    Data-dependent errors found on the device during a query (non-finite Z,
+ *    an integer result that could exceed int64) are sticky: dm_sync returns
+ *    them.  After an error the contents of Out are unspecified.
+ *  - Entry points are not thread-safe for one handle; distinct handles are
+ *    independent.  Queries on one handle must not overlap in time on
+ *    different streams.
+ */
+#ifndef DM_H
+#define DM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dm_handle dm_handle;
+
+typedef enum { DM_L1 = 1, DM_L2SQ = 2 } dm_metric;
+typedef enum { DM_F32 = 1, DM_F64 = 2, DM_I32 = 3, DM_I64 = 4 } dm_dtype;
+typedef enum {
+    DM_OK = 0,
+    DM_ERR_ARG = -1,       /* bad argument (NULL, size < 1, bad enum, short workspace) */
+    DM_ERR_NONFINITE = -2, /* NaN or Inf in X (prepare) or Z (query)                     */
+    DM_ERR_OVERFLOW = -3,  /* integer query whose exact result may not fit in int64      */
+    DM_ERR_NOMEM = -4,     /* device allocation failed                                   */
+    DM_ERR_DEVICE = -5,    /* no usable HIP device, or a HIP call failed                 */
+    DM_ERR_DTYPE = -6,     /* dtype not allowed here, or integer |x| >= 2^31              */
+    DM_ERR_STATE = -7      /* handle used in a way its kind does not support             */
+} dm_status;
+
+/* Static text for a status code (never NULL). */
+const char* dm_status_string(int32_t status);
+
+/*
+ * Bytes of device workspace dm_prepare needs for one dataset (persistent
+ * arrays plus the sort's temporary buffers).  Pure host function.
+ * Errors: DM_ERR_ARG for n < 1, d < 1, n * d >= 2^32, bad metric or dtype,
+ * bytes == NULL.
+ */
+dm_status dm_workspace_size(int64_t n, int32_t d, int32_t metric, int32_t dtype, size_t* bytes);
+
+/*
+ * Preparation (Algorithm 1 for l1): validates X, and for l1 builds per
+ * coordinate k the stable sorted order perm[k][r], its inverse rank[k][i] and
+ * the sorted values xs[k][r]; for every metric the FP64 (int64 for integer
+ * data) row sums s_i = sum_k x_ik and squared norms ||x_i||^2.  For l2 squared
+ * it keeps a copy of X.
+ *
+ * X: device, n x d row-major of `dtype`; only read during the call.
+ * workspace: device memory of at least dm_workspace_size bytes owned by the
+ *   caller, which must outlive the handle; NULL lets the library allocate
+ *   (and dm_free release) it.
+ * Blocking: returns after the device work finished.
+ * Errors: DM_ERR_ARG, DM_ERR_DTYPE (|x| >= 2^31 in integer data),
+ * DM_ERR_NONFINITE (NaN/Inf in X, or an FP64 value beyond the FP32 range),
+ * DM_ERR_NOMEM, DM_ERR_DEVICE.  On error *out is NULL and nothing leaks.
+ */
+dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_t dtype,
+                     void* workspace, size_t ws_bytes, void* stream, dm_handle** out);
+
+/*
+ * One query: Out = A Z for b right-hand sides at once (b = 1 is the single
+ * vector form; b > 1 shares every sorted permutation across the b columns,
+ * which is the matrix product of the Appendix C lemma on products AB taken b
+ * columns at a time).
+ *
+ * Z: device n x b of `z_dtype` (DM_F32 for float data; DM_I32 or DM_I64 for
+ * integer data).  Out: device n x b, float or int64.  Z and Out must not
+ * overlap.  1 <= b <= 64.
+ * Stream-ordered and asynchronous.  The library may grow per-handle scratch
+ * memory on the first call with a larger b (see dm_reserve).
+ * Errors (synchronous): DM_ERR_ARG, DM_ERR_DTYPE, DM_ERR_NOMEM, DM_ERR_DEVICE.
+ * Errors (sticky, via dm_sync): DM_ERR_NONFINITE, DM_ERR_OVERFLOW.
+ */
+dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream);
+
+/* Pre-size the per-handle query scratch for right-hand-side counts up to b, so
+ * that later dm_matvec calls allocate nothing.  Errors: DM_ERR_ARG, DM_ERR_NOMEM. */
+dm_status dm_reserve(dm_handle* h, int32_t b);
+
+/* Wait for the handle's last stream, then return and clear the sticky status. */
+dm_status dm_sync(dm_handle* h);
+
+/* Shape of a handle.  Any output pointer may be NULL. */
+dm_status dm_info(const dm_handle* h, int64_t* n, int32_t* d, int32_t* metric, int32_t* dtype);
+
+/*
+ * Copy the preparation results of an l1 handle into caller device buffers
+ * (any may be NULL): perm and rank are d x n uint32, xs is d x n float (float
+ * data) or int32 (integer data).  Stream-ordered.  Errors: DM_ERR_ARG,
+ * DM_ERR_STATE for an l2-squared handle.
+ */
+dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, void* xs, void* stream);
+
+/*
+ * Integer overflow guard (pure, host): nonzero when z_l1 * sum_ranges < 2^62,
+ * i.e. when every |(A z)_i| <= sum_j |z_j| * max_ij A_ij is certainly below
+ * 2^63 so that wrapping int64 arithmetic returns the exact result.
+ * sum_ranges is sum_k (max_k - min_k) for l1 and sum_k (max_k - min_k)^2 for
+ * l2 squared.  The device applies the same test during integer queries.
+ */
+int dm_int_bound_ok(double sum_ranges, double z_l1);
+
+/* Release a handle (and its workspace if the library allocated it).  NULL is a no-op. */
+void dm_free(dm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DM_H */

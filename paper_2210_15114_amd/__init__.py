@@ -1,0 +1,203 @@
+"""Implicit distance-matrix matrix-vector products on MI355X (gfx950).
+
+Thin Python binding over the C ABI in ``include/dm.h`` (``libdm.so``).  It
+only marshals arguments: tensors are caller-owned device memory allocated by
+PyTorch, streams are PyTorch's current stream, and every step of the
+computation runs in the library's HIP kernels.  There is no fallback: if the
+library is missing or no GPU is present, calls raise.
+
+    import torch, paper_2210_15114_amd as dm
+    h = dm.prepare(X_cuda, dm.L1)          # Algorithm 1 (sort every coordinate)
+    Y = h.matvec(Z_cuda)                    # A Z for b = Z.shape[1] right-hand sides
+    h.sync()                                # raises on a sticky device-side error
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "dm.h")
+
+L1 = 1
+L2SQ = 2
+F32, F64, I32, I64 = 1, 2, 3, 4
+
+OK = 0
+ERR_ARG, ERR_NONFINITE, ERR_OVERFLOW, ERR_NOMEM, ERR_DEVICE, ERR_DTYPE, ERR_STATE = -1, -2, -3, -4, -5, -6, -7
+
+_lib = None
+
+
+class DMError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, status_string(status), status))
+
+
+def lib():
+    """The loaded libdm.so (ctypes).  Raises ImportError when it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdm.so is not built; run `python -m paper_2210_15114_amd.build` "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.dm_status_string.argtypes = [i32]
+    L.dm_status_string.restype = ctypes.c_char_p
+    L.dm_workspace_size.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz)]
+    L.dm_workspace_size.restype = i32
+    L.dm_prepare.argtypes = [P, i64, i32, i32, i32, P, sz, P, ctypes.POINTER(P)]
+    L.dm_prepare.restype = i32
+    L.dm_matvec.argtypes = [P, P, i32, i32, P, P]
+    L.dm_matvec.restype = i32
+    L.dm_reserve.argtypes = [P, i32]
+    L.dm_reserve.restype = i32
+    L.dm_sync.argtypes = [P]
+    L.dm_sync.restype = i32
+    L.dm_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.dm_info.restype = i32
+    L.dm_copy_sorted.argtypes = [P, P, P, P, P]
+    L.dm_copy_sorted.restype = i32
+    L.dm_int_bound_ok.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.dm_int_bound_ok.restype = ctypes.c_int
+    L.dm_free.argtypes = [P]
+    L.dm_free.restype = None
+    _lib = L
+    return L
+
+
+def header_functions() -> list:
+    """Names of the functions include/dm.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dm_[a-z0-9_]+)\s*\(", text)))
+
+
+def status_string(status: int) -> str:
+    return lib().dm_status_string(int(status)).decode()
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        raise DMError(st, where)
+
+
+def workspace_size(n: int, d: int, metric: int, dtype: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().dm_workspace_size(n, d, metric, dtype, ctypes.byref(out)), "dm_workspace_size")
+    return out.value
+
+
+def int_bound_ok(sum_ranges: float, z_l1: float) -> bool:
+    return bool(lib().dm_int_bound_ok(float(sum_ranges), float(z_l1)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    m = {torch.float32: F32, torch.float64: F64, torch.int32: I32, torch.int64: I64}
+    if t not in m:
+        raise TypeError("unsupported dtype %s" % t)
+    return m[t]
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """A prepared point set (one dataset).  Owns its workspace tensor."""
+
+    def __init__(self, ptr, workspace, n, d, metric, dtype):
+        self._ptr = ptr
+        self._ws = workspace
+        self.n, self.d, self.metric, self.dtype = n, d, metric, dtype
+
+    @property
+    def is_int(self) -> bool:
+        return self.dtype in (I32, I64)
+
+    def matvec(self, Z, out=None, stream=None):
+        """Out = A Z (Z: n x b or n device tensor; float32, or int32/int64 for integer data)."""
+        torch = _torch()
+        squeeze = Z.dim() == 1
+        Zm = Z.unsqueeze(1) if squeeze else Z
+        if Zm.dim() != 2 or Zm.shape[0] != self.n:
+            raise ValueError("Z must be n x b")
+        b = Zm.shape[1]
+        odt = torch.int64 if self.is_int else torch.float32
+        if out is None:
+            out = torch.empty((self.n, b), dtype=odt, device=Zm.device)
+        elif out.shape != (self.n, b) and not (squeeze and out.shape == (self.n,)):
+            raise ValueError("out has the wrong shape")
+        st = lib().dm_matvec(self._ptr, _dev_ptr(Zm, "Z"), _dtype_code(Zm.dtype), b, _dev_ptr(out, "out"),
+                             _stream_ptr(stream))
+        _check(st, "dm_matvec")
+        return out.view(self.n) if squeeze and out.dim() == 2 else out
+
+    def reserve(self, b: int):
+        _check(lib().dm_reserve(self._ptr, b), "dm_reserve")
+
+    def sync(self):
+        _check(lib().dm_sync(self._ptr), "dm_sync")
+
+    def sorted(self, stream=None):
+        """(perm, rank, xs), each d x n on the device (l1 handles)."""
+        torch = _torch()
+        dev = self._ws.device
+        perm = torch.empty((self.d, self.n), dtype=torch.int32, device=dev)
+        rank = torch.empty((self.d, self.n), dtype=torch.int32, device=dev)
+        xs = torch.empty((self.d, self.n), dtype=torch.int32 if self.is_int else torch.float32, device=dev)
+        st = lib().dm_copy_sorted(self._ptr, _dev_ptr(perm, "perm"), _dev_ptr(rank, "rank"), _dev_ptr(xs, "xs"),
+                                  _stream_ptr(stream))
+        _check(st, "dm_copy_sorted")
+        return perm, rank, xs
+
+    def free(self):
+        if self._ptr:
+            lib().dm_free(self._ptr)
+            self._ptr = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def prepare(X, metric: int = L1, stream=None) -> Handle:
+    """Prepare a point set X (n x d device tensor: float32/float64/int32/int64)."""
+    torch = _torch()
+    if X.dim() != 2:
+        raise ValueError("X must be n x d")
+    n, d = X.shape
+    code = _dtype_code(X.dtype)
+    ws_bytes = workspace_size(n, d, metric, code)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=X.device)
+    off = (-ws.data_ptr()) % 256
+    wsv = ws[off:off + ws_bytes]
+    h = ctypes.c_void_p(None)
+    st = lib().dm_prepare(_dev_ptr(X, "X"), n, d, metric, code, ctypes.c_void_p(wsv.data_ptr()), ws_bytes,
+                          _stream_ptr(stream), ctypes.byref(h))
+    _check(st, "dm_prepare")
+    return Handle(h, ws, n, d, metric, code)

@@ -1,0 +1,437 @@
+// dm_api.hip - the C ABI (include/dm.h): argument validation, workspace
+// layout, the handle, and the order of kernel launches for preparation
+// (Algorithm 1) and queries (Algorithms 2 and 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dm.h"
+#include "dm_internal.h"
+
+using namespace dm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t al(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool valid_metric(int32_t m) { return m == DM_L1 || m == DM_L2SQ; }
+bool valid_dtype(int32_t t) { return t == DM_F32 || t == DM_F64 || t == DM_I32 || t == DM_I64; }
+bool int_dtype(int32_t t) { return t == DM_I32 || t == DM_I64; }
+size_t dtype_size(int32_t t) { return (t == DM_F64 || t == DM_I64) ? 8 : 4; }
+
+constexpr int32_t L2_MAX_D = 512;   // LDS staging bound of the l2-squared kernels
+constexpr int32_t MAX_B = 64;
+
+// Byte layout of one dataset's workspace.
+struct Layout {
+    int64_t ld = 0;         // stride between coordinates of the d x n arrays
+    uint32_t ntiles = 0;    // sort tiles
+    size_t perm = 0, xs = 0, rank = 0, rowsum = 0, rownrm = 0, xcopy = 0, kmin = 0, kmax = 0, flags = 0;
+    size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0;
+    size_t k1 = 0, v1 = 0, counts = 0;
+    size_t total = 0;
+};
+
+Layout make_layout(int64_t n, int32_t d, int32_t metric) {
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += al(bytes);
+        return at;
+    };
+    L.ld = (n + 63) / 64 * 64;
+    const size_t arr = (size_t)d * (size_t)L.ld * 4;
+    if (metric == DM_L1) {
+        L.ntiles = (uint32_t)((size_t)d * (size_t)((n + SORT_TILE - 1) / SORT_TILE));
+        L.perm = take(arr);
+        L.xs = take(arr);
+        L.rank = take(arr);
+    } else {
+        L.xcopy = take((size_t)n * d * 4);
+    }
+    L.rowsum = take((size_t)n * 8);
+    L.rownrm = take((size_t)n * 8);
+    L.kmin = take((size_t)d * 4);
+    L.kmax = take((size_t)d * 4);
+    L.flags = take(16);
+    if (metric == DM_L1) {
+        L.key_off = take((size_t)d * 8);
+        L.key_len = take((size_t)d * 8);
+        L.tile_off = take((size_t)(d + 1) * 4);
+        L.tile_seg = take((size_t)L.ntiles * 4);
+        L.k1 = take(arr);
+        L.v1 = take(arr);
+        L.counts = take((size_t)L.ntiles * 256 * 4);
+    }
+    L.total = o;
+    return L;
+}
+
+dm_status check_shape(int64_t n, int32_t d, int32_t metric, int32_t dtype) {
+    if (n < 1 || d < 1) return DM_ERR_ARG;
+    if (!valid_metric(metric) || !valid_dtype(dtype)) return DM_ERR_ARG;
+    const int64_t ld = (n + 63) / 64 * 64;
+    if ((uint64_t)ld * (uint64_t)d >= (1ull << 32)) return DM_ERR_ARG;   // 32-bit positions
+    if (metric == DM_L2SQ && d > L2_MAX_D) return DM_ERR_ARG;
+    return DM_OK;
+}
+
+dm_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return DM_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return DM_ERR_NOMEM;
+    return DM_ERR_DEVICE;
+}
+
+#define DM_TRY(expr)                         \
+    do {                                     \
+        hipError_t e_ = (expr);              \
+        if (e_ != hipSuccess) return from_hip(e_); \
+    } while (0)
+
+dm_status device_ready(int* dev) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return DM_ERR_DEVICE;
+    if (hipGetDevice(dev) != hipSuccess) return DM_ERR_DEVICE;
+    return DM_OK;
+}
+
+// Control block owned by a handle: sticky status, chained-scan state, totals.
+struct Ctl {
+    uint32_t status;
+    uint32_t pad[63];
+    ChainState chain;
+    double T0[1024];
+    double U[1024];
+    double zl1[1024];
+};
+
+}  // namespace
+
+struct dm_handle {
+    int device = 0;
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t metric = 0;
+    int32_t dtype = 0;
+    bool is_int = false;
+    Layout L;
+    char* ws = nullptr;
+    bool owns_ws = false;
+    Ctl* ctl = nullptr;
+    char* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    double guard_scale = 0.0;   // sum of ranges (l1) or squared ranges (l2 squared)
+    hipStream_t last = nullptr;
+
+    template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+void release(dm_handle* h) {
+    if (!h) return;
+    if (h->scratch) (void)hipFree(h->scratch);
+    if (h->ctl) (void)hipFree(h->ctl);
+    if (h->owns_ws && h->ws) (void)hipFree(h->ws);
+    delete h;
+}
+
+double key_to_double(uint32_t k, bool is_int) {
+    if (is_int) return (double)(int32_t)(k ^ 0x80000000u);
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+size_t query_scratch_bytes(const dm_handle* h, int32_t b) {
+    size_t s = al(totals_scratch_bytes(h->n, b));
+    if (h->metric == DM_L1) s += al(l1_record_words(h->n, b, h->is_int, h->is_int ? IN_I64 : IN_F32) * 8);
+    else s += al(l2_scratch_bytes(h->n, h->d, b));
+    return s;
+}
+
+dm_status ensure_scratch(dm_handle* h, int32_t b, hipStream_t s) {
+    size_t need = 0;
+    // record size depends on the rounded-up b and (for integers) not on the z type
+    for (int32_t bb = 1; bb <= b; bb <<= 1) need = std::max(need, query_scratch_bytes(h, bb));
+    need = std::max(need, query_scratch_bytes(h, b));
+    if (need <= h->scratch_bytes) return DM_OK;
+    if (h->scratch) {
+        DM_TRY(hipStreamSynchronize(h->last));
+        DM_TRY(hipFree(h->scratch));
+        h->scratch = nullptr;
+        h->scratch_bytes = 0;
+    }
+    void* p = nullptr;
+    DM_TRY(hipMalloc(&p, need));
+    h->scratch = (char*)p;
+    h->scratch_bytes = need;
+    // tagged words must never match a live tag: start from zero (tag 0 is never used)
+    DM_TRY(launch_fill_u32((uint32_t*)p, 0u, need / 4, s));
+    return DM_OK;
+}
+
+dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
+    const Layout& L = h->L;
+    const int64_t n = h->n;
+    const int32_t d = h->d;
+    // segment tables: coordinate k is segment k
+    const uint32_t tps = (uint32_t)((n + SORT_TILE - 1) / SORT_TILE);
+    std::vector<int64_t> koff(d), klen(d, n);
+    std::vector<uint32_t> toff(d + 1), tseg((size_t)L.ntiles);
+    for (int32_t k = 0; k < d; ++k) {
+        koff[k] = (int64_t)k * L.ld;
+        toff[k] = (uint32_t)k * tps;
+        for (uint32_t t = 0; t < tps; ++t) tseg[(size_t)k * tps + t] = (uint32_t)k;
+    }
+    toff[d] = (uint32_t)d * tps;
+    DM_TRY(hipMemcpyAsync(h->ws + L.key_off, koff.data(), koff.size() * 8, hipMemcpyHostToDevice, s));
+    DM_TRY(hipMemcpyAsync(h->ws + L.key_len, klen.data(), klen.size() * 8, hipMemcpyHostToDevice, s));
+    DM_TRY(hipMemcpyAsync(h->ws + L.tile_off, toff.data(), toff.size() * 4, hipMemcpyHostToDevice, s));
+    DM_TRY(hipMemcpyAsync(h->ws + L.tile_seg, tseg.data(), tseg.size() * 4, hipMemcpyHostToDevice, s));
+    DM_TRY(hipStreamSynchronize(s));   // the host vectors die with this frame
+
+    SegTables tb;
+    tb.key_off = h->at<int64_t>(L.key_off);
+    tb.key_len = h->at<int64_t>(L.key_len);
+    tb.tile_off = h->at<uint32_t>(L.tile_off);
+    tb.tile_seg = h->at<uint32_t>(L.tile_seg);
+    tb.nseg = d;
+    tb.ntiles = L.ntiles;
+
+    uint32_t* K0 = h->at<uint32_t>(L.xs);     // keys after transposition; becomes xs
+    uint32_t* V0 = h->at<uint32_t>(L.rank);   // ids after pass 1; becomes rank
+    uint32_t* K1 = h->at<uint32_t>(L.k1);
+    uint32_t* V1 = h->at<uint32_t>(L.v1);
+    uint32_t* perm = h->at<uint32_t>(L.perm);
+    uint32_t* counts = h->at<uint32_t>(L.counts);
+
+    DM_TRY(launch_prep_transpose(h->dtype, X, n, d, K0, L.ld, nullptr, h->at<uint32_t>(L.kmin),
+                                 h->at<uint32_t>(L.kmax), h->at<uint32_t>(L.flags), s));
+    DM_TRY(launch_row_stats(h->dtype, X, n, d, h->ws + L.rowsum, h->ws + L.rownrm, s));
+
+    const uint32_t* kin[4] = {K0, K1, K0, K1};
+    const uint32_t* vin[4] = {nullptr, V1, V0, V1};
+    uint32_t* kout[4] = {K1, K0, K1, K0};
+    uint32_t* vout[4] = {V1, V0, V1, perm};
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        DM_TRY(launch_sort_count(kin[pass], counts, tb, shift, s));
+        DM_TRY(launch_sort_scan(counts, tb, s));
+        DM_TRY(launch_sort_scatter(kin[pass], vin[pass], kout[pass], vout[pass], pass == 3 ? V0 : nullptr, counts,
+                                   tb, shift, pass == 0, pass == 3, h->is_int, s));
+    }
+    return DM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dm_status_string(int32_t status) {
+    switch (status) {
+    case DM_OK: return "ok";
+    case DM_ERR_ARG: return "invalid argument";
+    case DM_ERR_NONFINITE: return "non-finite value (NaN or Inf)";
+    case DM_ERR_OVERFLOW: return "integer result may exceed int64";
+    case DM_ERR_NOMEM: return "device memory allocation failed";
+    case DM_ERR_DEVICE: return "no usable HIP device or a HIP call failed";
+    case DM_ERR_DTYPE: return "dtype not allowed here (or integer |x| >= 2^31)";
+    case DM_ERR_STATE: return "operation not supported by this handle";
+    default: return "unknown status";
+    }
+}
+
+dm_status dm_workspace_size(int64_t n, int32_t d, int32_t metric, int32_t dtype, size_t* bytes) {
+    if (!bytes) return DM_ERR_ARG;
+    dm_status st = check_shape(n, d, metric, dtype);
+    if (st != DM_OK) return st;
+    *bytes = make_layout(n, d, metric).total;
+    return DM_OK;
+}
+
+int dm_int_bound_ok(double sum_ranges, double z_l1) {
+    if (!(sum_ranges >= 0.0) || !(z_l1 >= 0.0)) return 0;
+    return (z_l1 * sum_ranges < 4611686018427387904.0) ? 1 : 0;   // 2^62
+}
+
+dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_t dtype, void* workspace,
+                     size_t ws_bytes, void* stream, dm_handle** out) {
+    if (!out) return DM_ERR_ARG;
+    *out = nullptr;
+    if (!X) return DM_ERR_ARG;
+    dm_status st = check_shape(n, d, metric, dtype);
+    if (st != DM_OK) return st;
+    const Layout L = make_layout(n, d, metric);
+    if (workspace && ws_bytes < L.total) return DM_ERR_ARG;
+    if (workspace && ((uintptr_t)workspace % ALIGN) != 0) return DM_ERR_ARG;
+    int dev = 0;
+    if ((st = device_ready(&dev)) != DM_OK) return st;
+
+    hipStream_t s = (hipStream_t)stream;
+    dm_handle* h = new (std::nothrow) dm_handle();
+    if (!h) return DM_ERR_NOMEM;
+    h->device = dev;
+    h->n = n;
+    h->d = d;
+    h->metric = metric;
+    h->dtype = dtype;
+    h->is_int = int_dtype(dtype);
+    h->L = L;
+    auto fail = [&](dm_status e) {
+        release(h);
+        return e;
+    };
+    if (workspace) {
+        h->ws = (char*)workspace;
+    } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, L.total) != hipSuccess) return fail(DM_ERR_NOMEM);
+        h->ws = (char*)p;
+        h->owns_ws = true;
+    }
+    {
+        void* p = nullptr;
+        if (hipMalloc(&p, sizeof(Ctl)) != hipSuccess) return fail(DM_ERR_NOMEM);
+        h->ctl = (Ctl*)p;
+    }
+    Ctl init;
+    std::memset(&init, 0, sizeof(init));
+    init.chain.epoch = 1;
+    if (hipMemcpyAsync(h->ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(DM_ERR_DEVICE);
+    if (launch_fill_u32(h->at<uint32_t>(L.kmin), 0xffffffffu, (size_t)d, s) != hipSuccess ||
+        launch_fill_u32(h->at<uint32_t>(L.kmax), 0u, (size_t)d, s) != hipSuccess ||
+        launch_fill_u32(h->at<uint32_t>(L.flags), 0u, 4, s) != hipSuccess)
+        return fail(DM_ERR_DEVICE);
+
+    if (metric == DM_L1) {
+        if ((st = prepare_l1(h, X, s)) != DM_OK) return fail(st);
+    } else {
+        if (launch_prep_transpose(dtype, X, n, d, nullptr, 0, h->ws + L.xcopy, h->at<uint32_t>(L.kmin),
+                                  h->at<uint32_t>(L.kmax), h->at<uint32_t>(L.flags), s) != hipSuccess)
+            return fail(DM_ERR_DEVICE);
+        if (launch_row_stats(dtype, X, n, d, h->ws + L.rowsum, h->ws + L.rownrm, s) != hipSuccess)
+            return fail(DM_ERR_DEVICE);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(DM_ERR_DEVICE);
+    uint32_t flags = 0;
+    std::vector<uint32_t> kmin(d), kmax(d);
+    if (hipMemcpy(&flags, h->ws + L.flags, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(kmin.data(), h->ws + L.kmin, (size_t)d * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(kmax.data(), h->ws + L.kmax, (size_t)d * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(DM_ERR_DEVICE);
+    if (flags & FLAG_NONFINITE) return fail(DM_ERR_NONFINITE);
+    if (flags & FLAG_INT_RANGE) return fail(DM_ERR_DTYPE);
+    double g = 0.0;
+    for (int32_t k = 0; k < d; ++k) {
+        const double r = key_to_double(kmax[k], h->is_int) - key_to_double(kmin[k], h->is_int);
+        g += metric == DM_L1 ? r : r * r;
+    }
+    h->guard_scale = g;
+    h->last = s;
+    *out = h;
+    return DM_OK;
+}
+
+dm_status dm_reserve(dm_handle* h, int32_t b) {
+    if (!h || b < 1 || b > MAX_B) return DM_ERR_ARG;
+    dm_status st = ensure_scratch(h, b, h->last);
+    if (st != DM_OK) return st;
+    return hipStreamSynchronize(h->last) == hipSuccess ? DM_OK : DM_ERR_DEVICE;
+}
+
+dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream) {
+    if (!h || !Z || !Out || b < 1 || b > MAX_B) return DM_ERR_ARG;
+    if (!valid_dtype(z_dtype)) return DM_ERR_ARG;
+    if (h->is_int ? !(z_dtype == DM_I32 || z_dtype == DM_I64) : z_dtype != DM_F32) return DM_ERR_DTYPE;
+    const size_t zbytes = (size_t)h->n * b * dtype_size(z_dtype);
+    const size_t obytes = (size_t)h->n * b * (h->is_int ? 8 : 4);
+    const char* zp = (const char*)Z;
+    const char* op = (const char*)Out;
+    if (zp < op + obytes && op < zp + zbytes) return DM_ERR_ARG;   // overlap
+    hipStream_t s = (hipStream_t)stream;
+    dm_status st = ensure_scratch(h, b, s);
+    if (st != DM_OK) return st;
+    const int zkind = h->is_int ? (z_dtype == DM_I32 ? IN_I32 : IN_I64) : IN_F32;
+    char* sc = h->scratch;
+    TotalsOut tot;
+    tot.T0 = h->ctl->T0;
+    tot.U = h->ctl->U;
+    tot.zl1 = h->ctl->zl1;
+    tot.status = &h->ctl->status;
+    tot.partials = sc;
+    char* rest = sc + al(totals_scratch_bytes(h->n, b));
+    h->last = s;
+    if (h->metric == DM_L1) {
+        DM_TRY(launch_totals(h->is_int, zkind, Z, h->n, b, h->ws + h->L.rowsum, h->guard_scale, tot, s));
+        L1PassArgs a;
+        a.n = h->n;
+        a.Z = Z;
+        a.Out = Out;
+        a.T0 = tot.T0;
+        a.U = tot.U;
+        a.chain = &h->ctl->chain;
+        a.records = (uint64_t*)rest;
+        const size_t vsz = 4;
+        for (int32_t k = 0; k < h->d; ++k) {
+            a.perm = h->at<uint32_t>(h->L.perm) + (size_t)k * h->L.ld;
+            a.xs = h->ws + h->L.xs + (size_t)k * h->L.ld * vsz;
+            a.first = k == 0;
+            DM_TRY(launch_l1_pass(h->is_int, zkind, b, a, s));
+        }
+    } else {
+        DM_TRY(launch_l2sq(h->is_int, zkind, h->ws + h->L.xcopy, h->ws + h->L.rownrm, h->n, h->d, Z, b, Out, rest,
+                           tot, h->guard_scale, s));
+    }
+    return DM_OK;
+}
+
+dm_status dm_sync(dm_handle* h) {
+    if (!h) return DM_ERR_ARG;
+    if (hipStreamSynchronize(h->last) != hipSuccess) return DM_ERR_DEVICE;
+    uint32_t st = 0;
+    if (hipMemcpy(&st, &h->ctl->status, 4, hipMemcpyDeviceToHost) != hipSuccess) return DM_ERR_DEVICE;
+    if (st) {
+        const uint32_t zero = 0;
+        if (hipMemcpy(&h->ctl->status, &zero, 4, hipMemcpyHostToDevice) != hipSuccess) return DM_ERR_DEVICE;
+    }
+    if (st & QF_NONFINITE) return DM_ERR_NONFINITE;
+    if (st & QF_OVERFLOW) return DM_ERR_OVERFLOW;
+    return DM_OK;
+}
+
+dm_status dm_info(const dm_handle* h, int64_t* n, int32_t* d, int32_t* metric, int32_t* dtype) {
+    if (!h) return DM_ERR_ARG;
+    if (n) *n = h->n;
+    if (d) *d = h->d;
+    if (metric) *metric = h->metric;
+    if (dtype) *dtype = h->dtype;
+    return DM_OK;
+}
+
+dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, void* xs, void* stream) {
+    if (!h) return DM_ERR_ARG;
+    if (h->metric != DM_L1) return DM_ERR_STATE;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t w = (size_t)h->n * 4, sp = (size_t)h->L.ld * 4;
+    if (perm) DM_TRY(hipMemcpy2DAsync(perm, w, h->ws + h->L.perm, sp, w, h->d, hipMemcpyDeviceToDevice, s));
+    if (rank) DM_TRY(hipMemcpy2DAsync(rank, w, h->ws + h->L.rank, sp, w, h->d, hipMemcpyDeviceToDevice, s));
+    if (xs) DM_TRY(hipMemcpy2DAsync(xs, w, h->ws + h->L.xs, sp, w, h->d, hipMemcpyDeviceToDevice, s));
+    return DM_OK;
+}
+
+void dm_free(dm_handle* h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->last);
+    release(h);
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// dm_internal.h - host-side declarations shared by the C-ABI layer and the
+// kernel translation units.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dm {
+
+// element kinds of the point data as seen by the kernels
+enum InKind { IN_F32 = 1, IN_F64 = 2, IN_I32 = 3, IN_I64 = 4 };
+
+// prep flags written by the device
+enum PrepFlag : uint32_t { FLAG_NONFINITE = 1u, FLAG_INT_RANGE = 2u };
+
+// sticky query status bits (device side)
+enum QueryFlag : uint32_t { QF_NONFINITE = 1u, QF_OVERFLOW = 2u };
+
+constexpr int SORT_TILE = 4096;   // keys per sort tile (256 threads x 16)
+constexpr int SORT_THREADS = 256;
+
+// Self-maintained state of one chained-scan pass family.  `ticket` hands out
+// tile indices in dispatch order, `done` counts finished tiles; the last tile
+// of a pass resets both and advances `epoch`, which tags every word the pass
+// publishes.  Initialised to {0, 0, 1} once, never touched by the host again.
+struct ChainState {
+    uint32_t ticket;
+    uint32_t done;
+    uint32_t epoch;
+    uint32_t pad[61];
+};
+
+// Segment tables of a segmented sort: segment s holds keys
+// [key_off[s], key_off[s] + key_len[s]) and tiles [tile_off[s], tile_off[s+1]).
+struct SegTables {
+    const int64_t* key_off;    // S
+    const int64_t* key_len;    // S
+    const uint32_t* tile_off;  // S + 1
+    const uint32_t* tile_seg;  // T
+    int32_t nseg;
+    uint32_t ntiles;
+};
+
+// ---- preparation ----------------------------------------------------------
+hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d,
+                                 uint32_t* keys /* d rows of stride ld, or NULL */, int64_t ld,
+                                 void* xcopy /* n x d (4-byte) or NULL */,
+                                 uint32_t* kmin, uint32_t* kmax, uint32_t* flags,
+                                 hipStream_t s);
+hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d,
+                            void* rowsum /* n x 8B */, void* rownrm /* n x 8B */, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
+
+// ---- segmented radix sort (LSD, 4 passes of 8 bits) -----------------------
+hipError_t launch_sort_count(const uint32_t* keys, uint32_t* counts, const SegTables& t, int shift,
+                             hipStream_t s);
+hipError_t launch_sort_scan(uint32_t* counts, const SegTables& t, hipStream_t s);
+hipError_t launch_sort_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                               uint32_t* rank_out, const uint32_t* offs, const SegTables& t, int shift,
+                               bool first, bool last, bool is_int, hipStream_t s);
+
+// ---- l1 query --------------------------------------------------------------
+// totals: T0[c] = sum_j z_jc, U[c] = sum_j w_j z_jc, |z_c|_1; with guards.
+struct TotalsOut {
+    void* T0;        // b x (double | int64)
+    void* U;         // b x (double | int64)
+    double* zl1;     // b
+    void* partials;  // scratch
+    uint32_t* status;
+};
+int totals_partial_blocks(int64_t n);
+size_t totals_scratch_bytes(int64_t n, int32_t b);
+hipError_t launch_totals(bool is_int, int zkind, const void* Z, int64_t n, int32_t b, const void* w,
+                         double guard_scale, const TotalsOut& o, hipStream_t s);
+
+struct L1PassArgs {
+    const uint32_t* perm;   // n (this coordinate)
+    const void* xs;         // n (float | int32)
+    int64_t n;
+    const void* Z;          // n x b
+    void* Out;              // n x b (float | int64)
+    const void* T0;         // b
+    const void* U;          // b (added when first)
+    int first;
+    ChainState* chain;
+    uint64_t* records;      // 2 * ntiles * 4 * b words
+};
+int l1_tile_ranks(int32_t b, bool is_int, int zkind);
+size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind);
+hipError_t launch_l1_pass(bool is_int, int zkind, int32_t b, const L1PassArgs& a, hipStream_t s);
+
+// ---- l2 squared query ------------------------------------------------------
+size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b);
+hipError_t launch_l2sq(bool is_int, int zkind, const void* Xc, const void* nrm, int64_t n, int32_t d,
+                       const void* Z, int32_t b, void* Out, void* scratch, const TotalsOut& tot,
+                       double guard_scale, hipStream_t s);
+
+}  // namespace dm

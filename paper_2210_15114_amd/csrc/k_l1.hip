@@ -1,0 +1,563 @@
+// k_l1.hip - the l1 query (Algorithm 2, Section 2) for b right-hand sides.
+//
+// For one coordinate k with sorted order perm and sorted values xs, and
+// inclusive prefix sums in that order
+//     P0(r) = sum_{r' <= r} z[perm[r']],   P1(r) = sum_{r' <= r} xs[r'] z[perm[r']],
+// the coordinate's share of (A z) at point perm[r] is
+//     xs[r] (2 P0(r) - T0) - (2 P1(r) - T1)
+// (the S1..S4 split of the exactness proof, with S1 = P1, S2 = T1 - P1,
+// S3 = P0 and S4 = T0 - P0; the point's own term is zero, so including it in
+// the prefix changes nothing).  Summed over k the T1 terms give
+// U = sum_j s_j z_j with s_j = sum_k x_jk, so each pass adds
+//     c = xs (2 P0 - T0) - 2 P1
+// to Out[perm[r]] and the first pass also adds U.
+//
+// Algorithm 2 materialises the prefix arrays B_i and C_i and looks positions
+// up per point; here the two loops are fused into one pass per coordinate:
+// the sorted order is walked once, the prefixes live in registers, and each
+// result is scattered to its point's row.  Every pass visits each row of Out
+// exactly once (perm is a permutation), so passes are stream-ordered and a
+// pass needs no atomics on Out.
+//
+// One pass = one launch, one tile of TILE consecutive ranks per workgroup.
+// Tiles take indices from a ticket counter in dispatch order and chain their
+// prefixes with a decoupled look-back over tagged 64-bit words.  Float data
+// carries the prefixes between threads, waves and tiles as double-float
+// (hi, lo) FP32 pairs; inside a thread the short runs are plain FP32 relative
+// to that carry.  Integer data runs in wrapping int64, which is exact modulo
+// 2^64.
+#include "dm_device.h"
+#include "dm_internal.h"
+
+namespace dm {
+namespace {
+
+template <int BP> struct Lay {
+    static constexpr int CPL = BP >= 4 ? 4 : BP;  // columns per lane
+    static constexpr int LPR = BP / CPL;          // lanes per row
+    static constexpr int RPW = DM_WAVE / LPR;     // rows (slots) per wave
+    static constexpr int NS = 4 * RPW;            // slots per workgroup
+};
+
+// ---------------------------------------------------------------------------
+// arithmetic of the two data kinds
+// ---------------------------------------------------------------------------
+struct FloatPath {
+    using Z = float;
+    using O = float;
+    using X = float;
+    using L = float;   // thread-local partial sums
+    using C = dd;      // carries between threads, waves and tiles
+    using T = double;  // totals T0 and U
+    struct Fin { float d0, e1, u; };
+
+    __device__ static L lzero() { return 0.0f; }
+    __device__ static L ladd(L a, Z g) { return a + g; }
+    __device__ static L lmac(L a, X x, Z g) { return fmaf(x, g, a); }
+    __device__ static L lsum(L a, L b) { return a + b; }
+    __device__ static L shfl_up(L v, int o) { return __shfl_up(v, o, 64); }
+    __device__ static C czero() { return dd{0.0f, 0.0f}; }
+    __device__ static C cadd(C a, C b) { return dd_add(a, b); }
+    __device__ static C caddl(C a, L b) { return dd_add_f(a, b); }
+    __device__ static void enc(C c, uint32_t& w0, uint32_t& w1) {
+        w0 = __float_as_uint(c.hi);
+        w1 = __float_as_uint(c.lo);
+    }
+    __device__ static C dec(uint32_t w0, uint32_t w1) { return dd{__uint_as_float(w0), __uint_as_float(w1)}; }
+    __device__ static Fin fin(C b0, C b1, T t0, T u) {
+        Fin f;
+        f.d0 = (float)(2.0 * dd_to_f64(b0) - t0);
+        f.e1 = (float)(2.0 * dd_to_f64(b1));
+        f.u = (float)u;
+        return f;
+    }
+    __device__ static O out(L l0, L l1, X x, const Fin& f) {
+        const float a = fmaf(2.0f, l0, f.d0);
+        const float e = fmaf(2.0f, l1, f.e1);
+        return fmaf(x, a, -e);
+    }
+    __device__ static O oadd(O a, O b) { return a + b; }
+    __device__ static O ufirst(const Fin& f) { return f.u; }
+};
+
+template <typename ZT> struct IntPath {
+    using Z = ZT;
+    using O = int64_t;
+    using X = int32_t;
+    using L = int64_t;
+    using C = int64_t;
+    using T = int64_t;
+    struct Fin { int64_t d0, e1, u; };
+
+    __device__ static int64_t w(uint64_t v) { return (int64_t)v; }
+    __device__ static L lzero() { return 0; }
+    __device__ static L ladd(L a, Z g) { return w((uint64_t)a + (uint64_t)(int64_t)g); }
+    __device__ static L lmac(L a, X x, Z g) { return w((uint64_t)a + (uint64_t)(int64_t)x * (uint64_t)(int64_t)g); }
+    __device__ static L lsum(L a, L b) { return w((uint64_t)a + (uint64_t)b); }
+    __device__ static L shfl_up(L v, int o) { return __shfl_up(v, o, 64); }
+    __device__ static C czero() { return 0; }
+    __device__ static C cadd(C a, C b) { return w((uint64_t)a + (uint64_t)b); }
+    __device__ static C caddl(C a, L b) { return w((uint64_t)a + (uint64_t)b); }
+    __device__ static void enc(C c, uint32_t& w0, uint32_t& w1) {
+        w0 = (uint32_t)(uint64_t)c;
+        w1 = (uint32_t)((uint64_t)c >> 32);
+    }
+    __device__ static C dec(uint32_t w0, uint32_t w1) { return (int64_t)(((uint64_t)w1 << 32) | w0); }
+    __device__ static Fin fin(C b0, C b1, T t0, T u) {
+        Fin f;
+        f.d0 = w(2ull * (uint64_t)b0 - (uint64_t)t0);
+        f.e1 = w(2ull * (uint64_t)b1);
+        f.u = u;
+        return f;
+    }
+    __device__ static O out(L l0, L l1, X x, const Fin& f) {
+        const uint64_t a = (uint64_t)f.d0 + 2ull * (uint64_t)l0;
+        const uint64_t e = (uint64_t)f.e1 + 2ull * (uint64_t)l1;
+        return w((uint64_t)(int64_t)x * a - e);
+    }
+    __device__ static O oadd(O a, O b) { return w((uint64_t)a + (uint64_t)b); }
+    __device__ static O ufirst(const Fin& f) { return f.u; }
+};
+
+// load / store CPL consecutive columns of one row
+template <int CPL, bool VEC, typename E>
+__device__ __forceinline__ void load_row(const E* __restrict__ row, int col0, int b, bool valid, E (&v)[CPL]) {
+    if constexpr (VEC && CPL == 4 && sizeof(E) == 4) {
+        if (valid) {
+            const auto t = *reinterpret_cast<const uint4*>(row + col0);
+            v[0] = __builtin_bit_cast(E, t.x); v[1] = __builtin_bit_cast(E, t.y);
+            v[2] = __builtin_bit_cast(E, t.z); v[3] = __builtin_bit_cast(E, t.w);
+        } else {
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) v[j] = E(0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) v[j] = (valid && col0 + j < b) ? row[col0 + j] : E(0);
+    }
+}
+template <int CPL, bool VEC, typename E>
+__device__ __forceinline__ void store_row(E* __restrict__ row, int col0, int b, const E (&v)[CPL]) {
+    if constexpr (VEC && CPL == 4 && sizeof(E) == 4) {
+        uint4 t;
+        t.x = __builtin_bit_cast(uint32_t, v[0]); t.y = __builtin_bit_cast(uint32_t, v[1]);
+        t.z = __builtin_bit_cast(uint32_t, v[2]); t.w = __builtin_bit_cast(uint32_t, v[3]);
+        *reinterpret_cast<uint4*>(row + col0) = t;
+    } else {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j)
+            if (col0 + j < b) row[col0 + j] = v[j];
+    }
+}
+
+template <typename P, int BP, int R, bool VEC>
+__global__ __launch_bounds__(256) void l1_pass_kernel(
+    const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
+    const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
+    const typename P::T* __restrict__ T0, const typename P::T* __restrict__ U, int first,
+    ChainState* __restrict__ chain, uint64_t* __restrict__ rec)
+{
+    using L = typename P::L;
+    using C = typename P::C;
+    using Ly = Lay<BP>;
+    constexpr int CPL = Ly::CPL, LPR = Ly::LPR, RPW = Ly::RPW, NS = Ly::NS;
+    constexpr int TILE = NS * R;
+    constexpr int WPR = 4 * BP;  // tagged words per record: (P0 a, P0 b, P1 a, P1 b) per column
+
+    __shared__ uint32_t s_tile, s_tag;
+    __shared__ L s_wtot[4][2][BP];
+    __shared__ C s_wexcl[4][2][BP];
+    __shared__ C s_tot[2][BP];
+    __shared__ C s_carry[2][BP];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) {
+        s_tile = atomicAdd(&chain->ticket, 1u);
+        s_tag = __hip_atomic_load(&chain->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t tile = s_tile, tag = s_tag;
+    const int slot = w * RPW + lane / LPR;
+    const int col0 = (lane % LPR) * CPL;
+    const int64_t r0 = (int64_t)tile * TILE + (int64_t)slot * R;
+
+    // ---- gather: sorted ranks [r0, r0 + R) of this slot, CPL columns ----
+    uint32_t p[R];
+    typename P::X x[R];
+    typename P::Z g[R][CPL];
+    typename P::O o[R][CPL];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const bool valid = r0 + i < n;
+        p[i] = valid ? perm[r0 + i] : 0u;
+        x[i] = valid ? xs[r0 + i] : typename P::X(0);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const bool valid = r0 + i < n;
+        load_row<CPL, VEC>(Z + (size_t)p[i] * b, col0, b, valid, g[i]);
+        if (!first) {
+            load_row<CPL, VEC>(Out + (size_t)p[i] * b, col0, b, valid, o[i]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) o[i][j] = typename P::O(0);
+        }
+    }
+
+    // ---- thread aggregates and the exclusive scan over the wave's slots ----
+    L a0[CPL], a1[CPL], e0[CPL], e1[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) { a0[j] = P::lzero(); a1[j] = P::lzero(); }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            a0[j] = P::ladd(a0[j], g[i][j]);
+            a1[j] = P::lmac(a1[j], x[i], g[i][j]);
+        }
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        L i0 = a0[j], i1 = a1[j];
+#pragma unroll
+        for (int off = LPR; off < DM_WAVE; off <<= 1) {
+            const L t0 = P::shfl_up(i0, off), t1 = P::shfl_up(i1, off);
+            if (lane >= off) { i0 = P::lsum(i0, t0); i1 = P::lsum(i1, t1); }
+        }
+        const L x0 = P::shfl_up(i0, LPR), x1 = P::shfl_up(i1, LPR);
+        e0[j] = lane >= LPR ? x0 : P::lzero();
+        e1[j] = lane >= LPR ? x1 : P::lzero();
+        if (lane >= DM_WAVE - LPR) {
+            s_wtot[w][0][col0 + j] = i0;
+            s_wtot[w][1][col0 + j] = i1;
+        }
+    }
+    __syncthreads();
+
+    // ---- across the 4 waves; publish the tile aggregate ----
+    if (tid < 2 * BP) {
+        const int qt = tid / BP, c = tid % BP;
+        C acc = P::czero();
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+            s_wexcl[ww][qt][c] = acc;
+            acc = P::caddl(acc, s_wtot[ww][qt][c]);
+        }
+        s_tot[qt][c] = acc;
+        if (c < b) {
+            uint32_t w0, w1;
+            P::enc(acc, w0, w1);
+            uint64_t* dst = rec + ((size_t)tile * 2 + (tile == 0 ? 1 : 0)) * WPR + c * 4 + qt * 2;
+            publish_word(dst, tag_word(tag, w0));
+            publish_word(dst + 1, tag_word(tag, w1));
+        }
+    }
+    __syncthreads();
+
+    // ---- decoupled look-back (wave 0, lane = column) ----
+    if (w == 0) {
+        const int c = lane;
+        const bool act = c < b;
+        C c0 = P::czero(), c1 = P::czero();
+        if (tile > 0) {
+            int64_t pi = (int64_t)tile - 1;
+            for (;;) {
+                const uint64_t* ri = rec + ((size_t)pi * 2 + 1) * WPR + c * 4;
+                uint64_t v[4];
+                bool ok = true;
+                if (act) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        v[k] = peek_word(ri + k);
+                        ok = ok && (uint32_t)(v[k] >> 32) == tag;
+                    }
+                }
+                if (__all(ok)) {
+                    if (act) {
+                        c0 = P::cadd(c0, P::dec((uint32_t)v[0], (uint32_t)v[1]));
+                        c1 = P::cadd(c1, P::dec((uint32_t)v[2], (uint32_t)v[3]));
+                    }
+                    break;
+                }
+                const uint64_t* ra = rec + ((size_t)pi * 2) * WPR + c * 4;
+                ok = true;
+                if (act) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        v[k] = peek_word(ra + k);
+                        ok = ok && (uint32_t)(v[k] >> 32) == tag;
+                    }
+                }
+                if (__all(ok)) {
+                    if (act) {
+                        c0 = P::cadd(c0, P::dec((uint32_t)v[0], (uint32_t)v[1]));
+                        c1 = P::cadd(c1, P::dec((uint32_t)v[2], (uint32_t)v[3]));
+                    }
+                    --pi;
+                    continue;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (act) {
+            s_carry[0][c] = c0;
+            s_carry[1][c] = c1;
+            if (tile > 0) {
+                uint32_t w0, w1, w2, w3;
+                P::enc(P::cadd(c0, s_tot[0][c]), w0, w1);
+                P::enc(P::cadd(c1, s_tot[1][c]), w2, w3);
+                uint64_t* dst = rec + ((size_t)tile * 2 + 1) * WPR + c * 4;
+                publish_word(dst + 0, tag_word(tag, w0));
+                publish_word(dst + 1, tag_word(tag, w1));
+                publish_word(dst + 2, tag_word(tag, w2));
+                publish_word(dst + 3, tag_word(tag, w3));
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- combine and scatter ----
+    typename P::Fin f[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int c = col0 + j;
+        if (c < b) {
+            C b0 = P::caddl(P::cadd(s_carry[0][c], s_wexcl[w][0][c]), e0[j]);
+            C b1 = P::caddl(P::cadd(s_carry[1][c], s_wexcl[w][1][c]), e1[j]);
+            f[j] = P::fin(b0, b1, T0[c], first ? U[c] : typename P::T(0));
+        } else {
+            f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
+        }
+    }
+    L l0[CPL], l1[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) { l0[j] = P::lzero(); l1[j] = P::lzero(); }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        typename P::O res[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            l0[j] = P::ladd(l0[j], g[i][j]);
+            l1[j] = P::lmac(l1[j], x[i], g[i][j]);
+            const typename P::O cval = P::out(l0[j], l1[j], x[i], f[j]);
+            res[j] = first ? P::oadd(cval, P::ufirst(f[j])) : P::oadd(o[i][j], cval);
+        }
+        if (r0 + i < n) store_row<CPL, VEC>(Out + (size_t)p[i] * b, col0, b, res);
+    }
+
+    // ---- the last tile to finish resets the ticket and advances the tag ----
+    if (tid == 0) {
+        const uint32_t prev = atomicAdd(&chain->done, 1u);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(&chain->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&chain->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t next = tag + 1u == 0u ? 1u : tag + 1u;
+            __hip_atomic_store(&chain->epoch, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// totals: T0[c] = sum_j z_jc, U[c] = sum_j w_j z_jc, and ||z_c||_1
+// two fixed-order stages (per-block partials, then one block), so FP64
+// results are reproducible run to run.
+// ---------------------------------------------------------------------------
+constexpr int TOT_ROWS = 4096;  // rows per stage-1 block
+constexpr int TOT_MAXB = 1024;
+
+template <bool INT, typename ZT, typename WT>
+__global__ __launch_bounds__(256) void totals_stage1(const ZT* __restrict__ Z, int64_t n, int32_t b,
+                                                     const WT* __restrict__ wgt, void* __restrict__ partials,
+                                                     uint32_t* __restrict__ status)
+{
+    // thread layout: column c = tid % BPc, row lane = tid / BPc
+    int bpc = 1;
+    while (bpc < b && bpc < 256) bpc <<= 1;
+    const int rl = threadIdx.x / bpc, rs = 256 / bpc;
+    const int64_t j0 = (int64_t)blockIdx.x * TOT_ROWS;
+    const int64_t j1 = min(n, j0 + TOT_ROWS);
+    __shared__ double s_f[3][256];
+    __shared__ int64_t s_i[2][256];
+    uint32_t bad = 0;
+    for (int cbase = 0; cbase < b; cbase += bpc) {
+        const int c = cbase + (int)(threadIdx.x % bpc);
+        double f0 = 0.0, f1 = 0.0, fl = 0.0;
+        uint64_t i0 = 0, i1 = 0;
+        if (c < b) {
+            for (int64_t j = j0 + rl; j < j1; j += rs) {
+                const ZT z = Z[j * b + c];
+                if constexpr (INT) {
+                    i0 += (uint64_t)(int64_t)z;
+                    i1 += (uint64_t)(int64_t)wgt[j] * (uint64_t)(int64_t)z;
+                    fl += fabs((double)z);
+                } else {
+                    if (!isfinite(z)) bad = 1;
+                    f0 += (double)z;
+                    f1 += (double)wgt[j] * (double)z;
+                    fl += fabs((double)z);
+                }
+            }
+        }
+        s_f[0][threadIdx.x] = f0; s_f[1][threadIdx.x] = f1; s_f[2][threadIdx.x] = fl;
+        s_i[0][threadIdx.x] = (int64_t)i0; s_i[1][threadIdx.x] = (int64_t)i1;
+        __syncthreads();
+        if ((int)threadIdx.x < bpc && c < b) {
+            double a0 = 0, a1 = 0, al = 0;
+            uint64_t b0 = 0, b1 = 0;
+            for (int r = 0; r < rs; ++r) {
+                const int t = r * bpc + threadIdx.x;
+                a0 += s_f[0][t]; a1 += s_f[1][t]; al += s_f[2][t];
+                b0 += (uint64_t)s_i[0][t]; b1 += (uint64_t)s_i[1][t];
+            }
+            double* pf = (double*)partials + ((size_t)blockIdx.x * b + c) * 3;
+            if constexpr (INT) {
+                pf[0] = __longlong_as_double((long long)b0);
+                pf[1] = __longlong_as_double((long long)b1);
+            } else {
+                pf[0] = a0;
+                pf[1] = a1;
+            }
+            pf[2] = al;
+        }
+        __syncthreads();
+    }
+    if (!INT && bad) atomicOr(status, (uint32_t)QF_NONFINITE);
+}
+
+template <bool INT>
+__global__ __launch_bounds__(256) void totals_stage2(const void* __restrict__ partials, int nblk, int32_t b,
+                                                     void* __restrict__ T0, void* __restrict__ U,
+                                                     double* __restrict__ zl1, double guard_scale,
+                                                     uint32_t* __restrict__ status)
+{
+    for (int c = threadIdx.x; c < b; c += blockDim.x) {
+        double a0 = 0, a1 = 0, al = 0;
+        uint64_t b0 = 0, b1 = 0;
+        for (int k = 0; k < nblk; ++k) {
+            const double* pf = (const double*)partials + ((size_t)k * b + c) * 3;
+            if (INT) {
+                b0 += (uint64_t)__double_as_longlong(pf[0]);
+                b1 += (uint64_t)__double_as_longlong(pf[1]);
+            } else {
+                a0 += pf[0];
+                a1 += pf[1];
+            }
+            al += pf[2];
+        }
+        if (INT) {
+            ((int64_t*)T0)[c] = (int64_t)b0;
+            ((int64_t*)U)[c] = (int64_t)b1;
+            // every |(A z)_i| <= ||z||_1 * max_ij A_ij <= ||z||_1 * guard_scale
+            if (!(al * guard_scale < 4611686018427387904.0)) atomicOr(status, (uint32_t)QF_OVERFLOW);
+        } else {
+            ((double*)T0)[c] = a0;
+            ((double*)U)[c] = a1;
+        }
+        zl1[c] = al;
+    }
+}
+
+}  // namespace
+
+int totals_partial_blocks(int64_t n) { return (int)((n + TOT_ROWS - 1) / TOT_ROWS); }
+
+size_t totals_scratch_bytes(int64_t n, int32_t b) {
+    return (size_t)totals_partial_blocks(n) * (size_t)b * 3 * sizeof(double);
+}
+
+hipError_t launch_totals(bool is_int, int zkind, const void* Z, int64_t n, int32_t b, const void* w,
+                         double guard_scale, const TotalsOut& o, hipStream_t s)
+{
+    if (b < 1 || b > TOT_MAXB) return hipErrorInvalidValue;
+    const int nblk = totals_partial_blocks(n);
+    if (!is_int) {
+        totals_stage1<false, float, double><<<nblk, 256, 0, s>>>((const float*)Z, n, b, (const double*)w,
+                                                                 o.partials, o.status);
+    } else if (zkind == IN_I32) {
+        totals_stage1<true, int32_t, int64_t><<<nblk, 256, 0, s>>>((const int32_t*)Z, n, b, (const int64_t*)w,
+                                                                   o.partials, o.status);
+    } else {
+        totals_stage1<true, int64_t, int64_t><<<nblk, 256, 0, s>>>((const int64_t*)Z, n, b, (const int64_t*)w,
+                                                                   o.partials, o.status);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (is_int)
+        totals_stage2<true><<<1, 256, 0, s>>>(o.partials, nblk, b, o.T0, o.U, o.zl1, guard_scale, o.status);
+    else
+        totals_stage2<false><<<1, 256, 0, s>>>(o.partials, nblk, b, o.T0, o.U, o.zl1, guard_scale, o.status);
+    return hipGetLastError();
+}
+
+// ranks per slot (R) for each configuration
+template <int BP> constexpr int r_float() { return BP >= 4 ? 8 : 16; }
+template <int BP> constexpr int r_int() { return BP >= 4 ? 4 : 8; }
+
+static int bpad(int32_t b) {
+    int bp = 1;
+    while (bp < b) bp <<= 1;
+    return bp;
+}
+
+int l1_tile_ranks(int32_t b, bool is_int, int zkind) {
+    (void)zkind;
+    const int bp = bpad(b);
+    const int cpl = bp >= 4 ? 4 : bp;
+    const int ns = 4 * (64 / (bp / cpl));
+    int r;
+    switch (bp) {
+    case 1: r = is_int ? r_int<1>() : r_float<1>(); break;
+    case 2: r = is_int ? r_int<2>() : r_float<2>(); break;
+    case 4: r = is_int ? r_int<4>() : r_float<4>(); break;
+    case 8: r = is_int ? r_int<8>() : r_float<8>(); break;
+    case 16: r = is_int ? r_int<16>() : r_float<16>(); break;
+    case 32: r = is_int ? r_int<32>() : r_float<32>(); break;
+    default: r = is_int ? r_int<64>() : r_float<64>(); break;
+    }
+    return ns * r;
+}
+
+size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind) {
+    const int64_t tile = l1_tile_ranks(b, is_int, zkind);
+    const int64_t ntiles = (n + tile - 1) / tile;
+    return (size_t)ntiles * 2 * 4 * (size_t)bpad(b);
+}
+
+template <typename P, int BP, int R>
+static hipError_t launch_one(const L1PassArgs& a, int32_t b, hipStream_t s) {
+    constexpr int TILE = Lay<BP>::NS * R;
+    const int64_t ntiles = (a.n + TILE - 1) / TILE;
+    const bool vec = (b == BP) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
+    if (vec)
+        l1_pass_kernel<P, BP, R, true><<<(unsigned)ntiles, 256, 0, s>>>(
+            a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, a.chain, a.records);
+    else
+        l1_pass_kernel<P, BP, R, false><<<(unsigned)ntiles, 256, 0, s>>>(
+            a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, a.chain, a.records);
+    return hipGetLastError();
+}
+
+template <typename P, bool INT>
+static hipError_t dispatch_b(const L1PassArgs& a, int32_t b, hipStream_t s) {
+    switch (bpad(b)) {
+    case 1: return launch_one<P, 1, INT ? r_int<1>() : r_float<1>()>(a, b, s);
+    case 2: return launch_one<P, 2, INT ? r_int<2>() : r_float<2>()>(a, b, s);
+    case 4: return launch_one<P, 4, INT ? r_int<4>() : r_float<4>()>(a, b, s);
+    case 8: return launch_one<P, 8, INT ? r_int<8>() : r_float<8>()>(a, b, s);
+    case 16: return launch_one<P, 16, INT ? r_int<16>() : r_float<16>()>(a, b, s);
+    case 32: return launch_one<P, 32, INT ? r_int<32>() : r_float<32>()>(a, b, s);
+    case 64: return launch_one<P, 64, INT ? r_int<64>() : r_float<64>()>(a, b, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_l1_pass(bool is_int, int zkind, int32_t b, const L1PassArgs& a, hipStream_t s)
+{
+    if (b < 1 || b > 64) return hipErrorInvalidValue;
+    if (!is_int) return dispatch_b<FloatPath, false>(a, b, s);
+    if (zkind == IN_I32) return dispatch_b<IntPath<int32_t>, true>(a, b, s);
+    return dispatch_b<IntPath<int64_t>, true>(a, b, s);
+}
+
+}  // namespace dm

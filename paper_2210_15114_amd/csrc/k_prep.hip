@@ -1,0 +1,192 @@
+// k_prep.hip - preparation kernels: validation, the coordinate-major key
+// arrays that Algorithm 1 sorts, per-coordinate ranges, FP32 copy of X for the
+// l2-squared query and the FP64/int64 row statistics.
+#include "dm_device.h"
+#include "dm_internal.h"
+
+namespace dm {
+namespace {
+
+// Value of one input element as the kernels see it (FP32 for float data,
+// int32 for integer data) plus validity bits.
+template <int KIND> struct In;
+template <> struct In<IN_F32> {
+    using T = float;
+    using V = float;
+    __device__ static V conv(T x, uint32_t& bad) {
+        if (!isfinite(x)) bad |= FLAG_NONFINITE;
+        return x;
+    }
+    __device__ static uint32_t key(V v) { return f32_key(v); }
+};
+template <> struct In<IN_F64> {
+    using T = double;
+    using V = float;
+    __device__ static V conv(T x, uint32_t& bad) {
+        float v = (float)x;                   // round to nearest even
+        if (!isfinite(x) || !isfinite(v)) bad |= FLAG_NONFINITE;
+        return v;
+    }
+    __device__ static uint32_t key(V v) { return f32_key(v); }
+};
+template <> struct In<IN_I32> {
+    using T = int32_t;
+    using V = int32_t;
+    __device__ static V conv(T x, uint32_t& bad) {
+        if (x == INT32_MIN) bad |= FLAG_INT_RANGE;      // |x| < 2^31 required
+        return x;
+    }
+    __device__ static uint32_t key(V v) { return i32_key(v); }
+};
+template <> struct In<IN_I64> {
+    using T = int64_t;
+    using V = int32_t;
+    __device__ static V conv(T x, uint32_t& bad) {
+        if (x <= -(int64_t(1) << 31) || x >= (int64_t(1) << 31)) bad |= FLAG_INT_RANGE;
+        return (int32_t)x;
+    }
+    __device__ static uint32_t key(V v) { return i32_key(v); }
+};
+
+constexpr int TT = 64;  // transpose tile: 64 rows x 64 coordinates
+
+// One 64 x 64 tile of X: validates it, writes its keys coordinate-major
+// (coalesced both ways through LDS), its FP32/int32 copy row-major, and folds
+// the tile's per-coordinate min/max keys into kmin/kmax.
+template <int KIND>
+__global__ __launch_bounds__(256) void prep_transpose_kernel(
+    const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d,
+    uint32_t* __restrict__ keys, int64_t ld, typename In<KIND>::V* __restrict__ xcopy,
+    uint32_t* __restrict__ kmin, uint32_t* __restrict__ kmax, uint32_t* __restrict__ flags)
+{
+    using I = In<KIND>;
+    __shared__ uint32_t tile[TT][TT + 1];
+    __shared__ uint32_t smin[4][TT], smax[4][TT];
+    const int64_t r0 = (int64_t)blockIdx.x * TT;
+    const int32_t c0 = blockIdx.y * TT;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int32_t col = c0 + tx;
+    uint32_t bad = 0, lo = 0xffffffffu, hi = 0u;
+    for (int rr = ty; rr < TT; rr += 4) {
+        int64_t row = r0 + rr;
+        uint32_t k = 0;
+        if (row < n && col < d) {
+            typename I::V v = I::conv(X[row * d + col], bad);
+            if (xcopy) xcopy[row * d + col] = v;
+            k = I::key(v);
+            lo = min(lo, k);
+            hi = max(hi, k);
+        }
+        tile[rr][tx] = k;
+    }
+    smin[ty][tx] = lo;
+    smax[ty][tx] = hi;
+    if (bad) atomicOr(flags, bad);
+    __syncthreads();
+    if (ty == 0 && col < d) {
+        uint32_t a = min(min(smin[0][tx], smin[1][tx]), min(smin[2][tx], smin[3][tx]));
+        uint32_t b = max(max(smax[0][tx], smax[1][tx]), max(smax[2][tx], smax[3][tx]));
+        atomicMin(kmin + col, a);
+        atomicMax(kmax + col, b);
+    }
+    if (keys) {
+        for (int cc = ty; cc < TT; cc += 4) {
+            int32_t c = c0 + cc;
+            int64_t row = r0 + tx;
+            if (c < d && row < n) keys[(int64_t)c * ld + row] = tile[tx][cc];
+        }
+    }
+}
+
+// Row statistics s_i = sum_k x_ik and ||x_i||^2, one thread per row, k
+// ascending (fixed order, so the FP64 sums are reproducible).
+template <int KIND>
+__global__ __launch_bounds__(256) void row_stats_kernel(
+    const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d, void* rowsum, void* rownrm)
+{
+    using I = In<KIND>;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const typename I::T* xi = X + i * d;
+    uint32_t bad = 0;
+    if constexpr (KIND == IN_F32 || KIND == IN_F64) {
+        double s = 0.0, q = 0.0;
+        for (int32_t k = 0; k < d; ++k) {
+            double v = (double)I::conv(xi[k], bad);
+            s += v;
+            q += v * v;
+        }
+        ((double*)rowsum)[i] = s;
+        ((double*)rownrm)[i] = q;
+    } else {
+        // wrapping int64: exact modulo 2^64
+        uint64_t s = 0, q = 0;
+        for (int32_t k = 0; k < d; ++k) {
+            int64_t v = (int64_t)I::conv(xi[k], bad);
+            s += (uint64_t)v;
+            q += (uint64_t)(v * v);
+        }
+        ((int64_t*)rowsum)[i] = (int64_t)s;
+        ((int64_t*)rownrm)[i] = (int64_t)q;
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t count) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < count; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d, uint32_t* keys,
+                                 int64_t ld, void* xcopy, uint32_t* kmin, uint32_t* kmax, uint32_t* flags,
+                                 hipStream_t s)
+{
+    dim3 grid((unsigned)((n + TT - 1) / TT), (unsigned)((d + TT - 1) / TT));
+    switch (kind) {
+    case IN_F32:
+        prep_transpose_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, keys, ld, (float*)xcopy,
+                                                           kmin, kmax, flags);
+        break;
+    case IN_F64:
+        prep_transpose_kernel<IN_F64><<<grid, 256, 0, s>>>((const double*)X, n, d, keys, ld, (float*)xcopy,
+                                                           kmin, kmax, flags);
+        break;
+    case IN_I32:
+        prep_transpose_kernel<IN_I32><<<grid, 256, 0, s>>>((const int32_t*)X, n, d, keys, ld,
+                                                           (int32_t*)xcopy, kmin, kmax, flags);
+        break;
+    case IN_I64:
+        prep_transpose_kernel<IN_I64><<<grid, 256, 0, s>>>((const int64_t*)X, n, d, keys, ld,
+                                                           (int32_t*)xcopy, kmin, kmax, flags);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d, void* rowsum, void* rownrm,
+                            hipStream_t s)
+{
+    unsigned grid = (unsigned)((n + 255) / 256);
+    switch (kind) {
+    case IN_F32: row_stats_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, rowsum, rownrm); break;
+    case IN_F64: row_stats_kernel<IN_F64><<<grid, 256, 0, s>>>((const double*)X, n, d, rowsum, rownrm); break;
+    case IN_I32: row_stats_kernel<IN_I32><<<grid, 256, 0, s>>>((const int32_t*)X, n, d, rowsum, rownrm); break;
+    case IN_I64: row_stats_kernel<IN_I64><<<grid, 256, 0, s>>>((const int64_t*)X, n, d, rowsum, rownrm); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    fill_u32_kernel<<<(unsigned)blocks, 256, 0, s>>>(p, v, count);
+    return hipGetLastError();
+}
+
+}  // namespace dm

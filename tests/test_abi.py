@@ -1,0 +1,94 @@
+"""The C ABI on the CPU: the library loads, exports what include/dm.h declares,
+and rejects bad arguments with the documented status before any device call."""
+import ctypes
+
+import pytest
+
+dm = pytest.importorskip("paper_2210_15114_amd")
+
+
+@pytest.fixture(scope="module")
+def L():
+    try:
+        return dm.lib()
+    except ImportError as e:
+        pytest.fail("libdm.so must be built before the tests: %s" % e)
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+def test_exports_every_declared_symbol(L):
+    names = dm.header_functions()
+    assert "dm_prepare" in names and "dm_matvec" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    for code in (dm.OK, dm.ERR_ARG, dm.ERR_NONFINITE, dm.ERR_OVERFLOW, dm.ERR_NOMEM, dm.ERR_DEVICE,
+                 dm.ERR_DTYPE, dm.ERR_STATE):
+        s = dm.status_string(code)
+        assert s and s != "unknown status"
+    assert dm.status_string(12345) == "unknown status"
+
+
+def test_workspace_size_validation(L):
+    out = ctypes.c_size_t(0)
+    f = L.dm_workspace_size
+    assert f(0, 4, dm.L1, dm.F32, ctypes.byref(out)) == dm.ERR_ARG
+    assert f(10, 0, dm.L1, dm.F32, ctypes.byref(out)) == dm.ERR_ARG
+    assert f(10, 4, 7, dm.F32, ctypes.byref(out)) == dm.ERR_ARG
+    assert f(10, 4, dm.L1, 9, ctypes.byref(out)) == dm.ERR_ARG
+    assert f(10, 4, dm.L1, dm.F32, None) == dm.ERR_ARG
+    assert f(1 << 31, 4, dm.L1, dm.F32, ctypes.byref(out)) == dm.ERR_ARG       # 32-bit positions
+    assert f(10, 4096, dm.L2SQ, dm.F32, ctypes.byref(out)) == dm.ERR_ARG        # l2 staging bound
+    assert f(1000, 16, dm.L1, dm.F32, ctypes.byref(out)) == dm.OK
+    small = out.value
+    assert f(4000, 16, dm.L1, dm.F32, ctypes.byref(out)) == dm.OK
+    assert out.value > small > 3 * 16 * 1000 * 4
+    assert dm.workspace_size(1000, 16, dm.L2SQ, dm.F32) >= 1000 * 16 * 4
+
+
+def test_prepare_argument_errors_before_device(L):
+    h = ctypes.c_void_p(None)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation first
+    P = L.dm_prepare
+    assert P(None, 10, 4, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 0, 4, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, -1, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, 4, 3, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, 4, dm.L1, 0, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, 4, dm.L1, dm.F32, fake, 16, None, ctypes.byref(h)) == dm.ERR_ARG   # short workspace
+    assert P(fake, 10, 4, dm.L1, dm.F32, None, 0, None, None) == dm.ERR_ARG
+    assert h.value is None
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_prepare_without_device(L):
+    h = ctypes.c_void_p(None)
+    st = L.dm_prepare(ctypes.c_void_p(0x1000), 10, 4, dm.L1, dm.F32, None, 0, None, ctypes.byref(h))
+    assert st == dm.ERR_DEVICE
+    assert h.value is None
+
+
+def test_null_handle_calls(L):
+    assert L.dm_matvec(None, ctypes.c_void_p(0x1000), dm.F32, 1, ctypes.c_void_p(0x2000), None) == dm.ERR_ARG
+    assert L.dm_sync(None) == dm.ERR_ARG
+    assert L.dm_reserve(None, 4) == dm.ERR_ARG
+    assert L.dm_info(None, None, None, None, None) == dm.ERR_ARG
+    assert L.dm_copy_sorted(None, None, None, None, None) == dm.ERR_ARG
+    L.dm_free(None)
+
+
+def test_int_bound_guard(L):
+    assert dm.int_bound_ok(1000.0, 1000.0)
+    assert dm.int_bound_ok(2.0 ** 31, 2.0 ** 30)
+    assert not dm.int_bound_ok(2.0 ** 31, 2.0 ** 31)          # 2^62 is not below 2^62
+    assert not dm.int_bound_ok(float("nan"), 1.0)
+    assert not dm.int_bound_ok(-1.0, 1.0)

@@ -1,0 +1,229 @@
+"""GPU parity of the l1 path (Algorithms 1 and 2) against the CPU oracle.
+
+Integer inputs: bit-exact against the exact int64 oracle (the method is exact,
+theorem for p = 1 in Section 2).  Float inputs: the FP32 result against the
+FP64 oracle evaluated on the same FP32-rounded inputs, within
+  * the normalised bound max|y - o| / (||A||_F ||z||_2) <= 1e-6, and
+  * the arithmetic bound |y_i - o_i| <= (8 + 3d) u32 S_i,
+    S_i = sum_k (|x_ik| ||z||_1 + sum_j |x_jk z_j|),
+    which follows from the FP32 operations the kernel performs on terms no
+    larger than S_i (the compensated carries add nothing at this order).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import L1
+
+from gpu_helpers import U32, dev, float_errors, method_scale_l1, run
+
+pytestmark = pytest.mark.gpu
+dm = pytest.importorskip("paper_2210_15114_amd")
+
+
+def _check_float(X32, Z32, Y, rows=None, spec=1e-6):
+    e, o = float_errors(X32, Z32, Y, L1, rows)
+    n, d = X32.shape
+    r = np.arange(n) if rows is None else np.asarray(rows)
+    S = method_scale_l1(X32, Z32, r)
+    err = np.abs(Y.reshape(n, -1)[r].astype(np.float64) - o)
+    worst = float((err / ((8 + 3 * d) * U32 * S)).max())
+    print("errors", e, "bound-ratio", worst)
+    assert e["spec"] <= spec
+    assert e["per_row"] <= spec
+    assert worst <= 1.0
+    return e
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1: the sort
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,d", [(1, 1), (7, 3), (4096, 2), (5000, 5), (12289, 2)])
+def test_sort_matches_stable_argsort(n, d):
+    g = synth.rng(1000 + n)
+    X = g.standard_normal((n, d)).astype(np.float32)
+    if n > 40:
+        X[10:30, 0] = 0.0
+        X[30:40, 0] = -0.0
+        X[::7, d - 1] = 1.5          # a long tie run
+    h = dm.prepare(dev(X), L1)
+    perm, rank, xs = [t.cpu().numpy() for t in h.sorted()]
+    p_ref, r_ref, xs_ref = oracle.sort_coords(X)
+    assert np.array_equal(perm, p_ref)
+    assert np.array_equal(rank, r_ref)
+    assert np.array_equal(xs.view(np.uint32), np.where(xs_ref == 0, np.float32(0), xs_ref).view(np.uint32))
+
+
+def test_sort_integers_and_extremes():
+    g = synth.rng(77)
+    X = g.integers(-(2 ** 31) + 1, 2 ** 31 - 1, size=(9000, 3), endpoint=True).astype(np.int64)
+    X[0, 0], X[1, 0] = 2 ** 31 - 1, -(2 ** 31) + 1
+    X[:, 2] = 5
+    h = dm.prepare(dev(X), L1)
+    perm, rank, xs = [t.cpu().numpy() for t in h.sorted()]
+    p_ref, r_ref, xs_ref = oracle.sort_coords(X)
+    assert np.array_equal(perm, p_ref)
+    assert np.array_equal(rank, r_ref)
+    assert np.array_equal(xs.astype(np.int64), xs_ref)
+
+
+# ---------------------------------------------------------------------------
+# the first workload: n = 2048, d = 16
+# ---------------------------------------------------------------------------
+def test_workload1_float():
+    X, z = synth.workload1("float")
+    X32, z32 = X.astype(np.float32), z.astype(np.float32)
+    Y, _ = run(X32, z32, L1)
+    _check_float(X32, z32, Y)
+
+
+def test_workload1_float64_input_rounded_once():
+    X, z = synth.workload1("float")
+    Y64, _ = run(X, z.astype(np.float32), L1)          # the library rounds X to FP32
+    Y32, _ = run(X.astype(np.float32), z.astype(np.float32), L1)
+    assert np.array_equal(Y64, Y32)
+
+
+def test_workload1_integer_bit_exact():
+    X, z = synth.workload1("int")
+    Y, _ = run(X, z, L1)
+    o, ov = oracle.matvec_int(X, z, L1)
+    assert ov == 0
+    assert np.array_equal(Y, o)
+
+
+# ---------------------------------------------------------------------------
+# batched right-hand sides, ragged tiles
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("b", [1, 2, 3, 4, 8, 16, 32, 40, 64])
+def test_batched_integer_bit_exact(b):
+    g = synth.rng(200 + b)
+    n, d = 3001, 3
+    X = g.integers(-2 ** 15, 2 ** 15, size=(n, d)).astype(np.int32)
+    Z = np.rint(4096 * g.standard_normal((n, b))).astype(np.int32)
+    Y, _ = run(X, Z, L1)
+    o, ov = oracle.matvec_int(X, Z, L1)
+    assert ov == 0
+    assert np.array_equal(Y, o)
+
+
+def test_batched_int64_rhs_bit_exact():
+    g = synth.rng(301)
+    n, d, b = 2500, 4, 8
+    X = g.integers(-1000, 1000, size=(n, d)).astype(np.int64)
+    Z = g.integers(-(2 ** 32), 2 ** 32, size=(n, b)).astype(np.int64)   # beyond int32, inside the guard
+    Y, _ = run(X, Z, L1)
+    o, ov = oracle.matvec_int(X, Z, L1)
+    assert ov == 0
+    assert np.array_equal(Y, o)
+
+
+@pytest.mark.parametrize("b", [1, 8, 64])
+def test_batched_float(b):
+    g = synth.rng(400 + b)
+    n, d = 5000, 6
+    X = g.random((n, d), dtype=np.float32)
+    Z = g.standard_normal((n, b), dtype=np.float32)
+    Y, _ = run(X, Z, L1)
+    _check_float(X, Z, Y, rows=np.arange(0, n, 3))
+
+
+def test_columns_equal_single_vector_queries():
+    g = synth.rng(500)
+    n, d, b = 4100, 5, 16
+    X = g.integers(-500, 500, size=(n, d)).astype(np.int32)
+    Z = g.integers(-3000, 3000, size=(n, b)).astype(np.int32)
+    import paper_2210_15114_amd as dmm
+    h = dmm.prepare(dev(X), L1)
+    Yb = h.matvec(dev(Z)).cpu().numpy()
+    for c in (0, 7, 15):
+        yc = h.matvec(dev(np.ascontiguousarray(Z[:, c]))).cpu().numpy()
+        assert np.array_equal(yc, Yb[:, c])
+    h.sync()
+
+
+def test_integer_runs_are_deterministic():
+    g = synth.rng(600)
+    X = g.integers(-100, 100, size=(20000, 4)).astype(np.int32)
+    Z = g.integers(-100, 100, size=(20000, 64)).astype(np.int32)
+    import paper_2210_15114_amd as dmm
+    h = dmm.prepare(dev(X), L1)
+    a = h.matvec(dev(Z)).cpu().numpy()
+    b = h.matvec(dev(Z)).cpu().numpy()
+    h.sync()
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# degenerate cases
+# ---------------------------------------------------------------------------
+def test_single_point():
+    Y, _ = run(np.array([[1.5, -2.0]], np.float32), np.array([[3.0]], np.float32), L1)
+    assert Y.shape == (1, 1) and Y[0, 0] == 0.0
+
+
+def test_identical_points_and_outlier():
+    n = 777
+    X = np.tile(np.array([[3, -1, 2]], np.int32), (n, 1))
+    Y, _ = run(X, np.ones((n, 1), np.int32), L1)
+    assert np.all(Y == 0)
+    X[400, 1] += 1
+    Y, _ = run(X, np.ones((n, 1), np.int32), L1)
+    expect = np.ones(n, np.int64)
+    expect[400] = n - 1
+    assert np.array_equal(Y[:, 0], expect)
+
+
+def test_lattice_closed_form_float():
+    n, d = 10000, 2
+    i = np.arange(1, n + 1, dtype=np.int64)
+    X = np.stack([i, 3 * i], axis=1).astype(np.float32)      # exact in FP32
+    Y, _ = run(X, np.ones((n, 1), np.float32), L1)
+    expect = 4 * (i * (i - 1) // 2 + (n - i) * (n - i + 1) // 2)
+    rel = np.abs(Y[:, 0] - expect) / expect
+    assert rel.max() < 4 * U32 * 10
+
+
+# ---------------------------------------------------------------------------
+# errors
+# ---------------------------------------------------------------------------
+def test_nonfinite_inputs_rejected():
+    X = np.zeros((100, 2), np.float32)
+    X[5, 1] = np.nan
+    with pytest.raises(dm.DMError) as ei:
+        dm.prepare(dev(X), L1)
+    assert ei.value.status == dm.ERR_NONFINITE
+    X[5, 1] = 0
+    h = dm.prepare(dev(X), L1)
+    Z = np.ones((100, 1), np.float32)
+    Z[3] = np.inf
+    h.matvec(dev(Z))
+    with pytest.raises(dm.DMError) as ei:
+        h.sync()
+    assert ei.value.status == dm.ERR_NONFINITE
+    h.matvec(dev(np.ones((100, 1), np.float32)))
+    h.sync()                                       # sticky status was cleared
+
+
+def test_integer_range_and_overflow_guard():
+    X = np.array([[2 ** 31], [0]], dtype=np.int64)
+    with pytest.raises(dm.DMError) as ei:
+        dm.prepare(dev(X), L1)
+    assert ei.value.status == dm.ERR_DTYPE
+    X = np.array([[2 ** 31 - 1], [-(2 ** 31) + 1]], dtype=np.int64)
+    h = dm.prepare(dev(X), L1)
+    h.matvec(dev(np.array([[2 ** 31], [2 ** 31]], np.int64)))
+    with pytest.raises(dm.DMError) as ei:
+        h.sync()
+    assert ei.value.status == dm.ERR_OVERFLOW
+    Y = h.matvec(dev(np.array([[3], [1]], np.int64))).cpu().numpy()
+    h.sync()
+    assert Y[0, 0] == 2 ** 32 - 2 and Y[1, 0] == 3 * (2 ** 32 - 2)
+
+
+def test_wrong_rhs_dtype():
+    h = dm.prepare(dev(np.zeros((10, 2), np.float32)), L1)
+    with pytest.raises(dm.DMError) as ei:
+        h.matvec(dev(np.zeros((10, 1), np.int32)))
+    assert ei.value.status == dm.ERR_DTYPE
