@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of the l1 distance-matrix matvec on one MI355X.
+
+Workload: n = 2^22 points, d = 128 coordinates uniform on [0, 1) in FP32,
+Z = n x 64 right-hand sides N(0, 1) in FP32 (seeded, synthetic).
+
+* value: batched columns/s = 64 / (time of one b = 64 query), the query being
+  the totals kernel plus one chained-scan pass per coordinate (Algorithm 2);
+  the per-coordinate sort (Algorithm 1) is one-time preparation, timed once
+  and reported as prep_ms.
+* single-vector form: 64 sequential b = 1 queries on the 64 columns.
+* l2 squared: one b = 64 query of the low-rank form (Algorithm 3).
+* roofline: algorithmic bytes of one coordinate pass, 12 n b + 8 n (perm and
+  sorted values read once, the Z rows gathered once, the Out rows read and
+  written once), over the pass kernel's mean device time from HIP events on
+  the query stream, against the 8 TB/s HBM peak.
+* cpu_baseline: the FP64 CPU oracle (explicit rows of A, O(n^2 d)) on a
+  bounded sample of rows of the same workload, extrapolated to whole columns.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "l1_pass_n4194304_d128_b64_traffic.txt")
+PASS_SRC = os.path.join(ROOT, "paper_2210_15114_amd", "csrc", "k_l1.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def src_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per pass from committed counter runs, if they still describe the kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != src_hash(PASS_SRC):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 22)
+    ap.add_argument("--d", type=int, default=128)
+    ap.add_argument("--b", type=int, default=64)
+    ap.add_argument("--cpu-rows", type=int, default=96, help="oracle sample size for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-vector leg")
+    ap.add_argument("--no-l2", action="store_true", help="skip the l2-squared leg")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the method is measured on one GPU's share "
+              "(multi-GPU sharding is described in the design notes, not run)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2210_15114_amd as dm
+    import synth
+
+    n, d, b = args.n, args.d, args.b
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    log("generating inputs n=%d d=%d b=%d" % (n, d, b))
+    X, Z = synth.workload3(n, d, b)
+    Xd = torch.from_numpy(X).to(dev)
+    Zd = torch.from_numpy(Z).to(dev)
+    torch.cuda.synchronize()
+
+    # ---- achievable HBM bandwidth (plain copy of X) ----
+    buf = torch.empty_like(Xd)
+    for _ in range(2):
+        dm.copy_probe(buf, Xd)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 5
+    for _ in range(reps):
+        dm.copy_probe(buf, Xd)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2.0 * Xd.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del buf
+    log("copy probe %.0f GB/s" % copy_gbps)
+
+    # ---- preparation (Algorithm 1), timed once ----
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = dm.prepare(Xd, dm.L1)
+    prep_ms = (time.perf_counter() - t0) * 1e3
+    log("prep %.1f ms" % prep_ms)
+    h.reserve(b)
+    Out = torch.empty((n, b), dtype=torch.float32, device=dev)
+
+    # ---- batched queries ----
+    for _ in range(args.warmup):
+        h.matvec(Zd, out=Out)
+    h.sync()
+    torch.cuda.synchronize()
+    h.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        h.matvec(Zd, out=Out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h.sync()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    pass_ms, pass_n = h.profile_read(dm.K_L1_PASS)
+    tot_ms, tot_n = h.profile_read(dm.K_TOTALS)
+    h.profile(False)
+    avg_pass_ms = pass_ms / max(pass_n, 1)
+    cols_s = b / (ms_step * 1e-3)
+    log("batched: %.2f ms/step (wall %.2f ms), %.1f columns/s, pass %.3f ms x %d" %
+        (ms_step, wall * 1e3 / args.steps, cols_s, avg_pass_ms, pass_n // max(args.steps, 1)))
+
+    bytes_pass = 12.0 * n * b + 8.0 * n
+    achieved = bytes_pass / (avg_pass_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": read_traffic(),
+                "kernel": "l1_pass_kernel<FloatPath,64>", "bytes_per_launch": bytes_pass,
+                "avg_launch_ms": round(avg_pass_ms, 4), "launches": pass_n}
+
+    # ---- single-vector form on the same 64 columns ----
+    single = None
+    if not args.no_single:
+        Zc = Zd.t().contiguous()                     # 64 x n: row c is column c of Z
+        Oc = torch.empty_like(Zc)
+        h.matvec(Zc[0], out=Oc[0])                   # warm-up (scratch for b = 1)
+        h.sync()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for c in range(b):
+            h.matvec(Zc[c], out=Oc[c])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        h.sync()
+        t_single = e0.elapsed_time(e1) * 1e-3
+        single_cols = b / t_single
+        dif = (Oc.t() - Out).abs().max().item()
+        scale = Out.abs().max().item()
+        single = {"columns_per_s": round(single_cols, 2), "ms_per_column": round(t_single * 1e3 / b, 3),
+                  "max_abs_diff_vs_batched": dif, "max_abs_out": scale}
+        log("single-z: %.2f columns/s; batched/single = %.2f" % (single_cols, cols_s / single_cols))
+        del Zc, Oc
+
+    # ---- l2 squared ----
+    l2 = None
+    if not args.no_l2:
+        h2 = dm.prepare(Xd, dm.L2SQ)
+        O2 = torch.empty((n, b), dtype=torch.float32, device=dev)
+        for _ in range(max(1, args.warmup)):
+            h2.matvec(Zd, out=O2)
+        h2.sync()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            h2.matvec(Zd, out=O2)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        h2.sync()
+        ms2 = e0.elapsed_time(e1) / args.steps
+        bytes2 = 2.0 * n * d * 4 + 2.0 * n * b * 4 + n * 8
+        l2 = {"columns_per_s": round(b / (ms2 * 1e-3), 1), "ms_per_query": round(ms2, 3),
+              "achieved_GBps": round(bytes2 / (ms2 * 1e-3) / 1e9, 1)}
+        log("l2sq: %.3f ms/query" % ms2)
+        O2h = O2.cpu().numpy()
+        h2.free()
+        del O2
+
+    # ---- CPU oracle on a bounded sample (and the accuracy of the GPU result there) ----
+    cpu = None
+    errors = None
+    Outh = Out.cpu().numpy()
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import metrics
+        perm, _, _ = h.sorted()
+        p0 = perm[0].cpu().numpy()
+        pl = perm[d - 1].cpu().numpy()
+        extra = [p0[0], p0[-1], pl[0], pl[-1]]
+        s = synth.seeds(3)
+        rows = synth.subsample_rows(n, args.cpu_rows, s["sub"], extra)
+        X64 = X.astype(np.float64)
+        Z64 = Z.astype(np.float64)
+        threads = oracle.num_threads()
+        t0 = time.perf_counter()
+        o, rn, ad = oracle.matvec(X64, Z64, oracle.L1, rows)
+        t_or = time.perf_counter() - t0
+        cols_cpu = b / (t_or * n / rows.size)
+        cpu = {"value": cols_cpu, "unit": "columns/s", "cores": threads, "kind": "oracle",
+               "sample": "%d of %d rows (uniform seeded sample plus the scan-boundary points), all %d columns, "
+                         "%.1f s; extrapolated by n/rows" % (rows.size, n, b, t_or)}
+        frob = metrics.frob_from_rows(rn, n)
+        errors = {"l1": metrics.errors(Outh[rows], o, rn, ad, Z64, frob)}
+        if l2 is not None:
+            o2, rn2, ad2 = oracle.matvec(X64, Z64, oracle.L2SQ, rows[:16])
+            frob2 = float(np.sqrt(max(rn2.mean() * n, 0.0)))
+            errors["l2sq_16rows"] = metrics.errors(O2h[rows[:16]], o2, rn2, ad2, Z64, frob2)
+        log("cpu oracle: %.3g columns/s on %d threads; errors %s" % (cols_cpu, threads, errors))
+
+    result = {
+        "metric": "l1 dist-matvec columns/s (n=4M,d=128,b=64) batched vs single-z; % HBM peak",
+        "value": round(cols_s, 2),
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "l1 batched matvec, n=%d points, d=%d coordinates U[0,1) FP32, "
+                               "Z %dx%d N(0,1) FP32" % (n, d, n, b), "n": n, "d": d, "b": b},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "single_z": single,
+        "batched_vs_single": round(cols_s / single["columns_per_s"], 2) if single else None,
+        "hbm_frac": roofline["frac"],
+        "copy_probe_GBps": round(copy_gbps, 1),
+        "prep_ms": round(prep_ms, 1),
+        "totals_ms_per_step": round(tot_ms / max(args.steps, 1), 4),
+        "l2sq": l2,
+        "errors": errors,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -133,6 +133,24 @@ dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, voi
  */
 int dm_int_bound_ok(double sum_ranges, double z_l1);
 
+/*
+ * Measurement support.  While profiling is on, every launch of the listed
+ * kernel classes is bracketed by HIP events on the query stream;
+ * dm_profile_read waits for them and returns the summed device time and the
+ * number of launches since profiling was last switched on.
+ * Errors: DM_ERR_ARG (NULL handle, bad class), DM_ERR_DEVICE.
+ */
+typedef enum { DM_K_L1_PASS = 0, DM_K_TOTALS = 1, DM_K_L2 = 2, DM_K_CLASSES = 3 } dm_kernel_class;
+dm_status dm_profile_enable(dm_handle* h, int32_t on);
+dm_status dm_profile_read(dm_handle* h, int32_t kernel_class, double* total_ms, int64_t* launches);
+
+/*
+ * Streaming copy of `bytes` bytes from src to dst (device pointers, 16-byte
+ * aligned, not overlapping), used to calibrate achievable HBM bandwidth and
+ * hardware byte counters.  Stream-ordered.  Errors: DM_ERR_ARG, DM_ERR_DEVICE.
+ */
+dm_status dm_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
+
 /* Release a handle (and its workspace if the library allocated it).  NULL is a no-op. */
 void dm_free(dm_handle* h);
 

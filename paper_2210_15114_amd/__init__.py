@@ -67,6 +67,12 @@ def lib():
     L.dm_int_bound_ok.restype = ctypes.c_int
     L.dm_free.argtypes = [P]
     L.dm_free.restype = None
+    L.dm_profile_enable.argtypes = [P, i32]
+    L.dm_profile_enable.restype = i32
+    L.dm_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.dm_profile_read.restype = i32
+    L.dm_copy_probe.argtypes = [P, P, sz, P]
+    L.dm_copy_probe.restype = i32
     _lib = L
     return L
 
@@ -95,6 +101,18 @@ def workspace_size(n: int, d: int, metric: int, dtype: int) -> int:
 
 def int_bound_ok(sum_ranges: float, z_l1: float) -> bool:
     return bool(lib().dm_int_bound_ok(float(sum_ranges), float(z_l1)))
+
+
+K_L1_PASS, K_TOTALS, K_L2 = 0, 1, 2
+
+
+def copy_probe(dst, src, stream=None):
+    """Streaming device copy of src into dst (same byte size), for bandwidth calibration."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(lib().dm_copy_probe(_dev_ptr(dst, "dst"), _dev_ptr(src, "src"), nbytes, _stream_ptr(stream)),
+           "dm_copy_probe")
 
 
 def _torch():
@@ -171,6 +189,17 @@ class Handle:
                                   _stream_ptr(stream))
         _check(st, "dm_copy_sorted")
         return perm, rank, xs
+
+    def profile(self, on: bool = True):
+        _check(lib().dm_profile_enable(self._ptr, 1 if on else 0), "dm_profile_enable")
+
+    def profile_read(self, kernel_class: int):
+        """(total device ms, launches) of one kernel class since profiling was switched on."""
+        ms = ctypes.c_double(0.0)
+        cnt = ctypes.c_int64(0)
+        _check(lib().dm_profile_read(self._ptr, kernel_class, ctypes.byref(ms), ctypes.byref(cnt)),
+               "dm_profile_read")
+        return ms.value, cnt.value
 
     def free(self):
         if self._ptr:

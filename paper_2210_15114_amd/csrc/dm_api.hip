@@ -129,6 +129,14 @@ struct dm_handle {
     double guard_scale = 0.0;   // sum of ranges (l1) or squared ranges (l2 squared)
     hipStream_t last = nullptr;
 
+    // measurement: event pairs around launches while profiling is on
+    struct Ev { hipEvent_t a = nullptr, b = nullptr; int cls = 0; };
+    bool prof = false;
+    std::vector<Ev> evs;
+    size_t ev_used = 0;
+    double prof_ms[DM_K_CLASSES] = {0, 0, 0};
+    int64_t prof_n[DM_K_CLASSES] = {0, 0, 0};
+
     template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -136,6 +144,10 @@ namespace {
 
 void release(dm_handle* h) {
     if (!h) return;
+    for (auto& e : h->evs) {
+        if (e.a) (void)hipEventDestroy(e.a);
+        if (e.b) (void)hipEventDestroy(e.b);
+    }
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
@@ -177,6 +189,27 @@ dm_status ensure_scratch(dm_handle* h, int32_t b, hipStream_t s) {
     DM_TRY(launch_fill_u32((uint32_t*)p, 0u, need / 4, s));
     return DM_OK;
 }
+
+// Bracket one launch with events when profiling is on.
+struct ProfScope {
+    dm_handle* h;
+    dm_handle::Ev* ev = nullptr;
+    hipStream_t s;
+    ProfScope(dm_handle* hh, int cls, hipStream_t ss) : h(hh), s(ss) {
+        if (!h->prof) return;
+        if (h->ev_used == h->evs.size()) {
+            dm_handle::Ev e;
+            if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return;
+            h->evs.push_back(e);
+        }
+        ev = &h->evs[h->ev_used++];
+        ev->cls = cls;
+        (void)hipEventRecord(ev->a, s);
+    }
+    ~ProfScope() {
+        if (ev) (void)hipEventRecord(ev->b, s);
+    }
+};
 
 dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
     const Layout& L = h->L;
@@ -371,7 +404,10 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
     char* rest = sc + al(totals_scratch_bytes(h->n, b));
     h->last = s;
     if (h->metric == DM_L1) {
-        DM_TRY(launch_totals(h->is_int, zkind, Z, h->n, b, h->ws + h->L.rowsum, h->guard_scale, tot, s));
+        {
+            ProfScope ps(h, DM_K_TOTALS, s);
+            DM_TRY(launch_totals(h->is_int, zkind, Z, h->n, b, h->ws + h->L.rowsum, h->guard_scale, tot, s));
+        }
         L1PassArgs a;
         a.n = h->n;
         a.Z = Z;
@@ -385,9 +421,11 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
             a.perm = h->at<uint32_t>(h->L.perm) + (size_t)k * h->L.ld;
             a.xs = h->ws + h->L.xs + (size_t)k * h->L.ld * vsz;
             a.first = k == 0;
+            ProfScope ps(h, DM_K_L1_PASS, s);
             DM_TRY(launch_l1_pass(h->is_int, zkind, b, a, s));
         }
     } else {
+        ProfScope ps(h, DM_K_L2, s);
         DM_TRY(launch_l2sq(h->is_int, zkind, h->ws + h->L.xcopy, h->ws + h->L.rownrm, h->n, h->d, Z, b, Out, rest,
                            tot, h->guard_scale, s));
     }
@@ -425,6 +463,43 @@ dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, voi
     if (perm) DM_TRY(hipMemcpy2DAsync(perm, w, h->ws + h->L.perm, sp, w, h->d, hipMemcpyDeviceToDevice, s));
     if (rank) DM_TRY(hipMemcpy2DAsync(rank, w, h->ws + h->L.rank, sp, w, h->d, hipMemcpyDeviceToDevice, s));
     if (xs) DM_TRY(hipMemcpy2DAsync(xs, w, h->ws + h->L.xs, sp, w, h->d, hipMemcpyDeviceToDevice, s));
+    return DM_OK;
+}
+
+dm_status dm_profile_enable(dm_handle* h, int32_t on) {
+    if (!h) return DM_ERR_ARG;
+    h->prof = on != 0;
+    h->ev_used = 0;
+    for (int c = 0; c < DM_K_CLASSES; ++c) {
+        h->prof_ms[c] = 0.0;
+        h->prof_n[c] = 0;
+    }
+    return DM_OK;
+}
+
+dm_status dm_profile_read(dm_handle* h, int32_t kernel_class, double* total_ms, int64_t* launches) {
+    if (!h || kernel_class < 0 || kernel_class >= DM_K_CLASSES) return DM_ERR_ARG;
+    for (size_t i = 0; i < h->ev_used; ++i) {
+        auto& e = h->evs[i];
+        float ms = 0.0f;
+        if (hipEventSynchronize(e.b) != hipSuccess || hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess)
+            return DM_ERR_DEVICE;
+        h->prof_ms[e.cls] += ms;
+        h->prof_n[e.cls] += 1;
+    }
+    h->ev_used = 0;
+    if (total_ms) *total_ms = h->prof_ms[kernel_class];
+    if (launches) *launches = h->prof_n[kernel_class];
+    return DM_OK;
+}
+
+dm_status dm_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || bytes == 0) return DM_ERR_ARG;
+    if (((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return DM_ERR_ARG;
+    const char* d = (const char*)dst;
+    const char* s = (const char*)src;
+    if (d < s + bytes && s < d + bytes) return DM_ERR_ARG;
+    DM_TRY(launch_copy_probe(dst, src, bytes, (hipStream_t)stream));
     return DM_OK;
 }
 

@@ -50,6 +50,7 @@ hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d,
 hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d,
                             void* rowsum /* n x 8B */, void* rownrm /* n x 8B */, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
+hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // ---- segmented radix sort (LSD, 4 passes of 8 bits) -----------------------
 hipError_t launch_sort_count(const uint32_t* keys, uint32_t* counts, const SegTables& t, int shift,

@@ -136,7 +136,25 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t count) {
     for (; i < count; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// plain streaming copy, 16 bytes per lane per iteration
+__global__ __launch_bounds__(256) void copy_probe_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                         size_t n16) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) dst[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    copy_probe_kernel<<<(unsigned)blocks, 256, 0, s>>>((uint4*)dst, (const uint4*)src, n16);
+    return hipGetLastError();
+}
 
 hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d, uint32_t* keys,
                                  int64_t ld, void* xcopy, uint32_t* kmin, uint32_t* kmax, uint32_t* flags,
