@@ -337,7 +337,6 @@ dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_
     }
     Ctl init;
     std::memset(&init, 0, sizeof(init));
-    init.chain.epoch = 1;
     if (hipMemcpyAsync(h->ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(DM_ERR_DEVICE);
     if (launch_fill_u32(h->at<uint32_t>(L.kmin), 0xffffffffu, (size_t)d, s) != hipSuccess ||

@@ -19,15 +19,15 @@ enum QueryFlag : uint32_t { QF_NONFINITE = 1u, QF_OVERFLOW = 2u };
 constexpr int SORT_TILE = 4096;   // keys per sort tile (256 threads x 16)
 constexpr int SORT_THREADS = 256;
 
-// Self-maintained state of one chained-scan pass family.  `ticket` hands out
-// tile indices in dispatch order, `done` counts finished tiles; the last tile
-// of a pass resets both and advances `epoch`, which tags every word the pass
-// publishes.  Initialised to {0, 0, 1} once, never touched by the host again.
+// Ticket counters of the chained-scan passes, one per tile shape.  A pass of
+// a shape with T tiles on a grid of G persistent workgroups consumes exactly
+// T + G tickets (each workgroup stops on the first ticket past the last tile),
+// so ticket / (T + G) numbers the passes of that shape and, with the shape,
+// forms the tag of every word the pass publishes.  Zeroed once when a handle
+// is created and never reset; the host never reads them.
+constexpr int CHAIN_CLASSES = 32;
 struct ChainState {
-    uint32_t ticket;
-    uint32_t done;
-    uint32_t epoch;
-    uint32_t pad[61];
+    uint64_t ticket[CHAIN_CLASSES];
 };
 
 // Segment tables of a segmented sort: segment s holds keys

@@ -26,6 +26,8 @@
 // (hi, lo) FP32 pairs; inside a thread the short runs are plain FP32 relative
 // to that carry.  Integer data runs in wrapping int64, which is exact modulo
 // 2^64.
+#include <type_traits>
+
 #include "dm_device.h"
 #include "dm_internal.h"
 
@@ -57,6 +59,7 @@ struct FloatPath {
     __device__ static L lsum(L a, L b) { return a + b; }
     __device__ static L shfl_up(L v, int o) { return __shfl_up(v, o, 64); }
     __device__ static C czero() { return dd{0.0f, 0.0f}; }
+    __device__ static C cshfl_xor(C v, int m) { return dd{__shfl_xor(v.hi, m, 64), __shfl_xor(v.lo, m, 64)}; }
     __device__ static C cadd(C a, C b) { return dd_add(a, b); }
     __device__ static C caddl(C a, L b) { return dd_add_f(a, b); }
     __device__ static void enc(C c, uint32_t& w0, uint32_t& w1) {
@@ -96,6 +99,7 @@ template <typename ZT> struct IntPath {
     __device__ static L lsum(L a, L b) { return w((uint64_t)a + (uint64_t)b); }
     __device__ static L shfl_up(L v, int o) { return __shfl_up(v, o, 64); }
     __device__ static C czero() { return 0; }
+    __device__ static C cshfl_xor(C v, int m) { return __shfl_xor(v, m, 64); }
     __device__ static C cadd(C a, C b) { return w((uint64_t)a + (uint64_t)b); }
     __device__ static C caddl(C a, L b) { return w((uint64_t)a + (uint64_t)b); }
     __device__ static void enc(C c, uint32_t& w0, uint32_t& w1) {
@@ -150,209 +154,274 @@ __device__ __forceinline__ void store_row(E* __restrict__ row, int col0, int b, 
     }
 }
 
-template <typename P, int BP, int R, bool VEC>
+template <typename P, int BP, int R, int SUB, int OC, bool VEC>
 __global__ __launch_bounds__(256) void l1_pass_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
     const typename P::T* __restrict__ T0, const typename P::T* __restrict__ U, int first,
-    ChainState* __restrict__ chain, uint64_t* __restrict__ rec)
+    uint64_t* __restrict__ ticket_ctr, int cls, int64_t ntiles,
+    uint64_t* __restrict__ rec, uint64_t* __restrict__ stat)
 {
     using L = typename P::L;
     using C = typename P::C;
     using Ly = Lay<BP>;
     constexpr int CPL = Ly::CPL, LPR = Ly::LPR, RPW = Ly::RPW, NS = Ly::NS;
-    constexpr int TILE = NS * R;
-    constexpr int WPR = 4 * BP;  // tagged words per record: (P0 a, P0 b, P1 a, P1 b) per column
+    constexpr int CHUNK = NS * R;       // ranks per sub-chunk (one register load per slot)
+    constexpr int TILE = CHUNK * SUB;   // ranks per tile
+    constexpr int WPR = 4 * BP;         // tagged words per record: (P0 a, P0 b, P1 a, P1 b) per column
+    static_assert(R % OC == 0, "Out chunk must divide the ranks per slot");
 
-    __shared__ uint32_t s_tile, s_tag;
+    __shared__ uint64_t s_ticket;
+    __shared__ C s_red[4][2][BP];
+    __shared__ C s_tot[2][BP];
     __shared__ L s_wtot[4][2][BP];
     __shared__ C s_wexcl[4][2][BP];
-    __shared__ C s_tot[2][BP];
-    __shared__ C s_carry[2][BP];
+    __shared__ C s_run[2][BP];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) {
-        s_tile = atomicAdd(&chain->ticket, 1u);
-        s_tag = __hip_atomic_load(&chain->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const uint32_t tile = s_tile, tag = s_tag;
     const int slot = w * RPW + lane / LPR;
     const int col0 = (lane % LPR) * CPL;
-    const int64_t r0 = (int64_t)tile * TILE + (int64_t)slot * R;
+    // Each workgroup takes tiles in ticket order until it draws one of the G
+    // tickets past the last tile, so a pass consumes ntiles + G tickets.
+    const uint64_t per_pass = (uint64_t)ntiles + gridDim.x;
+    if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
+    __syncthreads();
+    uint64_t ticket = s_ticket;
 
-    // ---- gather: sorted ranks [r0, r0 + R) of this slot, CPL columns ----
-    uint32_t p[R];
-    typename P::X x[R];
-    typename P::Z g[R][CPL];
-    typename P::O o[R][CPL];
+    for (;;) {
+        const uint64_t tile = ticket % per_pass;
+        if (tile >= (uint64_t)ntiles) break;
+        const uint32_t tag = ((uint32_t)(cls + 1) << 24) | (uint32_t)((ticket / per_pass) & 0xffffffu);
+        const int64_t tbase = (int64_t)tile * TILE + (int64_t)slot * R;
+
+        // ================= phase 1: the tile's totals =================
+        C t0[CPL], t1[CPL];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const bool valid = r0 + i < n;
-        p[i] = valid ? perm[r0 + i] : 0u;
-        x[i] = valid ? xs[r0 + i] : typename P::X(0);
-    }
+        for (int j = 0; j < CPL; ++j) { t0[j] = P::czero(); t1[j] = P::czero(); }
+        for (int s = 0; s < SUB; ++s) {
+            const int64_t r0 = tbase + (int64_t)s * CHUNK;
+            uint32_t p[R];
+            typename P::X x[R];
+            typename P::Z g[R][CPL];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const bool valid = r0 + i < n;
-        load_row<CPL, VEC>(Z + (size_t)p[i] * b, col0, b, valid, g[i]);
-        if (!first) {
-            load_row<CPL, VEC>(Out + (size_t)p[i] * b, col0, b, valid, o[i]);
-        } else {
+            for (int i = 0; i < R; ++i) {
+                const bool valid = r0 + i < n;
+                p[i] = valid ? perm[r0 + i] : 0u;
+                x[i] = valid ? xs[r0 + i] : typename P::X(0);
+            }
 #pragma unroll
-            for (int j = 0; j < CPL; ++j) o[i][j] = typename P::O(0);
+            for (int i = 0; i < R; ++i) load_row<CPL, VEC>(Z + (size_t)p[i] * b, col0, b, r0 + i < n, g[i]);
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                L a0 = P::lzero(), a1 = P::lzero();
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    a0 = P::ladd(a0, g[i][j]);
+                    a1 = P::lmac(a1, x[i], g[i][j]);
+                }
+                t0[j] = P::caddl(t0[j], a0);
+                t1[j] = P::caddl(t1[j], a1);
+            }
         }
-    }
-
-    // ---- thread aggregates and the exclusive scan over the wave's slots ----
-    L a0[CPL], a1[CPL], e0[CPL], e1[CPL];
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) { a0[j] = P::lzero(); a1[j] = P::lzero(); }
-#pragma unroll
-    for (int i = 0; i < R; ++i)
+        // sum over the slots of the wave (lanes that share columns), then the waves
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
-            a0[j] = P::ladd(a0[j], g[i][j]);
-            a1[j] = P::lmac(a1[j], x[i], g[i][j]);
-        }
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        L i0 = a0[j], i1 = a1[j];
-#pragma unroll
-        for (int off = LPR; off < DM_WAVE; off <<= 1) {
-            const L t0 = P::shfl_up(i0, off), t1 = P::shfl_up(i1, off);
-            if (lane >= off) { i0 = P::lsum(i0, t0); i1 = P::lsum(i1, t1); }
+            for (int off = LPR; off < DM_WAVE; off <<= 1) {
+                t0[j] = P::cadd(t0[j], P::cshfl_xor(t0[j], off));
+                t1[j] = P::cadd(t1[j], P::cshfl_xor(t1[j], off));
+            }
+            if (lane < LPR) {
+                s_red[w][0][col0 + j] = t0[j];
+                s_red[w][1][col0 + j] = t1[j];
+            }
         }
-        const L x0 = P::shfl_up(i0, LPR), x1 = P::shfl_up(i1, LPR);
-        e0[j] = lane >= LPR ? x0 : P::lzero();
-        e1[j] = lane >= LPR ? x1 : P::lzero();
-        if (lane >= DM_WAVE - LPR) {
-            s_wtot[w][0][col0 + j] = i0;
-            s_wtot[w][1][col0 + j] = i1;
+        __syncthreads();
+        if (tid < 2 * BP) {
+            const int qt = tid / BP, c = tid % BP;
+            const C acc = P::cadd(P::cadd(s_red[0][qt][c], s_red[1][qt][c]), P::cadd(s_red[2][qt][c], s_red[3][qt][c]));
+            s_tot[qt][c] = acc;
+            if (c < b) {
+                uint32_t w0, w1;
+                P::enc(acc, w0, w1);
+                uint64_t* dst = rec + ((size_t)tile * 2 + (tile == 0 ? 1 : 0)) * WPR + c * 4 + qt * 2;
+                publish_word(dst, tag_word(tag, w0));
+                publish_word(dst + 1, tag_word(tag, w1));
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
+        if (tid == 0) publish_word(stat + tile, tag_word(tag, tile == 0 ? 2u : 1u));
 
-    // ---- across the 4 waves; publish the tile aggregate ----
-    if (tid < 2 * BP) {
-        const int qt = tid / BP, c = tid % BP;
-        C acc = P::czero();
-#pragma unroll
-        for (int ww = 0; ww < 4; ++ww) {
-            s_wexcl[ww][qt][c] = acc;
-            acc = P::caddl(acc, s_wtot[ww][qt][c]);
-        }
-        s_tot[qt][c] = acc;
-        if (c < b) {
-            uint32_t w0, w1;
-            P::enc(acc, w0, w1);
-            uint64_t* dst = rec + ((size_t)tile * 2 + (tile == 0 ? 1 : 0)) * WPR + c * 4 + qt * 2;
-            publish_word(dst, tag_word(tag, w0));
-            publish_word(dst + 1, tag_word(tag, w1));
-        }
-    }
-    __syncthreads();
-
-    // ---- decoupled look-back (wave 0, lane = column) ----
-    if (w == 0) {
-        const int c = lane;
-        const bool act = c < b;
-        C c0 = P::czero(), c1 = P::czero();
-        if (tile > 0) {
-            int64_t pi = (int64_t)tile - 1;
-            for (;;) {
-                const uint64_t* ri = rec + ((size_t)pi * 2 + 1) * WPR + c * 4;
-                uint64_t v[4];
-                bool ok = true;
-                if (act) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        v[k] = peek_word(ri + k);
-                        ok = ok && (uint32_t)(v[k] >> 32) == tag;
-                    }
-                }
-                if (__all(ok)) {
-                    if (act) {
-                        c0 = P::cadd(c0, P::dec((uint32_t)v[0], (uint32_t)v[1]));
-                        c1 = P::cadd(c1, P::dec((uint32_t)v[2], (uint32_t)v[3]));
-                    }
-                    break;
-                }
-                const uint64_t* ra = rec + ((size_t)pi * 2) * WPR + c * 4;
-                ok = true;
-                if (act) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        v[k] = peek_word(ra + k);
-                        ok = ok && (uint32_t)(v[k] >> 32) == tag;
-                    }
-                }
-                if (__all(ok)) {
-                    if (act) {
-                        c0 = P::cadd(c0, P::dec((uint32_t)v[0], (uint32_t)v[1]));
-                        c1 = P::cadd(c1, P::dec((uint32_t)v[2], (uint32_t)v[3]));
-                    }
-                    --pi;
+        // ================= decoupled look-back (wave 0) =================
+        // Lane l reads the status word of tile hi - l.  The nearest predecessor
+        // with an inclusive record ends the walk; every tile in between must
+        // have published its aggregate.  Status words are hints: the payload
+        // words carry their own tags and are re-checked, so a hint that ran
+        // ahead of its payload only costs a retry.
+        if (w == 0) {
+            const int c = lane;
+            const bool act = c < b;
+            C c0 = P::czero(), c1 = P::czero();
+            int64_t hi = (int64_t)tile - 1;
+            while (hi >= 0) {
+                const int64_t q = hi - lane;
+                const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
+                const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
+                const uint64_t mI = __ballot(state == 2u);
+                const uint64_t mA = __ballot(state >= 1u);
+                const int la = (~mA) ? __builtin_ctzll(~mA) : 64;   // leading lanes with a record
+                const int li = mI ? __builtin_ctzll(mI) : 64;        // nearest inclusive record
+                bool fin;
+                int take;
+                if (li < 64 && li <= la) {
+                    fin = true;
+                    take = li;
+                } else if (la > 0) {
+                    fin = false;
+                    take = la;
+                } else {
+                    __builtin_amdgcn_s_sleep(2);
                     continue;
                 }
-                __builtin_amdgcn_s_sleep(1);
+                C s0 = P::czero(), s1 = P::czero();
+                bool ok = true;
+                if (act) {
+                    for (int j = 0; j <= take; ++j) {
+                        if (j == take && !fin) break;
+                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * 4;
+                        uint64_t v[4];
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            v[kk] = peek_word(src + kk);
+                            ok = ok && (uint32_t)(v[kk] >> 32) == tag;
+                        }
+                        s0 = P::cadd(s0, P::dec((uint32_t)v[0], (uint32_t)v[1]));
+                        s1 = P::cadd(s1, P::dec((uint32_t)v[2], (uint32_t)v[3]));
+                    }
+                }
+                if (!__all(ok)) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                c0 = P::cadd(c0, s0);
+                c1 = P::cadd(c1, s1);
+                if (fin) break;
+                hi -= take;
+            }
+            if (act) {
+                s_run[0][c] = c0;
+                s_run[1][c] = c1;
+                if (tile > 0) {
+                    uint32_t w0, w1, w2, w3;
+                    P::enc(P::cadd(c0, s_tot[0][c]), w0, w1);
+                    P::enc(P::cadd(c1, s_tot[1][c]), w2, w3);
+                    uint64_t* dst = rec + ((size_t)tile * 2 + 1) * WPR + c * 4;
+                    publish_word(dst + 0, tag_word(tag, w0));
+                    publish_word(dst + 1, tag_word(tag, w1));
+                    publish_word(dst + 2, tag_word(tag, w2));
+                    publish_word(dst + 3, tag_word(tag, w3));
+                }
+            }
+            if (tile > 0 && lane == 0) publish_word(stat + tile, tag_word(tag, 2u));
+        }
+        __syncthreads();
+
+        // ================= phase 2: scan and scatter, sub-chunk by sub-chunk =================
+        // The Z rows are read a second time; they were fetched moments ago in
+        // phase 1 and are normally still in the memory-side cache.
+        for (int s = 0; s < SUB; ++s) {
+            const int64_t r0 = tbase + (int64_t)s * CHUNK;
+            uint32_t p[R];
+            typename P::X x[R];
+            typename P::Z g[R][CPL];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const bool valid = r0 + i < n;
+                p[i] = valid ? perm[r0 + i] : 0u;
+                x[i] = valid ? xs[r0 + i] : typename P::X(0);
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) load_row<CPL, VEC>(Z + (size_t)p[i] * b, col0, b, r0 + i < n, g[i]);
+
+            L e0[CPL], e1[CPL];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                L i0 = P::lzero(), i1 = P::lzero();
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    i0 = P::ladd(i0, g[i][j]);
+                    i1 = P::lmac(i1, x[i], g[i][j]);
+                }
+#pragma unroll
+                for (int off = LPR; off < DM_WAVE; off <<= 1) {
+                    const L u0 = P::shfl_up(i0, off), u1 = P::shfl_up(i1, off);
+                    if (lane >= off) { i0 = P::lsum(i0, u0); i1 = P::lsum(i1, u1); }
+                }
+                const L x0 = P::shfl_up(i0, LPR), x1 = P::shfl_up(i1, LPR);
+                e0[j] = lane >= LPR ? x0 : P::lzero();
+                e1[j] = lane >= LPR ? x1 : P::lzero();
+                if (lane >= DM_WAVE - LPR) {
+                    s_wtot[w][0][col0 + j] = i0;
+                    s_wtot[w][1][col0 + j] = i1;
+                }
+            }
+            __syncthreads();
+            if (tid < 2 * BP) {
+                const int qt = tid / BP, c = tid % BP;
+                C acc = s_run[qt][c];
+#pragma unroll
+                for (int ww = 0; ww < 4; ++ww) {
+                    s_wexcl[ww][qt][c] = acc;
+                    acc = P::caddl(acc, s_wtot[ww][qt][c]);
+                }
+                s_run[qt][c] = acc;
+            }
+            __syncthreads();
+
+            typename P::Fin f[CPL];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                const int c = col0 + j;
+                if (c < b) {
+                    const C b0 = P::caddl(s_wexcl[w][0][c], e0[j]);
+                    const C b1 = P::caddl(s_wexcl[w][1][c], e1[j]);
+                    f[j] = P::fin(b0, b1, T0[c], first ? U[c] : typename P::T(0));
+                } else {
+                    f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
+                }
+            }
+            L l0[CPL], l1[CPL];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) { l0[j] = P::lzero(); l1[j] = P::lzero(); }
+#pragma unroll
+            for (int i0 = 0; i0 < R; i0 += OC) {
+                typename P::O o[OC][CPL];
+#pragma unroll
+                for (int i = 0; i < OC; ++i) {
+                    if (!first) {
+                        load_row<CPL, VEC>(Out + (size_t)p[i0 + i] * b, col0, b, r0 + i0 + i < n, o[i]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < CPL; ++j) o[i][j] = P::ufirst(f[j]);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < OC; ++i) {
+                    typename P::O res[CPL];
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) {
+                        l0[j] = P::ladd(l0[j], g[i0 + i][j]);
+                        l1[j] = P::lmac(l1[j], x[i0 + i], g[i0 + i][j]);
+                        res[j] = P::oadd(o[i][j], P::out(l0[j], l1[j], x[i0 + i], f[j]));
+                    }
+                    if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + (size_t)p[i0 + i] * b, col0, b, res);
+                }
             }
         }
-        if (act) {
-            s_carry[0][c] = c0;
-            s_carry[1][c] = c1;
-            if (tile > 0) {
-                uint32_t w0, w1, w2, w3;
-                P::enc(P::cadd(c0, s_tot[0][c]), w0, w1);
-                P::enc(P::cadd(c1, s_tot[1][c]), w2, w3);
-                uint64_t* dst = rec + ((size_t)tile * 2 + 1) * WPR + c * 4;
-                publish_word(dst + 0, tag_word(tag, w0));
-                publish_word(dst + 1, tag_word(tag, w1));
-                publish_word(dst + 2, tag_word(tag, w2));
-                publish_word(dst + 3, tag_word(tag, w3));
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- combine and scatter ----
-    typename P::Fin f[CPL];
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        const int c = col0 + j;
-        if (c < b) {
-            C b0 = P::caddl(P::cadd(s_carry[0][c], s_wexcl[w][0][c]), e0[j]);
-            C b1 = P::caddl(P::cadd(s_carry[1][c], s_wexcl[w][1][c]), e1[j]);
-            f[j] = P::fin(b0, b1, T0[c], first ? U[c] : typename P::T(0));
-        } else {
-            f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
-        }
-    }
-    L l0[CPL], l1[CPL];
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) { l0[j] = P::lzero(); l1[j] = P::lzero(); }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        typename P::O res[CPL];
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            l0[j] = P::ladd(l0[j], g[i][j]);
-            l1[j] = P::lmac(l1[j], x[i], g[i][j]);
-            const typename P::O cval = P::out(l0[j], l1[j], x[i], f[j]);
-            res[j] = first ? P::oadd(cval, P::ufirst(f[j])) : P::oadd(o[i][j], cval);
-        }
-        if (r0 + i < n) store_row<CPL, VEC>(Out + (size_t)p[i] * b, col0, b, res);
-    }
-
-    // ---- the last tile to finish resets the ticket and advances the tag ----
-    if (tid == 0) {
-        const uint32_t prev = atomicAdd(&chain->done, 1u);
-        if (prev == gridDim.x - 1) {
-            __hip_atomic_store(&chain->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&chain->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t next = tag + 1u == 0u ? 1u : tag + 1u;
-            __hip_atomic_store(&chain->epoch, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
+        __syncthreads();
+        ticket = s_ticket;
+        __syncthreads();
     }
 }
 
@@ -489,8 +558,13 @@ hipError_t launch_totals(bool is_int, int zkind, const void* Z, int64_t n, int32
 }
 
 // ranks per slot (R) for each configuration
-template <int BP> constexpr int r_float() { return BP >= 4 ? 8 : 16; }
+template <int BP> constexpr int r_float() { return BP >= 32 ? 16 : BP >= 4 ? 8 : 16; }
 template <int BP> constexpr int r_int() { return BP >= 4 ? 4 : 8; }
+template <int BP, int R> constexpr int out_chunk() { return BP >= 4 ? (R >= 4 ? 4 : R) : R; }
+// sub-chunks per tile: tiles of about 1024 ranks for wide blocks, 4 sub-chunks for narrow ones
+template <int BP, int R> constexpr int sub_chunks() {
+    return (Lay<BP>::NS * R) >= 1024 ? 4 : 1024 / (Lay<BP>::NS * R);
+}
 
 static int bpad(int32_t b) {
     int bp = 1;
@@ -498,43 +572,72 @@ static int bpad(int32_t b) {
     return bp;
 }
 
+template <int BP> static int tile_ranks_bp(bool is_int) {
+    return is_int ? Lay<BP>::NS * r_int<BP>() * sub_chunks<BP, r_int<BP>()>()
+                  : Lay<BP>::NS * r_float<BP>() * sub_chunks<BP, r_float<BP>()>();
+}
+
 int l1_tile_ranks(int32_t b, bool is_int, int zkind) {
     (void)zkind;
-    const int bp = bpad(b);
-    const int cpl = bp >= 4 ? 4 : bp;
-    const int ns = 4 * (64 / (bp / cpl));
-    int r;
-    switch (bp) {
-    case 1: r = is_int ? r_int<1>() : r_float<1>(); break;
-    case 2: r = is_int ? r_int<2>() : r_float<2>(); break;
-    case 4: r = is_int ? r_int<4>() : r_float<4>(); break;
-    case 8: r = is_int ? r_int<8>() : r_float<8>(); break;
-    case 16: r = is_int ? r_int<16>() : r_float<16>(); break;
-    case 32: r = is_int ? r_int<32>() : r_float<32>(); break;
-    default: r = is_int ? r_int<64>() : r_float<64>(); break;
+    switch (bpad(b)) {
+    case 1: return tile_ranks_bp<1>(is_int);
+    case 2: return tile_ranks_bp<2>(is_int);
+    case 4: return tile_ranks_bp<4>(is_int);
+    case 8: return tile_ranks_bp<8>(is_int);
+    case 16: return tile_ranks_bp<16>(is_int);
+    case 32: return tile_ranks_bp<32>(is_int);
+    default: return tile_ranks_bp<64>(is_int);
     }
-    return ns * r;
 }
 
 size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind) {
     const int64_t tile = l1_tile_ranks(b, is_int, zkind);
     const int64_t ntiles = (n + tile - 1) / tile;
-    return (size_t)ntiles * 2 * 4 * (size_t)bpad(b);
+    return (size_t)ntiles * (2 * 4 * (size_t)bpad(b) + 1);   // two records and one status word per tile
+}
+
+template <int BP> constexpr int log2c() { return BP <= 1 ? 0 : 1 + log2c<BP / 2>(); }
+
+template <typename P, int BP, int R, int SUB, int OC, bool VEC>
+static int persistent_grid(int64_t ntiles) {
+    static int per_cu = -1, cus = -1;
+    if (per_cu < 0) {
+        int dev = 0, nb = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, l1_pass_kernel<P, BP, R, SUB, OC, VEC>, 256, 0) !=
+                hipSuccess || nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    int64_t g = (int64_t)per_cu * cus;
+    if (g > ntiles) g = ntiles;
+    return (int)g;
 }
 
 template <typename P, int BP, int R>
 static hipError_t launch_one(const L1PassArgs& a, int32_t b, hipStream_t s) {
-    constexpr int TILE = Lay<BP>::NS * R;
+    constexpr int SUB = sub_chunks<BP, R>();
+    constexpr int TILE = Lay<BP>::NS * R * SUB;
+    constexpr int OC = out_chunk<BP, R>();
+    // one ticket counter per kernel instantiation family (data path x BP)
+    constexpr int kind = std::is_same<P, FloatPath>::value ? 0 : std::is_same<P, IntPath<int32_t>>::value ? 1 : 2;
+    const int cls = kind * 8 + log2c<BP>();
     const int64_t ntiles = (a.n + TILE - 1) / TILE;
+    uint64_t* stat = a.records + (size_t)ntiles * 2 * 4 * BP;
+    uint64_t* ctr = &a.chain->ticket[cls];
     const bool vec = (b == BP) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
+    // one grid size per tile shape: every pass of a shape must use the same
+    // grid, since the ticket count of a pass is ntiles + grid
+    const int grid = persistent_grid<P, BP, R, SUB, OC, false>(ntiles);
     if (vec)
-        l1_pass_kernel<P, BP, R, true><<<(unsigned)ntiles, 256, 0, s>>>(
+        l1_pass_kernel<P, BP, R, SUB, OC, true><<<grid, 256, 0, s>>>(
             a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, a.chain, a.records);
+            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, cls, ntiles, a.records, stat);
     else
-        l1_pass_kernel<P, BP, R, false><<<(unsigned)ntiles, 256, 0, s>>>(
+        l1_pass_kernel<P, BP, R, SUB, OC, false><<<grid, 256, 0, s>>>(
             a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, a.chain, a.records);
+            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, cls, ntiles, a.records, stat);
     return hipGetLastError();
 }
 
