@@ -67,6 +67,20 @@ struct FloatPath {
         w1 = __float_as_uint(c.lo);
     }
     __device__ static C dec(uint32_t w0, uint32_t w1) { return dd{__uint_as_float(w0), __uint_as_float(w1)}; }
+    // Record words: one 64-bit word per value, hi in the upper half, lo with
+    // its 12 low mantissa bits replaced by a 12-bit tag (the carry keeps about
+    // 36 significant bits in transit, far more than the FP32 result needs).
+    static constexpr int WPV = 1;
+    __device__ static uint32_t tag12(uint32_t tag) { return (((tag >> 24) & 31u) << 7) | (tag & 127u); }
+    __device__ static void put(uint64_t* dst, C v, uint32_t tag) {
+        const uint32_t lo = (__float_as_uint(v.lo) & 0xfffff000u) | tag12(tag);
+        publish_word(dst, ((uint64_t)__float_as_uint(v.hi) << 32) | lo);
+    }
+    __device__ static bool get(const uint64_t* src, uint32_t tag, C& v) {
+        const uint64_t w = peek_word(src);
+        v = dd{__uint_as_float((uint32_t)(w >> 32)), __uint_as_float((uint32_t)w & 0xfffff000u)};
+        return ((uint32_t)w & 0xfffu) == tag12(tag);
+    }
     __device__ static Fin fin(C b0, C b1, T t0, T u) {
         Fin f;
         f.d0 = (float)(2.0 * dd_to_f64(b0) - t0);
@@ -107,6 +121,17 @@ template <typename ZT> struct IntPath {
         w1 = (uint32_t)((uint64_t)c >> 32);
     }
     __device__ static C dec(uint32_t w0, uint32_t w1) { return (int64_t)(((uint64_t)w1 << 32) | w0); }
+    // Record words: two 64-bit words per value, each a 32-bit half with the full tag.
+    static constexpr int WPV = 2;
+    __device__ static void put(uint64_t* dst, C v, uint32_t tag) {
+        publish_word(dst, tag_word(tag, (uint32_t)(uint64_t)v));
+        publish_word(dst + 1, tag_word(tag, (uint32_t)((uint64_t)v >> 32)));
+    }
+    __device__ static bool get(const uint64_t* src, uint32_t tag, C& v) {
+        const uint64_t a = peek_word(src), b = peek_word(src + 1);
+        v = (int64_t)(((b & 0xffffffffull) << 32) | (a & 0xffffffffull));
+        return (uint32_t)(a >> 32) == tag && (uint32_t)(b >> 32) == tag;
+    }
     __device__ static Fin fin(C b0, C b1, T t0, T u) {
         Fin f;
         f.d0 = w(2ull * (uint64_t)b0 - (uint64_t)t0);
@@ -155,7 +180,7 @@ __device__ __forceinline__ void store_row(E* __restrict__ row, int col0, int b, 
 }
 
 template <typename P, int BP, int R, int SUB, int OC, bool VEC>
-__global__ __launch_bounds__(256) void l1_pass_kernel(
+__global__ __launch_bounds__(256, 2) void l1_pass_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
     const typename P::T* __restrict__ T0, const typename P::T* __restrict__ U, int first,
@@ -168,7 +193,7 @@ __global__ __launch_bounds__(256) void l1_pass_kernel(
     constexpr int CPL = Ly::CPL, LPR = Ly::LPR, RPW = Ly::RPW, NS = Ly::NS;
     constexpr int CHUNK = NS * R;       // ranks per sub-chunk (one register load per slot)
     constexpr int TILE = CHUNK * SUB;   // ranks per tile
-    constexpr int WPR = 4 * BP;         // tagged words per record: (P0 a, P0 b, P1 a, P1 b) per column
+    constexpr int WPR = 2 * BP * P::WPV;   // words per record: (P0, P1) per column, every column of BP
     static_assert(R % OC == 0, "Out chunk must divide the ranks per slot");
 
     __shared__ uint64_t s_ticket;
@@ -241,13 +266,9 @@ __global__ __launch_bounds__(256) void l1_pass_kernel(
             const int qt = tid / BP, c = tid % BP;
             const C acc = P::cadd(P::cadd(s_red[0][qt][c], s_red[1][qt][c]), P::cadd(s_red[2][qt][c], s_red[3][qt][c]));
             s_tot[qt][c] = acc;
-            if (c < b) {
-                uint32_t w0, w1;
-                P::enc(acc, w0, w1);
-                uint64_t* dst = rec + ((size_t)tile * 2 + (tile == 0 ? 1 : 0)) * WPR + c * 4 + qt * 2;
-                publish_word(dst, tag_word(tag, w0));
-                publish_word(dst + 1, tag_word(tag, w1));
-            }
+            // every column of BP is written each pass (padding columns hold zeros),
+            // so no word of a record can outlive the pass that wrote it
+            P::put(rec + ((size_t)tile * 2 + (tile == 0 ? 1 : 0)) * WPR + (c * 2 + qt) * P::WPV, acc, tag);
         }
         __syncthreads();
         if (tid == 0) publish_word(stat + tile, tag_word(tag, tile == 0 ? 2u : 1u));
@@ -255,12 +276,13 @@ __global__ __launch_bounds__(256) void l1_pass_kernel(
         // ================= decoupled look-back (wave 0) =================
         // Lane l reads the status word of tile hi - l.  The nearest predecessor
         // with an inclusive record ends the walk; every tile in between must
-        // have published its aggregate.  Status words are hints: the payload
-        // words carry their own tags and are re-checked, so a hint that ran
-        // ahead of its payload only costs a retry.
+        // have published its aggregate, and runs of aggregates are summed 64
+        // at a time while no inclusive record is in sight.  Status words are
+        // hints: payload words carry their own tags and are re-checked, so a
+        // hint that ran ahead of its payload only costs a retry.
         if (w == 0) {
             const int c = lane;
-            const bool act = c < b;
+            const bool act = c < BP;
             C c0 = P::czero(), c1 = P::czero();
             int64_t hi = (int64_t)tile - 1;
             while (hi >= 0) {
@@ -288,15 +310,12 @@ __global__ __launch_bounds__(256) void l1_pass_kernel(
                 if (act) {
                     for (int j = 0; j <= take; ++j) {
                         if (j == take && !fin) break;
-                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * 4;
-                        uint64_t v[4];
-#pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) {
-                            v[kk] = peek_word(src + kk);
-                            ok = ok && (uint32_t)(v[kk] >> 32) == tag;
-                        }
-                        s0 = P::cadd(s0, P::dec((uint32_t)v[0], (uint32_t)v[1]));
-                        s1 = P::cadd(s1, P::dec((uint32_t)v[2], (uint32_t)v[3]));
+                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * 2 * P::WPV;
+                        C v0, v1;
+                        ok = P::get(src, tag, v0) && ok;
+                        ok = P::get(src + P::WPV, tag, v1) && ok;
+                        s0 = P::cadd(s0, v0);
+                        s1 = P::cadd(s1, v1);
                     }
                 }
                 if (!__all(ok)) {
@@ -312,14 +331,9 @@ __global__ __launch_bounds__(256) void l1_pass_kernel(
                 s_run[0][c] = c0;
                 s_run[1][c] = c1;
                 if (tile > 0) {
-                    uint32_t w0, w1, w2, w3;
-                    P::enc(P::cadd(c0, s_tot[0][c]), w0, w1);
-                    P::enc(P::cadd(c1, s_tot[1][c]), w2, w3);
-                    uint64_t* dst = rec + ((size_t)tile * 2 + 1) * WPR + c * 4;
-                    publish_word(dst + 0, tag_word(tag, w0));
-                    publish_word(dst + 1, tag_word(tag, w1));
-                    publish_word(dst + 2, tag_word(tag, w2));
-                    publish_word(dst + 3, tag_word(tag, w3));
+                    uint64_t* dst = rec + ((size_t)tile * 2 + 1) * WPR + c * 2 * P::WPV;
+                    P::put(dst, P::cadd(c0, s_tot[0][c]), tag);
+                    P::put(dst + P::WPV, P::cadd(c1, s_tot[1][c]), tag);
                 }
             }
             if (tile > 0 && lane == 0) publish_word(stat + tile, tag_word(tag, 2u));
@@ -418,6 +432,290 @@ __global__ __launch_bounds__(256) void l1_pass_kernel(
                 }
             }
         }
+        if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
+        __syncthreads();
+        ticket = s_ticket;
+        __syncthreads();
+    }
+}
+
+// Variant that keeps the whole tile on chip: a tile is two sub-chunks; the
+// first is staged in LDS (as per-thread storage) and the second stays in
+// registers, so phase 2 reads no Z row twice.  Used where the staging fits.
+template <typename P, int BP, int R, int OC, bool VEC>
+__global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
+    const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
+    const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
+    const typename P::T* __restrict__ T0, const typename P::T* __restrict__ U, int first,
+    uint64_t* __restrict__ ticket_ctr, int cls, int64_t ntiles,
+    uint64_t* __restrict__ rec, uint64_t* __restrict__ stat)
+{
+    using L = typename P::L;
+    using C = typename P::C;
+    using Ly = Lay<BP>;
+    constexpr int CPL = Ly::CPL, LPR = Ly::LPR, RPW = Ly::RPW, NS = Ly::NS;
+    constexpr int CHUNK = NS * R;       // ranks per sub-chunk (one register load per slot)
+    constexpr int SUB = 2;
+    constexpr int TILE = CHUNK * SUB;   // ranks per tile
+    constexpr int WPR = 2 * BP * P::WPV;   // words per record: (P0, P1) per column, every column of BP
+    static_assert(R % OC == 0, "Out chunk must divide the ranks per slot");
+
+    __shared__ uint64_t s_ticket;
+    __shared__ C s_red[4][2][BP];
+    __shared__ C s_tot[2][BP];
+    __shared__ L s_wtot[4][2][BP];
+    __shared__ C s_wexcl[4][2][BP];
+    __shared__ C s_run[2][BP];
+    __shared__ typename P::Z s_g[R][256][CPL];   // sub-chunk 0 of the tile, per thread
+    __shared__ uint32_t s_p[NS][R];
+    __shared__ typename P::X s_x[NS][R];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int slot = w * RPW + lane / LPR;
+    const int col0 = (lane % LPR) * CPL;
+    // Each workgroup takes tiles in ticket order until it draws one of the G
+    // tickets past the last tile, so a pass consumes ntiles + G tickets.
+    const uint64_t per_pass = (uint64_t)ntiles + gridDim.x;
+    if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
+    __syncthreads();
+    uint64_t ticket = s_ticket;
+
+    for (;;) {
+        const uint64_t tile = ticket % per_pass;
+        if (tile >= (uint64_t)ntiles) break;
+        const uint32_t tag = ((uint32_t)(cls + 1) << 24) | (uint32_t)((ticket / per_pass) & 0xffffffu);
+        const int64_t tbase = (int64_t)tile * TILE + (int64_t)slot * R;
+
+        // ================= phase 1: the tile's totals =================
+        C t0[CPL], t1[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) { t0[j] = P::czero(); t1[j] = P::czero(); }
+        uint32_t pk[R];
+        typename P::X xk[R];
+        typename P::Z gk[R][CPL];
+#pragma unroll
+        for (int s = 0; s < SUB; ++s) {
+            const int64_t r0 = tbase + (int64_t)s * CHUNK;
+            uint32_t p[R];
+            typename P::X x[R];
+            typename P::Z g[R][CPL];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const bool valid = r0 + i < n;
+                p[i] = valid ? perm[r0 + i] : 0u;
+                x[i] = valid ? xs[r0 + i] : typename P::X(0);
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) load_row<CPL, VEC>(Z + (size_t)p[i] * b, col0, b, r0 + i < n, g[i]);
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                L a0 = P::lzero(), a1 = P::lzero();
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    a0 = P::ladd(a0, g[i][j]);
+                    a1 = P::lmac(a1, x[i], g[i][j]);
+                }
+                t0[j] = P::caddl(t0[j], a0);
+                t1[j] = P::caddl(t1[j], a1);
+            }
+            if (s == 0) {
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) s_g[i][tid][j] = g[i][j];
+                if (lane % LPR == 0) {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        s_p[slot][i] = p[i];
+                        s_x[slot][i] = x[i];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    pk[i] = p[i];
+                    xk[i] = x[i];
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) gk[i][j] = g[i][j];
+                }
+            }
+        }
+        // sum over the slots of the wave (lanes that share columns), then the waves
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+#pragma unroll
+            for (int off = LPR; off < DM_WAVE; off <<= 1) {
+                t0[j] = P::cadd(t0[j], P::cshfl_xor(t0[j], off));
+                t1[j] = P::cadd(t1[j], P::cshfl_xor(t1[j], off));
+            }
+            if (lane < LPR) {
+                s_red[w][0][col0 + j] = t0[j];
+                s_red[w][1][col0 + j] = t1[j];
+            }
+        }
+        __syncthreads();
+        if (tid < 2 * BP) {
+            const int qt = tid / BP, c = tid % BP;
+            const C acc = P::cadd(P::cadd(s_red[0][qt][c], s_red[1][qt][c]), P::cadd(s_red[2][qt][c], s_red[3][qt][c]));
+            s_tot[qt][c] = acc;
+            // every column of BP is written each pass (padding columns hold zeros),
+            // so no word of a record can outlive the pass that wrote it
+            P::put(rec + ((size_t)tile * 2 + (tile == 0 ? 1 : 0)) * WPR + (c * 2 + qt) * P::WPV, acc, tag);
+        }
+        __syncthreads();
+        if (tid == 0) publish_word(stat + tile, tag_word(tag, tile == 0 ? 2u : 1u));
+
+        // ================= decoupled look-back (wave 0) =================
+        // Lane l reads the status word of tile hi - l.  The nearest predecessor
+        // with an inclusive record ends the walk; every tile in between must
+        // have published its aggregate, and runs of aggregates are summed 64
+        // at a time while no inclusive record is in sight.  Status words are
+        // hints: payload words carry their own tags and are re-checked, so a
+        // hint that ran ahead of its payload only costs a retry.
+        if (w == 0) {
+            const int c = lane;
+            const bool act = c < BP;
+            C c0 = P::czero(), c1 = P::czero();
+            int64_t hi = (int64_t)tile - 1;
+            while (hi >= 0) {
+                const int64_t q = hi - lane;
+                const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
+                const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
+                const uint64_t mI = __ballot(state == 2u);
+                const uint64_t mA = __ballot(state >= 1u);
+                const int la = (~mA) ? __builtin_ctzll(~mA) : 64;   // leading lanes with a record
+                const int li = mI ? __builtin_ctzll(mI) : 64;        // nearest inclusive record
+                bool fin;
+                int take;
+                if (li < 64 && li <= la) {
+                    fin = true;
+                    take = li;
+                } else if (la > 0) {
+                    fin = false;
+                    take = la;
+                } else {
+                    __builtin_amdgcn_s_sleep(2);
+                    continue;
+                }
+                C s0 = P::czero(), s1 = P::czero();
+                bool ok = true;
+                if (act) {
+                    for (int j = 0; j <= take; ++j) {
+                        if (j == take && !fin) break;
+                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * 2 * P::WPV;
+                        C v0, v1;
+                        ok = P::get(src, tag, v0) && ok;
+                        ok = P::get(src + P::WPV, tag, v1) && ok;
+                        s0 = P::cadd(s0, v0);
+                        s1 = P::cadd(s1, v1);
+                    }
+                }
+                if (!__all(ok)) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                c0 = P::cadd(c0, s0);
+                c1 = P::cadd(c1, s1);
+                if (fin) break;
+                hi -= take;
+            }
+            if (act) {
+                s_run[0][c] = c0;
+                s_run[1][c] = c1;
+                if (tile > 0) {
+                    uint64_t* dst = rec + ((size_t)tile * 2 + 1) * WPR + c * 2 * P::WPV;
+                    P::put(dst, P::cadd(c0, s_tot[0][c]), tag);
+                    P::put(dst + P::WPV, P::cadd(c1, s_tot[1][c]), tag);
+                }
+            }
+            if (tile > 0 && lane == 0) publish_word(stat + tile, tag_word(tag, 2u));
+        }
+        __syncthreads();
+
+        // ================= phase 2: scan and scatter, sub-chunk by sub-chunk =================
+        // sub-chunk 0 is read back from LDS, sub-chunk 1 from registers
+        auto phase2 = [&](const int64_t r0, auto&& getp, auto&& getx, auto&& getg) {
+            L e0[CPL], e1[CPL];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                L i0 = P::lzero(), i1 = P::lzero();
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    i0 = P::ladd(i0, getg(i, j));
+                    i1 = P::lmac(i1, getx(i), getg(i, j));
+                }
+#pragma unroll
+                for (int off = LPR; off < DM_WAVE; off <<= 1) {
+                    const L u0 = P::shfl_up(i0, off), u1 = P::shfl_up(i1, off);
+                    if (lane >= off) { i0 = P::lsum(i0, u0); i1 = P::lsum(i1, u1); }
+                }
+                const L x0 = P::shfl_up(i0, LPR), x1 = P::shfl_up(i1, LPR);
+                e0[j] = lane >= LPR ? x0 : P::lzero();
+                e1[j] = lane >= LPR ? x1 : P::lzero();
+                if (lane >= DM_WAVE - LPR) {
+                    s_wtot[w][0][col0 + j] = i0;
+                    s_wtot[w][1][col0 + j] = i1;
+                }
+            }
+            __syncthreads();
+            if (tid < 2 * BP) {
+                const int qt = tid / BP, c = tid % BP;
+                C acc = s_run[qt][c];
+#pragma unroll
+                for (int ww = 0; ww < 4; ++ww) {
+                    s_wexcl[ww][qt][c] = acc;
+                    acc = P::caddl(acc, s_wtot[ww][qt][c]);
+                }
+                s_run[qt][c] = acc;
+            }
+            __syncthreads();
+
+            typename P::Fin f[CPL];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                const int c = col0 + j;
+                if (c < b) {
+                    const C b0 = P::caddl(s_wexcl[w][0][c], e0[j]);
+                    const C b1 = P::caddl(s_wexcl[w][1][c], e1[j]);
+                    f[j] = P::fin(b0, b1, T0[c], first ? U[c] : typename P::T(0));
+                } else {
+                    f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
+                }
+            }
+            L l0[CPL], l1[CPL];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) { l0[j] = P::lzero(); l1[j] = P::lzero(); }
+#pragma unroll
+            for (int i0 = 0; i0 < R; i0 += OC) {
+                typename P::O o[OC][CPL];
+#pragma unroll
+                for (int i = 0; i < OC; ++i) {
+                    if (!first) {
+                        load_row<CPL, VEC>(Out + (size_t)getp(i0 + i) * b, col0, b, r0 + i0 + i < n, o[i]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < CPL; ++j) o[i][j] = P::ufirst(f[j]);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < OC; ++i) {
+                    typename P::O res[CPL];
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) {
+                        l0[j] = P::ladd(l0[j], getg(i0 + i, j));
+                        l1[j] = P::lmac(l1[j], getx(i0 + i), getg(i0 + i, j));
+                        res[j] = P::oadd(o[i][j], P::out(l0[j], l1[j], getx(i0 + i), f[j]));
+                    }
+                    if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + (size_t)getp(i0 + i) * b, col0, b, res);
+                }
+            }
+        };
+        phase2(
+            tbase, [&](int i) { return s_p[slot][i]; }, [&](int i) { return s_x[slot][i]; },
+            [&](int i, int j) { return s_g[i][tid][j]; });
+        phase2(
+            tbase + CHUNK, [&](int i) { return pk[i]; }, [&](int i) { return xk[i]; },
+            [&](int i, int j) { return gk[i][j]; });
         if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
         __syncthreads();
         ticket = s_ticket;
@@ -572,9 +870,14 @@ static int bpad(int32_t b) {
     return bp;
 }
 
+// Tiles of the l1 pass kernels: the keep kernel (whole tile on chip, two
+// sub-chunks) for float blocks of 32 or more columns, the re-gathering kernel
+// (four sub-chunks) otherwise.
+template <typename P, int BP> constexpr bool use_keep() { return std::is_same<P, FloatPath>::value && BP >= 32; }
+
 template <int BP> static int tile_ranks_bp(bool is_int) {
     return is_int ? Lay<BP>::NS * r_int<BP>() * sub_chunks<BP, r_int<BP>()>()
-                  : Lay<BP>::NS * r_float<BP>() * sub_chunks<BP, r_float<BP>()>();
+                  : Lay<BP>::NS * r_float<BP>() * (use_keep<FloatPath, BP>() ? 2 : sub_chunks<BP, r_float<BP>()>());
 }
 
 int l1_tile_ranks(int32_t b, bool is_int, int zkind) {
@@ -593,22 +896,35 @@ int l1_tile_ranks(int32_t b, bool is_int, int zkind) {
 size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind) {
     const int64_t tile = l1_tile_ranks(b, is_int, zkind);
     const int64_t ntiles = (n + tile - 1) / tile;
-    return (size_t)ntiles * (2 * 4 * (size_t)bpad(b) + 1);   // two records and one status word per tile
+    const size_t wpv = is_int ? 2 : 1;
+    return (size_t)ntiles * (2 * 2 * wpv * (size_t)bpad(b) + 1);   // two records and one status word per tile
 }
 
 template <int BP> constexpr int log2c() { return BP <= 1 ? 0 : 1 + log2c<BP / 2>(); }
 
-template <typename P, int BP, int R, int SUB, int OC, bool VEC>
-static int persistent_grid(int64_t ntiles) {
-    static int per_cu = -1, cus = -1;
-    if (per_cu < 0) {
-        int dev = 0, nb = 0;
+// Persistent grid: as many workgroups as fit on the device at once (never more
+// than one per tile).  Cached per kernel; every pass of one kernel shape gets
+// the same grid, which the ticket arithmetic relies on.
+static int persistent_grid_of(int64_t ntiles, const void* fn, const void* fn2) {
+    struct Entry { const void* fn; int per_cu; };
+    static Entry cache[64];
+    static int cached = 0, cus = -1;
+    if (cus < 0) {
+        int dev = 0;
         (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, l1_pass_kernel<P, BP, R, SUB, OC, VEC>, 256, 0) !=
-                hipSuccess || nb < 1)
-            nb = 1;
-        per_cu = nb;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    }
+    // the smaller occupancy of the two variants (vector and scalar row access)
+    // of one shape, so that every pass of the shape uses the same grid
+    int per_cu = 0;
+    for (int i = 0; i < cached; ++i)
+        if (cache[i].fn == fn) per_cu = cache[i].per_cu;
+    if (per_cu == 0) {
+        int nb = 0, nb2 = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, fn2, 256, 0) != hipSuccess || nb2 < 1) nb2 = 1;
+        per_cu = nb < nb2 ? nb : nb2;
+        if (cached < 64) cache[cached++] = Entry{fn, per_cu};
     }
     int64_t g = (int64_t)per_cu * cus;
     if (g > ntiles) g = ntiles;
@@ -617,27 +933,42 @@ static int persistent_grid(int64_t ntiles) {
 
 template <typename P, int BP, int R>
 static hipError_t launch_one(const L1PassArgs& a, int32_t b, hipStream_t s) {
-    constexpr int SUB = sub_chunks<BP, R>();
+    constexpr bool KEEP = use_keep<P, BP>();
+    constexpr int SUB = KEEP ? 2 : sub_chunks<BP, R>();
     constexpr int TILE = Lay<BP>::NS * R * SUB;
     constexpr int OC = out_chunk<BP, R>();
     // one ticket counter per kernel instantiation family (data path x BP)
     constexpr int kind = std::is_same<P, FloatPath>::value ? 0 : std::is_same<P, IntPath<int32_t>>::value ? 1 : 2;
     const int cls = kind * 8 + log2c<BP>();
     const int64_t ntiles = (a.n + TILE - 1) / TILE;
-    uint64_t* stat = a.records + (size_t)ntiles * 2 * 4 * BP;
+    uint64_t* stat = a.records + (size_t)ntiles * 2 * 2 * P::WPV * BP;
     uint64_t* ctr = &a.chain->ticket[cls];
     const bool vec = (b == BP) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
     // one grid size per tile shape: every pass of a shape must use the same
     // grid, since the ticket count of a pass is ntiles + grid
-    const int grid = persistent_grid<P, BP, R, SUB, OC, false>(ntiles);
-    if (vec)
-        l1_pass_kernel<P, BP, R, SUB, OC, true><<<grid, 256, 0, s>>>(
-            a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, cls, ntiles, a.records, stat);
-    else
-        l1_pass_kernel<P, BP, R, SUB, OC, false><<<grid, 256, 0, s>>>(
-            a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, cls, ntiles, a.records, stat);
+    if constexpr (KEEP) {
+        const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_keep_kernel<P, BP, R, OC, false>,
+                                            (const void*)l1_pass_keep_kernel<P, BP, R, OC, true>);
+        if (vec)
+            l1_pass_keep_kernel<P, BP, R, OC, true><<<grid, 256, 0, s>>>(
+                a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, cls, ntiles, a.records, stat);
+        else
+            l1_pass_keep_kernel<P, BP, R, OC, false><<<grid, 256, 0, s>>>(
+                a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, cls, ntiles, a.records, stat);
+    } else {
+        const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_kernel<P, BP, R, SUB, OC, false>,
+                                            (const void*)l1_pass_kernel<P, BP, R, SUB, OC, true>);
+        if (vec)
+            l1_pass_kernel<P, BP, R, SUB, OC, true><<<grid, 256, 0, s>>>(
+                a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, cls, ntiles, a.records, stat);
+        else
+            l1_pass_kernel<P, BP, R, SUB, OC, false><<<grid, 256, 0, s>>>(
+                a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, cls, ntiles, a.records, stat);
+    }
     return hipGetLastError();
 }
 
