@@ -790,36 +790,54 @@ __global__ __launch_bounds__(256) void totals_stage1(const ZT* __restrict__ Z, i
     if (!INT && bad) atomicOr(status, (uint32_t)QF_NONFINITE);
 }
 
+// one block per column: threads take strided slices of the partials, then a
+// fixed tree in LDS (reproducible FP64 sums)
 template <bool INT>
 __global__ __launch_bounds__(256) void totals_stage2(const void* __restrict__ partials, int nblk, int32_t b,
                                                      void* __restrict__ T0, void* __restrict__ U,
                                                      double* __restrict__ zl1, double guard_scale,
                                                      uint32_t* __restrict__ status)
 {
-    for (int c = threadIdx.x; c < b; c += blockDim.x) {
-        double a0 = 0, a1 = 0, al = 0;
-        uint64_t b0 = 0, b1 = 0;
-        for (int k = 0; k < nblk; ++k) {
-            const double* pf = (const double*)partials + ((size_t)k * b + c) * 3;
-            if (INT) {
-                b0 += (uint64_t)__double_as_longlong(pf[0]);
-                b1 += (uint64_t)__double_as_longlong(pf[1]);
-            } else {
-                a0 += pf[0];
-                a1 += pf[1];
-            }
-            al += pf[2];
-        }
+    __shared__ double s_f[3][256];
+    __shared__ uint64_t s_i[2][256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    double a0 = 0, a1 = 0, al = 0;
+    uint64_t b0 = 0, b1 = 0;
+    for (int k = t; k < nblk; k += 256) {
+        const double* pf = (const double*)partials + ((size_t)k * b + c) * 3;
         if (INT) {
-            ((int64_t*)T0)[c] = (int64_t)b0;
-            ((int64_t*)U)[c] = (int64_t)b1;
-            // every |(A z)_i| <= ||z||_1 * max_ij A_ij <= ||z||_1 * guard_scale
-            if (!(al * guard_scale < 4611686018427387904.0)) atomicOr(status, (uint32_t)QF_OVERFLOW);
+            b0 += (uint64_t)__double_as_longlong(pf[0]);
+            b1 += (uint64_t)__double_as_longlong(pf[1]);
         } else {
-            ((double*)T0)[c] = a0;
-            ((double*)U)[c] = a1;
+            a0 += pf[0];
+            a1 += pf[1];
         }
-        zl1[c] = al;
+        al += pf[2];
+    }
+    s_f[0][t] = a0; s_f[1][t] = a1; s_f[2][t] = al;
+    s_i[0][t] = b0; s_i[1][t] = b1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            s_f[0][t] += s_f[0][t + h];
+            s_f[1][t] += s_f[1][t + h];
+            s_f[2][t] += s_f[2][t + h];
+            s_i[0][t] += s_i[0][t + h];
+            s_i[1][t] += s_i[1][t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (INT) {
+            ((int64_t*)T0)[c] = (int64_t)s_i[0][0];
+            ((int64_t*)U)[c] = (int64_t)s_i[1][0];
+            // every |(A z)_i| <= ||z||_1 * max_ij A_ij <= ||z||_1 * guard_scale
+            if (!(s_f[2][0] * guard_scale < 4611686018427387904.0)) atomicOr(status, (uint32_t)QF_OVERFLOW);
+        } else {
+            ((double*)T0)[c] = s_f[0][0];
+            ((double*)U)[c] = s_f[1][0];
+        }
+        zl1[c] = s_f[2][0];
     }
 }
 
@@ -849,9 +867,9 @@ hipError_t launch_totals(bool is_int, int zkind, const void* Z, int64_t n, int32
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (is_int)
-        totals_stage2<true><<<1, 256, 0, s>>>(o.partials, nblk, b, o.T0, o.U, o.zl1, guard_scale, o.status);
+        totals_stage2<true><<<b, 256, 0, s>>>(o.partials, nblk, b, o.T0, o.U, o.zl1, guard_scale, o.status);
     else
-        totals_stage2<false><<<1, 256, 0, s>>>(o.partials, nblk, b, o.T0, o.U, o.zl1, guard_scale, o.status);
+        totals_stage2<false><<<b, 256, 0, s>>>(o.partials, nblk, b, o.T0, o.U, o.zl1, guard_scale, o.status);
     return hipGetLastError();
 }
 
