@@ -134,6 +134,35 @@ dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, voi
 int dm_int_bound_ok(double sum_ranges, double z_l1);
 
 /*
+ * Many point sets in one query.  Each dataset is prepared exactly as by
+ * dm_prepare (l1 only; all datasets share one segmented sort), and one call
+ * of dm_matvec_multi answers A_s Z_s for every dataset s with the same b.
+ * The query is captured once per b in a hipGraph (descriptor upload, totals,
+ * one launch per coordinate round) and replayed on every call.
+ *
+ * sets: host array of count descriptors; X device, n x d row-major.
+ * Z[s]: device n_s x b, float for float datasets, int32 for integer ones.
+ * Out[s]: device n_s x b, float or int64.  Z and Out are host arrays of
+ * count device pointers.  1 <= b <= 64.
+ * A call that changes any Z/Out pointer waits for the previous call's upload
+ * of the pointer table to have run.  Errors as for dm_prepare / dm_matvec;
+ * a non-l1 metric is DM_ERR_ARG; dm_matvec_multi on a single-dataset handle
+ * (or dm_matvec on a multi-dataset handle) is DM_ERR_STATE.
+ */
+typedef struct {
+    const void* X;
+    int64_t n;
+    int32_t d;
+    int32_t metric;
+    int32_t dtype;
+} dm_dataset;
+dm_status dm_workspace_size_multi(const dm_dataset* sets, int32_t count, size_t* bytes);
+dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspace, size_t ws_bytes, void* stream,
+                           dm_handle** out);
+dm_status dm_matvec_multi(dm_handle* h, const void* const* Z, int32_t b, void* const* Out, void* stream);
+dm_status dm_multi_count(const dm_handle* h, int32_t* count);
+
+/*
  * Measurement support.  While profiling is on, every launch of the listed
  * kernel classes is bracketed by HIP events on the query stream;
  * dm_profile_read waits for them and returns the summed device time and the

@@ -31,6 +31,12 @@ ERR_ARG, ERR_NONFINITE, ERR_OVERFLOW, ERR_NOMEM, ERR_DEVICE, ERR_DTYPE, ERR_STAT
 _lib = None
 
 
+class Dataset(ctypes.Structure):
+    """dm_dataset: one point set of a multi-dataset handle."""
+    _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("metric", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
 class DMError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -73,6 +79,14 @@ def lib():
     L.dm_profile_read.restype = i32
     L.dm_copy_probe.argtypes = [P, P, sz, P]
     L.dm_copy_probe.restype = i32
+    L.dm_workspace_size_multi.argtypes = [ctypes.POINTER(Dataset), i32, ctypes.POINTER(sz)]
+    L.dm_workspace_size_multi.restype = i32
+    L.dm_prepare_multi.argtypes = [ctypes.POINTER(Dataset), i32, P, sz, P, ctypes.POINTER(P)]
+    L.dm_prepare_multi.restype = i32
+    L.dm_matvec_multi.argtypes = [P, ctypes.POINTER(P), i32, ctypes.POINTER(P), P]
+    L.dm_matvec_multi.restype = i32
+    L.dm_multi_count.argtypes = [P, ctypes.POINTER(i32)]
+    L.dm_multi_count.restype = i32
     _lib = L
     return L
 
@@ -230,3 +244,73 @@ def prepare(X, metric: int = L1, stream=None) -> Handle:
                           _stream_ptr(stream), ctypes.byref(h))
     _check(st, "dm_prepare")
     return Handle(h, ws, n, d, metric, code)
+
+
+class MultiHandle:
+    """Many prepared point sets answered together (one captured graph per b)."""
+
+    def __init__(self, ptr, workspace, shapes, dtypes):
+        self._ptr = ptr
+        self._ws = workspace
+        self.shapes = shapes          # [(n, d)]
+        self.dtypes = dtypes          # dtype codes
+
+    def matvec(self, Zs, outs=None, stream=None):
+        """Outs[s] = A_s Zs[s] for every dataset (same b for all)."""
+        torch = _torch()
+        if len(Zs) != len(self.shapes):
+            raise ValueError("one Z per dataset")
+        b = Zs[0].shape[1]
+        if outs is None:
+            outs = [torch.empty((n, b), dtype=torch.int64 if t in (I32, I64) else torch.float32, device=Z.device)
+                    for (n, _), t, Z in zip(self.shapes, self.dtypes, Zs)]
+        zp = (ctypes.c_void_p * len(Zs))()
+        op = (ctypes.c_void_p * len(Zs))()
+        for i, (Z, O, (n, _), t) in enumerate(zip(Zs, outs, self.shapes, self.dtypes)):
+            if Z.dim() != 2 or Z.shape != (n, b):
+                raise ValueError("Z[%d] must be n x b" % i)
+            want = torch.int32 if t in (I32, I64) else torch.float32
+            if Z.dtype != want:
+                raise DMError(ERR_DTYPE, "dm_matvec_multi")
+            zp[i] = _dev_ptr(Z, "Z").value
+            op[i] = _dev_ptr(O, "out").value
+        self._keep = (Zs, outs)       # the graph reads these pointers when it runs
+        _check(lib().dm_matvec_multi(self._ptr, zp, b, op, _stream_ptr(stream)), "dm_matvec_multi")
+        return outs
+
+    def sync(self):
+        _check(lib().dm_sync(self._ptr), "dm_sync")
+
+    def free(self):
+        if self._ptr:
+            lib().dm_free(self._ptr)
+            self._ptr = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def prepare_multi(Xs, stream=None) -> MultiHandle:
+    """Prepare many point sets (list of n_s x d_s device tensors) for l1 queries."""
+    torch = _torch()
+    arr = (Dataset * len(Xs))()
+    shapes, codes = [], []
+    for i, X in enumerate(Xs):
+        if X.dim() != 2:
+            raise ValueError("X[%d] must be n x d" % i)
+        code = _dtype_code(X.dtype)
+        arr[i] = Dataset(_dev_ptr(X, "X").value, X.shape[0], X.shape[1], L1, code)
+        shapes.append((X.shape[0], X.shape[1]))
+        codes.append(code)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().dm_workspace_size_multi(arr, len(Xs), ctypes.byref(nbytes)), "dm_workspace_size_multi")
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=Xs[0].device)
+    off = (-ws.data_ptr()) % 256
+    h = ctypes.c_void_p(None)
+    _check(lib().dm_prepare_multi(arr, len(Xs), ctypes.c_void_p(ws.data_ptr() + off), nbytes.value,
+                                  _stream_ptr(stream), ctypes.byref(h)), "dm_prepare_multi")
+    return MultiHandle(h, ws, shapes, codes)

@@ -113,7 +113,10 @@ struct Ctl {
 
 }  // namespace
 
+struct MultiState;
+
 struct dm_handle {
+    MultiState* multi = nullptr;   // non-NULL for a multi-dataset handle
     int device = 0;
     int64_t n = 0;
     int32_t d = 0;
@@ -126,6 +129,9 @@ struct dm_handle {
     Ctl* ctl = nullptr;
     char* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // look-back record regions, one per pass kernel shape (zeroed when created)
+    struct Region { int cls; uint64_t* ptr; size_t words; };
+    std::vector<Region> regions;
     double guard_scale = 0.0;   // sum of ranges (l1) or squared ranges (l2 squared)
     hipStream_t last = nullptr;
 
@@ -142,13 +148,17 @@ struct dm_handle {
 
 namespace {
 
+void release_multi(MultiState* m);
+
 void release(dm_handle* h) {
     if (!h) return;
+    if (h->multi) release_multi(h->multi);
     for (auto& e : h->evs) {
         if (e.a) (void)hipEventDestroy(e.a);
         if (e.b) (void)hipEventDestroy(e.b);
     }
     if (h->scratch) (void)hipFree(h->scratch);
+    for (auto& r : h->regions) (void)hipFree(r.ptr);
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
     delete h;
@@ -164,9 +174,30 @@ double key_to_double(uint32_t k, bool is_int) {
 
 size_t query_scratch_bytes(const dm_handle* h, int32_t b) {
     size_t s = al(totals_scratch_bytes(h->n, b));
-    if (h->metric == DM_L1) s += al(l1_record_words(h->n, b, h->is_int, h->is_int ? IN_I64 : IN_F32) * 8);
-    else s += al(l2_scratch_bytes(h->n, h->d, b));
+    if (h->metric != DM_L1) s += al(l2_scratch_bytes(h->n, h->d, b));
     return s;
+}
+
+// the record region of one pass shape, created (and zeroed) on first use
+dm_status region_for(dm_handle* h, const L1Shape& sh, hipStream_t s, uint64_t** out) {
+    for (auto& r : h->regions)
+        if (r.cls == sh.cls && r.words >= sh.record_words) {
+            *out = r.ptr;
+            return DM_OK;
+        }
+    for (auto it = h->regions.begin(); it != h->regions.end(); ++it)
+        if (it->cls == sh.cls) {   // too small (cannot happen for a fixed n): replace
+            DM_TRY(hipStreamSynchronize(h->last));
+            DM_TRY(hipFree(it->ptr));
+            h->regions.erase(it);
+            break;
+        }
+    void* p = nullptr;
+    DM_TRY(hipMalloc(&p, sh.record_words * 8));
+    DM_TRY(launch_fill_u32((uint32_t*)p, 0u, sh.record_words * 2, s));
+    h->regions.push_back(dm_handle::Region{sh.cls, (uint64_t*)p, sh.record_words});
+    *out = (uint64_t*)p;
+    return DM_OK;
 }
 
 dm_status ensure_scratch(dm_handle* h, int32_t b, hipStream_t s) {
@@ -185,7 +216,6 @@ dm_status ensure_scratch(dm_handle* h, int32_t b, hipStream_t s) {
     DM_TRY(hipMalloc(&p, need));
     h->scratch = (char*)p;
     h->scratch_bytes = need;
-    // tagged words must never match a live tag: start from zero (tag 0 is never used)
     DM_TRY(launch_fill_u32((uint32_t*)p, 0u, need / 4, s));
     return DM_OK;
 }
@@ -236,6 +266,7 @@ dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
     tb.key_len = h->at<int64_t>(L.key_len);
     tb.tile_off = h->at<uint32_t>(L.tile_off);
     tb.tile_seg = h->at<uint32_t>(L.tile_seg);
+    tb.seg_int = nullptr;
     tb.nseg = d;
     tb.ntiles = L.ntiles;
 
@@ -375,13 +406,22 @@ dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_
 
 dm_status dm_reserve(dm_handle* h, int32_t b) {
     if (!h || b < 1 || b > MAX_B) return DM_ERR_ARG;
+    if (h->multi) return DM_ERR_STATE;
     dm_status st = ensure_scratch(h, b, h->last);
     if (st != DM_OK) return st;
+    if (h->metric == DM_L1) {
+        const int kinds[2] = {h->is_int ? IN_I32 : IN_F32, IN_I64};
+        for (int ki = 0; ki < (h->is_int ? 2 : 1); ++ki) {
+            uint64_t* r = nullptr;
+            if ((st = region_for(h, l1_shape(h->n, b, h->is_int, kinds[ki]), h->last, &r)) != DM_OK) return st;
+        }
+    }
     return hipStreamSynchronize(h->last) == hipSuccess ? DM_OK : DM_ERR_DEVICE;
 }
 
 dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream) {
     if (!h || !Z || !Out || b < 1 || b > MAX_B) return DM_ERR_ARG;
+    if (h->multi) return DM_ERR_STATE;
     if (!valid_dtype(z_dtype)) return DM_ERR_ARG;
     if (h->is_int ? !(z_dtype == DM_I32 || z_dtype == DM_I64) : z_dtype != DM_F32) return DM_ERR_DTYPE;
     const size_t zbytes = (size_t)h->n * b * dtype_size(z_dtype);
@@ -414,7 +454,10 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         a.T0 = tot.T0;
         a.U = tot.U;
         a.chain = &h->ctl->chain;
-        a.records = (uint64_t*)rest;
+        {
+            dm_status rs = region_for(h, l1_shape(h->n, b, h->is_int, zkind), s, &a.records);
+            if (rs != DM_OK) return rs;
+        }
         const size_t vsz = 4;
         for (int32_t k = 0; k < h->d; ++k) {
             a.perm = h->at<uint32_t>(h->L.perm) + (size_t)k * h->L.ld;
@@ -456,6 +499,7 @@ dm_status dm_info(const dm_handle* h, int64_t* n, int32_t* d, int32_t* metric, i
 
 dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, void* xs, void* stream) {
     if (!h) return DM_ERR_ARG;
+    if (h->multi) return DM_ERR_STATE;
     if (h->metric != DM_L1) return DM_ERR_STATE;
     hipStream_t s = (hipStream_t)stream;
     const size_t w = (size_t)h->n * 4, sp = (size_t)h->L.ld * 4;
@@ -506,6 +550,439 @@ void dm_free(dm_handle* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->last);
     release(h);
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// many datasets in one query
+// ===========================================================================
+namespace {
+
+struct MultiSet {
+    int64_t n = 0, ld = 0, base = 0;   // base: first key of the dataset in the concatenated arrays
+    int32_t d = 0, dtype = 0;
+    bool is_int = false;
+    size_t rowsum = 0, rownrm = 0, kmin = 0, kmax = 0;
+    double guard = 0.0;
+};
+
+struct MultiPlan {
+    int32_t b = 0;
+    int32_t rounds = 0;
+    std::vector<int64_t> ntiles;   // [round][kind]
+    std::vector<int> grids;
+    std::vector<MultiTile*> tiles;
+    std::vector<uint64_t*> records;
+    uint64_t* tickets = nullptr;   // one per (round, kind)
+    double* partials = nullptr;
+    double* tot = nullptr;         // per dataset: T0 (b) and U (b)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct MultiLayout {
+    size_t perm = 0, xs = 0, rank = 0, k1 = 0, v1 = 0, counts = 0, flags = 0;
+    size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0, seg_int = 0;
+    int64_t total_keys = 0;
+    uint32_t ntiles = 0;
+    int32_t nseg = 0;
+    size_t total = 0;
+};
+
+}  // namespace
+
+struct MultiState {
+    std::vector<MultiSet> sets;
+    MultiLayout L;
+    int32_t maxd = 0;
+    MultiDs* d_ds = nullptr;     // device descriptors
+    MultiDs* h_ds = nullptr;     // pinned host mirror (source of the captured upload)
+    uint32_t* d_blk = nullptr;   // dataset of every totals block
+    int nblk = 0;
+    MultiPlan plan;
+    hipStream_t cap = nullptr;   // capture stream
+    hipEvent_t done = nullptr;   // recorded after every graph launch
+    bool launched = false;
+};
+
+namespace {
+
+void free_plan(MultiPlan& p) {
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    for (auto* t : p.tiles) if (t) (void)hipFree(t);
+    for (auto* r : p.records) if (r) (void)hipFree(r);
+    if (p.tickets) (void)hipFree(p.tickets);
+    if (p.partials) (void)hipFree(p.partials);
+    if (p.tot) (void)hipFree(p.tot);
+    p = MultiPlan();
+}
+
+dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSet>* out, MultiLayout* L) {
+    if (!sets || count < 1) return DM_ERR_ARG;
+    std::vector<MultiSet> v((size_t)count);
+    int64_t keys = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const dm_dataset& ds = sets[i];
+        if (ds.n < 1 || ds.d < 1 || ds.metric != DM_L1 || !valid_dtype(ds.dtype)) return DM_ERR_ARG;
+        v[i].n = ds.n;
+        v[i].d = ds.d;
+        v[i].dtype = ds.dtype;
+        v[i].is_int = int_dtype(ds.dtype);
+        v[i].ld = (ds.n + 63) / 64 * 64;
+        v[i].base = keys;
+        keys += (int64_t)ds.d * v[i].ld;
+        if (keys >= (int64_t)1 << 32) return DM_ERR_ARG;   // 32-bit sort positions
+    }
+    MultiLayout M;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += al(bytes);
+        return at;
+    };
+    M.total_keys = keys;
+    const size_t arr = (size_t)keys * 4;
+    M.perm = take(arr);
+    M.xs = take(arr);
+    M.rank = take(arr);
+    int32_t nseg = 0;
+    uint32_t ntiles = 0;
+    for (auto& m : v) {
+        m.rowsum = take((size_t)m.n * 8);
+        m.rownrm = take((size_t)m.n * 8);
+        m.kmin = take((size_t)m.d * 4);
+        m.kmax = take((size_t)m.d * 4);
+        nseg += m.d;
+        ntiles += (uint32_t)m.d * (uint32_t)((m.n + SORT_TILE - 1) / SORT_TILE);
+    }
+    M.nseg = nseg;
+    M.ntiles = ntiles;
+    M.flags = take(16);
+    M.key_off = take((size_t)nseg * 8);
+    M.key_len = take((size_t)nseg * 8);
+    M.tile_off = take((size_t)(nseg + 1) * 4);
+    M.tile_seg = take((size_t)ntiles * 4);
+    M.seg_int = take((size_t)nseg);
+    M.k1 = take(arr);
+    M.v1 = take(arr);
+    M.counts = take((size_t)ntiles * 256 * 4);
+    M.total = o;
+    if (out) *out = std::move(v);
+    if (L) *L = M;
+    return DM_OK;
+}
+
+// Build the round tables, record regions and the captured graph for b.
+dm_status build_plan(dm_handle* h, int32_t b) {
+    MultiState* m = h->multi;
+    MultiPlan& p = m->plan;
+    if (m->launched) DM_TRY(hipEventSynchronize(m->done));
+    free_plan(p);
+    p.b = b;
+    p.rounds = m->maxd;
+    const int nsets = (int)m->sets.size();
+    // per-dataset totals storage and descriptors
+    {
+        void* q = nullptr;
+        DM_TRY(hipMalloc(&q, (size_t)nsets * 2 * b * 8));
+        p.tot = (double*)q;
+        DM_TRY(hipMalloc(&q, (size_t)m->nblk * b * 3 * 8 + 8));
+        p.partials = (double*)q;
+        DM_TRY(hipMalloc(&q, (size_t)p.rounds * 2 * 8));
+        p.tickets = (uint64_t*)q;
+        DM_TRY(launch_fill_u32((uint32_t*)q, 0u, (size_t)p.rounds * 4, m->cap));
+    }
+    for (int s = 0; s < nsets; ++s) {
+        m->h_ds[s].T0 = p.tot + (size_t)s * 2 * b;
+        m->h_ds[s].U = p.tot + (size_t)s * 2 * b + b;
+    }
+    // datasets largest first inside every round, so long segments start early
+    std::vector<int> order(nsets);
+    for (int s = 0; s < nsets; ++s) order[s] = s;
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return m->sets[a].n > m->sets[c].n; });
+    p.ntiles.assign((size_t)p.rounds * 2, 0);
+    p.grids.assign((size_t)p.rounds * 2, 0);
+    p.tiles.assign((size_t)p.rounds * 2, nullptr);
+    p.records.assign((size_t)p.rounds * 2, nullptr);
+    for (int k = 0; k < p.rounds; ++k)
+        for (int kind = 0; kind < 2; ++kind) {
+            const int tr = multi_tile_ranks(b, kind == 1);
+            std::vector<MultiTile> t;
+            for (int s : order) {
+                const MultiSet& ms = m->sets[s];
+                if (ms.is_int != (kind == 1) || ms.d <= k) continue;
+                const int64_t nt = (ms.n + tr - 1) / tr;
+                for (int64_t i = 0; i < nt; ++i) t.push_back(MultiTile{(uint32_t)s, (uint32_t)i});
+            }
+            const size_t ix = (size_t)k * 2 + kind;
+            p.ntiles[ix] = (int64_t)t.size();
+            if (t.empty()) continue;
+            void* q = nullptr;
+            DM_TRY(hipMalloc(&q, t.size() * sizeof(MultiTile)));
+            p.tiles[ix] = (MultiTile*)q;
+            DM_TRY(hipMemcpyAsync(q, t.data(), t.size() * sizeof(MultiTile), hipMemcpyHostToDevice, m->cap));
+            const size_t words = multi_record_words((int64_t)t.size(), b, kind == 1);
+            DM_TRY(hipMalloc(&q, words * 8));
+            p.records[ix] = (uint64_t*)q;
+            DM_TRY(launch_fill_u32((uint32_t*)q, 0u, words * 2, m->cap));
+            p.grids[ix] = multi_grid((int64_t)t.size(), b, kind == 1);
+            DM_TRY(hipStreamSynchronize(m->cap));   // the host vector dies with this scope
+        }
+    // capture: descriptor upload, totals, every round
+    DM_TRY(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipMemcpyAsync(m->d_ds, m->h_ds, (size_t)nsets * sizeof(MultiDs), hipMemcpyHostToDevice, m->cap);
+    if (e == hipSuccess)
+        e = launch_multi_totals(m->d_ds, m->d_blk, m->nblk, nsets, b, p.partials, &h->ctl->status, m->cap);
+    for (int k = 0; k < p.rounds && e == hipSuccess; ++k)
+        for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) {
+            const size_t ix = (size_t)k * 2 + kind;
+            if (p.ntiles[ix] == 0) continue;
+            e = launch_multi_pass(kind == 1, b, m->d_ds, p.tiles[ix], p.ntiles[ix], k, p.tickets + ix, p.records[ix],
+                                  p.grids[ix], m->cap);
+        }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(m->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return from_hip(e != hipSuccess ? e : e2);
+    }
+    p.graph = g;
+    DM_TRY(hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0));
+    return DM_OK;
+}
+
+void release_multi(MultiState* m) {
+    if (!m) return;
+    if (m->launched) (void)hipEventSynchronize(m->done);
+    free_plan(m->plan);
+    if (m->d_ds) (void)hipFree(m->d_ds);
+    if (m->h_ds) (void)hipHostFree(m->h_ds);
+    if (m->d_blk) (void)hipFree(m->d_blk);
+    if (m->done) (void)hipEventDestroy(m->done);
+    if (m->cap) (void)hipStreamDestroy(m->cap);
+    delete m;
+}
+
+}  // namespace
+
+extern "C" {
+
+dm_status dm_workspace_size_multi(const dm_dataset* sets, int32_t count, size_t* bytes) {
+    if (!bytes) return DM_ERR_ARG;
+    MultiLayout L;
+    dm_status st = check_multi(sets, count, nullptr, &L);
+    if (st != DM_OK) return st;
+    *bytes = L.total;
+    return DM_OK;
+}
+
+dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspace, size_t ws_bytes, void* stream,
+                           dm_handle** out) {
+    if (!out) return DM_ERR_ARG;
+    *out = nullptr;
+    std::vector<MultiSet> v;
+    MultiLayout L;
+    dm_status st = check_multi(sets, count, &v, &L);
+    if (st != DM_OK) return st;
+    for (int32_t i = 0; i < count; ++i)
+        if (!sets[i].X) return DM_ERR_ARG;
+    if (workspace && (ws_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0)) return DM_ERR_ARG;
+    int dev = 0;
+    if ((st = device_ready(&dev)) != DM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    dm_handle* h = new (std::nothrow) dm_handle();
+    if (!h) return DM_ERR_NOMEM;
+    MultiState* m = new (std::nothrow) MultiState();
+    if (!m) {
+        delete h;
+        return DM_ERR_NOMEM;
+    }
+    h->multi = m;
+    h->device = dev;
+    h->metric = DM_L1;
+    h->n = 0;
+    for (auto& q : v) {
+        h->n += q.n;
+        m->maxd = std::max(m->maxd, q.d);
+    }
+    h->d = m->maxd;
+    h->dtype = 0;
+    m->sets = v;
+    m->L = L;
+    auto fail = [&](dm_status e) {
+        release(h);
+        return e;
+    };
+    if (workspace) {
+        h->ws = (char*)workspace;
+    } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, L.total) != hipSuccess) return fail(DM_ERR_NOMEM);
+        h->ws = (char*)p;
+        h->owns_ws = true;
+    }
+    {
+        void* p = nullptr;
+        if (hipMalloc(&p, sizeof(Ctl)) != hipSuccess) return fail(DM_ERR_NOMEM);
+        h->ctl = (Ctl*)p;
+    }
+    if (hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess)
+        return fail(DM_ERR_DEVICE);
+    Ctl init;
+    std::memset(&init, 0, sizeof(init));
+    if (hipMemcpyAsync(h->ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(DM_ERR_DEVICE);
+    if (launch_fill_u32(h->at<uint32_t>(L.flags), 0u, 4, s) != hipSuccess) return fail(DM_ERR_DEVICE);
+    // per dataset: validation, keys into the xs array, row statistics
+    for (int32_t i = 0; i < count; ++i) {
+        const MultiSet& q = m->sets[i];
+        if (launch_fill_u32(h->at<uint32_t>(q.kmin), 0xffffffffu, (size_t)q.d, s) != hipSuccess ||
+            launch_fill_u32(h->at<uint32_t>(q.kmax), 0u, (size_t)q.d, s) != hipSuccess)
+            return fail(DM_ERR_DEVICE);
+        if (launch_prep_transpose(q.dtype, sets[i].X, q.n, q.d, h->at<uint32_t>(L.xs) + q.base, q.ld, nullptr,
+                                  h->at<uint32_t>(q.kmin), h->at<uint32_t>(q.kmax), h->at<uint32_t>(L.flags),
+                                  s) != hipSuccess ||
+            launch_row_stats(q.dtype, sets[i].X, q.n, q.d, h->ws + q.rowsum, h->ws + q.rownrm, s) != hipSuccess)
+            return fail(DM_ERR_DEVICE);
+    }
+    // one segmented sort over every (dataset, coordinate) segment
+    {
+        std::vector<int64_t> koff, klen;
+        std::vector<uint32_t> toff, tseg;
+        std::vector<uint8_t> sint;
+        uint32_t t = 0;
+        for (const auto& q : m->sets) {
+            const uint32_t tps = (uint32_t)((q.n + SORT_TILE - 1) / SORT_TILE);
+            for (int32_t k = 0; k < q.d; ++k) {
+                const uint32_t seg = (uint32_t)koff.size();
+                koff.push_back(q.base + (int64_t)k * q.ld);
+                klen.push_back(q.n);
+                sint.push_back(q.is_int ? 1 : 0);
+                toff.push_back(t);
+                for (uint32_t j = 0; j < tps; ++j) tseg.push_back(seg);
+                t += tps;
+            }
+        }
+        toff.push_back(t);
+        if (hipMemcpyAsync(h->ws + L.key_off, koff.data(), koff.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(h->ws + L.key_len, klen.data(), klen.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(h->ws + L.tile_off, toff.data(), toff.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(h->ws + L.tile_seg, tseg.data(), tseg.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(h->ws + L.seg_int, sint.data(), sint.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(DM_ERR_DEVICE);
+        SegTables tb;
+        tb.key_off = h->at<int64_t>(L.key_off);
+        tb.key_len = h->at<int64_t>(L.key_len);
+        tb.tile_off = h->at<uint32_t>(L.tile_off);
+        tb.tile_seg = h->at<uint32_t>(L.tile_seg);
+        tb.seg_int = h->at<uint8_t>(L.seg_int);
+        tb.nseg = L.nseg;
+        tb.ntiles = L.ntiles;
+        uint32_t* K0 = h->at<uint32_t>(L.xs);
+        uint32_t* V0 = h->at<uint32_t>(L.rank);
+        uint32_t* K1 = h->at<uint32_t>(L.k1);
+        uint32_t* V1 = h->at<uint32_t>(L.v1);
+        uint32_t* perm = h->at<uint32_t>(L.perm);
+        uint32_t* counts = h->at<uint32_t>(L.counts);
+        const uint32_t* kin[4] = {K0, K1, K0, K1};
+        const uint32_t* vin[4] = {nullptr, V1, V0, V1};
+        uint32_t* kout[4] = {K1, K0, K1, K0};
+        uint32_t* vout[4] = {V1, V0, V1, perm};
+        for (int pass = 0; pass < 4; ++pass) {
+            const int shift = 8 * pass;
+            if (launch_sort_count(kin[pass], counts, tb, shift, s) != hipSuccess ||
+                launch_sort_scan(counts, tb, s) != hipSuccess ||
+                launch_sort_scatter(kin[pass], vin[pass], kout[pass], vout[pass], pass == 3 ? V0 : nullptr, counts,
+                                    tb, shift, pass == 0, pass == 3, false, s) != hipSuccess)
+                return fail(DM_ERR_DEVICE);
+        }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(DM_ERR_DEVICE);
+    uint32_t flags = 0;
+    if (hipMemcpy(&flags, h->ws + L.flags, 4, hipMemcpyDeviceToHost) != hipSuccess) return fail(DM_ERR_DEVICE);
+    if (flags & FLAG_NONFINITE) return fail(DM_ERR_NONFINITE);
+    if (flags & FLAG_INT_RANGE) return fail(DM_ERR_DTYPE);
+    // descriptors (pinned mirror and device copy) and the totals block table
+    const int nsets = count;
+    if (hipHostMalloc((void**)&m->h_ds, (size_t)nsets * sizeof(MultiDs), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&m->d_ds, (size_t)nsets * sizeof(MultiDs)) != hipSuccess)
+        return fail(DM_ERR_NOMEM);
+    std::vector<uint32_t> blk;
+    for (int32_t i = 0; i < nsets; ++i) {
+        MultiSet& q = m->sets[i];
+        std::vector<uint32_t> kmin(q.d), kmax(q.d);
+        if (hipMemcpy(kmin.data(), h->ws + q.kmin, (size_t)q.d * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(kmax.data(), h->ws + q.kmax, (size_t)q.d * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(DM_ERR_DEVICE);
+        double g = 0.0;
+        for (int32_t k = 0; k < q.d; ++k) g += key_to_double(kmax[k], q.is_int) - key_to_double(kmin[k], q.is_int);
+        q.guard = g;
+        MultiDs& D = m->h_ds[i];
+        std::memset(&D, 0, sizeof(D));
+        D.perm = h->at<uint32_t>(L.perm) + q.base;
+        D.xs = h->at<uint32_t>(L.xs) + q.base;
+        D.rowsum = h->ws + q.rowsum;
+        D.n = q.n;
+        D.ld = q.ld;
+        D.d = q.d;
+        D.is_int = q.is_int ? 1 : 0;
+        D.guard = g;
+        D.tot_blk0 = (int64_t)blk.size();
+        const int nb = (int)((q.n + multi_totals_rows() - 1) / multi_totals_rows());
+        D.tot_nblk = nb;
+        for (int j = 0; j < nb; ++j) blk.push_back((uint32_t)i);
+    }
+    m->nblk = (int)blk.size();
+    if (hipMalloc((void**)&m->d_blk, blk.size() * 4) != hipSuccess) return fail(DM_ERR_NOMEM);
+    if (hipMemcpy(m->d_blk, blk.data(), blk.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(DM_ERR_DEVICE);
+    h->last = s;
+    *out = h;
+    return DM_OK;
+}
+
+dm_status dm_matvec_multi(dm_handle* h, const void* const* Z, int32_t b, void* const* Out, void* stream) {
+    if (!h || !Z || !Out || b < 1 || b > MAX_B) return DM_ERR_ARG;
+    if (!h->multi) return DM_ERR_STATE;
+    MultiState* m = h->multi;
+    const int nsets = (int)m->sets.size();
+    for (int i = 0; i < nsets; ++i) {
+        if (!Z[i] || !Out[i]) return DM_ERR_ARG;
+        const size_t zb = (size_t)m->sets[i].n * b * 4, ob = (size_t)m->sets[i].n * b * (m->sets[i].is_int ? 8 : 4);
+        const char* zp = (const char*)Z[i];
+        const char* op = (const char*)Out[i];
+        if (zp < op + ob && op < zp + zb) return DM_ERR_ARG;
+    }
+    dm_status st;
+    if (m->plan.b != b && (st = build_plan(h, b)) != DM_OK) return st;
+    // refresh the pointer table only when it changes (the previous launch's
+    // upload must have run before the pinned mirror is rewritten)
+    bool same = true;
+    for (int i = 0; i < nsets && same; ++i) same = m->h_ds[i].Z == Z[i] && m->h_ds[i].Out == Out[i];
+    if (!same) {
+        if (m->launched) DM_TRY(hipEventSynchronize(m->done));
+        for (int i = 0; i < nsets; ++i) {
+            m->h_ds[i].Z = Z[i];
+            m->h_ds[i].Out = Out[i];
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    DM_TRY(hipGraphLaunch(m->plan.exec, s));
+    DM_TRY(hipEventRecord(m->done, s));
+    m->launched = true;
+    h->last = s;
+    return DM_OK;
+}
+
+dm_status dm_multi_count(const dm_handle* h, int32_t* count) {
+    if (!h || !count) return DM_ERR_ARG;
+    if (!h->multi) return DM_ERR_STATE;
+    *count = (int32_t)h->multi->sets.size();
+    return DM_OK;
 }
 
 }  // extern "C"

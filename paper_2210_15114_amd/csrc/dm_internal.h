@@ -37,6 +37,7 @@ struct SegTables {
     const int64_t* key_len;    // S
     const uint32_t* tile_off;  // S + 1
     const uint32_t* tile_seg;  // T
+    const uint8_t* seg_int;    // S (integer keys?) or NULL: all segments of one kind
     int32_t nseg;
     uint32_t ntiles;
 };
@@ -84,11 +85,48 @@ struct L1PassArgs {
     const void* U;          // b (added when first)
     int first;
     ChainState* chain;
-    uint64_t* records;      // 2 * ntiles * 4 * b words
+    uint64_t* records;      // the shape's own record region (l1_shape)
 };
 int l1_tile_ranks(int32_t b, bool is_int, int zkind);
 size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind);
+// kernel shape of a pass: its ticket class and the words of its record region
+// (each shape owns its region, so no shape ever reads another's words)
+struct L1Shape {
+    int cls;
+    size_t record_words;
+};
+L1Shape l1_shape(int64_t n, int32_t b, bool is_int, int zkind);
 hipError_t launch_l1_pass(bool is_int, int zkind, int32_t b, const L1PassArgs& a, hipStream_t s);
+
+// ---- many datasets in one query --------------------------------------------
+// Per-dataset descriptor read by the multi-dataset kernels; Z and Out are
+// refreshed before every query (a captured host-to-device copy).
+struct MultiDs {
+    const uint32_t* perm;   // d x ld
+    const void* xs;         // d x ld (float | int32)
+    const void* rowsum;     // n (double | int64): weights of U
+    const void* Z;          // n x b (float | int32)
+    void* Out;              // n x b (float | int64)
+    void* T0;               // b (double | int64)
+    void* U;                // b (double | int64)
+    int64_t n, ld;
+    int32_t d, is_int;
+    double guard;           // sum of coordinate ranges (integer overflow guard)
+    int64_t tot_blk0;       // first totals block of this dataset
+    int32_t tot_nblk, pad;
+};
+struct MultiTile {
+    uint32_t ds;  // dataset
+    uint32_t t;   // tile index inside the dataset's coordinate segment
+};
+int multi_tile_ranks(int32_t b, bool is_int);
+size_t multi_record_words(int64_t ntiles, int32_t b, bool is_int);
+int multi_grid(int64_t ntiles, int32_t b, bool is_int);
+int multi_totals_rows();
+hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nblocks, int ndatasets, int32_t b,
+                               double* partials, uint32_t* status, hipStream_t s);
+hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
+                             int k, uint64_t* ticket, uint64_t* records, int grid, hipStream_t s);
 
 // ---- l2 squared query ------------------------------------------------------
 size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b);

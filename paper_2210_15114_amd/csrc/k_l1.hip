@@ -30,154 +30,12 @@
 
 #include "dm_device.h"
 #include "dm_internal.h"
+#include "l1_common.h"
 
 namespace dm {
 namespace {
 
-template <int BP> struct Lay {
-    static constexpr int CPL = BP >= 4 ? 4 : BP;  // columns per lane
-    static constexpr int LPR = BP / CPL;          // lanes per row
-    static constexpr int RPW = DM_WAVE / LPR;     // rows (slots) per wave
-    static constexpr int NS = 4 * RPW;            // slots per workgroup
-};
-
-// ---------------------------------------------------------------------------
-// arithmetic of the two data kinds
-// ---------------------------------------------------------------------------
-struct FloatPath {
-    using Z = float;
-    using O = float;
-    using X = float;
-    using L = float;   // thread-local partial sums
-    using C = dd;      // carries between threads, waves and tiles
-    using T = double;  // totals T0 and U
-    struct Fin { float d0, e1, u; };
-
-    __device__ static L lzero() { return 0.0f; }
-    __device__ static L ladd(L a, Z g) { return a + g; }
-    __device__ static L lmac(L a, X x, Z g) { return fmaf(x, g, a); }
-    __device__ static L lsum(L a, L b) { return a + b; }
-    __device__ static L shfl_up(L v, int o) { return __shfl_up(v, o, 64); }
-    __device__ static C czero() { return dd{0.0f, 0.0f}; }
-    __device__ static C cshfl_xor(C v, int m) { return dd{__shfl_xor(v.hi, m, 64), __shfl_xor(v.lo, m, 64)}; }
-    __device__ static C cadd(C a, C b) { return dd_add(a, b); }
-    __device__ static C caddl(C a, L b) { return dd_add_f(a, b); }
-    __device__ static void enc(C c, uint32_t& w0, uint32_t& w1) {
-        w0 = __float_as_uint(c.hi);
-        w1 = __float_as_uint(c.lo);
-    }
-    __device__ static C dec(uint32_t w0, uint32_t w1) { return dd{__uint_as_float(w0), __uint_as_float(w1)}; }
-    // Record words: one 64-bit word per value, hi in the upper half, lo with
-    // its 12 low mantissa bits replaced by a 12-bit tag (the carry keeps about
-    // 36 significant bits in transit, far more than the FP32 result needs).
-    static constexpr int WPV = 1;
-    __device__ static uint32_t tag12(uint32_t tag) { return (((tag >> 24) & 31u) << 7) | (tag & 127u); }
-    __device__ static void put(uint64_t* dst, C v, uint32_t tag) {
-        const uint32_t lo = (__float_as_uint(v.lo) & 0xfffff000u) | tag12(tag);
-        publish_word(dst, ((uint64_t)__float_as_uint(v.hi) << 32) | lo);
-    }
-    __device__ static bool get(const uint64_t* src, uint32_t tag, C& v) {
-        const uint64_t w = peek_word(src);
-        v = dd{__uint_as_float((uint32_t)(w >> 32)), __uint_as_float((uint32_t)w & 0xfffff000u)};
-        return ((uint32_t)w & 0xfffu) == tag12(tag);
-    }
-    __device__ static Fin fin(C b0, C b1, T t0, T u) {
-        Fin f;
-        f.d0 = (float)(2.0 * dd_to_f64(b0) - t0);
-        f.e1 = (float)(2.0 * dd_to_f64(b1));
-        f.u = (float)u;
-        return f;
-    }
-    __device__ static O out(L l0, L l1, X x, const Fin& f) {
-        const float a = fmaf(2.0f, l0, f.d0);
-        const float e = fmaf(2.0f, l1, f.e1);
-        return fmaf(x, a, -e);
-    }
-    __device__ static O oadd(O a, O b) { return a + b; }
-    __device__ static O ufirst(const Fin& f) { return f.u; }
-};
-
-template <typename ZT> struct IntPath {
-    using Z = ZT;
-    using O = int64_t;
-    using X = int32_t;
-    using L = int64_t;
-    using C = int64_t;
-    using T = int64_t;
-    struct Fin { int64_t d0, e1, u; };
-
-    __device__ static int64_t w(uint64_t v) { return (int64_t)v; }
-    __device__ static L lzero() { return 0; }
-    __device__ static L ladd(L a, Z g) { return w((uint64_t)a + (uint64_t)(int64_t)g); }
-    __device__ static L lmac(L a, X x, Z g) { return w((uint64_t)a + (uint64_t)(int64_t)x * (uint64_t)(int64_t)g); }
-    __device__ static L lsum(L a, L b) { return w((uint64_t)a + (uint64_t)b); }
-    __device__ static L shfl_up(L v, int o) { return __shfl_up(v, o, 64); }
-    __device__ static C czero() { return 0; }
-    __device__ static C cshfl_xor(C v, int m) { return __shfl_xor(v, m, 64); }
-    __device__ static C cadd(C a, C b) { return w((uint64_t)a + (uint64_t)b); }
-    __device__ static C caddl(C a, L b) { return w((uint64_t)a + (uint64_t)b); }
-    __device__ static void enc(C c, uint32_t& w0, uint32_t& w1) {
-        w0 = (uint32_t)(uint64_t)c;
-        w1 = (uint32_t)((uint64_t)c >> 32);
-    }
-    __device__ static C dec(uint32_t w0, uint32_t w1) { return (int64_t)(((uint64_t)w1 << 32) | w0); }
-    // Record words: two 64-bit words per value, each a 32-bit half with the full tag.
-    static constexpr int WPV = 2;
-    __device__ static void put(uint64_t* dst, C v, uint32_t tag) {
-        publish_word(dst, tag_word(tag, (uint32_t)(uint64_t)v));
-        publish_word(dst + 1, tag_word(tag, (uint32_t)((uint64_t)v >> 32)));
-    }
-    __device__ static bool get(const uint64_t* src, uint32_t tag, C& v) {
-        const uint64_t a = peek_word(src), b = peek_word(src + 1);
-        v = (int64_t)(((b & 0xffffffffull) << 32) | (a & 0xffffffffull));
-        return (uint32_t)(a >> 32) == tag && (uint32_t)(b >> 32) == tag;
-    }
-    __device__ static Fin fin(C b0, C b1, T t0, T u) {
-        Fin f;
-        f.d0 = w(2ull * (uint64_t)b0 - (uint64_t)t0);
-        f.e1 = w(2ull * (uint64_t)b1);
-        f.u = u;
-        return f;
-    }
-    __device__ static O out(L l0, L l1, X x, const Fin& f) {
-        const uint64_t a = (uint64_t)f.d0 + 2ull * (uint64_t)l0;
-        const uint64_t e = (uint64_t)f.e1 + 2ull * (uint64_t)l1;
-        return w((uint64_t)(int64_t)x * a - e);
-    }
-    __device__ static O oadd(O a, O b) { return w((uint64_t)a + (uint64_t)b); }
-    __device__ static O ufirst(const Fin& f) { return f.u; }
-};
-
-// load / store CPL consecutive columns of one row
-template <int CPL, bool VEC, typename E>
-__device__ __forceinline__ void load_row(const E* __restrict__ row, int col0, int b, bool valid, E (&v)[CPL]) {
-    if constexpr (VEC && CPL == 4 && sizeof(E) == 4) {
-        if (valid) {
-            const auto t = *reinterpret_cast<const uint4*>(row + col0);
-            v[0] = __builtin_bit_cast(E, t.x); v[1] = __builtin_bit_cast(E, t.y);
-            v[2] = __builtin_bit_cast(E, t.z); v[3] = __builtin_bit_cast(E, t.w);
-        } else {
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) v[j] = E(0);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) v[j] = (valid && col0 + j < b) ? row[col0 + j] : E(0);
-    }
-}
-template <int CPL, bool VEC, typename E>
-__device__ __forceinline__ void store_row(E* __restrict__ row, int col0, int b, const E (&v)[CPL]) {
-    if constexpr (VEC && CPL == 4 && sizeof(E) == 4) {
-        uint4 t;
-        t.x = __builtin_bit_cast(uint32_t, v[0]); t.y = __builtin_bit_cast(uint32_t, v[1]);
-        t.z = __builtin_bit_cast(uint32_t, v[2]); t.w = __builtin_bit_cast(uint32_t, v[3]);
-        *reinterpret_cast<uint4*>(row + col0) = t;
-    } else {
-#pragma unroll
-        for (int j = 0; j < CPL; ++j)
-            if (col0 + j < b) row[col0 + j] = v[j];
-    }
-}
+using namespace l1;
 
 template <typename P, int BP, int R, int SUB, int OC, bool VEC>
 __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
@@ -216,7 +74,9 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
     for (;;) {
         const uint64_t tile = ticket % per_pass;
         if (tile >= (uint64_t)ntiles) break;
-        const uint32_t tag = ((uint32_t)(cls + 1) << 24) | (uint32_t)((ticket / per_pass) & 0xffffffu);
+        // nonzero pass tag; every word a pass reads is rewritten by that pass,
+        // so only the previous pass's words can be stale and they carry another tag
+        const uint32_t tag = (uint32_t)((ticket / per_pass) % 0xffffffffull) + 1u;
         const int64_t tbase = (int64_t)tile * TILE + (int64_t)slot * R;
 
         // ================= phase 1: the tile's totals =================
@@ -483,7 +343,9 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
     for (;;) {
         const uint64_t tile = ticket % per_pass;
         if (tile >= (uint64_t)ntiles) break;
-        const uint32_t tag = ((uint32_t)(cls + 1) << 24) | (uint32_t)((ticket / per_pass) & 0xffffffu);
+        // nonzero pass tag; every word a pass reads is rewritten by that pass,
+        // so only the previous pass's words can be stale and they carry another tag
+        const uint32_t tag = (uint32_t)((ticket / per_pass) % 0xffffffffull) + 1u;
         const int64_t tbase = (int64_t)tile * TILE + (int64_t)slot * R;
 
         // ================= phase 1: the tile's totals =================
@@ -909,6 +771,16 @@ int l1_tile_ranks(int32_t b, bool is_int, int zkind) {
     case 32: return tile_ranks_bp<32>(is_int);
     default: return tile_ranks_bp<64>(is_int);
     }
+}
+
+L1Shape l1_shape(int64_t n, int32_t b, bool is_int, int zkind) {
+    L1Shape sh;
+    const int kind = !is_int ? 0 : zkind == IN_I32 ? 1 : 2;
+    int lg = 0;
+    while ((1 << lg) < b) ++lg;
+    sh.cls = kind * 8 + lg;
+    sh.record_words = l1_record_words(n, b, is_int, zkind);
+    return sh;
 }
 
 size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind) {

@@ -1,0 +1,429 @@
+// k_multi.hip - one query over many point sets of uneven n and d (the
+// products AB of the Appendix C lemma, taken for a whole batch of datasets
+// at once; every dataset has its own sorted orders from Algorithm 1).
+//
+// Round k of a query processes coordinate k of every dataset with d > k;
+// rounds are stream-ordered, so the Out rows of a dataset are never touched
+// by two coordinates at once.  Inside a round every dataset's coordinate is a
+// segment of tiles; tiles of all segments are taken in ticket order by
+// persistent workgroups, and each tile chains its prefix to the previous
+// tiles of its own segment with the windowed look-back (the first tile of a
+// segment starts from zero).  A tile stays in registers from its gather to
+// its scatter.  The whole query (pointer table upload, totals, all rounds)
+// is captured once in a hipGraph and replayed.
+#include <type_traits>
+
+#include "dm_device.h"
+#include "dm_internal.h"
+#include "l1_common.h"
+
+namespace dm {
+namespace {
+
+using namespace l1;
+
+constexpr int MT_ROWS = 4096;   // rows per totals block
+
+// ---------------------------------------------------------------------------
+// totals of every dataset: T0[c] = sum_j z_jc, U[c] = sum_j s_j z_jc, ||z_c||_1
+// stage 1: one block per (dataset, 4096-row chunk); stage 2: one block per
+// (dataset, column), fixed-order sums.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void multi_totals_stage1(const MultiDs* __restrict__ ds,
+                                                           const uint32_t* __restrict__ blk_ds, int32_t b,
+                                                           double* __restrict__ partials,
+                                                           uint32_t* __restrict__ status)
+{
+    const uint32_t s = blk_ds[blockIdx.x];
+    const MultiDs D = ds[s];
+    const int64_t chunk = (int64_t)blockIdx.x - D.tot_blk0;
+    const int64_t j0 = chunk * MT_ROWS, j1 = min(D.n, j0 + MT_ROWS);
+    int bpc = 1;
+    while (bpc < b && bpc < 256) bpc <<= 1;
+    const int rl = threadIdx.x / bpc, rsn = 256 / bpc;
+    __shared__ double s_f[3][256];
+    __shared__ uint64_t s_i[2][256];
+    uint32_t bad = 0;
+    for (int cbase = 0; cbase < b; cbase += bpc) {
+        const int c = cbase + (int)(threadIdx.x % bpc);
+        double f0 = 0.0, f1 = 0.0, fl = 0.0;
+        uint64_t i0 = 0, i1 = 0;
+        if (c < b) {
+            for (int64_t j = j0 + rl; j < j1; j += rsn) {
+                if (D.is_int) {
+                    const int32_t z = ((const int32_t*)D.Z)[j * b + c];
+                    i0 += (uint64_t)(int64_t)z;
+                    i1 += (uint64_t)((const int64_t*)D.rowsum)[j] * (uint64_t)(int64_t)z;
+                    fl += fabs((double)z);
+                } else {
+                    const float z = ((const float*)D.Z)[j * b + c];
+                    if (!isfinite(z)) bad = 1;
+                    f0 += (double)z;
+                    f1 += ((const double*)D.rowsum)[j] * (double)z;
+                    fl += fabs((double)z);
+                }
+            }
+        }
+        s_f[0][threadIdx.x] = f0; s_f[1][threadIdx.x] = f1; s_f[2][threadIdx.x] = fl;
+        s_i[0][threadIdx.x] = i0; s_i[1][threadIdx.x] = i1;
+        __syncthreads();
+        if ((int)threadIdx.x < bpc && c < b) {
+            double a0 = 0, a1 = 0, al = 0;
+            uint64_t b0 = 0, b1 = 0;
+            for (int r = 0; r < rsn; ++r) {
+                const int t = r * bpc + threadIdx.x;
+                a0 += s_f[0][t]; a1 += s_f[1][t]; al += s_f[2][t];
+                b0 += s_i[0][t]; b1 += s_i[1][t];
+            }
+            double* pf = partials + ((size_t)blockIdx.x * b + c) * 3;
+            if (D.is_int) {
+                pf[0] = __longlong_as_double((long long)b0);
+                pf[1] = __longlong_as_double((long long)b1);
+            } else {
+                pf[0] = a0;
+                pf[1] = a1;
+            }
+            pf[2] = al;
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(status, (uint32_t)QF_NONFINITE);
+}
+
+__global__ __launch_bounds__(64) void multi_totals_stage2(const MultiDs* __restrict__ ds, int32_t b,
+                                                          const double* __restrict__ partials,
+                                                          uint32_t* __restrict__ status)
+{
+    const int s = blockIdx.x / b, c = blockIdx.x % b;
+    if (threadIdx.x != 0) return;
+    const MultiDs D = ds[s];
+    double a0 = 0, a1 = 0, al = 0;
+    uint64_t b0 = 0, b1 = 0;
+    for (int k = 0; k < D.tot_nblk; ++k) {
+        const double* pf = partials + ((size_t)(D.tot_blk0 + k) * b + c) * 3;
+        if (D.is_int) {
+            b0 += (uint64_t)__double_as_longlong(pf[0]);
+            b1 += (uint64_t)__double_as_longlong(pf[1]);
+        } else {
+            a0 += pf[0];
+            a1 += pf[1];
+        }
+        al += pf[2];
+    }
+    if (D.is_int) {
+        ((int64_t*)D.T0)[c] = (int64_t)b0;
+        ((int64_t*)D.U)[c] = (int64_t)b1;
+        if (!(al * D.guard < 4611686018427387904.0)) atomicOr(status, (uint32_t)QF_OVERFLOW);
+    } else {
+        ((double*)D.T0)[c] = a0;
+        ((double*)D.U)[c] = a1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one round: coordinate k of every dataset in the round's tile table
+// ---------------------------------------------------------------------------
+template <typename P, int BP, int R, int OC>
+__global__ __launch_bounds__(256) void multi_pass_kernel(const MultiDs* __restrict__ ds,
+                                                         const MultiTile* __restrict__ tiles, int64_t ntiles,
+                                                         int32_t k, int32_t b, uint64_t* __restrict__ ticket_ctr,
+                                                         uint64_t* __restrict__ rec, uint64_t* __restrict__ stat)
+{
+    using L = typename P::L;
+    using C = typename P::C;
+    using Ly = Lay<BP>;
+    constexpr int CPL = Ly::CPL, LPR = Ly::LPR, RPW = Ly::RPW, NS = Ly::NS;
+    constexpr int TILE = NS * R;
+    constexpr int WPR = 2 * BP * P::WPV;
+    static_assert(R % OC == 0, "Out chunk must divide the ranks per slot");
+
+    __shared__ uint64_t s_ticket;
+    __shared__ L s_wtot[4][2][BP];
+    __shared__ C s_wexcl[4][2][BP];
+    __shared__ C s_tot[2][BP];
+    __shared__ C s_carry[2][BP];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int slot = w * RPW + lane / LPR;
+    const int col0 = (lane % LPR) * CPL;
+    const uint64_t per_pass = (uint64_t)ntiles + gridDim.x;
+    if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
+    __syncthreads();
+    uint64_t ticket = s_ticket;
+    const bool first = k == 0;
+
+    for (;;) {
+        const uint64_t tile = ticket % per_pass;
+        if (tile >= (uint64_t)ntiles) break;
+        // nonzero pass tag; every word a pass reads is rewritten by that pass
+        const uint32_t tag = (uint32_t)((ticket / per_pass) % 0xffffffffull) + 1u;
+        const MultiTile mt = tiles[tile];
+        const MultiDs& D = ds[mt.ds];
+        const int64_t n = D.n;
+        const uint32_t* __restrict__ perm = D.perm + (size_t)k * D.ld;
+        const typename P::X* __restrict__ xs = (const typename P::X*)D.xs + (size_t)k * D.ld;
+        const typename P::Z* __restrict__ Z = (const typename P::Z*)D.Z;
+        typename P::O* __restrict__ Out = (typename P::O*)D.Out;
+        const typename P::T* __restrict__ T0 = (const typename P::T*)D.T0;
+        const typename P::T* __restrict__ U = (const typename P::T*)D.U;
+        const bool head = mt.t == 0;   // first tile of its segment
+        const int64_t r0 = (int64_t)mt.t * TILE + (int64_t)slot * R;
+
+        uint32_t p[R];
+        typename P::X x[R];
+        typename P::Z g[R][CPL];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const bool valid = r0 + i < n;
+            p[i] = valid ? perm[r0 + i] : 0u;
+            x[i] = valid ? xs[r0 + i] : typename P::X(0);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) load_row<CPL, false>(Z + (size_t)p[i] * b, col0, b, r0 + i < n, g[i]);
+
+        L e0[CPL], e1[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            L i0 = P::lzero(), i1 = P::lzero();
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                i0 = P::ladd(i0, g[i][j]);
+                i1 = P::lmac(i1, x[i], g[i][j]);
+            }
+#pragma unroll
+            for (int off = LPR; off < DM_WAVE; off <<= 1) {
+                const L u0 = P::shfl_up(i0, off), u1 = P::shfl_up(i1, off);
+                if (lane >= off) { i0 = P::lsum(i0, u0); i1 = P::lsum(i1, u1); }
+            }
+            const L x0 = P::shfl_up(i0, LPR), x1 = P::shfl_up(i1, LPR);
+            e0[j] = lane >= LPR ? x0 : P::lzero();
+            e1[j] = lane >= LPR ? x1 : P::lzero();
+            if (lane >= DM_WAVE - LPR) {
+                s_wtot[w][0][col0 + j] = i0;
+                s_wtot[w][1][col0 + j] = i1;
+            }
+        }
+        __syncthreads();
+        if (tid < 2 * BP) {
+            const int qt = tid / BP, c = tid % BP;
+            C acc = P::czero();
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) {
+                s_wexcl[ww][qt][c] = acc;
+                acc = P::caddl(acc, s_wtot[ww][qt][c]);
+            }
+            s_tot[qt][c] = acc;
+            P::put(rec + ((size_t)tile * 2 + (head ? 1 : 0)) * WPR + (c * 2 + qt) * P::WPV, acc, tag);
+        }
+        __syncthreads();
+        if (tid == 0) publish_word(stat + tile, tag_word(tag, head ? 2u : 1u));
+
+        // windowed look-back inside the segment (its head tile always has an
+        // inclusive record, so the walk never leaves the segment)
+        if (w == 0) {
+            const int c = lane;
+            const bool act = c < BP;
+            C c0 = P::czero(), c1 = P::czero();
+            int64_t hi = head ? -1 : (int64_t)tile - 1;
+            while (hi >= 0) {
+                const int64_t q = hi - lane;
+                const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
+                const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
+                const uint64_t mI = __ballot(state == 2u);
+                const uint64_t mA = __ballot(state >= 1u);
+                const int la = (~mA) ? __builtin_ctzll(~mA) : 64;
+                const int li = mI ? __builtin_ctzll(mI) : 64;
+                bool fin;
+                int take;
+                if (li < 64 && li <= la) {
+                    fin = true;
+                    take = li;
+                } else if (la > 0) {
+                    fin = false;
+                    take = la;
+                } else {
+                    __builtin_amdgcn_s_sleep(2);
+                    continue;
+                }
+                C s0 = P::czero(), s1 = P::czero();
+                bool ok = true;
+                if (act) {
+                    for (int j = 0; j <= take; ++j) {
+                        if (j == take && !fin) break;
+                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * 2 * P::WPV;
+                        C v0, v1;
+                        ok = P::get(src, tag, v0) && ok;
+                        ok = P::get(src + P::WPV, tag, v1) && ok;
+                        s0 = P::cadd(s0, v0);
+                        s1 = P::cadd(s1, v1);
+                    }
+                }
+                if (!__all(ok)) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                c0 = P::cadd(c0, s0);
+                c1 = P::cadd(c1, s1);
+                if (fin) break;
+                hi -= take;
+            }
+            if (act) {
+                s_carry[0][c] = c0;
+                s_carry[1][c] = c1;
+                if (!head) {
+                    uint64_t* dst = rec + ((size_t)tile * 2 + 1) * WPR + c * 2 * P::WPV;
+                    P::put(dst, P::cadd(c0, s_tot[0][c]), tag);
+                    P::put(dst + P::WPV, P::cadd(c1, s_tot[1][c]), tag);
+                }
+            }
+            if (!head && lane == 0) publish_word(stat + tile, tag_word(tag, 2u));
+        }
+        __syncthreads();
+
+        typename P::Fin f[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            const int c = col0 + j;
+            if (c < b) {
+                const C b0 = P::caddl(P::cadd(s_carry[0][c], s_wexcl[w][0][c]), e0[j]);
+                const C b1 = P::caddl(P::cadd(s_carry[1][c], s_wexcl[w][1][c]), e1[j]);
+                f[j] = P::fin(b0, b1, T0[c], first ? U[c] : typename P::T(0));
+            } else {
+                f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
+            }
+        }
+        L l0[CPL], l1[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) { l0[j] = P::lzero(); l1[j] = P::lzero(); }
+#pragma unroll
+        for (int i0 = 0; i0 < R; i0 += OC) {
+            typename P::O o[OC][CPL];
+#pragma unroll
+            for (int i = 0; i < OC; ++i) {
+                if (!first) {
+                    load_row<CPL, false>(Out + (size_t)p[i0 + i] * b, col0, b, r0 + i0 + i < n, o[i]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) o[i][j] = P::ufirst(f[j]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < OC; ++i) {
+                typename P::O res[CPL];
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) {
+                    l0[j] = P::ladd(l0[j], g[i0 + i][j]);
+                    l1[j] = P::lmac(l1[j], x[i0 + i], g[i0 + i][j]);
+                    res[j] = P::oadd(o[i][j], P::out(l0[j], l1[j], x[i0 + i], f[j]));
+                }
+                if (r0 + i0 + i < n) store_row<CPL, false>(Out + (size_t)p[i0 + i] * b, col0, b, res);
+            }
+        }
+        if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
+        __syncthreads();
+        ticket = s_ticket;
+        __syncthreads();
+    }
+}
+
+// ranks per slot of the multi-dataset pass (register-resident tiles)
+template <int BP, bool INT> constexpr int mr() { return INT ? (BP >= 16 ? 4 : 8) : (BP >= 32 ? 8 : 16); }
+template <int BP, int R> constexpr int moc() { return BP >= 4 ? (R >= 4 ? 4 : R) : R; }
+
+static int bpad2(int32_t b) {
+    int bp = 1;
+    while (bp < b) bp <<= 1;
+    return bp;
+}
+
+template <int BP, bool INT> static int mtile() { return Lay<BP>::NS * mr<BP, INT>(); }
+
+template <typename P, int BP>
+static const void* kfn() {
+    constexpr bool INT = !std::is_same<P, FloatPath>::value;
+    return (const void*)multi_pass_kernel<P, BP, mr<BP, INT>(), moc<BP, mr<BP, INT>()>()>;
+}
+
+template <typename P, int BP>
+static hipError_t launch_bp(const MultiDs* ds, const MultiTile* tiles, int64_t ntiles, int k, int32_t b,
+                            uint64_t* ctr, uint64_t* rec, int grid, hipStream_t s) {
+    constexpr bool INT = !std::is_same<P, FloatPath>::value;
+    constexpr int R = mr<BP, INT>();
+    constexpr int TILEW = 2 * 2 * P::WPV * BP;
+    uint64_t* stat = rec + (size_t)ntiles * TILEW;
+    multi_pass_kernel<P, BP, R, moc<BP, R>()><<<grid, 256, 0, s>>>(ds, tiles, ntiles, k, b, ctr, rec, stat);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int multi_tile_ranks(int32_t b, bool is_int) {
+    switch (bpad2(b)) {
+    case 1: return is_int ? mtile<1, true>() : mtile<1, false>();
+    case 2: return is_int ? mtile<2, true>() : mtile<2, false>();
+    case 4: return is_int ? mtile<4, true>() : mtile<4, false>();
+    case 8: return is_int ? mtile<8, true>() : mtile<8, false>();
+    case 16: return is_int ? mtile<16, true>() : mtile<16, false>();
+    case 32: return is_int ? mtile<32, true>() : mtile<32, false>();
+    default: return is_int ? mtile<64, true>() : mtile<64, false>();
+    }
+}
+
+size_t multi_record_words(int64_t ntiles, int32_t b, bool is_int) {
+    const size_t wpv = is_int ? 2 : 1;
+    return (size_t)ntiles * (2 * 2 * wpv * (size_t)bpad2(b) + 1);
+}
+
+int multi_grid(int64_t ntiles, int32_t b, bool is_int) {
+    static int cus = -1;
+    if (cus < 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    }
+    const void* fn = nullptr;
+    switch (bpad2(b)) {
+    case 1: fn = is_int ? kfn<IntPath<int32_t>, 1>() : kfn<FloatPath, 1>(); break;
+    case 2: fn = is_int ? kfn<IntPath<int32_t>, 2>() : kfn<FloatPath, 2>(); break;
+    case 4: fn = is_int ? kfn<IntPath<int32_t>, 4>() : kfn<FloatPath, 4>(); break;
+    case 8: fn = is_int ? kfn<IntPath<int32_t>, 8>() : kfn<FloatPath, 8>(); break;
+    case 16: fn = is_int ? kfn<IntPath<int32_t>, 16>() : kfn<FloatPath, 16>(); break;
+    case 32: fn = is_int ? kfn<IntPath<int32_t>, 32>() : kfn<FloatPath, 32>(); break;
+    default: fn = is_int ? kfn<IntPath<int32_t>, 64>() : kfn<FloatPath, 64>(); break;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 1;
+    int64_t g = (int64_t)nb * cus;
+    if (g > ntiles) g = ntiles;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+int multi_totals_rows() { return MT_ROWS; }
+
+hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nblocks, int ndatasets, int32_t b,
+                               double* partials, uint32_t* status, hipStream_t s)
+{
+    if (nblocks > 0) multi_totals_stage1<<<nblocks, 256, 0, s>>>(ds, blk_ds, b, partials, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    multi_totals_stage2<<<ndatasets * b, 64, 0, s>>>(ds, b, partials, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
+                             int k, uint64_t* ticket, uint64_t* records, int grid, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    switch (bpad2(b)) {
+#define DM_MCASE(BP)                                                                                   \
+    case BP:                                                                                           \
+        return is_int ? launch_bp<IntPath<int32_t>, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, s) \
+                      : launch_bp<FloatPath, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, s);
+        DM_MCASE(1) DM_MCASE(2) DM_MCASE(4) DM_MCASE(8) DM_MCASE(16) DM_MCASE(32) DM_MCASE(64)
+#undef DM_MCASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dm

@@ -167,7 +167,8 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_scatter_kernel(
         const uint32_t dig = (k >> shift) & 255u;
         const uint32_t gpos = o[dig] + (uint32_t)i - s_start[dig];
         if (LAST) {
-            uint32_t bits = IS_INT ? (uint32_t)key_i32(k) : __float_as_uint(key_f32(k));
+            const bool as_int = tb.seg_int ? tb.seg_int[r.seg] != 0 : IS_INT;
+            uint32_t bits = as_int ? (uint32_t)key_i32(k) : __float_as_uint(key_f32(k));
             kout[gpos] = bits;                                        // sorted values
             vout[gpos] = v;                                           // permutation
             rank_out[r.seg_base + v] = gpos - (uint32_t)r.seg_base;   // its inverse
