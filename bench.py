@@ -207,7 +207,7 @@ def main():
     achieved = bytes_pass / (avg_pass_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": read_traffic(),
-                "kernel": "l1_pass_kernel<FloatPath,64>", "bytes_per_launch": bytes_pass,
+                "kernel": "l1_pass_keep_kernel<FloatPath,64>", "bytes_per_launch": bytes_pass,
                 "avg_launch_ms": round(avg_pass_ms, 4), "launches": pass_n}
 
     # ---- single-vector form on the same 64 columns ----
