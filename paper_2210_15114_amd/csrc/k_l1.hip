@@ -134,59 +134,12 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
         if (tid == 0) publish_word(stat + tile, tag_word(tag, tile == 0 ? 2u : 1u));
 
         // ================= decoupled look-back (wave 0) =================
-        // Lane l reads the status word of tile hi - l.  The nearest predecessor
-        // with an inclusive record ends the walk; every tile in between must
-        // have published its aggregate, and runs of aggregates are summed 64
-        // at a time while no inclusive record is in sight.  Status words are
-        // hints: payload words carry their own tags and are re-checked, so a
-        // hint that ran ahead of its payload only costs a retry.
+        // the exclusive prefix of the tile, then its inclusive record
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
-            C c0 = P::czero(), c1 = P::czero();
-            int64_t hi = (int64_t)tile - 1;
-            while (hi >= 0) {
-                const int64_t q = hi - lane;
-                const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
-                const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
-                const uint64_t mI = __ballot(state == 2u);
-                const uint64_t mA = __ballot(state >= 1u);
-                const int la = (~mA) ? __builtin_ctzll(~mA) : 64;   // leading lanes with a record
-                const int li = mI ? __builtin_ctzll(mI) : 64;        // nearest inclusive record
-                bool fin;
-                int take;
-                if (li < 64 && li <= la) {
-                    fin = true;
-                    take = li;
-                } else if (la > 0) {
-                    fin = false;
-                    take = la;
-                } else {
-                    __builtin_amdgcn_s_sleep(2);
-                    continue;
-                }
-                C s0 = P::czero(), s1 = P::czero();
-                bool ok = true;
-                if (act) {
-                    for (int j = 0; j <= take; ++j) {
-                        if (j == take && !fin) break;
-                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * 2 * P::WPV;
-                        C v0, v1;
-                        ok = P::get(src, tag, v0) && ok;
-                        ok = P::get(src + P::WPV, tag, v1) && ok;
-                        s0 = P::cadd(s0, v0);
-                        s1 = P::cadd(s1, v1);
-                    }
-                }
-                if (!__all(ok)) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                c0 = P::cadd(c0, s0);
-                c1 = P::cadd(c1, s1);
-                if (fin) break;
-                hi -= take;
-            }
+            C c0, c1;
+            look_back<P, BP, WPR>(rec, stat, (int64_t)tile - 1, tag, lane, c0, c1);
             if (act) {
                 s_run[0][c] = c0;
                 s_run[1][c] = c1;
@@ -428,59 +381,12 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
         if (tid == 0) publish_word(stat + tile, tag_word(tag, tile == 0 ? 2u : 1u));
 
         // ================= decoupled look-back (wave 0) =================
-        // Lane l reads the status word of tile hi - l.  The nearest predecessor
-        // with an inclusive record ends the walk; every tile in between must
-        // have published its aggregate, and runs of aggregates are summed 64
-        // at a time while no inclusive record is in sight.  Status words are
-        // hints: payload words carry their own tags and are re-checked, so a
-        // hint that ran ahead of its payload only costs a retry.
+        // the exclusive prefix of the tile, then its inclusive record
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
-            C c0 = P::czero(), c1 = P::czero();
-            int64_t hi = (int64_t)tile - 1;
-            while (hi >= 0) {
-                const int64_t q = hi - lane;
-                const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
-                const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
-                const uint64_t mI = __ballot(state == 2u);
-                const uint64_t mA = __ballot(state >= 1u);
-                const int la = (~mA) ? __builtin_ctzll(~mA) : 64;   // leading lanes with a record
-                const int li = mI ? __builtin_ctzll(mI) : 64;        // nearest inclusive record
-                bool fin;
-                int take;
-                if (li < 64 && li <= la) {
-                    fin = true;
-                    take = li;
-                } else if (la > 0) {
-                    fin = false;
-                    take = la;
-                } else {
-                    __builtin_amdgcn_s_sleep(2);
-                    continue;
-                }
-                C s0 = P::czero(), s1 = P::czero();
-                bool ok = true;
-                if (act) {
-                    for (int j = 0; j <= take; ++j) {
-                        if (j == take && !fin) break;
-                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * 2 * P::WPV;
-                        C v0, v1;
-                        ok = P::get(src, tag, v0) && ok;
-                        ok = P::get(src + P::WPV, tag, v1) && ok;
-                        s0 = P::cadd(s0, v0);
-                        s1 = P::cadd(s1, v1);
-                    }
-                }
-                if (!__all(ok)) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                c0 = P::cadd(c0, s0);
-                c1 = P::cadd(c1, s1);
-                if (fin) break;
-                hi -= take;
-            }
+            C c0, c1;
+            look_back<P, BP, WPR>(rec, stat, (int64_t)tile - 1, tag, lane, c0, c1);
             if (act) {
                 s_run[0][c] = c0;
                 s_run[1][c] = c1;

@@ -223,50 +223,8 @@ __global__ __launch_bounds__(256) void multi_pass_kernel(const MultiDs* __restri
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
-            C c0 = P::czero(), c1 = P::czero();
-            int64_t hi = head ? -1 : (int64_t)tile - 1;
-            while (hi >= 0) {
-                const int64_t q = hi - lane;
-                const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
-                const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
-                const uint64_t mI = __ballot(state == 2u);
-                const uint64_t mA = __ballot(state >= 1u);
-                const int la = (~mA) ? __builtin_ctzll(~mA) : 64;
-                const int li = mI ? __builtin_ctzll(mI) : 64;
-                bool fin;
-                int take;
-                if (li < 64 && li <= la) {
-                    fin = true;
-                    take = li;
-                } else if (la > 0) {
-                    fin = false;
-                    take = la;
-                } else {
-                    __builtin_amdgcn_s_sleep(2);
-                    continue;
-                }
-                C s0 = P::czero(), s1 = P::czero();
-                bool ok = true;
-                if (act) {
-                    for (int j = 0; j <= take; ++j) {
-                        if (j == take && !fin) break;
-                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * 2 * P::WPV;
-                        C v0, v1;
-                        ok = P::get(src, tag, v0) && ok;
-                        ok = P::get(src + P::WPV, tag, v1) && ok;
-                        s0 = P::cadd(s0, v0);
-                        s1 = P::cadd(s1, v1);
-                    }
-                }
-                if (!__all(ok)) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                c0 = P::cadd(c0, s0);
-                c1 = P::cadd(c1, s1);
-                if (fin) break;
-                hi -= take;
-            }
+            C c0, c1;
+            look_back<P, BP, WPR>(rec, stat, head ? -1 : (int64_t)tile - 1, tag, lane, c0, c1);
             if (act) {
                 s_carry[0][c] = c0;
                 s_carry[1][c] = c1;

@@ -50,10 +50,9 @@ struct FloatPath {
         const uint32_t lo = (__float_as_uint(v.lo) & 0xfffff000u) | tag12(tag);
         publish_word(dst, ((uint64_t)__float_as_uint(v.hi) << 32) | lo);
     }
-    __device__ static bool get(const uint64_t* src, uint32_t tag, C& v) {
-        const uint64_t w = peek_word(src);
-        v = dd{__uint_as_float((uint32_t)(w >> 32)), __uint_as_float((uint32_t)w & 0xfffff000u)};
-        return ((uint32_t)w & 0xfffu) == tag12(tag);
+    __device__ static bool decode(const uint64_t* w, uint32_t tag, C& v) {
+        v = dd{__uint_as_float((uint32_t)(w[0] >> 32)), __uint_as_float((uint32_t)w[0] & 0xfffff000u)};
+        return ((uint32_t)w[0] & 0xfffu) == tag12(tag);
     }
     __device__ static Fin fin(C b0, C b1, T t0, T u) {
         Fin f;
@@ -101,10 +100,9 @@ template <typename ZT> struct IntPath {
         publish_word(dst, tag_word(tag, (uint32_t)(uint64_t)v));
         publish_word(dst + 1, tag_word(tag, (uint32_t)((uint64_t)v >> 32)));
     }
-    __device__ static bool get(const uint64_t* src, uint32_t tag, C& v) {
-        const uint64_t a = peek_word(src), b = peek_word(src + 1);
-        v = (int64_t)(((b & 0xffffffffull) << 32) | (a & 0xffffffffull));
-        return (uint32_t)(a >> 32) == tag && (uint32_t)(b >> 32) == tag;
+    __device__ static bool decode(const uint64_t* w, uint32_t tag, C& v) {
+        v = (int64_t)(((w[1] & 0xffffffffull) << 32) | (w[0] & 0xffffffffull));
+        return (uint32_t)(w[0] >> 32) == tag && (uint32_t)(w[1] >> 32) == tag;
     }
     __device__ static Fin fin(C b0, C b1, T t0, T u) {
         Fin f;
@@ -121,6 +119,94 @@ template <typename ZT> struct IntPath {
     __device__ static O oadd(O a, O b) { return w((uint64_t)a + (uint64_t)b); }
     __device__ static O ufirst(const Fin& f) { return f.u; }
 };
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back over the tiles of one chained scan, run by one wave.
+//
+// Tile t keeps two records of 2*BP values, (P0, P1) for every column: the
+// aggregate (the tile's own sums) at record 2t and the inclusive prefix at
+// record 2t+1, and a status word (1 = aggregate published, 2 = inclusive
+// published).  Starting at tile `hi`, lane l reads the status of tile hi-l,
+// so 64 predecessors are examined per round trip.  The walk sums aggregates
+// back to the nearest tile with an inclusive record and adds that record;
+// a run of 64 aggregates with no inclusive record in sight is summed and the
+// walk moves on.  Status words are hints only: payload words carry their own
+// tags and are checked, and a batch with a stale word is read again.  The
+// records of a batch are loaded before any is summed, LB at a time, so one
+// round trip to memory covers LB predecessors.  Summation runs from the
+// nearest predecessor outwards.  Lane c returns the exclusive prefix of
+// column c (lanes c >= BP return zero).
+// ---------------------------------------------------------------------------
+template <typename P, int BP, int WPR, int LB = 8>
+__device__ __forceinline__ void look_back(const uint64_t* __restrict__ rec, const uint64_t* __restrict__ stat,
+                                          int64_t hi, uint32_t tag, int lane, typename P::C& c0,
+                                          typename P::C& c1)
+{
+    using C = typename P::C;
+    constexpr int W = 2 * P::WPV;   // words of (P0, P1) for one column
+    const int c = lane;
+    const bool act = c < BP;
+    c0 = P::czero();
+    c1 = P::czero();
+    while (hi >= 0) {
+        const int64_t q = hi - lane;
+        const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
+        const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
+        const uint64_t mI = __ballot(state == 2u);
+        const uint64_t mA = __ballot(state >= 1u);
+        const int la = (~mA) ? __builtin_ctzll(~mA) : 64;   // leading lanes with a record
+        const int li = mI ? __builtin_ctzll(mI) : 64;        // nearest inclusive record
+        bool fin;
+        int take;
+        if (li < 64 && li <= la) {
+            fin = true;
+            take = li;
+        } else if (la > 0) {
+            fin = false;
+            take = la;
+        } else {
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        // records hi, hi-1, ..., hi-take+1 are aggregates; with fin, record
+        // hi-take is the inclusive one
+        const int cnt = take + (fin ? 1 : 0);
+        C s0 = P::czero(), s1 = P::czero();
+        bool ok = true;
+        if (act) {
+            for (int j0 = 0; j0 < cnt; j0 += LB) {
+                uint64_t wv[LB][W];
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const int j = j0 + u;
+                    if (j < cnt) {
+                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * W;
+#pragma unroll
+                        for (int k = 0; k < W; ++k) wv[u][k] = peek_word(src + k);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    if (j0 + u < cnt) {
+                        C v0, v1;
+                        ok = P::decode(wv[u], tag, v0) && ok;
+                        ok = P::decode(wv[u] + P::WPV, tag, v1) && ok;
+                        s0 = P::cadd(s0, v0);
+                        s1 = P::cadd(s1, v1);
+                    }
+                }
+            }
+        }
+        if (!__all(ok)) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        c0 = P::cadd(c0, s0);
+        c1 = P::cadd(c1, s1);
+        if (fin) break;
+        hi -= take;
+    }
+}
 
 // load / store CPL consecutive columns of one row
 template <int CPL, bool VEC, typename E>
