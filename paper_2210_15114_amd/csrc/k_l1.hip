@@ -135,11 +135,11 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
 
         // ================= decoupled look-back (wave 0) =================
         // the exclusive prefix of the tile, then its inclusive record
+        C c0, c1;
+        look_back_wg<P, BP, WPR>(rec, stat, (int64_t)tile - 1, tag, tid, s_red, c0, c1);
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
-            C c0, c1;
-            look_back<P, BP, WPR>(rec, stat, (int64_t)tile - 1, tag, lane, c0, c1);
             if (act) {
                 s_run[0][c] = c0;
                 s_run[1][c] = c1;
@@ -274,14 +274,14 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
     static_assert(R % OC == 0, "Out chunk must divide the ranks per slot");
 
     __shared__ uint64_t s_ticket;
-    __shared__ C s_red[4][2][BP];
+    __shared__ C s_red[4][2][BP];   // phase 1 wave sums, then look-back scratch, then phase 2 wave prefixes
     __shared__ C s_tot[2][BP];
     __shared__ L s_wtot[4][2][BP];
-    __shared__ C s_wexcl[4][2][BP];
+    C (*const s_wexcl)[2][BP] = s_red;
     __shared__ C s_run[2][BP];
     __shared__ typename P::Z s_g[R][256][CPL];   // sub-chunk 0 of the tile, per thread
-    __shared__ uint32_t s_p[NS][R];
-    __shared__ typename P::X s_x[NS][R];
+    __shared__ uint32_t s_p[SUB][NS][R];
+    __shared__ typename P::X s_x[SUB][NS][R];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int slot = w * RPW + lane / LPR;
@@ -305,8 +305,6 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
         C t0[CPL], t1[CPL];
 #pragma unroll
         for (int j = 0; j < CPL; ++j) { t0[j] = P::czero(); t1[j] = P::czero(); }
-        uint32_t pk[R];
-        typename P::X xk[R];
         typename P::Z gk[R][CPL];
 #pragma unroll
         for (int s = 0; s < SUB; ++s) {
@@ -333,26 +331,23 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
                 t0[j] = P::caddl(t0[j], a0);
                 t1[j] = P::caddl(t1[j], a1);
             }
+            if (lane % LPR == 0) {
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    s_p[s][slot][i] = p[i];
+                    s_x[s][slot][i] = x[i];
+                }
+            }
             if (s == 0) {
 #pragma unroll
                 for (int i = 0; i < R; ++i)
 #pragma unroll
                     for (int j = 0; j < CPL; ++j) s_g[i][tid][j] = g[i][j];
-                if (lane % LPR == 0) {
-#pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        s_p[slot][i] = p[i];
-                        s_x[slot][i] = x[i];
-                    }
-                }
             } else {
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    pk[i] = p[i];
-                    xk[i] = x[i];
+                for (int i = 0; i < R; ++i)
 #pragma unroll
                     for (int j = 0; j < CPL; ++j) gk[i][j] = g[i][j];
-                }
             }
         }
         // sum over the slots of the wave (lanes that share columns), then the waves
@@ -382,11 +377,11 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
 
         // ================= decoupled look-back (wave 0) =================
         // the exclusive prefix of the tile, then its inclusive record
+        C c0, c1;
+        look_back_wg<P, BP, WPR>(rec, stat, (int64_t)tile - 1, tag, tid, s_red, c0, c1);
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
-            C c0, c1;
-            look_back<P, BP, WPR>(rec, stat, (int64_t)tile - 1, tag, lane, c0, c1);
             if (act) {
                 s_run[0][c] = c0;
                 s_run[1][c] = c1;
@@ -401,7 +396,8 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
         __syncthreads();
 
         // ================= phase 2: scan and scatter, sub-chunk by sub-chunk =================
-        // sub-chunk 0 is read back from LDS, sub-chunk 1 from registers
+        // Z rows of sub-chunk 0 come back from LDS, those of sub-chunk 1 from
+        // registers; point ids and sorted values of both from LDS
         auto phase2 = [&](const int64_t r0, auto&& getp, auto&& getx, auto&& getg) {
             L e0[CPL], e1[CPL];
 #pragma unroll
@@ -479,10 +475,10 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
             }
         };
         phase2(
-            tbase, [&](int i) { return s_p[slot][i]; }, [&](int i) { return s_x[slot][i]; },
+            tbase, [&](int i) { return s_p[0][slot][i]; }, [&](int i) { return s_x[0][slot][i]; },
             [&](int i, int j) { return s_g[i][tid][j]; });
         phase2(
-            tbase + CHUNK, [&](int i) { return pk[i]; }, [&](int i) { return xk[i]; },
+            tbase + CHUNK, [&](int i) { return s_p[1][slot][i]; }, [&](int i) { return s_x[1][slot][i]; },
             [&](int i, int j) { return gk[i][j]; });
         if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
         __syncthreads();

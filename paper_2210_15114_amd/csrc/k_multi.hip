@@ -142,6 +142,7 @@ __global__ __launch_bounds__(256) void multi_pass_kernel(const MultiDs* __restri
     __shared__ C s_wexcl[4][2][BP];
     __shared__ C s_tot[2][BP];
     __shared__ C s_carry[2][BP];
+    __shared__ C s_lb[4][2][BP];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int slot = w * RPW + lane / LPR;
@@ -220,11 +221,11 @@ __global__ __launch_bounds__(256) void multi_pass_kernel(const MultiDs* __restri
 
         // windowed look-back inside the segment (its head tile always has an
         // inclusive record, so the walk never leaves the segment)
+        C c0, c1;
+        look_back_wg<P, BP, WPR>(rec, stat, head ? -1 : (int64_t)tile - 1, tag, tid, s_lb, c0, c1);
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
-            C c0, c1;
-            look_back<P, BP, WPR>(rec, stat, head ? -1 : (int64_t)tile - 1, tag, lane, c0, c1);
             if (act) {
                 s_carry[0][c] = c0;
                 s_carry[1][c] = c1;

@@ -208,6 +208,115 @@ __device__ __forceinline__ void look_back(const uint64_t* __restrict__ rec, cons
     }
 }
 
+// The same walk run by the whole workgroup of four waves.  Wave 0 reads the
+// status words and decides how many records to take; each wave then loads a
+// quarter of them (records j = w, w+4, ...; LB per wave per round trip), so
+// one round trip covers 4*LB predecessors.  Wave partials are combined in
+// wave order by wave 0.  Every thread of the workgroup must call it; the
+// result is valid in wave 0 (lane c holds column c).  s_part is LDS scratch
+// of the caller, free for the duration of the call.
+template <typename P, int BP, int WPR, int LB = 8>
+__device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, const uint64_t* __restrict__ stat,
+                                             int64_t hi, uint32_t tag, int tid,
+                                             typename P::C (*s_part)[2][BP], typename P::C& c0,
+                                             typename P::C& c1)
+{
+    using C = typename P::C;
+    constexpr int W = 2 * P::WPV;
+    constexpr int NW = 4;
+    __shared__ int s_take, s_cnt;
+    __shared__ int64_t s_hi;
+    __shared__ uint32_t s_ok[NW];
+    const int lane = tid & 63, w = tid >> 6;
+    const int c = lane;
+    const bool act = c < BP;
+    c0 = P::czero();
+    c1 = P::czero();
+    bool fin = false;
+    for (;;) {
+        if (w == 0) {
+            int take = 0, cnt = 0;
+            if (hi >= 0) {
+                for (;;) {
+                    const int64_t q = hi - lane;
+                    const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
+                    const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
+                    const uint64_t mI = __ballot(state == 2u);
+                    const uint64_t mA = __ballot(state >= 1u);
+                    const int la = (~mA) ? __builtin_ctzll(~mA) : 64;
+                    const int li = mI ? __builtin_ctzll(mI) : 64;
+                    if (li < 64 && li <= la) {
+                        fin = true;
+                        take = li;
+                        break;
+                    }
+                    if (la > 0) {
+                        fin = false;
+                        take = la;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                cnt = take + (fin ? 1 : 0);
+            }
+            if (lane == 0) {
+                s_take = take;
+                s_cnt = cnt;
+                s_hi = hi;
+            }
+        }
+        __syncthreads();
+        const int cnt = s_cnt;
+        if (cnt == 0) break;   // hi < 0: nothing (more) to read
+        const int take = s_take;
+        const int64_t h = s_hi;
+        C s0 = P::czero(), s1 = P::czero();
+        bool ok = true;
+        if (act) {
+            for (int j0 = w; j0 < cnt; j0 += NW * LB) {
+                uint64_t wv[LB][W];
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const int j = j0 + NW * u;
+                    if (j < cnt) {
+                        const uint64_t* src = rec + ((size_t)(h - j) * 2 + (j == take ? 1 : 0)) * WPR + c * W;
+#pragma unroll
+                        for (int k = 0; k < W; ++k) wv[u][k] = peek_word(src + k);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    if (j0 + NW * u < cnt) {
+                        C v0, v1;
+                        ok = P::decode(wv[u], tag, v0) && ok;
+                        ok = P::decode(wv[u] + P::WPV, tag, v1) && ok;
+                        s0 = P::cadd(s0, v0);
+                        s1 = P::cadd(s1, v1);
+                    }
+                }
+            }
+            s_part[w][0][c] = s0;
+            s_part[w][1][c] = s1;
+        }
+        const bool wok = __all(ok);
+        if (lane == 0) s_ok[w] = wok ? 1u : 0u;
+        __syncthreads();
+        if (w == 0) {
+            if (s_ok[0] & s_ok[1] & s_ok[2] & s_ok[3]) {
+                if (act) {
+                    const C p0 = P::cadd(P::cadd(s_part[0][0][c], s_part[1][0][c]), P::cadd(s_part[2][0][c], s_part[3][0][c]));
+                    const C p1 = P::cadd(P::cadd(s_part[0][1][c], s_part[1][1][c]), P::cadd(s_part[2][1][c], s_part[3][1][c]));
+                    c0 = P::cadd(c0, p0);
+                    c1 = P::cadd(c1, p1);
+                }
+                hi = fin ? -1 : hi - take;
+            } else {
+                __builtin_amdgcn_s_sleep(1);   // a record was stale: read the same window again
+            }
+        }
+    }
+}
+
 // load / store CPL consecutive columns of one row
 template <int CPL, bool VEC, typename E>
 __device__ __forceinline__ void load_row(const E* __restrict__ row, int col0, int b, bool valid, E (&v)[CPL]) {
