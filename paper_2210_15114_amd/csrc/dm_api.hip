@@ -455,8 +455,10 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         a.U = tot.U;
         a.chain = &h->ctl->chain;
         {
-            dm_status rs = region_for(h, l1_shape(h->n, b, h->is_int, zkind), s, &a.records);
+            const L1Shape sh = l1_shape(h->n, b, h->is_int, zkind);
+            dm_status rs = region_for(h, sh, s, &a.records);
             if (rs != DM_OK) return rs;
+            a.record_words = sh.record_words;
         }
         const size_t vsz = 4;
         for (int32_t k = 0; k < h->d; ++k) {

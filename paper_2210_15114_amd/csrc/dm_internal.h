@@ -86,6 +86,7 @@ struct L1PassArgs {
     int first;
     ChainState* chain;
     uint64_t* records;      // the shape's own record region (l1_shape)
+    size_t record_words;    // its size in 64-bit words; a launch that needs more is refused
 };
 int l1_tile_ranks(int32_t b, bool is_int, int zkind);
 size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind);

@@ -653,26 +653,38 @@ static int bpad(int32_t b) {
 }
 
 // Tiles of the l1 pass kernels: the keep kernel (whole tile on chip, two
-// sub-chunks) for float blocks of 32 or more columns, the re-gathering kernel
-// (four sub-chunks) otherwise.
-template <typename P, int BP> constexpr bool use_keep() { return std::is_same<P, FloatPath>::value && BP >= 32; }
+// sub-chunks) for float data and for integer blocks of up to 32 columns; the
+// re-gathering kernel for 64-column integer blocks, whose int64 rows leave
+// room for only 128-rank tiles on chip.  The tile of a configuration is
+// defined here once; the launch and the sizing of the record region both
+// take it from pass_tile.
+template <typename P, int BP> constexpr bool use_keep() { return std::is_same<P, FloatPath>::value || BP <= 32; }
+template <typename P, int BP> constexpr int pass_r() {
+    return std::is_same<P, FloatPath>::value ? r_float<BP>() : r_int<BP>();
+}
+template <typename P, int BP> constexpr int pass_sub() {
+    return use_keep<P, BP>() ? 2 : sub_chunks<BP, pass_r<P, BP>()>();
+}
+template <typename P, int BP> constexpr int pass_tile() { return Lay<BP>::NS * pass_r<P, BP>() * pass_sub<P, BP>(); }
+// two records of 2*BP values and one status word per tile
+template <typename P, int BP> constexpr size_t pass_tile_words() { return 2 * 2 * (size_t)P::WPV * BP + 1; }
 
-template <int BP> static int tile_ranks_bp(bool is_int) {
-    return is_int ? Lay<BP>::NS * r_int<BP>() * sub_chunks<BP, r_int<BP>()>()
-                  : Lay<BP>::NS * r_float<BP>() * (use_keep<FloatPath, BP>() ? 2 : sub_chunks<BP, r_float<BP>()>());
+template <typename P> static int tile_ranks_p(int32_t b) {
+    switch (bpad(b)) {
+    case 1: return pass_tile<P, 1>();
+    case 2: return pass_tile<P, 2>();
+    case 4: return pass_tile<P, 4>();
+    case 8: return pass_tile<P, 8>();
+    case 16: return pass_tile<P, 16>();
+    case 32: return pass_tile<P, 32>();
+    default: return pass_tile<P, 64>();
+    }
 }
 
 int l1_tile_ranks(int32_t b, bool is_int, int zkind) {
-    (void)zkind;
-    switch (bpad(b)) {
-    case 1: return tile_ranks_bp<1>(is_int);
-    case 2: return tile_ranks_bp<2>(is_int);
-    case 4: return tile_ranks_bp<4>(is_int);
-    case 8: return tile_ranks_bp<8>(is_int);
-    case 16: return tile_ranks_bp<16>(is_int);
-    case 32: return tile_ranks_bp<32>(is_int);
-    default: return tile_ranks_bp<64>(is_int);
-    }
+    if (!is_int) return tile_ranks_p<FloatPath>(b);
+    if (zkind == IN_I32) return tile_ranks_p<IntPath<int32_t>>(b);
+    return tile_ranks_p<IntPath<int64_t>>(b);
 }
 
 L1Shape l1_shape(int64_t n, int32_t b, bool is_int, int zkind) {
@@ -723,16 +735,19 @@ static int persistent_grid_of(int64_t ntiles, const void* fn, const void* fn2) {
     return (int)g;
 }
 
-template <typename P, int BP, int R>
+template <typename P, int BP>
 static hipError_t launch_one(const L1PassArgs& a, int32_t b, hipStream_t s) {
     constexpr bool KEEP = use_keep<P, BP>();
-    constexpr int SUB = KEEP ? 2 : sub_chunks<BP, R>();
-    constexpr int TILE = Lay<BP>::NS * R * SUB;
+    constexpr int R = pass_r<P, BP>();
+    constexpr int SUB = pass_sub<P, BP>();
+    constexpr int TILE = pass_tile<P, BP>();
     constexpr int OC = out_chunk<BP, R>();
     // one ticket counter per kernel instantiation family (data path x BP)
     constexpr int kind = std::is_same<P, FloatPath>::value ? 0 : std::is_same<P, IntPath<int32_t>>::value ? 1 : 2;
     const int cls = kind * 8 + log2c<BP>();
     const int64_t ntiles = (a.n + TILE - 1) / TILE;
+    // the region must hold every tile's records and status word
+    if ((size_t)ntiles * pass_tile_words<P, BP>() > a.record_words) return hipErrorInvalidValue;
     uint64_t* stat = a.records + (size_t)ntiles * 2 * 2 * P::WPV * BP;
     uint64_t* ctr = &a.chain->ticket[cls];
     const bool vec = (b == BP) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
@@ -764,16 +779,16 @@ static hipError_t launch_one(const L1PassArgs& a, int32_t b, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename P, bool INT>
+template <typename P>
 static hipError_t dispatch_b(const L1PassArgs& a, int32_t b, hipStream_t s) {
     switch (bpad(b)) {
-    case 1: return launch_one<P, 1, INT ? r_int<1>() : r_float<1>()>(a, b, s);
-    case 2: return launch_one<P, 2, INT ? r_int<2>() : r_float<2>()>(a, b, s);
-    case 4: return launch_one<P, 4, INT ? r_int<4>() : r_float<4>()>(a, b, s);
-    case 8: return launch_one<P, 8, INT ? r_int<8>() : r_float<8>()>(a, b, s);
-    case 16: return launch_one<P, 16, INT ? r_int<16>() : r_float<16>()>(a, b, s);
-    case 32: return launch_one<P, 32, INT ? r_int<32>() : r_float<32>()>(a, b, s);
-    case 64: return launch_one<P, 64, INT ? r_int<64>() : r_float<64>()>(a, b, s);
+    case 1: return launch_one<P, 1>(a, b, s);
+    case 2: return launch_one<P, 2>(a, b, s);
+    case 4: return launch_one<P, 4>(a, b, s);
+    case 8: return launch_one<P, 8>(a, b, s);
+    case 16: return launch_one<P, 16>(a, b, s);
+    case 32: return launch_one<P, 32>(a, b, s);
+    case 64: return launch_one<P, 64>(a, b, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -781,9 +796,9 @@ static hipError_t dispatch_b(const L1PassArgs& a, int32_t b, hipStream_t s) {
 hipError_t launch_l1_pass(bool is_int, int zkind, int32_t b, const L1PassArgs& a, hipStream_t s)
 {
     if (b < 1 || b > 64) return hipErrorInvalidValue;
-    if (!is_int) return dispatch_b<FloatPath, false>(a, b, s);
-    if (zkind == IN_I32) return dispatch_b<IntPath<int32_t>, true>(a, b, s);
-    return dispatch_b<IntPath<int64_t>, true>(a, b, s);
+    if (!is_int) return dispatch_b<FloatPath>(a, b, s);
+    if (zkind == IN_I32) return dispatch_b<IntPath<int32_t>>(a, b, s);
+    return dispatch_b<IntPath<int64_t>>(a, b, s);
 }
 
 }  // namespace dm
