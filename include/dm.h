@@ -110,6 +110,37 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
  * that later dm_matvec calls allocate nothing.  Errors: DM_ERR_ARG, DM_ERR_NOMEM. */
 dm_status dm_reserve(dm_handle* h, int32_t b);
 
+/*
+ * Tile tuning of the l1 pass (the per-coordinate gather-scan-scatter of
+ * Algorithm 2, Section 2).  Each pass configuration (data path, b rounded up
+ * to a power of two) has dm_variant_count() tile variants with identical
+ * results on integer data and results within the same error bounds on float
+ * data; they differ only in speed, which depends on n, b and the device.
+ *
+ * dm_tune times every variant on this handle's own sorted coordinates
+ * (`reps` passes each, after one untimed pass, with a zero right-hand side of
+ * n x b `z_dtype` values), keeps the fastest for later dm_matvec calls of the
+ * same configuration and stores it in *chosen.  ms_per_pass, if not NULL,
+ * receives dm_variant_count() mean pass times in milliseconds.  It allocates
+ * and frees temporary device memory (the right-hand side and the result) and
+ * synchronises `stream`.  If the environment variable DM_TUNE_CACHE names a
+ * file, the choice is appended to it as one text line, and handles prepared
+ * later on the same device type with the same metric, dtype, d and
+ * floor(log2 n) start from the cached choice instead of variant 0.
+ * Errors: DM_ERR_ARG (NULL handle, b outside 1..64, reps outside 1..4096, a
+ * metric other than l1), DM_ERR_DTYPE, DM_ERR_STATE (multi-dataset handle),
+ * DM_ERR_NOMEM, DM_ERR_DEVICE.
+ *
+ * dm_set_variant fixes the variant of a configuration (for callers that keep
+ * their own tuning results, and for tests); dm_get_variant reports the one in
+ * use.  Both are host-only and return the dm_tune argument errors.
+ */
+int32_t dm_variant_count(void);
+dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* stream, int32_t* chosen,
+                  double* ms_per_pass);
+dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t variant);
+dm_status dm_get_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t* variant);
+
 /* Wait for the handle's last stream, then return and clear the sticky status. */
 dm_status dm_sync(dm_handle* h);
 

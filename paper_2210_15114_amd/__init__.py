@@ -87,6 +87,14 @@ def lib():
     L.dm_matvec_multi.restype = i32
     L.dm_multi_count.argtypes = [P, ctypes.POINTER(i32)]
     L.dm_multi_count.restype = i32
+    L.dm_variant_count.argtypes = []
+    L.dm_variant_count.restype = i32
+    L.dm_tune.argtypes = [P, i32, i32, i32, P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    L.dm_tune.restype = i32
+    L.dm_set_variant.argtypes = [P, i32, i32, i32]
+    L.dm_set_variant.restype = i32
+    L.dm_get_variant.argtypes = [P, i32, i32, ctypes.POINTER(i32)]
+    L.dm_get_variant.restype = i32
     _lib = L
     return L
 
@@ -188,6 +196,31 @@ class Handle:
 
     def reserve(self, b: int):
         _check(lib().dm_reserve(self._ptr, b), "dm_reserve")
+
+    def _zcode(self, z_dtype):
+        torch = _torch()
+        if z_dtype is None:
+            z_dtype = torch.int32 if self.is_int else torch.float32
+        return _dtype_code(z_dtype)
+
+    def tune(self, b: int, z_dtype=None, reps: int = 6, stream=None):
+        """Time the l1 pass tile variants for b columns; keep the fastest.
+
+        Returns (chosen variant, list of mean pass times in ms)."""
+        nv = lib().dm_variant_count()
+        ms = (ctypes.c_double * nv)()
+        chosen = ctypes.c_int32(-1)
+        _check(lib().dm_tune(self._ptr, b, self._zcode(z_dtype), reps, _stream_ptr(stream), ctypes.byref(chosen),
+                             ms), "dm_tune")
+        return chosen.value, list(ms)
+
+    def set_variant(self, b: int, variant: int, z_dtype=None):
+        _check(lib().dm_set_variant(self._ptr, b, self._zcode(z_dtype), variant), "dm_set_variant")
+
+    def get_variant(self, b: int, z_dtype=None) -> int:
+        v = ctypes.c_int32(-1)
+        _check(lib().dm_get_variant(self._ptr, b, self._zcode(z_dtype), ctypes.byref(v)), "dm_get_variant")
+        return v.value
 
     def sync(self):
         _check(lib().dm_sync(self._ptr), "dm_sync")

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -134,6 +136,10 @@ struct dm_handle {
     std::vector<Region> regions;
     double guard_scale = 0.0;   // sum of ranges (l1) or squared ranges (l2 squared)
     hipStream_t last = nullptr;
+    // tile variant of the l1 pass per (data path, log2 of the padded block
+    // width); -1 until set, tuned or found in the tuning cache (then 0)
+    int8_t variant[3][8];
+    char arch[64] = {0};
 
     // measurement: event pairs around launches while profiling is on
     struct Ev { hipEvent_t a = nullptr, b = nullptr; int cls = 0; };
@@ -162,6 +168,83 @@ void release(dm_handle* h) {
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
     delete h;
+}
+
+void arch_name(int dev, char* out) {
+    hipDeviceProp_t p;
+    size_t i = 0;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) {
+        // the base name only ("gfx950:sramecc+:xnack-" -> "gfx950")
+        for (; i < 63 && p.gcnArchName[i] && p.gcnArchName[i] != ':'; ++i) out[i] = p.gcnArchName[i];
+    }
+    out[i] = 0;
+}
+
+int log2_pad(int32_t b) {
+    int lg = 0;
+    while ((1 << lg) < b) ++lg;
+    return lg;
+}
+int floor_log2(int64_t n) {
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= n) ++lg;
+    return lg;
+}
+int kind_index(bool is_int, int zkind) { return !is_int ? 0 : zkind == IN_I32 ? 1 : 2; }
+
+// the pass data path of a right-hand-side type on this handle
+dm_status zkind_of(const dm_handle* h, int32_t z_dtype, int* zkind) {
+    if (!valid_dtype(z_dtype)) return DM_ERR_ARG;
+    if (h->is_int ? !(z_dtype == DM_I32 || z_dtype == DM_I64) : z_dtype != DM_F32) return DM_ERR_DTYPE;
+    *zkind = h->is_int ? (z_dtype == DM_I32 ? IN_I32 : IN_I64) : IN_F32;
+    return DM_OK;
+}
+
+// Tuning cache: the text file named by DM_TUNE_CACHE, one line per tuned
+// configuration,
+//   dmtune1 <arch> <metric> <dtype> <data path> <floor log2 n> <d> <log2 padded b> <variant>
+// appended by dm_tune and read when a handle first needs the variant of a
+// configuration; the last matching line wins.
+int cache_lookup(const dm_handle* h, int kind, int lg) {
+    const char* path = std::getenv("DM_TUNE_CACHE");
+    if (!path || !*path || !h->arch[0]) return -1;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return -1;
+    char line[256];
+    int found = -1;
+    while (std::fgets(line, sizeof line, f)) {
+        char tag[16], arch[64];
+        int metric, dtype, k, lgn, d, l, v;
+        if (std::sscanf(line, "%15s %63s %d %d %d %d %d %d %d", tag, arch, &metric, &dtype, &k, &lgn, &d, &l, &v) != 9)
+            continue;
+        if (std::strcmp(tag, "dmtune1") != 0 || std::strcmp(arch, h->arch) != 0) continue;
+        if (metric == h->metric && dtype == h->dtype && k == kind && lgn == floor_log2(h->n) && d == h->d &&
+            l == lg && v >= 0 && v < L1_VARIANTS)
+            found = v;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const dm_handle* h, int kind, int lg, int v) {
+    const char* path = std::getenv("DM_TUNE_CACHE");
+    if (!path || !*path || !h->arch[0]) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "dmtune1 %s %d %d %d %d %d %d %d\n", h->arch, h->metric, h->dtype, kind, floor_log2(h->n), h->d,
+                 lg, v);
+    std::fclose(f);
+}
+
+// the tile variant used for (data path, padded block width): set, tuned,
+// cached, or the default
+int variant_for(dm_handle* h, int kind, int lg) {
+    int8_t& v = h->variant[kind][lg];
+    if (v < 0) {
+        const int c = cache_lookup(h, kind, lg);
+        v = (int8_t)(c >= 0 ? c : 0);
+    }
+    return v;
 }
 
 double key_to_double(uint32_t k, bool is_int) {
@@ -349,6 +432,8 @@ dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_
     h->dtype = dtype;
     h->is_int = int_dtype(dtype);
     h->L = L;
+    std::memset(h->variant, -1, sizeof h->variant);
+    arch_name(dev, h->arch);
     auto fail = [&](dm_status e) {
         release(h);
         return e;
@@ -413,7 +498,8 @@ dm_status dm_reserve(dm_handle* h, int32_t b) {
         const int kinds[2] = {h->is_int ? IN_I32 : IN_F32, IN_I64};
         for (int ki = 0; ki < (h->is_int ? 2 : 1); ++ki) {
             uint64_t* r = nullptr;
-            if ((st = region_for(h, l1_shape(h->n, b, h->is_int, kinds[ki]), h->last, &r)) != DM_OK) return st;
+            const int v = variant_for(h, kind_index(h->is_int, kinds[ki]), log2_pad(b));
+            if ((st = region_for(h, l1_shape(h->n, b, h->is_int, kinds[ki], v), h->last, &r)) != DM_OK) return st;
         }
     }
     return hipStreamSynchronize(h->last) == hipSuccess ? DM_OK : DM_ERR_DEVICE;
@@ -422,8 +508,11 @@ dm_status dm_reserve(dm_handle* h, int32_t b) {
 dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream) {
     if (!h || !Z || !Out || b < 1 || b > MAX_B) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    if (!valid_dtype(z_dtype)) return DM_ERR_ARG;
-    if (h->is_int ? !(z_dtype == DM_I32 || z_dtype == DM_I64) : z_dtype != DM_F32) return DM_ERR_DTYPE;
+    int zkind = 0;
+    {
+        const dm_status zs = zkind_of(h, z_dtype, &zkind);
+        if (zs != DM_OK) return zs;
+    }
     const size_t zbytes = (size_t)h->n * b * dtype_size(z_dtype);
     const size_t obytes = (size_t)h->n * b * (h->is_int ? 8 : 4);
     const char* zp = (const char*)Z;
@@ -432,7 +521,6 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
     hipStream_t s = (hipStream_t)stream;
     dm_status st = ensure_scratch(h, b, s);
     if (st != DM_OK) return st;
-    const int zkind = h->is_int ? (z_dtype == DM_I32 ? IN_I32 : IN_I64) : IN_F32;
     char* sc = h->scratch;
     TotalsOut tot;
     tot.T0 = h->ctl->T0;
@@ -455,10 +543,13 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         a.U = tot.U;
         a.chain = &h->ctl->chain;
         {
-            const L1Shape sh = l1_shape(h->n, b, h->is_int, zkind);
+            const int v = variant_for(h, kind_index(h->is_int, zkind), log2_pad(b));
+            const L1Shape sh = l1_shape(h->n, b, h->is_int, zkind, v);
             dm_status rs = region_for(h, sh, s, &a.records);
             if (rs != DM_OK) return rs;
             a.record_words = sh.record_words;
+            a.cls = sh.cls;
+            a.variant = v;
         }
         const size_t vsz = 4;
         for (int32_t k = 0; k < h->d; ++k) {
@@ -473,6 +564,104 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         DM_TRY(launch_l2sq(h->is_int, zkind, h->ws + h->L.xcopy, h->ws + h->L.rownrm, h->n, h->d, Z, b, Out, rest,
                            tot, h->guard_scale, s));
     }
+    return DM_OK;
+}
+
+dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t variant) {
+    if (!h || b < 1 || b > MAX_B || variant < 0 || variant >= L1_VARIANTS) return DM_ERR_ARG;
+    if (h->multi) return DM_ERR_STATE;
+    if (h->metric != DM_L1) return DM_ERR_ARG;
+    int zkind = 0;
+    const dm_status st = zkind_of(h, z_dtype, &zkind);
+    if (st != DM_OK) return st;
+    h->variant[kind_index(h->is_int, zkind)][log2_pad(b)] = (int8_t)variant;
+    return DM_OK;
+}
+
+dm_status dm_get_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t* variant) {
+    if (!h || !variant || b < 1 || b > MAX_B) return DM_ERR_ARG;
+    if (h->multi) return DM_ERR_STATE;
+    if (h->metric != DM_L1) return DM_ERR_ARG;
+    int zkind = 0;
+    const dm_status st = zkind_of(h, z_dtype, &zkind);
+    if (st != DM_OK) return st;
+    *variant = variant_for(h, kind_index(h->is_int, zkind), log2_pad(b));
+    return DM_OK;
+}
+
+int32_t dm_variant_count(void) { return L1_VARIANTS; }
+
+dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* stream, int32_t* chosen,
+                  double* ms_per_pass) {
+    if (!h || b < 1 || b > MAX_B || reps < 1 || reps > 4096) return DM_ERR_ARG;
+    if (h->multi) return DM_ERR_STATE;
+    if (h->metric != DM_L1) return DM_ERR_ARG;
+    int zkind = 0;
+    dm_status st = zkind_of(h, z_dtype, &zkind);
+    if (st != DM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int kind = kind_index(h->is_int, zkind), lg = log2_pad(b);
+    const size_t zb = (size_t)h->n * b * dtype_size(z_dtype);
+    const size_t ob = (size_t)h->n * b * (h->is_int ? 8 : 4);
+    void* Zt = nullptr;
+    void* Ot = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best = 1e300;
+    int bestv = 0;
+    // time every variant on this handle's own sorted coordinates with a zero
+    // right-hand side (the pass time does not depend on the values)
+    auto run = [&]() -> dm_status {
+        if (hipMalloc(&Zt, zb) != hipSuccess || hipMalloc(&Ot, ob) != hipSuccess) return DM_ERR_NOMEM;
+        DM_TRY(launch_fill_u32((uint32_t*)Zt, 0u, zb / 4, s));
+        DM_TRY(launch_fill_u32((uint32_t*)Ot, 0u, ob / 4, s));
+        DM_TRY(hipEventCreate(&e0));
+        DM_TRY(hipEventCreate(&e1));
+        L1PassArgs a;
+        a.n = h->n;
+        a.Z = Zt;
+        a.Out = Ot;
+        a.T0 = h->ctl->T0;
+        a.U = h->ctl->U;
+        a.chain = &h->ctl->chain;
+        a.first = 0;
+        for (int v = 0; v < L1_VARIANTS; ++v) {
+            const L1Shape sh = l1_shape(h->n, b, h->is_int, zkind, v);
+            const dm_status rs = region_for(h, sh, s, &a.records);
+            if (rs != DM_OK) return rs;
+            a.record_words = sh.record_words;
+            a.cls = sh.cls;
+            a.variant = v;
+            for (int i = -1; i < reps; ++i) {   // one untimed pass, then reps timed ones
+                if (i == 0) DM_TRY(hipEventRecord(e0, s));
+                const int32_t k = (i + 1) % h->d;
+                a.perm = h->at<uint32_t>(h->L.perm) + (size_t)k * h->L.ld;
+                a.xs = h->ws + h->L.xs + (size_t)k * h->L.ld * 4;
+                DM_TRY(launch_l1_pass(h->is_int, zkind, b, a, s));
+            }
+            DM_TRY(hipEventRecord(e1, s));
+            DM_TRY(hipEventSynchronize(e1));
+            float t = 0.0f;
+            DM_TRY(hipEventElapsedTime(&t, e0, e1));
+            const double per = (double)t / reps;
+            if (ms_per_pass) ms_per_pass[v] = per;
+            if (per < best) {
+                best = per;
+                bestv = v;
+            }
+        }
+        return DM_OK;
+    };
+    st = run();
+    if (hipStreamSynchronize(s) != hipSuccess && st == DM_OK) st = DM_ERR_DEVICE;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (Zt) (void)hipFree(Zt);
+    if (Ot) (void)hipFree(Ot);
+    if (st != DM_OK) return st;
+    h->variant[kind][lg] = (int8_t)bestv;
+    cache_store(h, kind, lg, bestv);
+    if (chosen) *chosen = bestv;
+    h->last = s;
     return DM_OK;
 }
 

@@ -25,7 +25,8 @@ constexpr int SORT_THREADS = 256;
 // so ticket / (T + G) numbers the passes of that shape and, with the shape,
 // forms the tag of every word the pass publishes.  Zeroed once when a handle
 // is created and never reset; the host never reads them.
-constexpr int CHAIN_CLASSES = 32;
+constexpr int L1_VARIANTS = 4;      // tile variants per l1 pass configuration (tuned per handle)
+constexpr int CHAIN_CLASSES = 96;   // 3 data paths x 8 block widths x L1_VARIANTS
 struct ChainState {
     uint64_t ticket[CHAIN_CLASSES];
 };
@@ -87,16 +88,25 @@ struct L1PassArgs {
     ChainState* chain;
     uint64_t* records;      // the shape's own record region (l1_shape)
     size_t record_words;    // its size in 64-bit words; a launch that needs more is refused
+    int cls;                // the shape's ticket class (l1_shape)
+    int variant;            // tile variant, 0 .. L1_VARIANTS-1
 };
-int l1_tile_ranks(int32_t b, bool is_int, int zkind);
-size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind);
+int l1_tile_ranks(int32_t b, bool is_int, int zkind, int variant);
+size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind, int variant);
+// per data path (k_l1_f32.hip, k_l1_i32.hip, k_l1_i64.hip)
+hipError_t launch_l1_pass_f32(const L1PassArgs& a, int32_t b, int variant, hipStream_t s);
+hipError_t launch_l1_pass_i32(const L1PassArgs& a, int32_t b, int variant, hipStream_t s);
+hipError_t launch_l1_pass_i64(const L1PassArgs& a, int32_t b, int variant, hipStream_t s);
+int l1_tile_ranks_f32(int32_t b, int variant);
+int l1_tile_ranks_i32(int32_t b, int variant);
+int l1_tile_ranks_i64(int32_t b, int variant);
 // kernel shape of a pass: its ticket class and the words of its record region
 // (each shape owns its region, so no shape ever reads another's words)
 struct L1Shape {
     int cls;
     size_t record_words;
 };
-L1Shape l1_shape(int64_t n, int32_t b, bool is_int, int zkind);
+L1Shape l1_shape(int64_t n, int32_t b, bool is_int, int zkind, int variant);
 hipError_t launch_l1_pass(bool is_int, int zkind, int32_t b, const L1PassArgs& a, hipStream_t s);
 
 // ---- many datasets in one query --------------------------------------------

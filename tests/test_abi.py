@@ -83,7 +83,14 @@ def test_null_handle_calls(L):
     assert L.dm_reserve(None, 4) == dm.ERR_ARG
     assert L.dm_info(None, None, None, None, None) == dm.ERR_ARG
     assert L.dm_copy_sorted(None, None, None, None, None) == dm.ERR_ARG
+    assert L.dm_tune(None, 8, dm.F32, 4, None, None, None) == dm.ERR_ARG
+    assert L.dm_set_variant(None, 8, dm.F32, 0) == dm.ERR_ARG
+    assert L.dm_get_variant(None, 8, dm.F32, None) == dm.ERR_ARG
     L.dm_free(None)
+
+
+def test_variant_count(L):
+    assert L.dm_variant_count() == 4
 
 
 def test_int_bound_guard(L):
