@@ -34,19 +34,23 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "l1_pass_n4194304_d128_b64_traffic.txt")
-PASS_SRC = os.path.join(ROOT, "paper_2210_15114_amd", "csrc", "k_l1.hip")
+PASS_SRCS = [os.path.join(ROOT, "paper_2210_15114_amd", "csrc", f) for f in ("l1_pass.h", "l1_common.h")]
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def src_hash(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def src_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per pass from committed counter runs, if they still describe the kernel."""
+def read_traffic(variant):
+    """HBM bytes per pass from committed counter runs, if they still describe
+    the kernel (same sources, same tile variant)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -54,12 +58,25 @@ def read_traffic():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256_16") != src_hash(PASS_SRC):
+    if kv.get("source_sha256_16") != src_hash(PASS_SRCS) or kv.get("variant") != str(variant):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def pass_kernel_name(variant, b):
+    """Kernel of a float l1 pass variant: 0/1 the keep kernel, 2/3 the
+    re-gathering kernel; odd variants halve the ranks per slot."""
+    bp = 1
+    while bp < b:
+        bp *= 2
+    r = 16 if (bp >= 32 or bp < 4) else 8
+    if variant & 1:
+        r //= 2
+    fam = "l1_pass_keep_kernel" if variant < 2 else "l1_pass_kernel"
+    return "%s<FloatPath,%d,R=%d>" % (fam, bp, r)
 
 
 def run_multi(args, dm, synth, np, torch, dev, stream):
@@ -176,6 +193,11 @@ def main():
     h = dm.prepare(Xd, dm.L1)
     prep_ms = (time.perf_counter() - t0) * 1e3
     log("prep %.1f ms" % prep_ms)
+    # tile variant of the pass, chosen by the library's tuner on this data
+    tuned = {}
+    vb, tms = h.tune(b, reps=4)
+    tuned["b%d" % b] = {"variant": vb, "ms_per_pass": [round(t, 4) for t in tms]}
+    log("tuned b=%d: variant %d, ms per pass %s" % (b, vb, ["%.3f" % t for t in tms]))
     h.reserve(b)
     Out = torch.empty((n, b), dtype=torch.float32, device=dev)
 
@@ -206,13 +228,16 @@ def main():
     bytes_pass = 12.0 * n * b + 8.0 * n
     achieved = bytes_pass / (avg_pass_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": read_traffic(),
-                "kernel": "l1_pass_keep_kernel<FloatPath,64>", "bytes_per_launch": bytes_pass,
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": read_traffic(vb),
+                "kernel": pass_kernel_name(vb, b), "variant": vb, "bytes_per_launch": bytes_pass,
                 "avg_launch_ms": round(avg_pass_ms, 4), "launches": pass_n}
 
     # ---- single-vector form on the same 64 columns ----
     single = None
     if not args.no_single:
+        v1, tms1 = h.tune(1, reps=8)
+        tuned["b1"] = {"variant": v1, "ms_per_pass": [round(t, 4) for t in tms1]}
+        log("tuned b=1: variant %d, ms per pass %s" % (v1, ["%.3f" % t for t in tms1]))
         Zc = Zd.t().contiguous()                     # 64 x n: row c is column c of Z
         Oc = torch.empty_like(Zc)
         h.matvec(Zc[0], out=Oc[0])                   # warm-up (scratch for b = 1)
@@ -313,6 +338,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "single_z": single,
+        "tuned_variants": tuned,
         "batched_vs_single": round(cols_s / single["columns_per_s"], 2) if single else None,
         "hbm_frac": roofline["frac"],
         "copy_probe_GBps": round(copy_gbps, 1),

@@ -496,7 +496,9 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
 // ranks per slot (R) of the default shape
 template <int BP> constexpr int r_float() { return BP >= 32 ? 16 : BP >= 4 ? 8 : 16; }
 template <int BP> constexpr int r_int() { return BP >= 4 ? 4 : 8; }
-template <int BP, int R> constexpr int out_chunk() { return BP >= 4 ? (R >= 4 ? 4 : R) : R; }
+// rows of Out read per batch in phase 2: more rows in flight where a thread
+// holds 16 or more ranks (measured faster for 32 and 64 columns)
+template <int BP, int R> constexpr int out_chunk() { return BP >= 4 ? (R >= 16 ? 8 : R >= 4 ? 4 : R) : R; }
 // sub-chunks per tile of the re-gathering kernel: tiles of about 1024 ranks
 // for wide blocks, 4 sub-chunks for narrow ones
 template <int BP, int R> constexpr int sub_chunks() {
