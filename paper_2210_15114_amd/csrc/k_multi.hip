@@ -124,7 +124,7 @@ __global__ __launch_bounds__(64) void multi_totals_stage2(const MultiDs* __restr
 // one round: coordinate k of every dataset in the round's tile table
 // ---------------------------------------------------------------------------
 template <typename P, int BP, int R, int OC>
-__global__ __launch_bounds__(256) void multi_pass_kernel(const MultiDs* __restrict__ ds,
+__global__ __launch_bounds__(256, 2) void multi_pass_kernel(const MultiDs* __restrict__ ds,
                                                          const MultiTile* __restrict__ tiles, int64_t ntiles,
                                                          int32_t k, int32_t b, uint64_t* __restrict__ ticket_ctr,
                                                          uint64_t* __restrict__ rec, uint64_t* __restrict__ stat)
@@ -222,7 +222,9 @@ __global__ __launch_bounds__(256) void multi_pass_kernel(const MultiDs* __restri
         // windowed look-back inside the segment (its head tile always has an
         // inclusive record, so the walk never leaves the segment)
         C c0, c1;
-        look_back_wg<P, BP, WPR>(rec, stat, head ? -1 : (int64_t)tile - 1, tag, tid, s_lb, c0, c1);
+        // two records per wave per round trip: the whole tile is held in registers,
+        // and deeper batches would cost occupancy
+        look_back_wg<P, BP, WPR, 2>(rec, stat, head ? -1 : (int64_t)tile - 1, tag, tid, s_lb, c0, c1);
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
