@@ -194,6 +194,35 @@ dm_status dm_matvec_multi(dm_handle* h, const void* const* Z, int32_t b, void* c
 dm_status dm_multi_count(const dm_handle* h, int32_t* count);
 
 /*
+ * Rank-k approximation A ~ U diag(lam) U^T by block Krylov iteration, using
+ * only products with A (the query model of Section 1; Appendix C.1 cites
+ * block Krylov methods for the top singular values, and Table 2 lists the
+ * low-rank application).  The paper gives no algorithm; this one:
+ *   Q_0 = orth(A Omega), Q_j = orth(A Q_{j-1} against Q_0..Q_{j-1}),
+ *   j < iters (block Gram-Schmidt twice, then Cholesky QR twice; columns
+ *   numerically dependent on earlier ones are dropped as zero columns);
+ *   T = Q^T A Q from the same products plus one more, A Q_{iters-1};
+ *   T = V diag(w) V^T by cyclic Jacobi; the `rank` pairs of largest |w|
+ *   give lam (in decreasing |lam|) and U = Q V_k.
+ * Products with A go through dm_matvec (FP32 in and out, block columns at a
+ * time: iters + 1 queries); everything else is FP64 on the device.
+ *
+ * h: a prepared float handle (l1 or l2 squared).  Omega: device n x block
+ * FP64, the start block, drawn by the caller (the library draws no random
+ * numbers).  U: device n x rank FP64 (out), orthonormal columns (zero
+ * columns only if A has fewer than `rank` independent directions in the
+ * basis).  lam: device rank FP64 (out).  sweeps (optional, host): Jacobi
+ * sweeps used.  1 <= block <= 64, iters >= 1, block * iters <= 1024,
+ * 1 <= rank <= min(64, block * iters).
+ * Allocates and frees device memory (about (iters + 2) n block doubles) and
+ * synchronises `stream`.
+ * Errors: DM_ERR_ARG, DM_ERR_DTYPE (integer handle), DM_ERR_STATE
+ * (multi-dataset handle), DM_ERR_NOMEM, DM_ERR_DEVICE, DM_ERR_NONFINITE.
+ */
+dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, const double* Omega, double* U,
+                     double* lam, void* stream, int32_t* sweeps);
+
+/*
  * Measurement support.  While profiling is on, every launch of the listed
  * kernel classes is bracketed by HIP events on the query stream;
  * dm_profile_read waits for them and returns the summed device time and the

@@ -95,6 +95,8 @@ def lib():
     L.dm_set_variant.restype = i32
     L.dm_get_variant.argtypes = [P, i32, i32, ctypes.POINTER(i32)]
     L.dm_get_variant.restype = i32
+    L.dm_lowrank.argtypes = [P, i32, i32, i32, P, P, P, P, ctypes.POINTER(i32)]
+    L.dm_lowrank.restype = i32
     _lib = L
     return L
 
@@ -224,6 +226,21 @@ class Handle:
 
     def sync(self):
         _check(lib().dm_sync(self._ptr), "dm_sync")
+
+    def lowrank(self, rank: int, omega, iters: int = 8, stream=None):
+        """Rank-`rank` approximation A ~ U diag(lam) U^T by block Krylov iteration.
+
+        omega: n x block float64 device tensor (the start block).  Returns
+        (U: n x rank float64, lam: rank float64, Jacobi sweeps used)."""
+        torch = _torch()
+        if omega.dim() != 2 or omega.shape[0] != self.n or omega.dtype != torch.float64:
+            raise ValueError("omega must be an n x block float64 tensor")
+        U = torch.empty((self.n, rank), dtype=torch.float64, device=omega.device)
+        lam = torch.empty(rank, dtype=torch.float64, device=omega.device)
+        sw = ctypes.c_int32(0)
+        _check(lib().dm_lowrank(self._ptr, rank, omega.shape[1], iters, _dev_ptr(omega, "omega"), _dev_ptr(U, "U"),
+                                _dev_ptr(lam, "lam"), _stream_ptr(stream), ctypes.byref(sw)), "dm_lowrank")
+        return U, lam, sw.value
 
     def sorted(self, stream=None):
         """(perm, rank, xs), each d x n on the device (l1 handles)."""

@@ -665,6 +665,106 @@ dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* 
     return DM_OK;
 }
 
+dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, const double* Omega, double* U,
+                     double* lam, void* stream, int32_t* sweeps) {
+    if (!h || !Omega || !U || !lam) return DM_ERR_ARG;
+    if (h->multi) return DM_ERR_STATE;
+    if (h->is_int) return DM_ERR_DTYPE;
+    if (block < 1 || block > lr_max_block() || iters < 1 || rank < 1 || rank > lr_max_block()) return DM_ERR_ARG;
+    const int64_t K64 = (int64_t)block * iters;
+    if (K64 > lr_max_basis() || rank > K64) return DM_ERR_ARG;
+    const int K = (int)K64, B = block;
+    const int64_t n = h->n;
+    hipStream_t s = (hipStream_t)stream;
+
+    // one allocation for the basis (iters blocks, plus one for the last
+    // product), the FP32 staging of the products, and the small matrices
+    const size_t nb = (size_t)n * B;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_basis = take(nb * (iters + 1) * sizeof(double));
+    const size_t o_zf = take(nb * sizeof(float));
+    const size_t o_yf = take(nb * sizeof(float));
+    const size_t o_part = take(lr_gram_scratch_doubles(n, B, B) * sizeof(double));
+    const size_t o_T = take((size_t)K * K * sizeof(double));
+    const size_t o_V = take((size_t)K * K * sizeof(double));
+    const size_t o_w = take((size_t)K * sizeof(double));
+    const size_t o_G = take((size_t)B * B * sizeof(double));
+    const size_t o_X = take((size_t)B * B * sizeof(double));
+    const size_t o_C = take((size_t)B * B * sizeof(double));
+    const size_t o_Vk = take((size_t)K * rank * sizeof(double));
+    const size_t o_sw = take(sizeof(int));
+    char* mem = nullptr;
+    if (hipMalloc(&mem, off) != hipSuccess) return DM_ERR_NOMEM;
+    double* basis = (double*)(mem + o_basis);
+    float* Zf = (float*)(mem + o_zf);
+    float* Yf = (float*)(mem + o_yf);
+    double* part = (double*)(mem + o_part);
+    double* T = (double*)(mem + o_T);
+    double* V = (double*)(mem + o_V);
+    double* w = (double*)(mem + o_w);
+    double* G = (double*)(mem + o_G);
+    double* X = (double*)(mem + o_X);
+    double* C = (double*)(mem + o_C);
+    double* Vk = (double*)(mem + o_Vk);
+    int* d_sweeps = (int*)(mem + o_sw);
+    auto Qb = [&](int i) { return basis + (size_t)i * nb; };
+    uint32_t* status = &h->ctl->status;
+    // a column is dropped when it is in the span of the earlier ones to
+    // relative accuracy 1e-10
+    const double rel = 1e-20;
+
+    auto run = [&]() -> dm_status {
+        const double* Qprev = Omega;
+        for (int j = 0; j <= iters; ++j) {
+            // Y = A Q_{j-1} (A Omega for j = 0), through the FP32 query
+            double* Y = Qb(j);
+            DM_TRY(lr_cvt(Qprev, Zf, nb, s));
+            const dm_status ms = dm_matvec(h, Zf, DM_F32, B, Yf, s);
+            if (ms != DM_OK) return ms;
+            DM_TRY(lr_cvt(Yf, Y, nb, s));
+            // Rayleigh-Ritz blocks T[i][j-1] = Q_i^T A Q_{j-1}, i < j
+            for (int i = 0; i < j; ++i)
+                DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, T + (size_t)i * B * K + (size_t)(j - 1) * B, K, 1.0, s));
+            if (j == iters) break;
+            // block Gram-Schmidt against Q_0 .. Q_{j-1}, twice
+            for (int pass = 0; pass < 2; ++pass)
+                for (int i = 0; i < j; ++i) {
+                    DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, C, B, -1.0, s));        // C = -Q_i^T Y
+                    DM_TRY(lr_update_rows(Y, B, B, Qb(i), B, B, C, B, 1.0, n, s));  // Y += Q_i C
+                }
+            // Cholesky QR, twice
+            for (int pass = 0; pass < 2; ++pass) {
+                DM_TRY(lr_gram(Y, B, Y, B, n, part, G, B, 1.0, s));
+                DM_TRY(lr_cholinv(G, B, rel, X, status, s));
+                DM_TRY(lr_update_rows(Y, B, B, Y, B, B, X, B, 0.0, n, s));
+            }
+            Qprev = Y;
+        }
+        DM_TRY(lr_symm(T, K, B, s));
+        DM_TRY(lr_eig(T, V, w, K, 60, 1e-14, d_sweeps, s));
+        DM_TRY(lr_topk(w, V, K, rank, lam, Vk, s));
+        // U = Q Vk, block by block
+        for (int i = 0; i < iters; ++i)
+            DM_TRY(lr_update_rows(U, rank, rank, Qb(i), B, B, Vk + (size_t)i * B * rank, rank, i == 0 ? 0.0 : 1.0,
+                                  n, s));
+        return DM_OK;
+    };
+    dm_status st = run();
+    if (hipStreamSynchronize(s) != hipSuccess && st == DM_OK) st = DM_ERR_DEVICE;
+    int sw = 0;
+    if (st == DM_OK && hipMemcpy(&sw, d_sweeps, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) st = DM_ERR_DEVICE;
+    (void)hipFree(mem);
+    if (sweeps) *sweeps = sw;
+    h->last = s;
+    if (st != DM_OK) return st;
+    return dm_sync(h);
+}
+
 dm_status dm_sync(dm_handle* h) {
     if (!h) return DM_ERR_ARG;
     if (hipStreamSynchronize(h->last) != hipSuccess) return DM_ERR_DEVICE;

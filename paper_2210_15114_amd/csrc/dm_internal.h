@@ -139,6 +139,23 @@ hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nb
 hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
                              int k, uint64_t* ticket, uint64_t* records, int grid, hipStream_t s);
 
+// ---- block-Krylov low rank (k_lowrank.hip) ---------------------------------
+int lr_max_block();
+int lr_max_basis();
+size_t lr_gram_scratch_doubles(int64_t n, int ma, int mb);
+// out[p * ldo + q] = scale * sum_r A[r][p] B[r][q]; part: lr_gram_scratch_doubles doubles
+hipError_t lr_gram(const double* A, int ma, const double* B, int mb, int64_t n, double* part, double* out,
+                   int ldo, double scale, hipStream_t s);
+// Y = beta Y + Q C (Y may be Q when beta is 0)
+hipError_t lr_update_rows(double* Y, int ldy, int mb, const double* Q, int ldq, int ma, const double* C, int ldc,
+                          double beta, int64_t n, hipStream_t s);
+hipError_t lr_cholinv(const double* G, int m, double rel, double* X, uint32_t* status, hipStream_t s);
+hipError_t lr_symm(double* T, int m, int bw, hipStream_t s);
+hipError_t lr_cvt(const double* a, float* b, size_t n, hipStream_t s);
+hipError_t lr_cvt(const float* a, double* b, size_t n, hipStream_t s);
+hipError_t lr_eig(double* T, double* V, double* w, int m, int max_sweeps, double tol, int* sweeps, hipStream_t s);
+hipError_t lr_topk(const double* w, const double* V, int m, int k, double* lam, double* Vk, hipStream_t s);
+
 // ---- l2 squared query ------------------------------------------------------
 size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b);
 hipError_t launch_l2sq(bool is_int, int zkind, const void* Xc, const void* nrm, int64_t n, int32_t d,

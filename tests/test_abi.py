@@ -86,6 +86,7 @@ def test_null_handle_calls(L):
     assert L.dm_tune(None, 8, dm.F32, 4, None, None, None) == dm.ERR_ARG
     assert L.dm_set_variant(None, 8, dm.F32, 0) == dm.ERR_ARG
     assert L.dm_get_variant(None, 8, dm.F32, None) == dm.ERR_ARG
+    assert L.dm_lowrank(None, 32, 40, 8, None, None, None, None, None) == dm.ERR_ARG
     L.dm_free(None)
 
 

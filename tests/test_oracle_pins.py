@@ -287,3 +287,42 @@ def test_error_metrics_order(oracle_mod):
     assert e["per_row"] >= e["spec"]
     assert e["max_abs"] == pytest.approx(1e-3, rel=1e-6)
     assert e["spec"] == pytest.approx(1e-3 / (frob * np.linalg.norm(Z, axis=0).min()), rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# low-rank references (Appendix C): Eckart-Young and block Krylov
+# ---------------------------------------------------------------------------
+def _known_spectrum(seed=31):
+    g = np.random.default_rng(seed)
+    V, _ = np.linalg.qr(g.standard_normal((6, 6)))
+    w = np.array([5.0, -4.0, 3.0, 0.5, -0.25, 0.1])
+    return V, w, (V * w) @ V.T
+
+
+def test_optimal_error_is_the_eigenvalue_tail():
+    from oracle import lowrank
+    V, w, A = _known_spectrum()
+    # singular values of a symmetric matrix are |eigenvalues|: 5, 4, 3, 0.5, 0.25, 0.1
+    assert abs(lowrank.optimal_error(A, 3) - np.sqrt(0.5 ** 2 + 0.25 ** 2 + 0.1 ** 2)) < 1e-12
+    assert abs(lowrank.optimal_error(A, 0) - np.linalg.norm(A)) < 1e-12
+    # the exact top eigenpairs attain it
+    assert abs(lowrank.approx_error(A, V[:, :3], w[:3]) - lowrank.optimal_error(A, 3)) < 1e-12
+
+
+def test_block_krylov_full_basis_gives_exact_eigenpairs():
+    from oracle import lowrank
+    V, w, A = _known_spectrum()
+    g = np.random.default_rng(7)
+    U, lam = lowrank.block_krylov(lambda W: A @ W, 6, 3, 3, 2, g.standard_normal((6, 3)))
+    assert np.allclose(lam, [5.0, -4.0, 3.0], atol=1e-12)
+    assert abs(lowrank.approx_error(A, U, lam) - lowrank.optimal_error(A, 3)) < 1e-12
+
+
+def test_block_krylov_recovers_l2sq_matrix_of_rank_d_plus_2(oracle_mod):
+    from oracle import lowrank
+    g = np.random.default_rng(11)
+    X = g.standard_normal((200, 2))
+    A = oracle_mod.explicit(X, oracle_mod.L2SQ)
+    assert np.linalg.matrix_rank(A) == 4
+    U, lam = lowrank.block_krylov(lambda W: A @ W, 200, 4, 4, 2, g.standard_normal((200, 4)))
+    assert lowrank.approx_error(A, U, lam) <= 1e-10 * np.linalg.norm(A)
