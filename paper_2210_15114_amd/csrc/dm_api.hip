@@ -692,6 +692,7 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     const size_t o_part = take(lr_gram_scratch_doubles(n, B, B) * sizeof(double));
     const size_t o_T = take((size_t)K * K * sizeof(double));
     const size_t o_V = take((size_t)K * K * sizeof(double));
+    const size_t o_T2 = take((size_t)K * K * sizeof(double));
     const size_t o_w = take((size_t)K * sizeof(double));
     const size_t o_G = take((size_t)B * B * sizeof(double));
     const size_t o_X = take((size_t)B * B * sizeof(double));
@@ -706,6 +707,7 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     double* part = (double*)(mem + o_part);
     double* T = (double*)(mem + o_T);
     double* V = (double*)(mem + o_V);
+    double* T2 = (double*)(mem + o_T2);
     double* w = (double*)(mem + o_w);
     double* G = (double*)(mem + o_G);
     double* X = (double*)(mem + o_X);
@@ -718,6 +720,7 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     // relative accuracy 1e-10
     const double rel = 1e-20;
 
+    int sw_used = 0;
     auto run = [&]() -> dm_status {
         const double* Qprev = Omega;
         for (int j = 0; j <= iters; ++j) {
@@ -746,7 +749,9 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
             Qprev = Y;
         }
         DM_TRY(lr_symm(T, K, B, s));
-        DM_TRY(lr_eig(T, V, w, K, 60, 1e-14, d_sweeps, s));
+        int sw_host = 0;
+        DM_TRY(lr_eig(T, T2, V, w, K, 60, 1e-14, d_sweeps, &sw_host, s));
+        sw_used = sw_host;
         DM_TRY(lr_topk(w, V, K, rank, lam, Vk, s));
         // U = Q Vk, block by block
         for (int i = 0; i < iters; ++i)
@@ -756,10 +761,8 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     };
     dm_status st = run();
     if (hipStreamSynchronize(s) != hipSuccess && st == DM_OK) st = DM_ERR_DEVICE;
-    int sw = 0;
-    if (st == DM_OK && hipMemcpy(&sw, d_sweeps, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) st = DM_ERR_DEVICE;
     (void)hipFree(mem);
-    if (sweeps) *sweeps = sw;
+    if (sweeps) *sweeps = sw_used;
     h->last = s;
     if (st != DM_OK) return st;
     return dm_sync(h);

@@ -12,7 +12,7 @@
 //     Y R^-1 of Cholesky QR, and U = Q V of the final step);
 //   * lr_chol     - the orthonormalising factor of Cholesky QR for a small
 //     Gram matrix (column-equilibrated), dropping dependent columns;
-//   * lr_jacobi   - eigenvalues and eigenvectors of the symmetric T by the
+//   * lr_jacobi_step - eigenvalues and eigenvectors of the symmetric T by the
 //     cyclic Jacobi method with the round-robin pair ordering (all pairs of
 //     one step are disjoint, so their rotations are applied together);
 //   * lr_select   - the k eigenpairs of largest |lambda|.
@@ -260,127 +260,147 @@ __global__ __launch_bounds__(256) void lr_cvt_f32_f64(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Cyclic Jacobi on the symmetric m x m matrix T (in place; one workgroup).
-// Step s of a sweep pairs index 0 with (s mod (m'-1)) + 1 and the others
-// around a circle (m' = m rounded up to even; a pair with the padding index
-// is skipped).  Each rotation zeroes T[p][q] (the rotation of the classical
-// Jacobi method), and V accumulates the rotations.  Sweeps stop when the
-// off-diagonal mass is at most tol^2 times the total, or after max_sweeps.
-// On return w[i] = T[i][i]; *sweeps_out is the number of sweeps done.
+// Cyclic Jacobi on the symmetric m x m matrix T, one launch per step.
+// Step s pairs index 0 with (s mod (m'-1)) + 1 and the other indices around
+// a circle (m' = m rounded up to even; a pair with the padding index m is
+// left alone), so the m'/2 pairs of a step are disjoint and their rotations
+// commute: T' = J^T T J changes each 2 x 2 block (rows of pair i, columns of
+// pair j) independently, T'_ij = J_i^T T_ij J_j.  Each rotation is the one
+// of the classical Jacobi method that zeroes T[p][q] (Golub and Van Loan,
+// symmetric Schur decomposition of a 2 x 2 block).  T is read from Tin and
+// written to Tout (every entry, every step), so each workgroup can take all
+// rotation angles from Tin while the others write; V accumulates V J in
+// place (workgroup j owns columns p_j and q_j).
 // ---------------------------------------------------------------------------
 constexpr int JMAX = 1024;   // largest m
 
-__global__ __launch_bounds__(1024) void lr_jacobi(double* __restrict__ T, double* __restrict__ V, double* __restrict__ w,
-                                                  int m, int max_sweeps, double tol, int* __restrict__ sweeps_out)
+__device__ __forceinline__ void jacobi_pair(int i, int s, int mp, int& p, int& q) {
+    auto pos = [&](int j) { return j == 0 ? 0 : 1 + (j - 1 + s) % (mp - 1); };
+    p = pos(i);
+    q = pos(mp - 1 - i);
+    if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void lr_jacobi_step(const double* __restrict__ Tin, double* __restrict__ Tout,
+                                                      double* __restrict__ V, int m, int s)
 {
     __shared__ int sp[JMAX / 2], sq[JMAX / 2];
     __shared__ double sc[JMAX / 2], ss[JMAX / 2];
-    __shared__ double red[2][1024];
     const int tid = threadIdx.x;
     const int mp = (m + 1) & ~1;
     const int half = mp / 2;
-    for (int i = tid; i < m * m; i += 1024) V[i] = (i / m == i % m) ? 1.0 : 0.0;
+    for (int i = tid; i < half; i += 256) {
+        int p, q;
+        jacobi_pair(i, s, mp, p, q);
+        double c = 1.0, sn = 0.0;
+        if (q < m) {
+            const double apq = Tin[p * m + q];
+            if (apq != 0.0) {
+                const double app = Tin[p * m + p], aqq = Tin[q * m + q];
+                const double th = (aqq - app) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                c = 1.0 / sqrt(t * t + 1.0);
+                sn = t * c;
+            }
+        }
+        sp[i] = p;
+        sq[i] = q;   // q == m marks the padding index
+        sc[i] = c;
+        ss[i] = sn;
+    }
     __syncthreads();
-    int sweep = 0;
-    for (; sweep < max_sweeps; ++sweep) {
-        // convergence test: off-diagonal mass against the total
-        double off = 0.0, tot = 0.0;
-        for (int i = tid; i < m * m; i += 1024) {
-            const double v = T[i];
-            tot += v * v;
-            if (i / m != i % m) off += v * v;
-        }
-        red[0][tid] = off;
-        red[1][tid] = tot;
-        __syncthreads();
-        for (int st = 512; st > 0; st >>= 1) {
-            if (tid < st) {
-                red[0][tid] += red[0][tid + st];
-                red[1][tid] += red[1][tid + st];
-            }
-            __syncthreads();
-        }
-        const bool done = red[0][0] <= tol * tol * red[1][0];
-        __syncthreads();
-        if (done) break;
-        for (int s = 0; s < mp - 1; ++s) {
-            if (tid < half) {
-                auto pos = [&](int j) { return j == 0 ? 0 : 1 + (j - 1 + s) % (mp - 1); };
-                int p = pos(tid), q = pos(mp - 1 - tid);
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                double c = 1.0, sn = 0.0;
-                if (q < m) {
-                    const double apq = T[p * m + q];
-                    if (apq != 0.0) {
-                        const double app = T[p * m + p], aqq = T[q * m + q];
-                        const double th = (aqq - app) / (2.0 * apq);
-                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        sn = t * c;
-                    }
-                }
-                sp[tid] = p;
-                sq[tid] = q < m ? q : p;   // a skipped pair rotates nothing
-                sc[tid] = c;
-                ss[tid] = q < m ? sn : 0.0;
-            }
-            __syncthreads();
-            // rows: T <- J^T T
-            for (int idx = tid; idx < half * m; idx += 1024) {
-                const int i = idx / m, j = idx % m;
-                const int p = sp[i], q = sq[i];
-                if (p == q) continue;
-                const double c = sc[i], sn = ss[i];
-                const double a = T[p * m + j], b = T[q * m + j];
-                T[p * m + j] = c * a - sn * b;
-                T[q * m + j] = sn * a + c * b;
-            }
-            __syncthreads();
-            // columns: T <- T J, and V <- V J
-            for (int idx = tid; idx < m * half; idx += 1024) {
-                const int r = idx / half, i = idx % half;
-                const int p = sp[i], q = sq[i];
-                if (p == q) continue;
-                const double c = sc[i], sn = ss[i];
-                const double a = T[r * m + p], b = T[r * m + q];
-                T[r * m + p] = c * a - sn * b;
-                T[r * m + q] = sn * a + c * b;
-                const double va = V[r * m + p], vb = V[r * m + q];
-                V[r * m + p] = c * va - sn * vb;
-                V[r * m + q] = sn * va + c * vb;
-            }
-            __syncthreads();
+    const int j = blockIdx.x;
+    const int pj = sp[j], qj = sq[j];
+    const double cj = sc[j], sj = ss[j];
+    const bool qv = qj < m;
+    for (int i = tid; i < half; i += 256) {
+        const int pi = sp[i], qi = sq[i];
+        const double ci = sc[i], si = ss[i];
+        const bool rv = qi < m;
+        // the block [[a, b], [c, d]] = rows (pi, qi) x columns (pj, qj)
+        double a = Tin[pi * m + pj];
+        double b = qv ? Tin[pi * m + qj] : 0.0;
+        double c = rv ? Tin[qi * m + pj] : 0.0;
+        double d = (rv && qv) ? Tin[qi * m + qj] : 0.0;
+        // rows: J_i^T
+        const double a1 = ci * a - si * c, c1 = si * a + ci * c;
+        const double b1 = ci * b - si * d, d1 = si * b + ci * d;
+        // columns: J_j
+        a = cj * a1 - sj * b1;
+        b = sj * a1 + cj * b1;
+        c = cj * c1 - sj * d1;
+        d = sj * c1 + cj * d1;
+        Tout[pi * m + pj] = a;
+        if (qv) Tout[pi * m + qj] = b;
+        if (rv) Tout[qi * m + pj] = c;
+        if (rv && qv) Tout[qi * m + qj] = d;
+    }
+    if (qv) {
+        for (int r = tid; r < m; r += 256) {
+            const double va = V[r * m + pj], vb = V[r * m + qj];
+            V[r * m + pj] = cj * va - sj * vb;
+            V[r * m + qj] = sj * va + cj * vb;
         }
     }
-    for (int i = tid; i < m; i += 1024) w[i] = T[i * m + i];
-    if (tid == 0) *sweeps_out = sweep;
 }
 
-// The k eigenpairs of largest |lambda| (ties by lower index), in decreasing
-// |lambda|: lam[t] and the columns Vk[:, t] = V[:, idx_t] (m x k).
-__global__ __launch_bounds__(256) void lr_select(const double* __restrict__ w, const double* __restrict__ V, int m, int k,
-                                                 double* __restrict__ lam, double* __restrict__ Vk)
+// V = I
+__global__ __launch_bounds__(256) void lr_identity(double* __restrict__ V, int m)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < m * m; i += gridDim.x * 256) V[i] = (i / m == i % m) ? 1.0 : 0.0;
+}
+
+// *done = 1 when the off-diagonal mass of T is at most tol^2 times the total;
+// w[i] = T[i][i]
+__global__ __launch_bounds__(1024) void lr_jacobi_check(const double* __restrict__ T, int m, double tol,
+                                                        int* __restrict__ done, double* __restrict__ w)
+{
+    __shared__ double red[2][1024];
+    const int tid = threadIdx.x;
+    double off = 0.0, tot = 0.0;
+    for (int i = tid; i < m * m; i += 1024) {
+        const double v = T[i];
+        tot += v * v;
+        if (i / m != i % m) off += v * v;
+    }
+    red[0][tid] = off;
+    red[1][tid] = tot;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (tid < st) {
+            red[0][tid] += red[0][tid + st];
+            red[1][tid] += red[1][tid + st];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *done = red[0][0] <= tol * tol * red[1][0] ? 1 : 0;
+    for (int i = tid; i < m; i += 1024) w[i] = T[i * m + i];
+}
+
+// The k eigenpairs of largest |lambda|, in decreasing |lambda| (ties by lower
+// index): index i takes place #{j : |w_j| > |w_i|, or equal with j < i}.
+__global__ __launch_bounds__(1024) void lr_select(const double* __restrict__ w, const double* __restrict__ V, int m,
+                                                  int k, double* __restrict__ lam, double* __restrict__ Vk)
 {
     __shared__ int sidx[MAXM];
-    if (threadIdx.x == 0) {
-        for (int t = 0; t < k; ++t) {
-            int best = -1;
-            for (int i = 0; i < m; ++i) {
-                bool taken = false;
-                for (int u = 0; u < t; ++u) taken = taken || sidx[u] == i;
-                if (taken) continue;
-                if (best < 0 || fabs(w[i]) > fabs(w[best])) best = i;
-            }
-            sidx[t] = best;
-            lam[t] = w[best];
+    for (int i = threadIdx.x; i < m; i += 1024) {
+        const double ai = fabs(w[i]);
+        int r = 0;
+        for (int j = 0; j < m; ++j) {
+            const double aj = fabs(w[j]);
+            r += (aj > ai || (aj == ai && j < i)) ? 1 : 0;
+        }
+        if (r < k) {
+            sidx[r] = i;
+            lam[r] = w[i];
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m * k; e += 256) {
+    for (int e = threadIdx.x; e < m * k; e += 1024) {
         const int r = e / k, t = e % k;
         Vk[e] = V[r * m + sidx[t]];
     }
@@ -444,17 +464,40 @@ hipError_t lr_cvt(const float* a, double* b, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t lr_eig(double* T, double* V, double* w, int m, int max_sweeps, double tol, int* sweeps, hipStream_t s)
+hipError_t lr_eig(double* T, double* T2, double* V, double* w, int m, int max_sweeps, double tol, int* d_done,
+                  int* sweeps, hipStream_t s)
 {
     if (m < 1 || m > JMAX) return hipErrorInvalidValue;
-    lr_jacobi<<<1, 1024, 0, s>>>(T, V, w, m, max_sweeps, tol, sweeps);
-    return hipGetLastError();
+    lr_identity<<<(m * m + 255) / 256 < 4096 ? (m * m + 255) / 256 : 4096, 256, 0, s>>>(V, m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int mp = (m + 1) & ~1;
+    double* cur = T;
+    double* nxt = T2;
+    int sweep = 0;
+    for (; sweep <= max_sweeps; ++sweep) {
+        lr_jacobi_check<<<1, 1024, 0, s>>>(cur, m, tol, d_done, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        int done = 0;
+        if ((e = hipMemcpyAsync(&done, d_done, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        if (done || sweep == max_sweeps || mp < 2) break;
+        for (int st = 0; st < mp - 1; ++st) {
+            lr_jacobi_step<<<mp / 2, 256, 0, s>>>(cur, nxt, V, m, st);
+            double* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    *sweeps = sweep;
+    return hipSuccess;
 }
 
 hipError_t lr_topk(const double* w, const double* V, int m, int k, double* lam, double* Vk, hipStream_t s)
 {
     if (k < 1 || k > MAXM || k > m) return hipErrorInvalidValue;
-    lr_select<<<1, 256, 0, s>>>(w, V, m, k, lam, Vk);
+    lr_select<<<1, 1024, 0, s>>>(w, V, m, k, lam, Vk);
     return hipGetLastError();
 }
 

@@ -317,11 +317,13 @@ __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, c
     }
 }
 
-// load / store CPL consecutive columns of one row
+// load / store CPL consecutive columns of one row.  VEC: one 16-byte access
+// per lane; the caller guarantees b % 4 == 0 and 16-byte aligned rows, so a
+// lane with col0 < b owns four whole columns.
 template <int CPL, bool VEC, typename E>
 __device__ __forceinline__ void load_row(const E* __restrict__ row, int col0, int b, bool valid, E (&v)[CPL]) {
     if constexpr (VEC && CPL == 4 && sizeof(E) == 4) {
-        if (valid) {
+        if (valid && col0 < b) {
             const auto t = *reinterpret_cast<const uint4*>(row + col0);
             v[0] = __builtin_bit_cast(E, t.x); v[1] = __builtin_bit_cast(E, t.y);
             v[2] = __builtin_bit_cast(E, t.z); v[3] = __builtin_bit_cast(E, t.w);
@@ -340,7 +342,7 @@ __device__ __forceinline__ void store_row(E* __restrict__ row, int col0, int b, 
         uint4 t;
         t.x = __builtin_bit_cast(uint32_t, v[0]); t.y = __builtin_bit_cast(uint32_t, v[1]);
         t.z = __builtin_bit_cast(uint32_t, v[2]); t.w = __builtin_bit_cast(uint32_t, v[3]);
-        *reinterpret_cast<uint4*>(row + col0) = t;
+        if (col0 < b) *reinterpret_cast<uint4*>(row + col0) = t;
     } else {
 #pragma unroll
         for (int j = 0; j < CPL; ++j)

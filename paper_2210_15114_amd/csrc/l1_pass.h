@@ -568,7 +568,8 @@ hipError_t launch_shape(const L1PassArgs& a, int32_t b, hipStream_t s) {
     if ((size_t)ntiles * S::TILE_WORDS > a.record_words) return hipErrorInvalidValue;
     uint64_t* stat = a.records + (size_t)ntiles * 2 * 2 * P::WPV * BP;
     uint64_t* ctr = &a.chain->ticket[a.cls];
-    const bool vec = (b == BP) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
+    // 16-byte row accesses: whole 4-column groups, 16-byte aligned rows
+    const bool vec = (b % 4 == 0) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
     // one grid size per tile shape: every pass of a shape must use the same
     // grid, since the ticket count of a pass is ntiles + grid
     if constexpr (S::KEEP) {
