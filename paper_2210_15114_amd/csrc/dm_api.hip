@@ -730,21 +730,26 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
             const dm_status ms = dm_matvec(h, Zf, DM_F32, B, Yf, s);
             if (ms != DM_OK) return ms;
             DM_TRY(lr_cvt(Yf, Y, nb, s));
-            // Rayleigh-Ritz blocks T[i][j-1] = Q_i^T A Q_{j-1}, i < j
-            for (int i = 0; i < j; ++i)
-                DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, T + (size_t)i * B * K + (size_t)(j - 1) * B, K, 1.0, s));
+            // Block Gram-Schmidt against Q_0 .. Q_{j-1}, twice.  The first
+            // pass's coefficients Q_i^T (A Q_{j-1}) are the Rayleigh-Ritz blocks
+            // T[i][j-1] (the earlier subtractions change them only by the
+            // rounding-level overlap of the orthonormal blocks), so they are
+            // written straight into T.
+            for (int i = 0; i < j; ++i) {
+                double* Tij = T + (size_t)i * B * K + (size_t)(j - 1) * B;
+                DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, Tij, K, 1.0, s));
+                if (j < iters) DM_TRY(lr_update_rows(Y, B, Qb(i), B, Tij, K, -1.0, 1.0, n, s));
+            }
             if (j == iters) break;
-            // block Gram-Schmidt against Q_0 .. Q_{j-1}, twice
-            for (int pass = 0; pass < 2; ++pass)
-                for (int i = 0; i < j; ++i) {
-                    DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, C, B, -1.0, s));        // C = -Q_i^T Y
-                    DM_TRY(lr_update_rows(Y, B, B, Qb(i), B, B, C, B, 1.0, n, s));  // Y += Q_i C
-                }
+            for (int i = 0; i < j; ++i) {
+                DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, C, B, 1.0, s));
+                DM_TRY(lr_update_rows(Y, B, Qb(i), B, C, B, -1.0, 1.0, n, s));
+            }
             // Cholesky QR, twice
             for (int pass = 0; pass < 2; ++pass) {
                 DM_TRY(lr_gram(Y, B, Y, B, n, part, G, B, 1.0, s));
                 DM_TRY(lr_cholinv(G, B, rel, X, status, s));
-                DM_TRY(lr_update_rows(Y, B, B, Y, B, B, X, B, 0.0, n, s));
+                DM_TRY(lr_update_rows(Y, B, Y, B, X, B, 1.0, 0.0, n, s));
             }
             Qprev = Y;
         }
@@ -755,8 +760,7 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
         DM_TRY(lr_topk(w, V, K, rank, lam, Vk, s));
         // U = Q Vk, block by block
         for (int i = 0; i < iters; ++i)
-            DM_TRY(lr_update_rows(U, rank, rank, Qb(i), B, B, Vk + (size_t)i * B * rank, rank, i == 0 ? 0.0 : 1.0,
-                                  n, s));
+            DM_TRY(lr_update_rows(U, rank, Qb(i), B, Vk + (size_t)i * B * rank, rank, 1.0, i == 0 ? 0.0 : 1.0, n, s));
         return DM_OK;
     };
     dm_status st = run();

@@ -146,8 +146,8 @@ size_t lr_gram_scratch_doubles(int64_t n, int ma, int mb);
 // out[p * ldo + q] = scale * sum_r A[r][p] B[r][q]; part: lr_gram_scratch_doubles doubles
 hipError_t lr_gram(const double* A, int ma, const double* B, int mb, int64_t n, double* part, double* out,
                    int ldo, double scale, hipStream_t s);
-// Y = beta Y + Q C (Y may be Q when beta is 0)
-hipError_t lr_update_rows(double* Y, int ldy, int mb, const double* Q, int ldq, int ma, const double* C, int ldc,
+// Y = beta Y + alpha Q C; Y n x mb, Q n x ma, C ma x ldc (Y may be Q when beta is 0)
+hipError_t lr_update_rows(double* Y, int mb, const double* Q, int ma, const double* C, int ldc, double alpha,
                           double beta, int64_t n, hipStream_t s);
 hipError_t lr_cholinv(const double* G, int m, double rel, double* X, uint32_t* status, hipStream_t s);
 hipError_t lr_symm(double* T, int m, int bw, hipStream_t s);

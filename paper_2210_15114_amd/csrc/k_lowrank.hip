@@ -8,7 +8,7 @@
 //   * lr_gram_partial / lr_reduce - C = A^T B of two n x m blocks, split over
 //     rows into fixed per-block partial sums and reduced in a fixed order
 //     (bit-reproducible run to run);
-//   * lr_update   - Y = beta Y + Q C, row by row (block Gram-Schmidt updates,
+//   * lr_update   - Y = beta Y + alpha Q C, row by row (block Gram-Schmidt updates,
 //     Y R^-1 of Cholesky QR, and U = Q V of the final step);
 //   * lr_chol     - the orthonormalising factor of Cholesky QR for a small
 //     Gram matrix (column-equilibrated), dropping dependent columns;
@@ -28,14 +28,18 @@ namespace {
 
 constexpr int GT = 64;     // rows per LDS tile
 constexpr int MAXM = 64;   // widest block
-constexpr int64_t LR_ROWS_PER_BLK = 4096;   // rows per partial Gram product
+constexpr int64_t LR_ROWS_PER_BLK = 1024;   // rows per partial Gram product
 
 // ---------------------------------------------------------------------------
 // C_part[blk] = sum over the block's rows r of A[r][p] * B[r][q]
-// A: n x ma, B: n x mb, row-major.  Each thread owns a 4 x 4 block of (p, q)
-// entries and a share of the rows of each tile; row shares are added in a
-// fixed order at the end.
+// A: n x ma, B: n x mb, row-major.  Tiles of GT rows are contiguous in
+// memory and are read flat (coalesced), one tile ahead into registers while
+// the current tile is multiplied out of LDS.  Each thread owns a 4 x 4 block
+// of (p, q) entries and a share of the rows of each tile; row shares are
+// added in a fixed order at the end.
 // ---------------------------------------------------------------------------
+constexpr int TPT = GT * MAXM / 256;   // tile doubles per thread
+
 __global__ __launch_bounds__(256) void lr_gram_partial(const double* __restrict__ A, int ma,
                                                        const double* __restrict__ B, int mb, int64_t n,
                                                        int64_t rows_per_blk, double* __restrict__ part)
@@ -50,6 +54,11 @@ __global__ __launch_bounds__(256) void lr_gram_partial(const double* __restrict_
     const int e = tid % ne, g = tid / ne;
     const bool active = tid < ne * groups;
     const int p0 = (e / pb) * 4, q0 = (e % pb) * 4;
+    // columns ma.. and mb.. up to the next multiple of 4 are read as zeros
+    for (int i = tid; i < GT * (MAXM + 4); i += 256) {
+        (&sA[0][0])[i] = 0.0;
+        (&sB[0][0])[i] = 0.0;
+    }
     double acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -57,14 +66,31 @@ __global__ __launch_bounds__(256) void lr_gram_partial(const double* __restrict_
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
     const int64_t rb = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t re = rb + rows_per_blk < n ? rb + rows_per_blk : n;
+    double ra[TPT], rbv[TPT];
+    auto fetch = [&](int64_t r0) {
+        const int nr = (int)(re - r0 < GT ? re - r0 : GT);
+        const double* a0 = A + r0 * ma;
+        const double* b0 = B + r0 * mb;
+        const int na = nr * ma, nb = nr * mb;
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const int i = tid + 256 * k;
+            ra[k] = i < na ? a0[i] : 0.0;
+            rbv[k] = i < nb ? b0[i] : 0.0;
+        }
+    };
+    if (rb < re) fetch(rb);
     for (int64_t r0 = rb; r0 < re; r0 += GT) {
         const int nr = (int)(re - r0 < GT ? re - r0 : GT);
-        for (int i = tid; i < GT * MAXM; i += 256) {
-            const int r = i / MAXM, c = i % MAXM;
-            sA[r][c] = (r < nr && c < ma) ? A[(r0 + r) * ma + c] : 0.0;
-            sB[r][c] = (r < nr && c < mb) ? B[(r0 + r) * mb + c] : 0.0;
+        __syncthreads();   // the previous tile is no longer read
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const int i = tid + 256 * k;
+            if (i < nr * ma) sA[i / ma][i % ma] = ra[k];
+            if (i < nr * mb) sB[i / mb][i % mb] = rbv[k];
         }
         __syncthreads();
+        if (r0 + GT < re) fetch(r0 + GT);
         if (active) {
             for (int r = g; r < nr; r += groups) {
                 double a[4], bq[4];
@@ -79,8 +105,8 @@ __global__ __launch_bounds__(256) void lr_gram_partial(const double* __restrict_
                     for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bq[j], acc[i][j]);
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
     // add the row shares in group order
     double* red = &sA[0][0];   // GT * (MAXM + 4) >= 256 * 16 doubles
     if (active) {
@@ -105,56 +131,86 @@ __global__ __launch_bounds__(256) void lr_gram_partial(const double* __restrict_
     }
 }
 
-// out[p * ldo + q] = scale * sum_blk part[blk][p][q], blocks added in order
+// out[p * ldo + q] = scale * sum_blk part[blk][p][q].  A workgroup owns 32
+// entries; its 8 thread groups add blocks g, g + 8, g + 16, ... in order and
+// the 8 group sums are then added in group order (a fixed order).
 __global__ __launch_bounds__(256) void lr_reduce(const double* __restrict__ part, int nblk, int ma, int mb,
                                                  double* __restrict__ out, int ldo, double scale)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= ma * mb) return;
+    __shared__ double red[8][32];
+    const int t = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + t;
+    const int cnt = ma * mb;
     double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += part[(size_t)k * ma * mb + e];
-    out[(size_t)(e / mb) * ldo + (e % mb)] = scale * s;
+    if (e < cnt)
+        for (int k = g; k < nblk; k += 8) s += part[(size_t)k * cnt + e];
+    red[g][t] = s;
+    __syncthreads();
+    if (g == 0 && e < cnt) {
+        double v = red[0][t];
+        for (int gg = 1; gg < 8; ++gg) v += red[gg][t];
+        out[(size_t)(e / mb) * ldo + (e % mb)] = scale * v;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Y[r][q] = beta * Y[r][q] + sum_p Q[r][p] C[p][q]   (q < mb, p < ma)
-// Y: n x ldy (columns 0..mb-1 written), Q: n x ldq, C: ma x ldc.  A workgroup
-// owns 64 rows; it stages its Q rows in LDS before writing Y, so Y may be Q
-// (in-place right multiplication).
+// Y = beta Y + alpha Q C, row by row: Y n x mb (leading dimension mb), Q n x
+// ma, C ma x ldc.  A workgroup owns GT rows: it reads its Q rows flat into
+// LDS, forms the products there, and writes its Y rows flat, so Y may be Q
+// (in-place right multiplication, beta = 0).  LDS is sized by the launch to
+// ma and mb (dynamic), so narrow blocks leave room for more workgroups.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void lr_update(double* Y, int ldy, int mb,
-                                                 const double* Q, int ldq, int ma,
-                                                 const double* __restrict__ C, int ldc, double beta, int64_t n)
+__global__ __launch_bounds__(256) void lr_update(double* Y, int mb, const double* Q, int ma,
+                                                 const double* __restrict__ C, int ldc, double alpha, double beta,
+                                                 int64_t n)
 {
-    __shared__ double sC[MAXM][MAXM + 1];
-    __shared__ double sQ[GT][MAXM + 1];
+    extern __shared__ double lds[];
+    const int lq = (ma > mb ? ma : mb) + 1;   // row stride of the Q / result tile
+    const int lc = mb + 1;                    // row stride of C
+    double* sQ = lds;                         // GT x lq
+    double* sC = lds + GT * lq;               // ma x lc
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * GT;
-    for (int i = tid; i < MAXM * MAXM; i += 256) {
-        const int p = i / MAXM, q = i % MAXM;
-        sC[p][q] = (p < ma && q < mb) ? C[(size_t)p * ldc + q] : 0.0;
-    }
-    for (int i = tid; i < GT * MAXM; i += 256) {
-        const int r = i / MAXM, c = i % MAXM;
-        sQ[r][c] = (r0 + r < n && c < ma) ? Q[(r0 + r) * ldq + c] : 0.0;
+    const int nr = (int)(n - r0 < GT ? n - r0 : GT);
+    for (int i = tid; i < ma * mb; i += 256) sC[(i / mb) * lc + (i % mb)] = alpha * C[(size_t)(i / mb) * ldc + (i % mb)];
+    {
+        const double* q0 = Q + r0 * ma;
+        const int nq = nr * ma;
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const int i = tid + 256 * k;
+            if (i < nq) sQ[(i / ma) * lq + (i % ma)] = q0[i];
+        }
     }
     __syncthreads();
     const int rr = tid >> 2, cg = tid & 3;
-    const int64_t row = r0 + rr;
-    if (row >= n) return;
     double out[MAXM / 4];
 #pragma unroll
     for (int k = 0; k < MAXM / 4; ++k) out[k] = 0.0;
-    for (int p = 0; p < ma; ++p) {
-        const double qv = sQ[rr][p];
+    if (rr < nr) {
+        for (int p = 0; p < ma; ++p) {
+            const double qv = sQ[rr * lq + p];
 #pragma unroll
-        for (int k = 0; k < MAXM / 4; ++k) out[k] = fma(qv, sC[p][cg + 4 * k], out[k]);
+            for (int k = 0; k < MAXM / 4; ++k)
+                if (cg + 4 * k < mb) out[k] = fma(qv, sC[p * lc + cg + 4 * k], out[k]);
+        }
     }
-    double* y = Y + row * ldy;
+    __syncthreads();   // all reads of sQ are done: it now holds the results
+    if (rr < nr) {
 #pragma unroll
-    for (int k = 0; k < MAXM / 4; ++k) {
-        const int q = cg + 4 * k;
-        if (q < mb) y[q] = beta == 0.0 ? out[k] : fma(beta, y[q], out[k]);
+        for (int k = 0; k < MAXM / 4; ++k)
+            if (cg + 4 * k < mb) sQ[rr * lq + cg + 4 * k] = out[k];
+    }
+    __syncthreads();
+    double* y0 = Y + r0 * mb;
+    const int ny = nr * mb;
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int i = tid + 256 * k;
+        if (i < ny) {
+            const double v = sQ[(i / mb) * lq + (i % mb)];
+            y0[i] = beta == 0.0 ? v : fma(beta, y0[i], v);
+        }
     }
 }
 
@@ -424,15 +480,17 @@ hipError_t lr_gram(const double* A, int ma, const double* B, int mb, int64_t n, 
     lr_gram_partial<<<(unsigned)nblk, 256, 0, s>>>(A, ma, B, mb, n, LR_ROWS_PER_BLK, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    lr_reduce<<<(ma * mb + 255) / 256, 256, 0, s>>>(part, (int)nblk, ma, mb, out, ldo, scale);
+    lr_reduce<<<(ma * mb + 31) / 32, 256, 0, s>>>(part, (int)nblk, ma, mb, out, ldo, scale);
     return hipGetLastError();
 }
 
-hipError_t lr_update_rows(double* Y, int ldy, int mb, const double* Q, int ldq, int ma, const double* C, int ldc,
+hipError_t lr_update_rows(double* Y, int mb, const double* Q, int ma, const double* C, int ldc, double alpha,
                           double beta, int64_t n, hipStream_t s)
 {
     if (ma < 1 || mb < 1 || ma > MAXM || mb > MAXM || n < 1) return hipErrorInvalidValue;
-    lr_update<<<(unsigned)((n + GT - 1) / GT), 256, 0, s>>>(Y, ldy, mb, Q, ldq, ma, C, ldc, beta, n);
+    const int lq = (ma > mb ? ma : mb) + 1;
+    const size_t lds = ((size_t)GT * lq + (size_t)ma * (mb + 1)) * sizeof(double);
+    lr_update<<<(unsigned)((n + GT - 1) / GT), 256, lds, s>>>(Y, mb, Q, ma, C, ldc, alpha, beta, n);
     return hipGetLastError();
 }
 
