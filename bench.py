@@ -10,6 +10,12 @@ Z = n x 64 right-hand sides N(0, 1) in FP32 (seeded, synthetic).
   and reported as prep_ms.
 * single-vector form: 64 sequential b = 1 queries on the 64 columns.
 * l2 squared: one b = 64 query of the low-rank form (Algorithm 3).
+* tuned_variants: the pass tile variant the library's tuner chose for b = 64
+  and b = 1 on this data, with the timed pass of every variant.
+* multi: 512 datasets of uneven n and d (float and integer), b = 8, one
+  captured-graph launch per query, with oracle spot checks.
+* lowrank: rank-32 block-Krylov approximation at n = 2^21, d = 32 (block 40,
+  8 iterations, 9 queries).
 * roofline: algorithmic bytes of one coordinate pass, 12 n b + 8 n (perm and
   sorted values read once, the Z rows gathered once, the Out rows read and
   written once), over the pass kernel's mean device time from HIP events on
@@ -64,6 +70,38 @@ def read_traffic(variant):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def run_lowrank(args, dm, synth, np, torch, dev):
+    """Rank-32 block-Krylov approximation of the l1 matrix at n = 2^21, d = 32
+    (50-component Gaussian mixture), block 40, 8 iterations: wall time of one
+    call (after one warm-up call), orthonormality of U, and the residual of
+    the top Ritz pair through one more query."""
+    n, d, k, block, iters = 1 << 21, 32, 32, 40, 8
+    X = synth.workload5(n, d)
+    om = synth.rhs_normal(n, block, synth.seeds(5)["Z"], np.float64)
+    Xd = torch.from_numpy(X).to(dev)
+    omd = torch.from_numpy(om).to(dev)
+    h = dm.prepare(Xd, dm.L1)
+    v, _ = h.tune(block, reps=3)
+    h.lowrank(k, omd, iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U, lam, sweeps = h.lowrank(k, omd, iters)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    orth = float((U.t() @ U - torch.eye(k, dtype=torch.float64, device=dev)).abs().max())
+    u1 = U[:, 0].float().contiguous()
+    y1 = h.matvec(u1)
+    h.sync()
+    l1 = float(lam[0])
+    resid = float(torch.linalg.vector_norm(y1.double() - l1 * u1.double()) / abs(l1))
+    h.free()
+    log("lowrank: %.1f ms (n=%d, rank %d, block %d, %d iterations), sweeps %d, orth %.2e, top residual %.2e" %
+        (ms, n, k, block, iters, sweeps, orth, resid))
+    return {"n": n, "d": d, "rank": k, "block": block, "iters": iters, "ms": round(ms, 1), "queries": iters + 1,
+            "jacobi_sweeps": sweeps, "orthonormality": orth, "top_ritz_residual": resid, "lam_top": l1,
+            "pass_variant": v}
 
 
 def pass_kernel_name(variant, b):
@@ -146,6 +184,7 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="skip the single-vector leg")
     ap.add_argument("--no-l2", action="store_true", help="skip the l2-squared leg")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-dataset leg")
+    ap.add_argument("--no-lowrank", action="store_true", help="skip the block-Krylov low-rank leg")
     ap.add_argument("--multi-count", type=int, default=512)
     args = ap.parse_args()
 
@@ -289,6 +328,11 @@ def main():
     if not args.no_multi:
         multi = run_multi(args, dm, synth, np, torch, dev, stream)
 
+    # ---- block-Krylov low rank ----
+    lowrank = None
+    if not args.no_lowrank:
+        lowrank = run_lowrank(args, dm, synth, np, torch, dev)
+
     # ---- CPU oracle on a bounded sample (and the accuracy of the GPU result there) ----
     cpu = None
     errors = None
@@ -346,6 +390,7 @@ def main():
         "totals_ms_per_step": round(tot_ms / max(args.steps, 1), 4),
         "l2sq": l2,
         "multi": multi,
+        "lowrank": lowrank,
         "errors": errors,
     }
     print(json.dumps(result), flush=True)
