@@ -867,6 +867,7 @@ struct MultiSet {
 
 struct MultiPlan {
     int32_t b = 0;
+    bool vec = false;              // 16-byte row accesses (captured into the graph)
     int32_t rounds = 0;
     std::vector<int64_t> ntiles;   // [round][kind]
     std::vector<int> grids;
@@ -973,12 +974,13 @@ dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSe
 }
 
 // Build the round tables, record regions and the captured graph for b.
-dm_status build_plan(dm_handle* h, int32_t b) {
+dm_status build_plan(dm_handle* h, int32_t b, bool vec) {
     MultiState* m = h->multi;
     MultiPlan& p = m->plan;
     if (m->launched) DM_TRY(hipEventSynchronize(m->done));
     free_plan(p);
     p.b = b;
+    p.vec = vec;
     p.rounds = m->maxd;
     const int nsets = (int)m->sets.size();
     // per-dataset totals storage and descriptors
@@ -1038,7 +1040,7 @@ dm_status build_plan(dm_handle* h, int32_t b) {
             const size_t ix = (size_t)k * 2 + kind;
             if (p.ntiles[ix] == 0) continue;
             e = launch_multi_pass(kind == 1, b, m->d_ds, p.tiles[ix], p.ntiles[ix], k, p.tickets + ix, p.records[ix],
-                                  p.grids[ix], m->cap);
+                                  p.grids[ix], p.vec, m->cap);
         }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(m->cap, &g);
@@ -1255,8 +1257,12 @@ dm_status dm_matvec_multi(dm_handle* h, const void* const* Z, int32_t b, void* c
         const char* op = (const char*)Out[i];
         if (zp < op + ob && op < zp + zb) return DM_ERR_ARG;
     }
+    // 16-byte row accesses when every row of every dataset allows them; a
+    // plan captured for the other choice is rebuilt
+    bool vec = b % 4 == 0;
+    for (int i = 0; i < nsets && vec; ++i) vec = ((uintptr_t)Z[i] % 16 == 0) && ((uintptr_t)Out[i] % 16 == 0);
     dm_status st;
-    if (m->plan.b != b && (st = build_plan(h, b)) != DM_OK) return st;
+    if ((m->plan.b != b || m->plan.vec != vec) && (st = build_plan(h, b, vec)) != DM_OK) return st;
     // refresh the pointer table only when it changes (the previous launch's
     // upload must have run before the pinned mirror is rewritten)
     bool same = true;

@@ -136,8 +136,9 @@ int multi_grid(int64_t ntiles, int32_t b, bool is_int);
 int multi_totals_rows();
 hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nblocks, int ndatasets, int32_t b,
                                double* partials, uint32_t* status, hipStream_t s);
+// vec: 16-byte row accesses; needs b % 4 == 0 and 16-byte aligned Z and Out of every dataset
 hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
-                             int k, uint64_t* ticket, uint64_t* records, int grid, hipStream_t s);
+                             int k, uint64_t* ticket, uint64_t* records, int grid, bool vec, hipStream_t s);
 
 // ---- block-Krylov low rank (k_lowrank.hip) ---------------------------------
 int lr_max_block();

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(64) void multi_totals_stage2(const MultiDs* __restr
 // ---------------------------------------------------------------------------
 // one round: coordinate k of every dataset in the round's tile table
 // ---------------------------------------------------------------------------
-template <typename P, int BP, int R, int OC>
+template <typename P, int BP, int R, int OC, bool VEC>
 __global__ __launch_bounds__(256, 2) void multi_pass_kernel(const MultiDs* __restrict__ ds,
                                                          const MultiTile* __restrict__ tiles, int64_t ntiles,
                                                          int32_t k, int32_t b, uint64_t* __restrict__ ticket_ctr,
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256, 2) void multi_pass_kernel(const MultiDs* __res
             x[i] = valid ? xs[r0 + i] : typename P::X(0);
         }
 #pragma unroll
-        for (int i = 0; i < R; ++i) load_row<CPL, false>(Z + (size_t)p[i] * b, col0, b, r0 + i < n, g[i]);
+        for (int i = 0; i < R; ++i) load_row<CPL, VEC>(Z + (size_t)p[i] * b, col0, b, r0 + i < n, g[i]);
 
         L e0[CPL], e1[CPL];
 #pragma unroll
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256, 2) void multi_pass_kernel(const MultiDs* __res
 #pragma unroll
             for (int i = 0; i < OC; ++i) {
                 if (!first) {
-                    load_row<CPL, false>(Out + (size_t)p[i0 + i] * b, col0, b, r0 + i0 + i < n, o[i]);
+                    load_row<CPL, VEC>(Out + (size_t)p[i0 + i] * b, col0, b, r0 + i0 + i < n, o[i]);
                 } else {
 #pragma unroll
                     for (int j = 0; j < CPL; ++j) o[i][j] = P::ufirst(f[j]);
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256, 2) void multi_pass_kernel(const MultiDs* __res
                     l1[j] = P::lmac(l1[j], x[i0 + i], g[i0 + i][j]);
                     res[j] = P::oadd(o[i][j], P::out(l0[j], l1[j], x[i0 + i], f[j]));
                 }
-                if (r0 + i0 + i < n) store_row<CPL, false>(Out + (size_t)p[i0 + i] * b, col0, b, res);
+                if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + (size_t)p[i0 + i] * b, col0, b, res);
             }
         }
         if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
@@ -299,21 +299,33 @@ static int bpad2(int32_t b) {
 
 template <int BP, bool INT> static int mtile() { return Lay<BP>::NS * mr<BP, INT>(); }
 
-template <typename P, int BP>
+template <typename P, int BP, bool VEC>
 static const void* kfn() {
     constexpr bool INT = !std::is_same<P, FloatPath>::value;
-    return (const void*)multi_pass_kernel<P, BP, mr<BP, INT>(), moc<BP, mr<BP, INT>()>()>;
+    return (const void*)multi_pass_kernel<P, BP, mr<BP, INT>(), moc<BP, mr<BP, INT>()>(), VEC>;
 }
 
+// VEC: 16-byte row accesses (b % 4 == 0 and every Z and Out row 16-byte
+// aligned, checked by the caller for all datasets)
 template <typename P, int BP>
 static hipError_t launch_bp(const MultiDs* ds, const MultiTile* tiles, int64_t ntiles, int k, int32_t b,
-                            uint64_t* ctr, uint64_t* rec, int grid, hipStream_t s) {
+                            uint64_t* ctr, uint64_t* rec, int grid, bool vec, hipStream_t s) {
     constexpr bool INT = !std::is_same<P, FloatPath>::value;
     constexpr int R = mr<BP, INT>();
     constexpr int TILEW = 2 * 2 * P::WPV * BP;
     uint64_t* stat = rec + (size_t)ntiles * TILEW;
-    multi_pass_kernel<P, BP, R, moc<BP, R>()><<<grid, 256, 0, s>>>(ds, tiles, ntiles, k, b, ctr, rec, stat);
+    if (vec)
+        multi_pass_kernel<P, BP, R, moc<BP, R>(), true><<<grid, 256, 0, s>>>(ds, tiles, ntiles, k, b, ctr, rec, stat);
+    else
+        multi_pass_kernel<P, BP, R, moc<BP, R>(), false><<<grid, 256, 0, s>>>(ds, tiles, ntiles, k, b, ctr, rec, stat);
     return hipGetLastError();
+}
+
+template <typename P, int BP> static int occ2() {
+    int a = 0, c = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kfn<P, BP, false>(), 256, 0) != hipSuccess || a < 1) a = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, kfn<P, BP, true>(), 256, 0) != hipSuccess || c < 1) c = 1;
+    return a < c ? a : c;
 }
 
 }  // namespace
@@ -342,18 +354,18 @@ int multi_grid(int64_t ntiles, int32_t b, bool is_int) {
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     }
-    const void* fn = nullptr;
+    // the smaller occupancy of the two row-access variants, so that a plan's
+    // grid does not depend on which one it launches
+    int nb = 1;
     switch (bpad2(b)) {
-    case 1: fn = is_int ? kfn<IntPath<int32_t>, 1>() : kfn<FloatPath, 1>(); break;
-    case 2: fn = is_int ? kfn<IntPath<int32_t>, 2>() : kfn<FloatPath, 2>(); break;
-    case 4: fn = is_int ? kfn<IntPath<int32_t>, 4>() : kfn<FloatPath, 4>(); break;
-    case 8: fn = is_int ? kfn<IntPath<int32_t>, 8>() : kfn<FloatPath, 8>(); break;
-    case 16: fn = is_int ? kfn<IntPath<int32_t>, 16>() : kfn<FloatPath, 16>(); break;
-    case 32: fn = is_int ? kfn<IntPath<int32_t>, 32>() : kfn<FloatPath, 32>(); break;
-    default: fn = is_int ? kfn<IntPath<int32_t>, 64>() : kfn<FloatPath, 64>(); break;
+    case 1: nb = is_int ? occ2<IntPath<int32_t>, 1>() : occ2<FloatPath, 1>(); break;
+    case 2: nb = is_int ? occ2<IntPath<int32_t>, 2>() : occ2<FloatPath, 2>(); break;
+    case 4: nb = is_int ? occ2<IntPath<int32_t>, 4>() : occ2<FloatPath, 4>(); break;
+    case 8: nb = is_int ? occ2<IntPath<int32_t>, 8>() : occ2<FloatPath, 8>(); break;
+    case 16: nb = is_int ? occ2<IntPath<int32_t>, 16>() : occ2<FloatPath, 16>(); break;
+    case 32: nb = is_int ? occ2<IntPath<int32_t>, 32>() : occ2<FloatPath, 32>(); break;
+    default: nb = is_int ? occ2<IntPath<int32_t>, 64>() : occ2<FloatPath, 64>(); break;
     }
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 1;
     int64_t g = (int64_t)nb * cus;
     if (g > ntiles) g = ntiles;
     if (g < 1) g = 1;
@@ -373,14 +385,15 @@ hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nb
 }
 
 hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
-                             int k, uint64_t* ticket, uint64_t* records, int grid, hipStream_t s)
+                             int k, uint64_t* ticket, uint64_t* records, int grid, bool vec, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
+    if (vec && b % 4 != 0) return hipErrorInvalidValue;
     switch (bpad2(b)) {
-#define DM_MCASE(BP)                                                                                   \
-    case BP:                                                                                           \
-        return is_int ? launch_bp<IntPath<int32_t>, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, s) \
-                      : launch_bp<FloatPath, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, s);
+#define DM_MCASE(BP)                                                                                         \
+    case BP:                                                                                                 \
+        return is_int ? launch_bp<IntPath<int32_t>, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, s) \
+                      : launch_bp<FloatPath, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, s);
         DM_MCASE(1) DM_MCASE(2) DM_MCASE(4) DM_MCASE(8) DM_MCASE(16) DM_MCASE(32) DM_MCASE(64)
 #undef DM_MCASE
     default: return hipErrorInvalidValue;
