@@ -16,6 +16,9 @@ Z = n x 64 right-hand sides N(0, 1) in FP32 (seeded, synthetic).
   captured-graph launch per query, with oracle spot checks.
 * lowrank: rank-32 block-Krylov approximation at n = 2^21, d = 32 (block 40,
   8 iterations, 9 queries).
+* single_vector_mixture: the plain single-vector method at n = 2^20, d = 64
+  (32-component Gaussian mixture): 100 timed queries, median / p10 / p90, for
+  l1 and l2 squared, with errors against the oracle.
 * roofline: algorithmic bytes of one coordinate pass, 12 n b + 8 n (perm and
   sorted values read once, the Z rows gathered once, the Out rows read and
   written once), over the pass kernel's mean device time from HIP events on
@@ -104,6 +107,68 @@ def run_lowrank(args, dm, synth, np, torch, dev):
             "pass_variant": v}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def pct(sorted_vals, q):
+    """The q-quantile of sorted values (nearest rank)."""
+    i = min(len(sorted_vals) - 1, max(0, int(round(q * (len(sorted_vals) - 1)))))
+    return sorted_vals[i]
+
+
+def run_single_mixture(args, dm, synth, np, torch, dev, stream):
+    """The plain single-vector method on the mixture workload: n = 2^20,
+    d = 64, 32 Gaussians; 100 distinct z on the device; preparation timed
+    once; 10 warm-up and 100 timed single-vector queries (median, p10, p90)
+    for l1 and l2 squared; errors against the oracle on sampled rows."""
+    import oracle
+    from oracle import metrics
+    n, d, nq = 1 << 20, 64, 100
+    X, Z = synth.workload2(n, d, nq)
+    Xd = torch.from_numpy(X).to(dev)
+    Zc = torch.from_numpy(np.ascontiguousarray(Z.T)).to(dev)      # nq x n: row q is query q
+    res = {"n": n, "d": d, "queries": nq}
+    rows = synth.subsample_rows(n, 8, synth.seeds(2)["sub"])
+    for name, metric in (("l1", dm.L1), ("l2sq", dm.L2SQ)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = dm.prepare(Xd, metric)
+        prep_ms = (time.perf_counter() - t0) * 1e3
+        if metric == dm.L1:
+            h.tune(1, reps=4)
+        out = torch.empty(n, dtype=torch.float32, device=dev)
+        for i in range(10):
+            h.matvec(Zc[i % nq], out=out)
+        h.sync()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nq)]
+        for q in range(nq):
+            evs[2 * q].record(stream)
+            h.matvec(Zc[q], out=out)
+            evs[2 * q + 1].record(stream)
+        torch.cuda.synchronize()
+        h.sync()
+        t = sorted(evs[2 * q].elapsed_time(evs[2 * q + 1]) for q in range(nq))
+        y = out.cpu().numpy().astype(np.float64)      # the result of the last query
+        z = Z[:, nq - 1].astype(np.float64)[:, None]
+        o, rn, ad = oracle.matvec(X.astype(np.float64), z, oracle.L1 if metric == dm.L1 else oracle.L2SQ, rows)
+        frob = metrics.frob_from_rows(rn, n) if metric == dm.L1 else metrics.frob_l2sq(X.astype(np.float64))
+        err = metrics.errors(y[rows][:, None], o, rn, ad, z, frob)
+        res[name] = {"prep_ms": round(prep_ms, 1), "median_ms": round(pct(t, 0.5), 4), "p10_ms": round(pct(t, 0.1), 4),
+                     "p90_ms": round(pct(t, 0.9), 4), "columns_per_s": round(1e3 / pct(t, 0.5), 1),
+                     "error_spec": err["spec"], "error_per_row": err["per_row"]}
+        log("mixture single-vector %s: median %.3f ms (p10 %.3f, p90 %.3f), prep %.1f ms, error %.2e" %
+            (name, pct(t, 0.5), pct(t, 0.1), pct(t, 0.9), prep_ms, err["spec"]))
+        h.free()
+    return res
+
+
 def pass_kernel_name(variant, b):
     """Kernel of a float l1 pass variant: 0/1 the keep kernel, 2/3 the
     re-gathering kernel; odd variants halve the ranks per slot."""
@@ -174,8 +239,8 @@ def run_multi(args, dm, synth, np, torch, dev, stream):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 22)
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--b", type=int, default=64)
@@ -185,6 +250,7 @@ def main():
     ap.add_argument("--no-l2", action="store_true", help="skip the l2-squared leg")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-dataset leg")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the block-Krylov low-rank leg")
+    ap.add_argument("--no-mixture", action="store_true", help="skip the single-vector mixture leg")
     ap.add_argument("--multi-count", type=int, default=512)
     args = ap.parse_args()
 
@@ -246,16 +312,18 @@ def main():
     h.sync()
     torch.cuda.synchronize()
     h.profile(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         h.matvec(Zd, out=Out)
-    e1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     h.sync()
-    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step = evs[0].elapsed_time(evs[-1]) / args.steps
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    median_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else 0.5 * (step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2])
     pass_ms, pass_n = h.profile_read(dm.K_L1_PASS)
     tot_ms, tot_n = h.profile_read(dm.K_TOTALS)
     h.profile(False)
@@ -266,8 +334,11 @@ def main():
 
     bytes_pass = 12.0 * n * b + 8.0 * n
     achieved = bytes_pass / (avg_pass_ms * 1e-3) / 1e9
+    traffic = read_traffic(vb)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": read_traffic(vb),
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "achievable_GBps": round(copy_gbps, 1), "frac_of_achievable": round(achieved / copy_gbps, 4),
+                "measured_GBps": round(traffic / (avg_pass_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "kernel": pass_kernel_name(vb, b), "variant": vb, "bytes_per_launch": bytes_pass,
                 "avg_launch_ms": round(avg_pass_ms, 4), "launches": pass_n}
 
@@ -328,6 +399,11 @@ def main():
     if not args.no_multi:
         multi = run_multi(args, dm, synth, np, torch, dev, stream)
 
+    # ---- plain single-vector method on the mixture workload ----
+    mixture = None
+    if not args.no_mixture:
+        mixture = run_single_mixture(args, dm, synth, np, torch, dev, stream)
+
     # ---- block-Krylov low rank ----
     lowrank = None
     if not args.no_lowrank:
@@ -353,7 +429,7 @@ def main():
         o, rn, ad = oracle.matvec(X64, Z64, oracle.L1, rows)
         t_or = time.perf_counter() - t0
         cols_cpu = b / (t_or * n / rows.size)
-        cpu = {"value": cols_cpu, "unit": "columns/s", "cores": threads, "kind": "oracle",
+        cpu = {"value": cols_cpu, "unit": "columns/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
                "sample": "%d of %d rows (uniform seeded sample plus the scan-boundary points), all %d columns, "
                          "%.1f s; extrapolated by n/rows" % (rows.size, n, b, t_or)}
         frob = metrics.frob_from_rows(rn, n)
@@ -372,6 +448,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
+        "median_ms_per_step": round(median_ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -391,6 +468,7 @@ def main():
         "l2sq": l2,
         "multi": multi,
         "lowrank": lowrank,
+        "single_vector_mixture": mixture,
         "errors": errors,
     }
     print(json.dumps(result), flush=True)
