@@ -223,6 +223,27 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
                      double* lam, void* stream, int32_t* sweeps);
 
 /*
+ * Approximate l2 distance products (Appendix A.4: the Gaussian embedding
+ * theorem, the preprocessing of Algorithm 10 and the approximate l2 theorem).
+ * Writes the embedded points
+ *     Xout[i][t] = (1 / (beta k)) sum_j G[t][j] X[i][j],  beta = sqrt(2/pi),
+ * so that ||Xout_i - Xout_j||_1 approximates ||x_i - x_j||_2 (relative error
+ * about 0.76 / sqrt(k) per entry for Gaussian G).  The caller then prepares
+ * Xout with the l1 metric (dm_prepare, d = k) and queries it with dm_matvec;
+ * that handle answers B z with B_ij = ||Xout_i - Xout_j||_1.
+ *
+ * X: device n x d, dtype DM_F32 / DM_F64 / DM_I32 / DM_I64 (row-major).
+ * G: device k x d FP64 with iid N(0, 1) entries, drawn by the caller (the
+ * library draws no random numbers).  Xout: device n x k FP32 (out), must not
+ * overlap X.  1 <= k <= 65536.  Accumulation is FP64, rounded once to FP32.
+ * Stream-ordered and asynchronous; non-finite X gives non-finite Xout, which
+ * dm_prepare then rejects.
+ * Errors: DM_ERR_ARG (NULL pointers, sizes, dtype, overlap), DM_ERR_DEVICE.
+ */
+dm_status dm_embed_l2(const void* X, int64_t n, int32_t d, int32_t dtype, const double* G, int32_t k, float* Xout,
+                      void* stream);
+
+/*
  * Measurement support.  While profiling is on, every launch of the listed
  * kernel classes is bracketed by HIP events on the query stream;
  * dm_profile_read waits for them and returns the summed device time and the

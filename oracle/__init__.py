@@ -22,6 +22,7 @@ Contents
                       reading that uses sum_j y_j and sum_j y_j ||x_j||^2.
 * ``metrics``       - error metrics and norms used to judge a result.
 * ``lowrank``       - FP64 references for the low-rank application (Appendix C).
+* ``approx_l2``     - FP64 references for the approximate l2 query (Appendix A.4).
 
 Readings of the paper that the oracle fixes (the paper is silent or garbled
 there) are listed in the repository's design notes; each function cites the
@@ -304,3 +305,4 @@ def alg3_query(X, y):
 
 from . import metrics  # noqa: E402  (re-export)
 from . import lowrank  # noqa: E402
+from . import approx_l2  # noqa: E402

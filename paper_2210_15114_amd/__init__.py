@@ -97,6 +97,8 @@ def lib():
     L.dm_get_variant.restype = i32
     L.dm_lowrank.argtypes = [P, i32, i32, i32, P, P, P, P, ctypes.POINTER(i32)]
     L.dm_lowrank.restype = i32
+    L.dm_embed_l2.argtypes = [P, i64, i32, i32, P, i32, P, P]
+    L.dm_embed_l2.restype = i32
     _lib = L
     return L
 
@@ -276,6 +278,30 @@ class Handle:
             self.free()
         except Exception:
             pass
+
+
+def embed_l2(X, G, stream=None):
+    """Embedded points X' (n x k float32) = (1 / (beta k)) X G^T, beta = sqrt(2/pi).
+
+    X: n x d device tensor; G: k x d float64 device tensor of iid N(0,1).  The
+    l1 distance matrix of X' approximates the l2 distance matrix of X."""
+    torch = _torch()
+    if X.dim() != 2 or G.dim() != 2 or G.shape[1] != X.shape[1] or G.dtype != torch.float64:
+        raise ValueError("X must be n x d and G a k x d float64 tensor")
+    n, d = X.shape
+    k = G.shape[0]
+    out = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    _check(lib().dm_embed_l2(_dev_ptr(X, "X"), n, d, _dtype_code(X.dtype), _dev_ptr(G, "G"), k, _dev_ptr(out, "out"),
+                             _stream_ptr(stream)), "dm_embed_l2")
+    return out
+
+
+def prepare_l2_approx(X, G, stream=None) -> "Handle":
+    """Handle whose queries approximate products with the l2 distance matrix of
+    X: the l1 path on the embedded points embed_l2(X, G)."""
+    Xe = embed_l2(X, G, stream)
+    h = prepare(Xe, L1, stream)
+    return h
 
 
 def prepare(X, metric: int = L1, stream=None) -> Handle:

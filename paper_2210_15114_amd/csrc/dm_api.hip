@@ -772,6 +772,20 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     return dm_sync(h);
 }
 
+dm_status dm_embed_l2(const void* X, int64_t n, int32_t d, int32_t dtype, const double* G, int32_t k, float* Xout,
+                      void* stream) {
+    if (!X || !G || !Xout || n < 1 || d < 1 || k < 1 || k > 65536 || !valid_dtype(dtype)) return DM_ERR_ARG;
+    const char* xp = (const char*)X;
+    const char* op = (const char*)Xout;
+    const size_t xb = (size_t)n * d * dtype_size(dtype), ob = (size_t)n * k * sizeof(float);
+    if (xp < op + ob && op < xp + xb) return DM_ERR_ARG;   // overlap
+    int dev = 0;
+    const dm_status st = device_ready(&dev);
+    if (st != DM_OK) return st;
+    DM_TRY(launch_embed_l2(dtype, X, n, d, G, k, Xout, (hipStream_t)stream));
+    return DM_OK;
+}
+
 dm_status dm_sync(dm_handle* h) {
     if (!h) return DM_ERR_ARG;
     if (hipStreamSynchronize(h->last) != hipSuccess) return DM_ERR_DEVICE;

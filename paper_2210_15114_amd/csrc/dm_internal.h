@@ -161,6 +161,11 @@ hipError_t lr_eig(double* T, double* T2, double* V, double* w, int m, int max_sw
                   int* sweeps, hipStream_t s);
 hipError_t lr_topk(const double* w, const double* V, int m, int k, double* lam, double* Vk, hipStream_t s);
 
+// ---- Gaussian embedding for approximate l2 queries (k_embed.hip) -----------
+// Xout (n x k FP32) = (1 / (beta k)) X G^T, beta = sqrt(2/pi); kind: InKind of X
+hipError_t launch_embed_l2(int kind, const void* X, int64_t n, int32_t d, const double* G, int32_t k, float* Xout,
+                           hipStream_t s);
+
 // ---- l2 squared query ------------------------------------------------------
 size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b);
 hipError_t launch_l2sq(bool is_int, int zkind, const void* Xc, const void* nrm, int64_t n, int32_t d,

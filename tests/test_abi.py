@@ -87,6 +87,18 @@ def test_null_handle_calls(L):
     assert L.dm_set_variant(None, 8, dm.F32, 0) == dm.ERR_ARG
     assert L.dm_get_variant(None, 8, dm.F32, None) == dm.ERR_ARG
     assert L.dm_lowrank(None, 32, 40, 8, None, None, None, None, None) == dm.ERR_ARG
+    assert L.dm_embed_l2(None, 10, 2, dm.F32, None, 4, None, None) == dm.ERR_ARG
+
+
+def test_embed_argument_errors_before_device(L):
+    X, G, O = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x40000)
+    assert L.dm_embed_l2(X, 0, 2, dm.F32, G, 4, O, None) == dm.ERR_ARG        # n
+    assert L.dm_embed_l2(X, 10, 2, dm.F32, G, 0, O, None) == dm.ERR_ARG       # k
+    assert L.dm_embed_l2(X, 10, 2, dm.F32, G, 70000, O, None) == dm.ERR_ARG   # k too large
+    assert L.dm_embed_l2(X, 10, 2, 99, G, 4, O, None) == dm.ERR_ARG           # dtype
+    assert L.dm_embed_l2(X, 10, 2, dm.F32, G, 4, X, None) == dm.ERR_ARG       # overlap
+    if not _has_gpu():
+        assert L.dm_embed_l2(X, 10, 2, dm.F32, G, 4, O, None) == dm.ERR_DEVICE
     L.dm_free(None)
 
 

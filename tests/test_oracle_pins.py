@@ -326,3 +326,38 @@ def test_block_krylov_recovers_l2sq_matrix_of_rank_d_plus_2(oracle_mod):
     assert np.linalg.matrix_rank(A) == 4
     U, lam = lowrank.block_krylov(lambda W: A @ W, 200, 4, 4, 2, g.standard_normal((200, 4)))
     assert lowrank.approx_error(A, U, lam) <= 1e-10 * np.linalg.norm(A)
+
+
+# ---------------------------------------------------------------------------
+# approximate l2 (Appendix A.4): the embedding constant and its concentration
+# ---------------------------------------------------------------------------
+def test_beta_is_the_mean_absolute_gaussian():
+    from scipy import integrate
+    from oracle import approx_l2
+    val, _ = integrate.quad(lambda x: abs(x) * np.exp(-0.5 * x * x) / np.sqrt(2 * np.pi), -np.inf, np.inf)
+    assert abs(approx_l2.BETA - val) < 1e-12
+
+
+def test_embedding_preserves_l2_norms_in_l1():
+    from oracle import approx_l2
+    g = np.random.default_rng(101)
+    X = g.standard_normal((5, 12)) * np.array([[1.0], [3.0], [0.01], [100.0], [7.0]])
+    G = g.standard_normal((40000, 12))
+    Y = approx_l2.embed(X, G)
+    ratio = np.abs(Y).sum(axis=1) / np.linalg.norm(X, axis=1)
+    # relative spread of one |g.x| / (beta ||x||) is sqrt(pi/2 - 1) = 0.755; over
+    # k = 40000 samples its mean is within 4 standard errors of 1 w.h.p.
+    assert np.all(np.abs(ratio - 1.0) < 4 * 0.755 / np.sqrt(40000))
+
+
+def test_embedded_l1_matrix_approximates_l2_matrix(oracle_mod):
+    from oracle import approx_l2
+    g = np.random.default_rng(202)
+    X = g.standard_normal((300, 10))
+    A = approx_l2.explicit_l2(X)
+    assert np.allclose(A, np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)), rtol=1e-12, atol=1e-12)
+    k = 2000
+    B = oracle_mod.explicit(approx_l2.embed(X, g.standard_normal((k, 10))), oracle_mod.L1)
+    rel = np.linalg.norm(A - B) / np.linalg.norm(A)
+    expect = np.sqrt(np.pi / 2 - 1) / np.sqrt(k)        # about 0.017
+    assert 0.5 * expect < rel < 1.5 * expect
