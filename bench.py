@@ -16,6 +16,8 @@ Z = n x 64 right-hand sides N(0, 1) in FP32 (seeded, synthetic).
   captured-graph launch per query, with oracle spot checks.
 * lowrank: rank-32 block-Krylov approximation at n = 2^21, d = 32 (block 40,
   8 iterations, 9 queries).
+* approx_l2: approximate Euclidean products through the l1 path on Gaussian
+  embeddings of the mixture points (k = 256): timings and the sampled error.
 * single_vector_mixture: the plain single-vector method at n = 2^20, d = 64
   (32-component Gaussian mixture): 100 timed queries, median / p10 / p90, for
   l1 and l2 squared, with errors against the oracle.
@@ -169,6 +171,52 @@ def run_single_mixture(args, dm, synth, np, torch, dev, stream):
     return res
 
 
+def run_approx_l2(args, dm, synth, np, torch, dev, stream):
+    """Approximate l2 products at n = 2^20, d = 64 (32-component mixture), k =
+    256 embedding rows: embedding, preparation of the embedded points, one
+    b = 64 query, and the relative Frobenius error of B against the exact
+    Euclidean matrix estimated from sampled rows."""
+    import oracle
+    from oracle import approx_l2
+    n, d, k, b = 1 << 20, 64, 256, 64
+    X, _ = synth.workload2(n, d, 1)
+    g = synth.rng(synth.seeds(2)["Z"] + 7)
+    G = g.standard_normal((k, d))
+    Z = synth.rhs_normal(n, b, synth.seeds(2)["Z"] + 8, np.float32)
+    Xd, Gd, Zd = torch.from_numpy(X).to(dev), torch.from_numpy(G).to(dev), torch.from_numpy(Z).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xe = dm.embed_l2(Xd, Gd)
+    torch.cuda.synchronize()
+    t_embed = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    h = dm.prepare(Xe, dm.L1)
+    t_prep = (time.perf_counter() - t0) * 1e3
+    h.tune(b, reps=3)
+    out = torch.empty((n, b), dtype=torch.float32, device=dev)
+    h.matvec(Zd, out=out)
+    h.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    reps = 3
+    for _ in range(reps):
+        h.matvec(Zd, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    h.sync()
+    ms = e0.elapsed_time(e1) / reps
+    h.free()
+    rows = synth.subsample_rows(n, 8, synth.seeds(2)["sub"] + 1)
+    A = approx_l2.explicit_l2(X, rows)
+    B = oracle.explicit(Xe.cpu().numpy(), oracle.L1, rows)
+    rel = float(np.linalg.norm(A - B) / np.linalg.norm(A))
+    log("approx l2: embed %.1f ms, prep %.1f ms, b=%d query %.2f ms, relative error %.4f (expected spread %.4f)" %
+        (t_embed, t_prep, b, ms, rel, np.sqrt(np.pi / 2 - 1) / np.sqrt(k)))
+    return {"n": n, "d": d, "k": k, "b": b, "embed_ms": round(t_embed, 2), "prep_ms": round(t_prep, 1),
+            "ms_per_query": round(ms, 3), "columns_per_s": round(b / (ms * 1e-3), 1),
+            "relative_frobenius_sampled_rows": rel, "expected_spread": float(np.sqrt(np.pi / 2 - 1) / np.sqrt(k))}
+
+
 def pass_kernel_name(variant, b):
     """Kernel of a float l1 pass variant: 0/1 the keep kernel, 2/3 the
     re-gathering kernel; odd variants halve the ranks per slot."""
@@ -251,6 +299,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-dataset leg")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the block-Krylov low-rank leg")
     ap.add_argument("--no-mixture", action="store_true", help="skip the single-vector mixture leg")
+    ap.add_argument("--no-approx-l2", action="store_true", help="skip the approximate l2 leg")
     ap.add_argument("--multi-count", type=int, default=512)
     args = ap.parse_args()
 
@@ -404,6 +453,11 @@ def main():
     if not args.no_mixture:
         mixture = run_single_mixture(args, dm, synth, np, torch, dev, stream)
 
+    # ---- approximate l2 through the l1 path ----
+    approx = None
+    if not args.no_approx_l2:
+        approx = run_approx_l2(args, dm, synth, np, torch, dev, stream)
+
     # ---- block-Krylov low rank ----
     lowrank = None
     if not args.no_lowrank:
@@ -469,6 +523,7 @@ def main():
         "multi": multi,
         "lowrank": lowrank,
         "single_vector_mixture": mixture,
+        "approx_l2": approx,
         "errors": errors,
     }
     print(json.dumps(result), flush=True)
