@@ -20,7 +20,7 @@ Contents
                       per-point lookups), for tiny inputs.
 * ``alg3_query``    - Algorithm 3 (l2 squared) in exact arithmetic, in the
                       reading that uses sum_j y_j and sum_j y_j ||x_j||^2.
-* ``metrics``       - error metrics and norms used to judge a result.
+* ``metrics``       - error metrics and norms used to assess a result.
 * ``lowrank``       - FP64 references for the low-rank application (Appendix C).
 * ``approx_l2``     - FP64 references for the approximate l2 query (Appendix A.4).
 

@@ -1,4 +1,4 @@
-"""Error metrics and matrix norms used to judge a computed ``A z``.
+"""Error metrics and matrix norms used to assess a computed ``A z``.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
