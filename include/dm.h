@@ -8,6 +8,11 @@
  *
  *   DM_L1    f(x, y) = sum_k |x(k) - y(k)|       Algorithms 1 and 2, Section 2
  *   DM_L2SQ  f(x, y) = sum_k (x(k) - y(k))^2     Algorithm 3, Appendix A
+ *   DM_TV    f(x, y) = (1/2) sum_k |x(k) - y(k)|  total variation distance of
+ *            distributions given as probability vectors (the TV theorem of
+ *            Appendix A.3): the l1 path with the result halved.  Float data
+ *            only (integer data: DM_ERR_DTYPE); the points are not checked
+ *            to lie on the simplex.
  *
  * l1: dm_prepare sorts the n values of every coordinate once (Algorithm 1;
  * stable, ties by ascending point index) and keeps the permutations, their
@@ -47,7 +52,7 @@ extern "C" {
 
 typedef struct dm_handle dm_handle;
 
-typedef enum { DM_L1 = 1, DM_L2SQ = 2 } dm_metric;
+typedef enum { DM_L1 = 1, DM_L2SQ = 2, DM_TV = 3 } dm_metric;
 typedef enum { DM_F32 = 1, DM_F64 = 2, DM_I32 = 3, DM_I64 = 4 } dm_dtype;
 typedef enum {
     DM_OK = 0,

@@ -39,6 +39,7 @@ import numpy as np
 
 L1 = 1
 L2SQ = 2
+TV = 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dm_oracle.c")

@@ -10,8 +10,10 @@
  *
  *     (A z)_i = sum_j z_j * f(x_i, x_j)
  *
- * with f(x, y) = sum_k |x(k) - y(k)|          (l1, Section 2)
- *  and f(x, y) = sum_k (x(k) - y(k))^2        (l2 squared, Appendix A, p = 2)
+ * with f(x, y) = sum_k |x(k) - y(k)|          (l1, Section 2),
+ *      f(x, y) = sum_k (x(k) - y(k))^2        (l2 squared, Appendix A, p = 2)
+ *  and f(x, y) = (1/2) sum_k |x(k) - y(k)|    (total variation of two
+ *      distributions given as probability vectors, Appendix A.3; FP64 only)
  *
  * Each requested row of A is formed explicitly, entry by entry (a difference,
  * then an absolute value or a square, summed over k), and then multiplied by
@@ -29,6 +31,7 @@
 
 #define DM_ORACLE_L1 1
 #define DM_ORACLE_L2SQ 2
+#define DM_ORACLE_TV 3
 
 /* One entry of A in FP64: f(x_i, x_j). */
 static double entry_f64(const double* xi, const double* xj, int32_t d, int metric)
@@ -36,12 +39,12 @@ static double entry_f64(const double* xi, const double* xj, int32_t d, int metri
     double a = 0.0;
     for (int32_t k = 0; k < d; ++k) {
         double diff = xi[k] - xj[k];
-        if (metric == DM_ORACLE_L1)
+        if (metric == DM_ORACLE_L1 || metric == DM_ORACLE_TV)
             a += fabs(diff);
         else
             a += diff * diff;
     }
-    return a;
+    return metric == DM_ORACLE_TV ? 0.5 * a : a;
 }
 
 /* One entry of A exactly, from int64 coordinates. */

@@ -23,6 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "dm.h")
 
 L1 = 1
 L2SQ = 2
+TV = 3
 F32, F64, I32, I64 = 1, 2, 3, 4
 
 OK = 0

@@ -21,7 +21,9 @@ namespace {
 constexpr size_t ALIGN = 256;
 inline size_t al(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-bool valid_metric(int32_t m) { return m == DM_L1 || m == DM_L2SQ; }
+bool valid_metric(int32_t m) { return m == DM_L1 || m == DM_L2SQ || m == DM_TV; }
+// metrics answered by the sorted l1 path (TV is half the l1 distance)
+bool sorted_metric(int32_t m) { return m == DM_L1 || m == DM_TV; }
 bool valid_dtype(int32_t t) { return t == DM_F32 || t == DM_F64 || t == DM_I32 || t == DM_I64; }
 bool int_dtype(int32_t t) { return t == DM_I32 || t == DM_I64; }
 size_t dtype_size(int32_t t) { return (t == DM_F64 || t == DM_I64) ? 8 : 4; }
@@ -49,7 +51,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t metric) {
     };
     L.ld = (n + 63) / 64 * 64;
     const size_t arr = (size_t)d * (size_t)L.ld * 4;
-    if (metric == DM_L1) {
+    if (sorted_metric(metric)) {
         L.ntiles = (uint32_t)((size_t)d * (size_t)((n + SORT_TILE - 1) / SORT_TILE));
         L.perm = take(arr);
         L.xs = take(arr);
@@ -62,7 +64,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t metric) {
     L.kmin = take((size_t)d * 4);
     L.kmax = take((size_t)d * 4);
     L.flags = take(16);
-    if (metric == DM_L1) {
+    if (sorted_metric(metric)) {
         L.key_off = take((size_t)d * 8);
         L.key_len = take((size_t)d * 8);
         L.tile_off = take((size_t)(d + 1) * 4);
@@ -81,6 +83,7 @@ dm_status check_shape(int64_t n, int32_t d, int32_t metric, int32_t dtype) {
     const int64_t ld = (n + 63) / 64 * 64;
     if ((uint64_t)ld * (uint64_t)d >= (1ull << 32)) return DM_ERR_ARG;   // 32-bit positions
     if (metric == DM_L2SQ && d > L2_MAX_D) return DM_ERR_ARG;
+    if (metric == DM_TV && int_dtype(dtype)) return DM_ERR_DTYPE;   // TV is defined on distributions
     return DM_OK;
 }
 
@@ -257,7 +260,7 @@ double key_to_double(uint32_t k, bool is_int) {
 
 size_t query_scratch_bytes(const dm_handle* h, int32_t b) {
     size_t s = al(totals_scratch_bytes(h->n, b));
-    if (h->metric != DM_L1) s += al(l2_scratch_bytes(h->n, h->d, b));
+    if (!sorted_metric(h->metric)) s += al(l2_scratch_bytes(h->n, h->d, b));
     return s;
 }
 
@@ -460,7 +463,7 @@ dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_
         launch_fill_u32(h->at<uint32_t>(L.flags), 0u, 4, s) != hipSuccess)
         return fail(DM_ERR_DEVICE);
 
-    if (metric == DM_L1) {
+    if (sorted_metric(metric)) {
         if ((st = prepare_l1(h, X, s)) != DM_OK) return fail(st);
     } else {
         if (launch_prep_transpose(dtype, X, n, d, nullptr, 0, h->ws + L.xcopy, h->at<uint32_t>(L.kmin),
@@ -481,7 +484,7 @@ dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_
     double g = 0.0;
     for (int32_t k = 0; k < d; ++k) {
         const double r = key_to_double(kmax[k], h->is_int) - key_to_double(kmin[k], h->is_int);
-        g += metric == DM_L1 ? r : r * r;
+        g += sorted_metric(metric) ? r : r * r;
     }
     h->guard_scale = g;
     h->last = s;
@@ -494,7 +497,7 @@ dm_status dm_reserve(dm_handle* h, int32_t b) {
     if (h->multi) return DM_ERR_STATE;
     dm_status st = ensure_scratch(h, b, h->last);
     if (st != DM_OK) return st;
-    if (h->metric == DM_L1) {
+    if (sorted_metric(h->metric)) {
         const int kinds[2] = {h->is_int ? IN_I32 : IN_F32, IN_I64};
         for (int ki = 0; ki < (h->is_int ? 2 : 1); ++ki) {
             uint64_t* r = nullptr;
@@ -530,7 +533,7 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
     tot.partials = sc;
     char* rest = sc + al(totals_scratch_bytes(h->n, b));
     h->last = s;
-    if (h->metric == DM_L1) {
+    if (sorted_metric(h->metric)) {
         {
             ProfScope ps(h, DM_K_TOTALS, s);
             DM_TRY(launch_totals(h->is_int, zkind, Z, h->n, b, h->ws + h->L.rowsum, h->guard_scale, tot, s));
@@ -559,6 +562,9 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
             ProfScope ps(h, DM_K_L1_PASS, s);
             DM_TRY(launch_l1_pass(h->is_int, zkind, b, a, s));
         }
+        // TV(x, y) = l1(x, y) / 2 (the TV theorem of Appendix A.3); the
+        // halving is exact in floating point
+        if (h->metric == DM_TV) DM_TRY(launch_scale_f32((float*)Out, (size_t)h->n * b, 0.5f, s));
     } else {
         ProfScope ps(h, DM_K_L2, s);
         DM_TRY(launch_l2sq(h->is_int, zkind, h->ws + h->L.xcopy, h->ws + h->L.rownrm, h->n, h->d, Z, b, Out, rest,
@@ -570,7 +576,7 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
 dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t variant) {
     if (!h || b < 1 || b > MAX_B || variant < 0 || variant >= L1_VARIANTS) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    if (h->metric != DM_L1) return DM_ERR_ARG;
+    if (!sorted_metric(h->metric)) return DM_ERR_ARG;
     int zkind = 0;
     const dm_status st = zkind_of(h, z_dtype, &zkind);
     if (st != DM_OK) return st;
@@ -581,7 +587,7 @@ dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t varia
 dm_status dm_get_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t* variant) {
     if (!h || !variant || b < 1 || b > MAX_B) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    if (h->metric != DM_L1) return DM_ERR_ARG;
+    if (!sorted_metric(h->metric)) return DM_ERR_ARG;
     int zkind = 0;
     const dm_status st = zkind_of(h, z_dtype, &zkind);
     if (st != DM_OK) return st;
@@ -595,7 +601,7 @@ dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* 
                   double* ms_per_pass) {
     if (!h || b < 1 || b > MAX_B || reps < 1 || reps > 4096) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    if (h->metric != DM_L1) return DM_ERR_ARG;
+    if (!sorted_metric(h->metric)) return DM_ERR_ARG;
     int zkind = 0;
     dm_status st = zkind_of(h, z_dtype, &zkind);
     if (st != DM_OK) return st;
@@ -812,7 +818,7 @@ dm_status dm_info(const dm_handle* h, int64_t* n, int32_t* d, int32_t* metric, i
 dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, void* xs, void* stream) {
     if (!h) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    if (h->metric != DM_L1) return DM_ERR_STATE;
+    if (!sorted_metric(h->metric)) return DM_ERR_STATE;
     hipStream_t s = (hipStream_t)stream;
     const size_t w = (size_t)h->n * 4, sp = (size_t)h->L.ld * 4;
     if (perm) DM_TRY(hipMemcpy2DAsync(perm, w, h->ws + h->L.perm, sp, w, h->d, hipMemcpyDeviceToDevice, s));

@@ -163,6 +163,8 @@ hipError_t lr_topk(const double* w, const double* V, int m, int k, double* lam, 
 
 // ---- Gaussian embedding for approximate l2 queries (k_embed.hip) -----------
 // Xout (n x k FP32) = (1 / (beta k)) X G^T, beta = sqrt(2/pi); kind: InKind of X
+// p[i] *= s for i < count
+hipError_t launch_scale_f32(float* p, size_t count, float s, hipStream_t st);
 hipError_t launch_embed_l2(int kind, const void* X, int64_t n, int32_t d, const double* G, int32_t k, float* Xout,
                            hipStream_t s);
 

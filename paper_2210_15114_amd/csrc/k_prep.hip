@@ -144,7 +144,23 @@ __global__ __launch_bounds__(256) void copy_probe_kernel(uint4* __restrict__ dst
     for (; i < n16; i += stride) dst[i] = src[i];
 }
 
+// p[i] *= s
+__global__ __launch_bounds__(256) void scale_f32_kernel(float* __restrict__ p, size_t count, float s)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] *= s;
+}
+
 }  // namespace
+
+hipError_t launch_scale_f32(float* p, size_t count, float s, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    scale_f32_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, count, s);
+    return hipGetLastError();
+}
 
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s)
 {

@@ -62,7 +62,8 @@ def test_prepare_argument_errors_before_device(L):
     assert P(None, 10, 4, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
     assert P(fake, 0, 4, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
     assert P(fake, 10, -1, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
-    assert P(fake, 10, 4, 3, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, 4, 9, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, 4, dm.TV, dm.I32, None, 0, None, ctypes.byref(h)) == dm.ERR_DTYPE
     assert P(fake, 10, 4, dm.L1, 0, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
     assert P(fake, 10, 4, dm.L1, dm.F32, fake, 16, None, ctypes.byref(h)) == dm.ERR_ARG   # short workspace
     assert P(fake, 10, 4, dm.L1, dm.F32, None, 0, None, None) == dm.ERR_ARG

@@ -1,0 +1,38 @@
+"""Total variation products (the TV theorem of Appendix A.3): the l1 path with
+the result halved, on distributions given as probability vectors.  Float
+results against the FP64 oracle's TV matrix within half the l1 bounds;
+integer data is rejected."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_helpers import U32, dev, float_errors, method_scale_l1
+
+pytestmark = pytest.mark.gpu
+dm = pytest.importorskip("paper_2210_15114_amd")
+
+
+@pytest.mark.parametrize("b", [1, 8])
+def test_tv_matches_oracle(b):
+    g = synth.rng(5050 + b)
+    n, d = 3001, 10
+    X = g.dirichlet(np.ones(d), size=n).astype(np.float32)
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    h = dm.prepare(dev(X), dm.TV)
+    Y = h.matvec(dev(Z)).cpu().numpy()
+    h.sync()
+    h.free()
+    e, o = float_errors(X, Z, Y, oracle.TV)
+    S = method_scale_l1(X, Z, np.arange(n))
+    ratio = float((np.abs(Y.reshape(n, -1).astype(np.float64) - o) / (0.5 * (8 + 3 * d) * U32 * S)).max())
+    print("tv errors", e, "bound-ratio", ratio)
+    assert e["spec"] <= 1e-6 and ratio <= 1.0
+
+
+def test_tv_rejects_integer_points():
+    X = np.ones((10, 3), dtype=np.int32)
+    with pytest.raises(dm.DMError) as ex:
+        dm.prepare(dev(X), dm.TV)
+    assert ex.value.status == dm.ERR_DTYPE

@@ -361,3 +361,23 @@ def test_embedded_l1_matrix_approximates_l2_matrix(oracle_mod):
     rel = np.linalg.norm(A - B) / np.linalg.norm(A)
     expect = np.sqrt(np.pi / 2 - 1) / np.sqrt(k)        # about 0.017
     assert 0.5 * expect < rel < 1.5 * expect
+
+
+# ---------------------------------------------------------------------------
+# total variation (Appendix A.3): the largest difference of event probabilities
+# ---------------------------------------------------------------------------
+def test_tv_is_the_largest_event_difference(oracle_mod):
+    import itertools
+    g = np.random.default_rng(303)
+    d = 7
+    X = g.dirichlet(np.ones(d), size=6)
+    A = oracle_mod.explicit(X, oracle_mod.TV)
+    for i in range(6):
+        for j in range(6):
+            best = 0.0
+            for r in range(d + 1):
+                for S in itertools.combinations(range(d), r):
+                    idx = list(S)
+                    best = max(best, abs(X[i, idx].sum() - X[j, idx].sum()))
+            assert abs(A[i, j] - best) < 1e-14
+    assert np.all(A <= 1.0 + 1e-15) and np.all(A >= 0.0)
