@@ -13,6 +13,11 @@
  *            Appendix A.3): the l1 path with the result halved.  Float data
  *            only (integer data: DM_ERR_DTYPE); the points are not checked
  *            to lie on the simplex.
+ *   DM_L3    f(x, y) = sum_k |x(k) - y(k)|^3     l_p^p for odd p (the odd-p
+ *   DM_L5    f(x, y) = sum_k |x(k) - y(k)|^5     theorem of Appendix A.1): the
+ *            sort of Algorithm 1 and prefix sums of z x^t, t = 0 .. p, combined
+ *            as sum_t C(p, t) (-1)^t x^(p-t) (2 P_t - T_t).  Integer data is
+ *            exact under the guard ||z||_1 sum_k range_k^p < 2^62.
  *
  * l1: dm_prepare sorts the n values of every coordinate once (Algorithm 1;
  * stable, ties by ascending point index) and keeps the permutations, their
@@ -52,7 +57,7 @@ extern "C" {
 
 typedef struct dm_handle dm_handle;
 
-typedef enum { DM_L1 = 1, DM_L2SQ = 2, DM_TV = 3 } dm_metric;
+typedef enum { DM_L1 = 1, DM_L2SQ = 2, DM_TV = 3, DM_L3 = 4, DM_L5 = 5 } dm_metric;
 typedef enum { DM_F32 = 1, DM_F64 = 2, DM_I32 = 3, DM_I64 = 4 } dm_dtype;
 typedef enum {
     DM_OK = 0,

@@ -40,6 +40,8 @@ import numpy as np
 L1 = 1
 L2SQ = 2
 TV = 3
+L3 = 4
+L5 = 5
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dm_oracle.c")
@@ -241,6 +243,41 @@ def totals(X, Z):
 # ----------------------------------------------------------------------------
 # Algorithm 2 step by step (exact, tiny inputs)
 # ----------------------------------------------------------------------------
+def odd_p_query(X, y, p: int):
+    """The l_p^p query for odd p in exact arithmetic, by the sort of
+    Algorithm 1 and prefix sums of powers (the odd-p theorem of Appendix A.1,
+    whose proof the paper omits).
+
+    Reading of the combination: for odd p, |a - b|^p = sign(a - b)(a - b)^p,
+    and the binomial expansion of (a - b)^p splits the sum over the points
+    before a point's position (sign +) and after it (sign -):
+        sum_j y_j |x_k(i) - x_j(i)|^p
+          = sum_t C(p, t) (-1)^t x_k(i)^(p-t) (2 P_t - T_t),
+    with P_t the inclusive partial sum of y_j x_j(i)^t up to the point's
+    position in the stable sorted order and T_t the full sum.  Ties contribute
+    zero to either side.  For p = 1 this is Algorithm 2.
+    """
+    from math import comb
+    X = [[Fraction(v) if not isinstance(v, Fraction) else v for v in row] for row in np.asarray(X, dtype=object).tolist()]
+    y = [Fraction(v) if not isinstance(v, Fraction) else v for v in np.asarray(y, dtype=object).ravel().tolist()]
+    n = len(X)
+    d = len(X[0]) if n else 0
+    z = [Fraction(0)] * n
+    for i in range(d):
+        order = sorted(range(n), key=lambda j: (X[j][i], j))
+        P = [[Fraction(0)] * (p + 1) for _ in range(n)]
+        acc = [Fraction(0)] * (p + 1)
+        for q, j in enumerate(order):
+            for t in range(p + 1):
+                acc[t] += y[j] * X[j][i] ** t
+            P[q] = list(acc)
+        T = acc
+        for q, k in enumerate(order):
+            x = X[k][i]
+            z[k] += sum(comb(p, t) * (-1) ** t * x ** (p - t) * (2 * P[q][t] - T[t]) for t in range(p + 1))
+    return z
+
+
 def alg2_query(X, y):
     """Algorithm 2 (Section 2) in exact arithmetic for integer or rational inputs.
 

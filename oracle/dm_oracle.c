@@ -12,8 +12,10 @@
  *
  * with f(x, y) = sum_k |x(k) - y(k)|          (l1, Section 2),
  *      f(x, y) = sum_k (x(k) - y(k))^2        (l2 squared, Appendix A, p = 2)
- *  and f(x, y) = (1/2) sum_k |x(k) - y(k)|    (total variation of two
+ *      f(x, y) = (1/2) sum_k |x(k) - y(k)|    (total variation of two
  *      distributions given as probability vectors, Appendix A.3; FP64 only)
+ *  and f(x, y) = sum_k |x(k) - y(k)|^p, p = 3 or 5   (l_p^p for odd p,
+ *      Appendix A.1; the power by repeated multiplication)
  *
  * Each requested row of A is formed explicitly, entry by entry (a difference,
  * then an absolute value or a square, summed over k), and then multiplied by
@@ -32,6 +34,8 @@
 #define DM_ORACLE_L1 1
 #define DM_ORACLE_L2SQ 2
 #define DM_ORACLE_TV 3
+#define DM_ORACLE_L3 4
+#define DM_ORACLE_L5 5
 
 /* One entry of A in FP64: f(x_i, x_j). */
 static double entry_f64(const double* xi, const double* xj, int32_t d, int metric)
@@ -39,10 +43,15 @@ static double entry_f64(const double* xi, const double* xj, int32_t d, int metri
     double a = 0.0;
     for (int32_t k = 0; k < d; ++k) {
         double diff = xi[k] - xj[k];
-        if (metric == DM_ORACLE_L1 || metric == DM_ORACLE_TV)
+        if (metric == DM_ORACLE_L1 || metric == DM_ORACLE_TV) {
             a += fabs(diff);
-        else
+        } else if (metric == DM_ORACLE_L3 || metric == DM_ORACLE_L5) {
+            double ad = fabs(diff), pw = ad;
+            for (int e = 1; e < (metric == DM_ORACLE_L3 ? 3 : 5); ++e) pw *= ad;
+            a += pw;
+        } else {
             a += diff * diff;
+        }
     }
     return metric == DM_ORACLE_TV ? 0.5 * a : a;
 }
@@ -53,10 +62,17 @@ static __int128 entry_i128(const int64_t* xi, const int64_t* xj, int32_t d, int 
     __int128 a = 0;
     for (int32_t k = 0; k < d; ++k) {
         __int128 diff = (__int128)xi[k] - (__int128)xj[k];
-        if (metric == DM_ORACLE_L1)
-            a += diff < 0 ? -diff : diff;
-        else
+        __int128 ad = diff < 0 ? -diff : diff;
+        if (metric == DM_ORACLE_L1) {
+            a += ad;
+        } else if (metric == DM_ORACLE_L3 || metric == DM_ORACLE_L5) {
+            /* exact while |diff|^p fits: |diff| < 2^25 for p = 5 */
+            __int128 pw = ad;
+            for (int e = 1; e < (metric == DM_ORACLE_L3 ? 3 : 5); ++e) pw *= ad;
+            a += pw;
+        } else {
             a += diff * diff;
+        }
     }
     return a;
 }

@@ -24,6 +24,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "dm.h")
 L1 = 1
 L2SQ = 2
 TV = 3
+L3 = 4
+L5 = 5
 F32, F64, I32, I64 = 1, 2, 3, 4
 
 OK = 0

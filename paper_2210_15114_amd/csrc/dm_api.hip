@@ -21,9 +21,15 @@ namespace {
 constexpr size_t ALIGN = 256;
 inline size_t al(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-bool valid_metric(int32_t m) { return m == DM_L1 || m == DM_L2SQ || m == DM_TV; }
-// metrics answered by the sorted l1 path (TV is half the l1 distance)
-bool sorted_metric(int32_t m) { return m == DM_L1 || m == DM_TV; }
+bool valid_metric(int32_t m) { return m == DM_L1 || m == DM_L2SQ || m == DM_TV || m == DM_L3 || m == DM_L5; }
+// the power p of f(x, y) = sum_k |x(k) - y(k)|^p (TV: p = 1, halved)
+int metric_power(int32_t m) { return m == DM_L2SQ ? 2 : m == DM_L3 ? 3 : m == DM_L5 ? 5 : 1; }
+// metrics answered by the l1 pass (TV is half the l1 distance)
+bool l1_pass_metric(int32_t m) { return m == DM_L1 || m == DM_TV; }
+// odd p >= 3: the sorted path with p + 1 running sums
+bool lp_metric(int32_t m) { return m == DM_L3 || m == DM_L5; }
+// metrics that sort the coordinates at preparation (Algorithm 1)
+bool sorted_metric(int32_t m) { return l1_pass_metric(m) || lp_metric(m); }
 bool valid_dtype(int32_t t) { return t == DM_F32 || t == DM_F64 || t == DM_I32 || t == DM_I64; }
 bool int_dtype(int32_t t) { return t == DM_I32 || t == DM_I64; }
 size_t dtype_size(int32_t t) { return (t == DM_F64 || t == DM_I64) ? 8 : 4; }
@@ -56,9 +62,10 @@ Layout make_layout(int64_t n, int32_t d, int32_t metric) {
         L.perm = take(arr);
         L.xs = take(arr);
         L.rank = take(arr);
-    } else {
-        L.xcopy = take((size_t)n * d * 4);
     }
+    // a row-major FP32 / int32 copy of X: for the l2-squared products and for
+    // the per-coordinate moments of odd p
+    if (!sorted_metric(metric) || lp_metric(metric)) L.xcopy = take((size_t)n * d * 4);
     L.rowsum = take((size_t)n * 8);
     L.rownrm = take((size_t)n * 8);
     L.kmin = take((size_t)d * 4);
@@ -261,7 +268,17 @@ double key_to_double(uint32_t k, bool is_int) {
 size_t query_scratch_bytes(const dm_handle* h, int32_t b) {
     size_t s = al(totals_scratch_bytes(h->n, b));
     if (!sorted_metric(h->metric)) s += al(l2_scratch_bytes(h->n, h->d, b));
+    if (lp_metric(h->metric)) s += al(lp_moments_bytes(h->n, h->d, b, metric_power(h->metric)));
     return s;
+}
+
+// the ticket class and record region size of an odd-p pass
+L1Shape lp_shape(const dm_handle* h, int32_t b, int zkind) {
+    L1Shape sh;
+    const int pw = metric_power(h->metric);
+    sh.cls = L1_CLASSES + (kind_index(h->is_int, zkind) * 8 + log2_pad(b)) * 2 + (pw == 5 ? 1 : 0);
+    sh.record_words = lp_record_words(h->n, b, h->is_int, pw);
+    return sh;
 }
 
 // the record region of one pass shape, created (and zeroed) on first use
@@ -363,9 +380,9 @@ dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
     uint32_t* perm = h->at<uint32_t>(L.perm);
     uint32_t* counts = h->at<uint32_t>(L.counts);
 
-    DM_TRY(launch_prep_transpose(h->dtype, X, n, d, K0, L.ld, nullptr, h->at<uint32_t>(L.kmin),
-                                 h->at<uint32_t>(L.kmax), h->at<uint32_t>(L.flags), s));
-    DM_TRY(launch_row_stats(h->dtype, X, n, d, h->ws + L.rowsum, h->ws + L.rownrm, s));
+    DM_TRY(launch_prep_transpose(h->dtype, X, n, d, K0, L.ld, lp_metric(h->metric) ? h->ws + L.xcopy : nullptr,
+                                 h->at<uint32_t>(L.kmin), h->at<uint32_t>(L.kmax), h->at<uint32_t>(L.flags), s));
+    DM_TRY(launch_row_stats(h->dtype, X, n, d, h->ws + L.rowsum, h->ws + L.rownrm, s, metric_power(h->metric)));
 
     const uint32_t* kin[4] = {K0, K1, K0, K1};
     const uint32_t* vin[4] = {nullptr, V1, V0, V1};
@@ -484,7 +501,9 @@ dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_
     double g = 0.0;
     for (int32_t k = 0; k < d; ++k) {
         const double r = key_to_double(kmax[k], h->is_int) - key_to_double(kmin[k], h->is_int);
-        g += sorted_metric(metric) ? r : r * r;
+        double rp = r;
+        for (int e = 1; e < metric_power(metric); ++e) rp *= r;
+        g += rp;
     }
     h->guard_scale = g;
     h->last = s;
@@ -501,6 +520,10 @@ dm_status dm_reserve(dm_handle* h, int32_t b) {
         const int kinds[2] = {h->is_int ? IN_I32 : IN_F32, IN_I64};
         for (int ki = 0; ki < (h->is_int ? 2 : 1); ++ki) {
             uint64_t* r = nullptr;
+            if (lp_metric(h->metric)) {
+                if ((st = region_for(h, lp_shape(h, b, kinds[ki]), h->last, &r)) != DM_OK) return st;
+                continue;
+            }
             const int v = variant_for(h, kind_index(h->is_int, kinds[ki]), log2_pad(b));
             if ((st = region_for(h, l1_shape(h->n, b, h->is_int, kinds[ki], v), h->last, &r)) != DM_OK) return st;
         }
@@ -533,7 +556,41 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
     tot.partials = sc;
     char* rest = sc + al(totals_scratch_bytes(h->n, b));
     h->last = s;
-    if (sorted_metric(h->metric)) {
+    if (lp_metric(h->metric)) {
+        // odd p: totals T0 and U (weights sum_k x^p), the moments T_1 .. T_(p-1)
+        // of every coordinate, then one pass per coordinate
+        const int pw = metric_power(h->metric);
+        {
+            ProfScope ps(h, DM_K_TOTALS, s);
+            DM_TRY(launch_totals(h->is_int, zkind, Z, h->n, b, h->ws + h->L.rowsum, h->guard_scale, tot, s));
+        }
+        void* M = nullptr;
+        DM_TRY(launch_lp_moments(h->is_int, zkind, pw, h->ws + h->L.xcopy, Z, h->n, h->d, b, rest, &M, s));
+        LpPassArgs a;
+        a.n = h->n;
+        a.Z = Z;
+        a.Out = Out;
+        a.T0 = tot.T0;
+        a.U = tot.U;
+        a.mstride = (int64_t)h->d * b;
+        a.chain = &h->ctl->chain;
+        a.status = &h->ctl->status;
+        {
+            const L1Shape sh = lp_shape(h, b, zkind);
+            dm_status rs = region_for(h, sh, s, &a.records);
+            if (rs != DM_OK) return rs;
+            a.record_words = sh.record_words;
+            a.cls = sh.cls;
+        }
+        for (int32_t k = 0; k < h->d; ++k) {
+            a.perm = h->at<uint32_t>(h->L.perm) + (size_t)k * h->L.ld;
+            a.xs = h->ws + h->L.xs + (size_t)k * h->L.ld * 4;
+            a.Mk = (const char*)M + (size_t)k * b * 8;
+            a.first = k == 0;
+            ProfScope ps(h, DM_K_L1_PASS, s);
+            DM_TRY(launch_lp_pass(h->is_int, zkind, pw, b, a, s));
+        }
+    } else if (l1_pass_metric(h->metric)) {
         {
             ProfScope ps(h, DM_K_TOTALS, s);
             DM_TRY(launch_totals(h->is_int, zkind, Z, h->n, b, h->ws + h->L.rowsum, h->guard_scale, tot, s));
@@ -545,6 +602,7 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         a.T0 = tot.T0;
         a.U = tot.U;
         a.chain = &h->ctl->chain;
+        a.status = &h->ctl->status;
         {
             const int v = variant_for(h, kind_index(h->is_int, zkind), log2_pad(b));
             const L1Shape sh = l1_shape(h->n, b, h->is_int, zkind, v);
@@ -576,7 +634,7 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
 dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t variant) {
     if (!h || b < 1 || b > MAX_B || variant < 0 || variant >= L1_VARIANTS) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    if (!sorted_metric(h->metric)) return DM_ERR_ARG;
+    if (!l1_pass_metric(h->metric)) return DM_ERR_ARG;
     int zkind = 0;
     const dm_status st = zkind_of(h, z_dtype, &zkind);
     if (st != DM_OK) return st;
@@ -587,7 +645,7 @@ dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t varia
 dm_status dm_get_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t* variant) {
     if (!h || !variant || b < 1 || b > MAX_B) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    if (!sorted_metric(h->metric)) return DM_ERR_ARG;
+    if (!l1_pass_metric(h->metric)) return DM_ERR_ARG;
     int zkind = 0;
     const dm_status st = zkind_of(h, z_dtype, &zkind);
     if (st != DM_OK) return st;
@@ -601,7 +659,7 @@ dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* 
                   double* ms_per_pass) {
     if (!h || b < 1 || b > MAX_B || reps < 1 || reps > 4096) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    if (!sorted_metric(h->metric)) return DM_ERR_ARG;
+    if (!l1_pass_metric(h->metric)) return DM_ERR_ARG;
     int zkind = 0;
     dm_status st = zkind_of(h, z_dtype, &zkind);
     if (st != DM_OK) return st;
@@ -629,6 +687,7 @@ dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* 
         a.T0 = h->ctl->T0;
         a.U = h->ctl->U;
         a.chain = &h->ctl->chain;
+        a.status = &h->ctl->status;
         a.first = 0;
         for (int v = 0; v < L1_VARIANTS; ++v) {
             const L1Shape sh = l1_shape(h->n, b, h->is_int, zkind, v);
@@ -803,6 +862,7 @@ dm_status dm_sync(dm_handle* h) {
     }
     if (st & QF_NONFINITE) return DM_ERR_NONFINITE;
     if (st & QF_OVERFLOW) return DM_ERR_OVERFLOW;
+    if (st & QF_STALL) return DM_ERR_DEVICE;
     return DM_OK;
 }
 
@@ -1060,7 +1120,7 @@ dm_status build_plan(dm_handle* h, int32_t b, bool vec) {
             const size_t ix = (size_t)k * 2 + kind;
             if (p.ntiles[ix] == 0) continue;
             e = launch_multi_pass(kind == 1, b, m->d_ds, p.tiles[ix], p.ntiles[ix], k, p.tickets + ix, p.records[ix],
-                                  p.grids[ix], p.vec, m->cap);
+                                  p.grids[ix], p.vec, &h->ctl->status, m->cap);
         }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(m->cap, &g);

@@ -14,7 +14,9 @@ enum InKind { IN_F32 = 1, IN_F64 = 2, IN_I32 = 3, IN_I64 = 4 };
 enum PrepFlag : uint32_t { FLAG_NONFINITE = 1u, FLAG_INT_RANGE = 2u };
 
 // sticky query status bits (device side)
-enum QueryFlag : uint32_t { QF_NONFINITE = 1u, QF_OVERFLOW = 2u };
+// QF_STALL: a chained scan waited too long for a predecessor's record (a
+// library fault, not a data error); the query's result is then invalid
+enum QueryFlag : uint32_t { QF_NONFINITE = 1u, QF_OVERFLOW = 2u, QF_STALL = 4u };
 
 constexpr int SORT_TILE = 4096;   // keys per sort tile (256 threads x 16)
 constexpr int SORT_THREADS = 256;
@@ -26,7 +28,8 @@ constexpr int SORT_THREADS = 256;
 // forms the tag of every word the pass publishes.  Zeroed once when a handle
 // is created and never reset; the host never reads them.
 constexpr int L1_VARIANTS = 4;      // tile variants per l1 pass configuration (tuned per handle)
-constexpr int CHAIN_CLASSES = 96;   // 3 data paths x 8 block widths x L1_VARIANTS
+constexpr int L1_CLASSES = 96;      // 3 data paths x 8 block widths x L1_VARIANTS
+constexpr int CHAIN_CLASSES = L1_CLASSES + 48;   // plus odd p: 3 data paths x 8 block widths x (p = 3, 5)
 struct ChainState {
     uint64_t ticket[CHAIN_CLASSES];
 };
@@ -50,7 +53,7 @@ hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d,
                                  uint32_t* kmin, uint32_t* kmax, uint32_t* flags,
                                  hipStream_t s);
 hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d,
-                            void* rowsum /* n x 8B */, void* rownrm /* n x 8B */, hipStream_t s);
+                            void* rowsum /* n x 8B */, void* rownrm /* n x 8B */, hipStream_t s, int p = 1);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s);
 
@@ -90,6 +93,7 @@ struct L1PassArgs {
     size_t record_words;    // its size in 64-bit words; a launch that needs more is refused
     int cls;                // the shape's ticket class (l1_shape)
     int variant;            // tile variant, 0 .. L1_VARIANTS-1
+    uint32_t* status;       // sticky query flags (QF_STALL on a stuck chain)
 };
 int l1_tile_ranks(int32_t b, bool is_int, int zkind, int variant);
 size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind, int variant);
@@ -138,7 +142,8 @@ hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nb
                                double* partials, uint32_t* status, hipStream_t s);
 // vec: 16-byte row accesses; needs b % 4 == 0 and 16-byte aligned Z and Out of every dataset
 hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
-                             int k, uint64_t* ticket, uint64_t* records, int grid, bool vec, hipStream_t s);
+                             int k, uint64_t* ticket, uint64_t* records, int grid, bool vec, uint32_t* status,
+                             hipStream_t s);
 
 // ---- block-Krylov low rank (k_lowrank.hip) ---------------------------------
 int lr_max_block();
@@ -160,6 +165,33 @@ hipError_t lr_cvt(const float* a, double* b, size_t n, hipStream_t s);
 hipError_t lr_eig(double* T, double* T2, double* V, double* w, int m, int max_sweeps, double tol, int* d_done,
                   int* sweeps, hipStream_t s);
 hipError_t lr_topk(const double* w, const double* V, int m, int k, double* lam, double* Vk, hipStream_t s);
+
+// ---- l_p^p for odd p >= 3 (k_lp.hip) ---------------------------------------
+struct LpPassArgs {
+    const uint32_t* perm;   // n (this coordinate)
+    const void* xs;         // n (float | int32)
+    int64_t n;
+    const void* Z;          // n x b
+    void* Out;              // n x b (float | int64)
+    const void* T0;         // b: sum of z
+    const void* Mk;         // moments of this coordinate: Mk[(t - 1) * mstride + c], t = 1 .. p-1
+    int64_t mstride;
+    const void* U;          // b: sum_j w_j z_j, w_j = sum_k x_jk^p (added when first)
+    int first;
+    ChainState* chain;
+    int cls;                // ticket class (L1_CLASSES + ...)
+    uint64_t* records;
+    size_t record_words;
+    uint32_t* status;       // sticky query flags (QF_STALL on a stuck chain)
+};
+int lp_tile_ranks(int32_t b, int p);
+size_t lp_record_words(int64_t n, int32_t b, bool is_int, int p);
+size_t lp_moments_bytes(int64_t n, int32_t d, int32_t b, int p);
+// M[t - 1][k][c] = sum_j z_jc x_jk^t (t = 1 .. p-1) from the point copy Xc;
+// *M is set inside scratch (lp_moments_bytes)
+hipError_t launch_lp_moments(bool is_int, int zkind, int p, const void* Xc, const void* Z, int64_t n, int32_t d,
+                             int32_t b, void* scratch, void** M, hipStream_t s);
+hipError_t launch_lp_pass(bool is_int, int zkind, int p, int32_t b, const LpPassArgs& a, hipStream_t s);
 
 // ---- Gaussian embedding for approximate l2 queries (k_embed.hip) -----------
 // Xout (n x k FP32) = (1 / (beta k)) X G^T, beta = sqrt(2/pi); kind: InKind of X

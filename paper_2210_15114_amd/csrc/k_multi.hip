@@ -127,7 +127,8 @@ template <typename P, int BP, int R, int OC, bool VEC>
 __global__ __launch_bounds__(256, 2) void multi_pass_kernel(const MultiDs* __restrict__ ds,
                                                          const MultiTile* __restrict__ tiles, int64_t ntiles,
                                                          int32_t k, int32_t b, uint64_t* __restrict__ ticket_ctr,
-                                                         uint64_t* __restrict__ rec, uint64_t* __restrict__ stat)
+                                                         uint64_t* __restrict__ rec, uint64_t* __restrict__ stat,
+                                                         uint32_t* __restrict__ status)
 {
     using L = typename P::L;
     using C = typename P::C;
@@ -221,10 +222,11 @@ __global__ __launch_bounds__(256, 2) void multi_pass_kernel(const MultiDs* __res
 
         // windowed look-back inside the segment (its head tile always has an
         // inclusive record, so the walk never leaves the segment)
-        C c0, c1;
+        C cc[2];
         // two records per wave per round trip: the whole tile is held in registers,
         // and deeper batches would cost occupancy
-        look_back_wg<P, BP, WPR, 2>(rec, stat, head ? -1 : (int64_t)tile - 1, tag, tid, s_lb, c0, c1);
+        look_back_wg<P, BP, 2, 2>(rec, stat, head ? -1 : (int64_t)tile - 1, tag, tid, s_lb, cc, status);
+        const C c0 = cc[0], c1 = cc[1];
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
@@ -309,15 +311,15 @@ static const void* kfn() {
 // aligned, checked by the caller for all datasets)
 template <typename P, int BP>
 static hipError_t launch_bp(const MultiDs* ds, const MultiTile* tiles, int64_t ntiles, int k, int32_t b,
-                            uint64_t* ctr, uint64_t* rec, int grid, bool vec, hipStream_t s) {
+                            uint64_t* ctr, uint64_t* rec, int grid, bool vec, uint32_t* status, hipStream_t s) {
     constexpr bool INT = !std::is_same<P, FloatPath>::value;
     constexpr int R = mr<BP, INT>();
     constexpr int TILEW = 2 * 2 * P::WPV * BP;
     uint64_t* stat = rec + (size_t)ntiles * TILEW;
     if (vec)
-        multi_pass_kernel<P, BP, R, moc<BP, R>(), true><<<grid, 256, 0, s>>>(ds, tiles, ntiles, k, b, ctr, rec, stat);
+        multi_pass_kernel<P, BP, R, moc<BP, R>(), true><<<grid, 256, 0, s>>>(ds, tiles, ntiles, k, b, ctr, rec, stat, status);
     else
-        multi_pass_kernel<P, BP, R, moc<BP, R>(), false><<<grid, 256, 0, s>>>(ds, tiles, ntiles, k, b, ctr, rec, stat);
+        multi_pass_kernel<P, BP, R, moc<BP, R>(), false><<<grid, 256, 0, s>>>(ds, tiles, ntiles, k, b, ctr, rec, stat, status);
     return hipGetLastError();
 }
 
@@ -385,15 +387,16 @@ hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nb
 }
 
 hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
-                             int k, uint64_t* ticket, uint64_t* records, int grid, bool vec, hipStream_t s)
+                             int k, uint64_t* ticket, uint64_t* records, int grid, bool vec, uint32_t* status,
+                             hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     if (vec && b % 4 != 0) return hipErrorInvalidValue;
     switch (bpad2(b)) {
 #define DM_MCASE(BP)                                                                                         \
     case BP:                                                                                                 \
-        return is_int ? launch_bp<IntPath<int32_t>, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, s) \
-                      : launch_bp<FloatPath, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, s);
+        return is_int ? launch_bp<IntPath<int32_t>, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, status, s) \
+                      : launch_bp<FloatPath, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, status, s);
         DM_MCASE(1) DM_MCASE(2) DM_MCASE(4) DM_MCASE(8) DM_MCASE(16) DM_MCASE(32) DM_MCASE(64)
 #undef DM_MCASE
     default: return hipErrorInvalidValue;

@@ -101,8 +101,10 @@ __global__ __launch_bounds__(256) void prep_transpose_kernel(
 // Row statistics s_i = sum_k x_ik and ||x_i||^2, one thread per row, k
 // ascending (fixed order, so the FP64 sums are reproducible).
 template <int KIND>
+// rowsum[i] = sum_k x_ik^p (p = 1: the row sum; p odd >= 3: the weights of
+// the l_p^p query's constant term), rownrm[i] = sum_k x_ik^2
 __global__ __launch_bounds__(256) void row_stats_kernel(
-    const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d, void* rowsum, void* rownrm)
+    const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d, int p, void* rowsum, void* rownrm)
 {
     using I = In<KIND>;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,7 +115,9 @@ __global__ __launch_bounds__(256) void row_stats_kernel(
         double s = 0.0, q = 0.0;
         for (int32_t k = 0; k < d; ++k) {
             double v = (double)I::conv(xi[k], bad);
-            s += v;
+            double vp = v;
+            for (int e = 1; e < p; ++e) vp *= v;
+            s += vp;
             q += v * v;
         }
         ((double*)rowsum)[i] = s;
@@ -123,8 +127,10 @@ __global__ __launch_bounds__(256) void row_stats_kernel(
         uint64_t s = 0, q = 0;
         for (int32_t k = 0; k < d; ++k) {
             int64_t v = (int64_t)I::conv(xi[k], bad);
-            s += (uint64_t)v;
-            q += (uint64_t)(v * v);
+            uint64_t vp = (uint64_t)v;
+            for (int e = 1; e < p; ++e) vp *= (uint64_t)v;
+            s += vp;
+            q += (uint64_t)v * (uint64_t)v;
         }
         ((int64_t*)rowsum)[i] = (int64_t)s;
         ((int64_t*)rownrm)[i] = (int64_t)q;
@@ -201,14 +207,14 @@ hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d, 
 }
 
 hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d, void* rowsum, void* rownrm,
-                            hipStream_t s)
+                            hipStream_t s, int p)
 {
     unsigned grid = (unsigned)((n + 255) / 256);
     switch (kind) {
-    case IN_F32: row_stats_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, rowsum, rownrm); break;
-    case IN_F64: row_stats_kernel<IN_F64><<<grid, 256, 0, s>>>((const double*)X, n, d, rowsum, rownrm); break;
-    case IN_I32: row_stats_kernel<IN_I32><<<grid, 256, 0, s>>>((const int32_t*)X, n, d, rowsum, rownrm); break;
-    case IN_I64: row_stats_kernel<IN_I64><<<grid, 256, 0, s>>>((const int64_t*)X, n, d, rowsum, rownrm); break;
+    case IN_F32: row_stats_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, p, rowsum, rownrm); break;
+    case IN_F64: row_stats_kernel<IN_F64><<<grid, 256, 0, s>>>((const double*)X, n, d, p, rowsum, rownrm); break;
+    case IN_I32: row_stats_kernel<IN_I32><<<grid, 256, 0, s>>>((const int32_t*)X, n, d, p, rowsum, rownrm); break;
+    case IN_I64: row_stats_kernel<IN_I64><<<grid, 256, 0, s>>>((const int64_t*)X, n, d, p, rowsum, rownrm); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

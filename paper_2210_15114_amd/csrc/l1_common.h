@@ -4,6 +4,7 @@
 // and their tagged record words, and row access helpers.
 #pragma once
 #include "dm_device.h"
+#include "dm_internal.h"
 
 namespace dm {
 namespace l1 {
@@ -121,108 +122,47 @@ template <typename ZT> struct IntPath {
 };
 
 // ---------------------------------------------------------------------------
-// Decoupled look-back over the tiles of one chained scan, run by one wave.
+// Decoupled look-back over the tiles of one chained scan.
 //
-// Tile t keeps two records of 2*BP values, (P0, P1) for every column: the
-// aggregate (the tile's own sums) at record 2t and the inclusive prefix at
-// record 2t+1, and a status word (1 = aggregate published, 2 = inclusive
-// published).  Starting at tile `hi`, lane l reads the status of tile hi-l,
-// so 64 predecessors are examined per round trip.  The walk sums aggregates
-// back to the nearest tile with an inclusive record and adds that record;
-// a run of 64 aggregates with no inclusive record in sight is summed and the
-// walk moves on.  Status words are hints only: payload words carry their own
-// tags and are checked, and a batch with a stale word is read again.  The
-// records of a batch are loaded before any is summed, LB at a time, so one
-// round trip to memory covers LB predecessors.  Summation runs from the
-// nearest predecessor outwards.  Lane c returns the exclusive prefix of
-// column c (lanes c >= BP return zero).
+// Tile t keeps two records, each holding NM running sums for every column
+// (P0, P1 for l1): the aggregate (the tile's own sums) at record 2t and the
+// inclusive prefix at record 2t+1, and a status word (1 = aggregate
+// published, 2 = inclusive published).  Starting at tile `hi`, lane l reads
+// the status of tile hi-l, so 64 predecessors are examined per round trip.
+// The walk sums aggregates back to the nearest tile with an inclusive record
+// and adds that record; a run of 64 aggregates with no inclusive record in
+// sight is summed and the walk moves on.  Status words are hints only:
+// payload words carry their own tags and are checked, and a batch with a
+// stale word is read again.  The records of a batch are loaded before any is
+// summed, so one round trip to memory covers many predecessors.  Summation
+// runs from the nearest predecessor outwards.
 // ---------------------------------------------------------------------------
-template <typename P, int BP, int WPR, int LB = 8>
-__device__ __forceinline__ void look_back(const uint64_t* __restrict__ rec, const uint64_t* __restrict__ stat,
-                                          int64_t hi, uint32_t tag, int lane, typename P::C& c0,
-                                          typename P::C& c1)
-{
-    using C = typename P::C;
-    constexpr int W = 2 * P::WPV;   // words of (P0, P1) for one column
-    const int c = lane;
-    const bool act = c < BP;
-    c0 = P::czero();
-    c1 = P::czero();
-    while (hi >= 0) {
-        const int64_t q = hi - lane;
-        const uint64_t st = q >= 0 ? peek_word(stat + q) : 0ull;
-        const uint32_t state = (uint32_t)(st >> 32) == tag ? (uint32_t)st : 0u;
-        const uint64_t mI = __ballot(state == 2u);
-        const uint64_t mA = __ballot(state >= 1u);
-        const int la = (~mA) ? __builtin_ctzll(~mA) : 64;   // leading lanes with a record
-        const int li = mI ? __builtin_ctzll(mI) : 64;        // nearest inclusive record
-        bool fin;
-        int take;
-        if (li < 64 && li <= la) {
-            fin = true;
-            take = li;
-        } else if (la > 0) {
-            fin = false;
-            take = la;
-        } else {
-            __builtin_amdgcn_s_sleep(2);
-            continue;
-        }
-        // records hi, hi-1, ..., hi-take+1 are aggregates; with fin, record
-        // hi-take is the inclusive one
-        const int cnt = take + (fin ? 1 : 0);
-        C s0 = P::czero(), s1 = P::czero();
-        bool ok = true;
-        if (act) {
-            for (int j0 = 0; j0 < cnt; j0 += LB) {
-                uint64_t wv[LB][W];
-#pragma unroll
-                for (int u = 0; u < LB; ++u) {
-                    const int j = j0 + u;
-                    if (j < cnt) {
-                        const uint64_t* src = rec + ((size_t)(hi - j) * 2 + (j == take ? 1 : 0)) * WPR + c * W;
-#pragma unroll
-                        for (int k = 0; k < W; ++k) wv[u][k] = peek_word(src + k);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < LB; ++u) {
-                    if (j0 + u < cnt) {
-                        C v0, v1;
-                        ok = P::decode(wv[u], tag, v0) && ok;
-                        ok = P::decode(wv[u] + P::WPV, tag, v1) && ok;
-                        s0 = P::cadd(s0, v0);
-                        s1 = P::cadd(s1, v1);
-                    }
-                }
-            }
-        }
-        if (!__all(ok)) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        c0 = P::cadd(c0, s0);
-        c1 = P::cadd(c1, s1);
-        if (fin) break;
-        hi -= take;
-    }
-}
+// The same walk run by the whole workgroup of four waves, for records of
+// NM running sums per column (P0, P1 for l1; P0..Pp for odd p).  Wave 0 reads
+// the status words and decides how many records to take; each wave then
+// loads a quarter of them (records j = w, w+4, ...; LB per wave per round
+// trip), so one round trip covers 4*LB predecessors.  Wave partials are
+// combined in wave order by wave 0.  Every thread of the workgroup must call
+// it; the result is valid in wave 0 (lane c holds column c).  s_part is LDS
+// scratch of the caller, free for the duration of the call.  Record layout:
+// column c's value t at word (c * NM + t) * WPV of a record of NM * BP * WPV
+// words.
+//
+// Every wait is bounded: after LOOK_BACK_SPINS polls without progress (about
+// a second; a correct chain waits microseconds) the walk gives up, sets
+// QF_STALL in *status and treats the missing prefix as zero, so that the
+// kernel always completes and the host sees the fault.
+constexpr uint32_t LOOK_BACK_SPINS = 1u << 20;
 
-// The same walk run by the whole workgroup of four waves.  Wave 0 reads the
-// status words and decides how many records to take; each wave then loads a
-// quarter of them (records j = w, w+4, ...; LB per wave per round trip), so
-// one round trip covers 4*LB predecessors.  Wave partials are combined in
-// wave order by wave 0.  Every thread of the workgroup must call it; the
-// result is valid in wave 0 (lane c holds column c).  s_part is LDS scratch
-// of the caller, free for the duration of the call.
-template <typename P, int BP, int WPR, int LB = 8>
+template <typename P, int BP, int NM, int LB = 8>
 __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, const uint64_t* __restrict__ stat,
                                              int64_t hi, uint32_t tag, int tid,
-                                             typename P::C (*s_part)[2][BP], typename P::C& c0,
-                                             typename P::C& c1)
+                                             typename P::C (*s_part)[NM][BP], typename P::C (&cc)[NM],
+                                             uint32_t* __restrict__ status)
 {
     using C = typename P::C;
-    constexpr int W = 2 * P::WPV;
+    constexpr int WPR = NM * BP * P::WPV;
+    constexpr int W = NM * P::WPV;   // words of one column's NM values
     constexpr int NW = 4;
     __shared__ int s_take, s_cnt;
     __shared__ int64_t s_hi;
@@ -230,9 +170,10 @@ __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, c
     const int lane = tid & 63, w = tid >> 6;
     const int c = lane;
     const bool act = c < BP;
-    c0 = P::czero();
-    c1 = P::czero();
+#pragma unroll
+    for (int t = 0; t < NM; ++t) cc[t] = P::czero();
     bool fin = false;
+    uint32_t spins = 0;
     for (;;) {
         if (w == 0) {
             int take = 0, cnt = 0;
@@ -255,9 +196,14 @@ __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, c
                         take = la;
                         break;
                     }
+                    if (++spins > LOOK_BACK_SPINS) {
+                        if (lane == 0) atomicOr(status, (uint32_t)QF_STALL);
+                        hi = -1;
+                        break;
+                    }
                     __builtin_amdgcn_s_sleep(2);
                 }
-                cnt = take + (fin ? 1 : 0);
+                if (hi >= 0) cnt = take + (fin ? 1 : 0);
             }
             if (lane == 0) {
                 s_take = take;
@@ -270,7 +216,9 @@ __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, c
         if (cnt == 0) break;   // hi < 0: nothing (more) to read
         const int take = s_take;
         const int64_t h = s_hi;
-        C s0 = P::czero(), s1 = P::czero();
+        C sum[NM];
+#pragma unroll
+        for (int t = 0; t < NM; ++t) sum[t] = P::czero();
         bool ok = true;
         if (act) {
             for (int j0 = w; j0 < cnt; j0 += NW * LB) {
@@ -287,16 +235,17 @@ __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, c
 #pragma unroll
                 for (int u = 0; u < LB; ++u) {
                     if (j0 + NW * u < cnt) {
-                        C v0, v1;
-                        ok = P::decode(wv[u], tag, v0) && ok;
-                        ok = P::decode(wv[u] + P::WPV, tag, v1) && ok;
-                        s0 = P::cadd(s0, v0);
-                        s1 = P::cadd(s1, v1);
+#pragma unroll
+                        for (int t = 0; t < NM; ++t) {
+                            C v;
+                            ok = P::decode(wv[u] + t * P::WPV, tag, v) && ok;
+                            sum[t] = P::cadd(sum[t], v);
+                        }
                     }
                 }
             }
-            s_part[w][0][c] = s0;
-            s_part[w][1][c] = s1;
+#pragma unroll
+            for (int t = 0; t < NM; ++t) s_part[w][t][c] = sum[t];
         }
         const bool wok = __all(ok);
         if (lane == 0) s_ok[w] = wok ? 1u : 0u;
@@ -304,12 +253,15 @@ __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, c
         if (w == 0) {
             if (s_ok[0] & s_ok[1] & s_ok[2] & s_ok[3]) {
                 if (act) {
-                    const C p0 = P::cadd(P::cadd(s_part[0][0][c], s_part[1][0][c]), P::cadd(s_part[2][0][c], s_part[3][0][c]));
-                    const C p1 = P::cadd(P::cadd(s_part[0][1][c], s_part[1][1][c]), P::cadd(s_part[2][1][c], s_part[3][1][c]));
-                    c0 = P::cadd(c0, p0);
-                    c1 = P::cadd(c1, p1);
+#pragma unroll
+                    for (int t = 0; t < NM; ++t)
+                        cc[t] = P::cadd(cc[t], P::cadd(P::cadd(s_part[0][t][c], s_part[1][t][c]),
+                                                       P::cadd(s_part[2][t][c], s_part[3][t][c])));
                 }
                 hi = fin ? -1 : hi - take;
+            } else if (++spins > LOOK_BACK_SPINS) {
+                if (lane == 0) atomicOr(status, (uint32_t)QF_STALL);
+                hi = -1;
             } else {
                 __builtin_amdgcn_s_sleep(1);   // a record was stale: read the same window again
             }

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
     const typename P::T* __restrict__ T0, const typename P::T* __restrict__ U, int first,
     uint64_t* __restrict__ ticket_ctr, int cls, int64_t ntiles,
-    uint64_t* __restrict__ rec, uint64_t* __restrict__ stat)
+    uint64_t* __restrict__ rec, uint64_t* __restrict__ stat, uint32_t* __restrict__ status)
 {
     using L = typename P::L;
     using C = typename P::C;
@@ -138,8 +138,9 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
 
         // ================= decoupled look-back (wave 0) =================
         // the exclusive prefix of the tile, then its inclusive record
-        C c0, c1;
-        look_back_wg<P, BP, WPR>(rec, stat, (int64_t)tile - 1, tag, tid, s_red, c0, c1);
+        C cc[2];
+        look_back_wg<P, BP, 2>(rec, stat, (int64_t)tile - 1, tag, tid, s_red, cc, status);
+        const C c0 = cc[0], c1 = cc[1];
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
     const typename P::T* __restrict__ T0, const typename P::T* __restrict__ U, int first,
     uint64_t* __restrict__ ticket_ctr, int cls, int64_t ntiles,
-    uint64_t* __restrict__ rec, uint64_t* __restrict__ stat)
+    uint64_t* __restrict__ rec, uint64_t* __restrict__ stat, uint32_t* __restrict__ status)
 {
     using L = typename P::L;
     using C = typename P::C;
@@ -380,8 +381,9 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
 
         // ================= decoupled look-back (wave 0) =================
         // the exclusive prefix of the tile, then its inclusive record
-        C c0, c1;
-        look_back_wg<P, BP, WPR>(rec, stat, (int64_t)tile - 1, tag, tid, s_red, c0, c1);
+        C cc[2];
+        look_back_wg<P, BP, 2>(rec, stat, (int64_t)tile - 1, tag, tid, s_red, cc, status);
+        const C c0 = cc[0], c1 = cc[1];
         if (w == 0) {
             const int c = lane;
             const bool act = c < BP;
@@ -578,22 +580,22 @@ hipError_t launch_shape(const L1PassArgs& a, int32_t b, hipStream_t s) {
         if (vec)
             l1_pass_keep_kernel<P, BP, R, OC, true><<<grid, 256, 0, s>>>(
                 a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat);
+                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat, a.status);
         else
             l1_pass_keep_kernel<P, BP, R, OC, false><<<grid, 256, 0, s>>>(
                 a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat);
+                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat, a.status);
     } else {
         const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_kernel<P, BP, R, SUB, OC, false>,
                                             (const void*)l1_pass_kernel<P, BP, R, SUB, OC, true>);
         if (vec)
             l1_pass_kernel<P, BP, R, SUB, OC, true><<<grid, 256, 0, s>>>(
                 a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat);
+                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat, a.status);
         else
             l1_pass_kernel<P, BP, R, SUB, OC, false><<<grid, 256, 0, s>>>(
                 a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat);
+                (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat, a.status);
     }
     return hipGetLastError();
 }

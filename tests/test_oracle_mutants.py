@@ -29,7 +29,7 @@ MUTANTS = {
                             "        for (int64_t j = 1; j < n; ++j) {\n            double a = entry_f64"),
     "row_index_ignored": ("        const double* xi = X + rows[t] * (int64_t)d;\n        double* y",
                           "        const double* xi = X + t * (int64_t)d;\n        double* y"),
-    "int_dropped_abs": ("a += diff < 0 ? -diff : diff;", "a += diff;"),
+    "int_dropped_abs": ("__int128 ad = diff < 0 ? -diff : diff;", "__int128 ad = diff;"),
     "int_wrong_column": ("acc[c] += a * (__int128)zj[c];", "acc[c] += a * (__int128)zj[0];"),
     "int_overflow_unchecked": ("if (acc[c] > (__int128)INT64_MAX || acc[c] < (__int128)INT64_MIN) overflow += 1;", ""),
 }

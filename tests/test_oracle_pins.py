@@ -381,3 +381,45 @@ def test_tv_is_the_largest_event_difference(oracle_mod):
                     best = max(best, abs(X[i, idx].sum() - X[j, idx].sum()))
             assert abs(A[i, j] - best) < 1e-14
     assert np.all(A <= 1.0 + 1e-15) and np.all(A >= 0.0)
+
+
+# ---------------------------------------------------------------------------
+# odd p (Appendix A.1): the moment-prefix combination and the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("p", [1, 3, 5])
+def test_odd_p_combination_equals_definition_exactly(p):
+    from fractions import Fraction
+    import oracle
+    g = np.random.default_rng(600 + p)
+    X = g.integers(-6, 7, size=(9, 3))
+    X[3] = X[5]                                   # ties
+    y = g.integers(-5, 6, size=9)
+    z = oracle.odd_p_query(X, y, p)
+    for k in range(9):
+        ref = sum(Fraction(int(y[j])) * sum(abs(int(X[k][i]) - int(X[j][i])) ** p for i in range(3)) for j in range(9))
+        assert z[k] == ref
+
+
+@pytest.mark.parametrize("metric,p", [(4, 3), (5, 5)])
+def test_odd_p_oracle_against_exact(oracle_mod, metric, p):
+    g = np.random.default_rng(700 + p)
+    X = g.integers(-50, 51, size=(40, 4)).astype(np.int64)
+    Z = g.integers(-9, 10, size=(40, 2)).astype(np.int64)
+    o, ov = oracle_mod.matvec_int(X, Z, metric)
+    assert ov == 0
+    for c in range(2):
+        ref = [sum(int(Z[j, c]) * sum(abs(int(X[k, i]) - int(X[j, i])) ** p for i in range(4)) for j in range(40))
+               for k in range(40)]
+        assert [int(v) for v in o[:, c]] == ref
+    of, _, _ = oracle_mod.matvec(X.astype(np.float64), Z.astype(np.float64), metric)
+    assert np.array_equal(of, o.astype(np.float64))     # below 2^53 the FP64 oracle is exact too
+
+
+def test_l3_lattice_sum_of_cubes(oracle_mod):
+    # x_i = i on a line: sum_j |i - j|^3 = (i(i-1)/2)^2 + ((n-i)(n-i+1)/2)^2
+    n = 300
+    X = np.arange(1, n + 1, dtype=np.float64)[:, None]
+    o, _, _ = oracle_mod.matvec(X, np.ones((n, 1)), oracle_mod.L3)
+    i = np.arange(1, n + 1, dtype=np.float64)
+    ref = (i * (i - 1) / 2) ** 2 + ((n - i) * (n - i + 1) / 2) ** 2
+    assert np.array_equal(o[:, 0], ref)
