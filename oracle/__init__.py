@@ -20,6 +20,11 @@ Contents
                       per-point lookups), for tiny inputs.
 * ``alg3_query``    - Algorithm 3 (l2 squared) in exact arithmetic, in the
                       reading that uses sum_j y_j and sum_j y_j ||x_j||^2.
+* ``odd_p_query``   - l_p^p for odd p (Appendix A.1) in exact arithmetic.
+* ``even_p_query``  - Algorithm 5 (even p) in exact arithmetic, with the
+                      binomial coefficients and weights restored.
+* ``kl_query``      - Algorithm 4 (KL divergence), FP64, in the paper's order.
+* ``mahalanobis_query`` - Algorithms 8 and 9 (the bilinear form x^T M y), FP64.
 * ``metrics``       - error metrics and norms used to assess a result.
 * ``lowrank``       - FP64 references for the low-rank application (Appendix C).
 * ``approx_l2``     - FP64 references for the approximate l2 query (Appendix A.4).
@@ -42,6 +47,13 @@ L2SQ = 2
 TV = 3
 L3 = 4
 L5 = 5
+L4 = 6
+L6 = 7
+KL = 8
+CE = 9
+MAHA2 = 10
+BILINEAR = 11
+MATRIX_METRICS = (MAHA2, BILINEAR)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dm_oracle.c")
@@ -68,9 +80,9 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i64, i32, c_int = ctypes.c_int64, ctypes.c_int32, ctypes.c_int
-        lib.oracle_rows_f64.argtypes = [P, i64, i32, c_int, P, i64, P]
+        lib.oracle_rows_f64.argtypes = [P, i64, i32, c_int, P, P, i64, P]
         lib.oracle_rows_f64.restype = None
-        lib.oracle_matvec_f64.argtypes = [P, i64, i32, c_int, P, i32, P, i64, P, P, P]
+        lib.oracle_matvec_f64.argtypes = [P, i64, i32, c_int, P, P, i32, P, i64, P, P, P]
         lib.oracle_matvec_f64.restype = None
         lib.oracle_matvec_i64.argtypes = [P, i64, i32, c_int, P, i32, P, i64, P]
         lib.oracle_matvec_i64.restype = i64
@@ -100,12 +112,24 @@ def _rows_arg(n, rows):
 # ----------------------------------------------------------------------------
 # the plain definition
 # ----------------------------------------------------------------------------
-def matvec(X, Z, metric: int, rows=None):
+def _matrix_arg(metric, M, d):
+    if metric not in MATRIX_METRICS:
+        return None
+    if M is None:
+        raise ValueError("this metric needs the d x d matrix M")
+    M = np.ascontiguousarray(np.asarray(M, dtype=np.float64))
+    if M.shape != (d, d):
+        raise ValueError("M must be d x d")
+    return M
+
+
+def matvec(X, Z, metric: int, rows=None, M=None):
     """FP64 (A z) for the given rows, with the row norms and |A||z| sums.
 
     Follows the definition of the query in Section 1 and the expansion at the
     start of the proof of the p = 1 theorem in Section 2 (sum over j of
-    z_j times the distance), forming every entry explicitly.
+    z_j times the distance), forming every entry explicitly.  M (d x d) is
+    the matrix of MAHA2 and BILINEAR.
 
     Returns (Y, rownorm2, absdot): Y is m x b, rownorm2 = ||A_i||_2^2 (m),
     absdot = sum_j |A_ij| |z_jc| (m x b).
@@ -120,13 +144,14 @@ def matvec(X, Z, metric: int, rows=None):
         raise ValueError("Z rows != n")
     b = Z.shape[1]
     r = _rows_arg(n, rows)
+    Mm = _matrix_arg(metric, M, d)
     m = r.size
     Y = np.zeros((m, b), dtype=np.float64)
     rn = np.zeros(m, dtype=np.float64)
     ad = np.zeros((m, b), dtype=np.float64)
     if m:
-        _load().oracle_matvec_f64(_ptr(X), n, d, metric, _ptr(Z), b, _ptr(r), m,
-                                  _ptr(Y), _ptr(rn), _ptr(ad))
+        _load().oracle_matvec_f64(_ptr(X), n, d, metric, None if Mm is None else _ptr(Mm), _ptr(Z), b,
+                                  _ptr(r), m, _ptr(Y), _ptr(rn), _ptr(ad))
     return Y, rn, ad
 
 
@@ -152,14 +177,16 @@ def matvec_int(X, Z, metric: int, rows=None):
     return Y, ov
 
 
-def explicit(X, metric: int, rows=None) -> np.ndarray:
+def explicit(X, metric: int, rows=None, M=None) -> np.ndarray:
     """Rows of the explicit distance matrix A (FP64), m x n."""
     X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
     n, d = X.shape
     r = _rows_arg(n, rows)
+    Mm = _matrix_arg(metric, M, d)
     A = np.zeros((r.size, n), dtype=np.float64)
     if r.size:
-        _load().oracle_rows_f64(_ptr(X), n, d, metric, _ptr(r), r.size, _ptr(A))
+        _load().oracle_rows_f64(_ptr(X), n, d, metric, None if Mm is None else _ptr(Mm), _ptr(r), r.size,
+                                _ptr(A))
     return A
 
 
@@ -339,6 +366,54 @@ def alg3_query(X, y):
     s1 = sum(y)
     s2 = sum(y[j] * nrm[j] for j in range(n))
     return [nrm[k] * s1 + s2 - 2 * sum(X[k][i] * v[i] for i in range(d)) for k in range(n)]
+
+
+def even_p_query(X, y, p: int):
+    """The l_p^p query for even p in exact arithmetic, by the moment expansion
+    of Algorithm 5 (Appendix A.1), step by step in the algorithm's order.
+
+    Reading: the printed moments S_(i,t) lack the binomial coefficients and the
+    weights y_j, and the printed sum starts at t = 1.  The binomial theorem
+    gives (x_k(i) - x_j(i))^p = sum_(t=0..p) C(p, t) x_k(i)^t (-x_j(i))^(p-t),
+    so the moments are
+        S_(i,t) = C(p, t) sum_j y_j (-x_j(i))^(p-t),   t = 0 .. p,
+    and z(k) = sum_i sum_(t=0..p) x_k(i)^t S_(i,t).
+    """
+    from math import comb
+    X = [[Fraction(v) if not isinstance(v, Fraction) else v for v in row] for row in np.asarray(X, dtype=object).tolist()]
+    y = [Fraction(v) if not isinstance(v, Fraction) else v for v in np.asarray(y, dtype=object).ravel().tolist()]
+    n = len(X)
+    d = len(X[0]) if n else 0
+    S = [[comb(p, t) * sum(y[j] * (-X[j][i]) ** (p - t) for j in range(n)) for t in range(p + 1)]
+         for i in range(d)]
+    return [sum(X[k][i] ** t * S[i][t] for i in range(d) for t in range(p + 1)) for k in range(n)]
+
+
+def kl_query(X, y):
+    """Algorithm 4 (the KL query of Appendix A) in FP64, in the algorithm's
+    order: S_i = sum_j y_j log x_j(i) per coordinate, the entropies
+    H_k = -sum_i x_k(i) log x_k(i) per point (0 log 0 = 0), Y = sum_j y_j, and
+    z(k) = -H_k Y - sum_i x_k(i) S_i.  X must be positive wherever a
+    logarithm of it is taken.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    S = np.log(X).T @ y
+    H = -np.where(X > 0, X * np.log(np.where(X > 0, X, 1.0)), 0.0).sum(axis=1)
+    Y = y.sum(axis=0)
+    return -np.multiply.outer(H, Y) - X @ S
+
+
+def mahalanobis_query(X, y, M):
+    """Algorithms 8 and 9 (Appendix A.2) in FP64: the preprocessing forms
+    S = M X^T (column j is M x_j); a query takes v = S y and returns
+    z(k) = <x_k, v>.  This is the query of the bilinear form x^T M y that the
+    paragraph writes as its f.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    S = np.asarray(M, dtype=np.float64) @ X.T
+    v = S @ np.asarray(y, dtype=np.float64)
+    return X @ v
 
 
 from . import metrics  # noqa: E402  (re-export)

@@ -14,14 +14,24 @@
  *      f(x, y) = sum_k (x(k) - y(k))^2        (l2 squared, Appendix A, p = 2)
  *      f(x, y) = (1/2) sum_k |x(k) - y(k)|    (total variation of two
  *      distributions given as probability vectors, Appendix A.3; FP64 only)
- *  and f(x, y) = sum_k |x(k) - y(k)|^p, p = 3 or 5   (l_p^p for odd p,
+ *      f(x, y) = sum_k |x(k) - y(k)|^p, p = 3 or 5   (l_p^p for odd p,
  *      Appendix A.1; the power by repeated multiplication)
+ *      f(x, y) = sum_k (x(k) - y(k))^p, p = 4 or 6    (l_p^p for even p,
+ *      the even-p theorem of Appendix A.1)
+ * and, FP64 only, with a d x d matrix M where one is named:
+ *      f(x, y) = sum_k x(k) log(x(k) / y(k))     (KL divergence D(x || y),
+ *                the KL theorem of Appendix A; 0 log 0 = 0)
+ *      f(x, y) = -sum_k x(k) log y(k)           (cross entropy, Appendix A.3)
+ *      f(x, y) = (x - y)^T M (x - y)            (squared Mahalanobis distance)
+ *      f(x, y) = x^T M y                        (the bilinear form that the
+ *                Mahalanobis paragraph of Appendix A.2 writes down)
  *
- * Each requested row of A is formed explicitly, entry by entry (a difference,
- * then an absolute value or a square, summed over k), and then multiplied by
- * Z with j ascending.  No prefix sums, no sorting and no norm expansion are
- * used, so the oracle shares neither the l1 method's scan nor the l2-squared
- * low-rank form's cancellation.
+ * Each requested row of A is formed explicitly, entry by entry (a difference
+ * then an absolute value or a power, a logarithm of a ratio, or a quadratic
+ * form, summed over the coordinates), and then multiplied by Z with j
+ * ascending.  No prefix sums, no sorting, no moment or norm expansion are
+ * used, so the oracle shares neither the l1 method's scan nor the
+ * cancellation of the expanded forms.
  *
  * Floating point: every quantity is FP64, compiled with -ffp-contract=off.
  * Integer variant: int64 inputs, entries and products in __int128, so the
@@ -36,10 +46,40 @@
 #define DM_ORACLE_TV 3
 #define DM_ORACLE_L3 4
 #define DM_ORACLE_L5 5
+#define DM_ORACLE_L4 6
+#define DM_ORACLE_L6 7
+#define DM_ORACLE_KL 8
+#define DM_ORACLE_CE 9
+#define DM_ORACLE_MAHA2 10
+#define DM_ORACLE_BILINEAR 11
+
+/* The distances that need a logarithm or the matrix M, entry by entry as
+ * written in their definitions above. */
+static double entry_form_f64(const double* xi, const double* xj, int32_t d, int metric, const double* M)
+{
+    double a = 0.0;
+    if (metric == DM_ORACLE_KL) {
+        for (int32_t k = 0; k < d; ++k)
+            if (xi[k] != 0.0) a += xi[k] * log(xi[k] / xj[k]);
+    } else if (metric == DM_ORACLE_CE) {
+        for (int32_t k = 0; k < d; ++k)
+            if (xi[k] != 0.0) a -= xi[k] * log(xj[k]);
+    } else if (metric == DM_ORACLE_MAHA2) {
+        for (int32_t k = 0; k < d; ++k)
+            for (int32_t l = 0; l < d; ++l)
+                a += (xi[k] - xj[k]) * M[(int64_t)k * d + l] * (xi[l] - xj[l]);
+    } else {
+        for (int32_t k = 0; k < d; ++k)
+            for (int32_t l = 0; l < d; ++l)
+                a += xi[k] * M[(int64_t)k * d + l] * xj[l];
+    }
+    return a;
+}
 
 /* One entry of A in FP64: f(x_i, x_j). */
-static double entry_f64(const double* xi, const double* xj, int32_t d, int metric)
+static double entry_f64(const double* xi, const double* xj, int32_t d, int metric, const double* M)
 {
+    if (metric >= DM_ORACLE_KL) return entry_form_f64(xi, xj, d, metric, M);
     double a = 0.0;
     for (int32_t k = 0; k < d; ++k) {
         double diff = xi[k] - xj[k];
@@ -48,6 +88,10 @@ static double entry_f64(const double* xi, const double* xj, int32_t d, int metri
         } else if (metric == DM_ORACLE_L3 || metric == DM_ORACLE_L5) {
             double ad = fabs(diff), pw = ad;
             for (int e = 1; e < (metric == DM_ORACLE_L3 ? 3 : 5); ++e) pw *= ad;
+            a += pw;
+        } else if (metric == DM_ORACLE_L4 || metric == DM_ORACLE_L6) {
+            double pw = diff;
+            for (int e = 1; e < (metric == DM_ORACLE_L4 ? 4 : 6); ++e) pw *= diff;
             a += pw;
         } else {
             a += diff * diff;
@@ -70,6 +114,11 @@ static __int128 entry_i128(const int64_t* xi, const int64_t* xj, int32_t d, int 
             __int128 pw = ad;
             for (int e = 1; e < (metric == DM_ORACLE_L3 ? 3 : 5); ++e) pw *= ad;
             a += pw;
+        } else if (metric == DM_ORACLE_L4 || metric == DM_ORACLE_L6) {
+            /* exact while d |diff|^p < 2^127: |diff| < 2^21 for p = 6 */
+            __int128 pw = diff;
+            for (int e = 1; e < (metric == DM_ORACLE_L4 ? 4 : 6); ++e) pw *= diff;
+            a += pw;
         } else {
             a += diff * diff;
         }
@@ -79,16 +128,16 @@ static __int128 entry_i128(const int64_t* xi, const int64_t* xj, int32_t d, int 
 
 /*
  * Rows `rows[0..m)` of the explicit distance matrix, A_out is m x n row-major.
- * X is n x d row-major.
+ * X is n x d row-major; M is d x d row-major (NULL unless the metric uses it).
  */
-void oracle_rows_f64(const double* X, int64_t n, int32_t d, int metric,
+void oracle_rows_f64(const double* X, int64_t n, int32_t d, int metric, const double* M,
                      const int64_t* rows, int64_t m, double* A_out)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < m; ++t) {
         const double* xi = X + rows[t] * (int64_t)d;
         for (int64_t j = 0; j < n; ++j)
-            A_out[t * n + j] = entry_f64(xi, X + j * (int64_t)d, d, metric);
+            A_out[t * n + j] = entry_f64(xi, X + j * (int64_t)d, d, metric, M);
     }
 }
 
@@ -97,7 +146,7 @@ void oracle_rows_f64(const double* X, int64_t n, int32_t d, int metric,
  * rownorm2[t]  = sum_j A[rows[t], j]^2                 (may be NULL)
  * absdot[t, c] = sum_j |A[rows[t], j]| * |Z[j, c]|     (may be NULL)
  */
-void oracle_matvec_f64(const double* X, int64_t n, int32_t d, int metric,
+void oracle_matvec_f64(const double* X, int64_t n, int32_t d, int metric, const double* M,
                        const double* Z, int32_t b, const int64_t* rows, int64_t m,
                        double* Y, double* rownorm2, double* absdot)
 {
@@ -112,7 +161,7 @@ void oracle_matvec_f64(const double* X, int64_t n, int32_t d, int metric,
             if (ad) ad[c] = 0.0;
         }
         for (int64_t j = 0; j < n; ++j) {
-            double a = entry_f64(xi, X + j * (int64_t)d, d, metric);
+            double a = entry_f64(xi, X + j * (int64_t)d, d, metric, M);
             const double* zj = Z + j * (int64_t)b;
             for (int32_t c = 0; c < b; ++c) {
                 y[c] += a * zj[c];

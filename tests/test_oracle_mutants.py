@@ -32,6 +32,17 @@ MUTANTS = {
     "int_dropped_abs": ("__int128 ad = diff < 0 ? -diff : diff;", "__int128 ad = diff;"),
     "int_wrong_column": ("acc[c] += a * (__int128)zj[c];", "acc[c] += a * (__int128)zj[0];"),
     "int_overflow_unchecked": ("if (acc[c] > (__int128)INT64_MAX || acc[c] < (__int128)INT64_MIN) overflow += 1;", ""),
+    "even_p_wrong_power": ("(metric == DM_ORACLE_L4 ? 4 : 6); ++e) pw *= diff;",
+                           "(metric == DM_ORACLE_L4 ? 3 : 6); ++e) pw *= diff;"),
+    "int_even_p_odd_power": ("for (int e = 1; e < (metric == DM_ORACLE_L4 ? 4 : 6); ++e) pw *= diff;\n            a += pw;\n        } else {\n            a += diff * diff;\n        }\n    }\n    return a;",
+                             "for (int e = 1; e < (metric == DM_ORACLE_L4 ? 4 : 5); ++e) pw *= diff;\n            a += pw;\n        } else {\n            a += diff * diff;\n        }\n    }\n    return a;"),
+    "kl_swapped_arguments": ("a += xi[k] * log(xi[k] / xj[k]);", "a += xj[k] * log(xj[k] / xi[k]);"),
+    "kl_dropped_entropy": ("a += xi[k] * log(xi[k] / xj[k]);", "a -= xi[k] * log(xj[k]);"),
+    "ce_wrong_sign": ("if (xi[k] != 0.0) a -= xi[k] * log(xj[k]);", "if (xi[k] != 0.0) a += xi[k] * log(xj[k]);"),
+    "maha_one_sided": ("a += (xi[k] - xj[k]) * M[(int64_t)k * d + l] * (xi[l] - xj[l]);",
+                       "a += xi[k] * M[(int64_t)k * d + l] * (xi[l] - xj[l]);"),
+    "bilinear_transposed": ("a += xi[k] * M[(int64_t)k * d + l] * xj[l];",
+                            "a += xi[k] * M[(int64_t)l * d + k] * xj[l];"),
 }
 
 
@@ -100,7 +111,43 @@ def _pins():
         Z = np.array([[2 ** 32], [2 ** 32]], dtype=np.int64)
         return oracle.matvec_int(X, Z, L1)[1] == 2
 
+    def even_p():
+        Xi = g.integers(-7, 8, size=(12, 2)).astype(np.int64)
+        zi = g.integers(-5, 6, size=12).astype(np.int64)
+        for metric, p in ((oracle.L4, 4), (oracle.L6, 6)):
+            Y, ov = oracle.matvec_int(Xi, zi[:, None], metric)
+            Yf, _, _ = oracle.matvec(Xi.astype(float), zi[:, None].astype(float), metric)
+            ex = [int(v) for v in oracle.even_p_query(Xi, zi, p)]
+            if ov or Y[:, 0].tolist() != ex or Yf[:, 0].tolist() != [float(v) for v in ex]:
+                return False
+        return True
+
+    def divergences():
+        from scipy.stats import entropy
+        P = g.random((6, 3)) + 0.1
+        P /= P.sum(axis=1, keepdims=True)
+        A = oracle.explicit(P, oracle.KL)
+        C = oracle.explicit(P, oracle.CE)
+        kl = np.array([[entropy(P[i], P[j]) for j in range(6)] for i in range(6)])
+        ce = np.array([[entropy(P[i]) + kl[i, j] for j in range(6)] for i in range(6)])
+        return bool(np.allclose(A, kl, rtol=1e-12, atol=1e-15) and np.allclose(C, ce, rtol=1e-12, atol=1e-15))
+
+    def quadratic_forms():
+        from scipy.spatial.distance import cdist
+        Xq = g.standard_normal((9, 3))
+        B = g.standard_normal((3, 3))
+        M = B @ B.T + 0.5 * np.eye(3)
+        ok = np.allclose(oracle.explicit(Xq, oracle.MAHA2, M=M), cdist(Xq, Xq, "mahalanobis", VI=M) ** 2,
+                         rtol=1e-10, atol=1e-12)
+        Zq = g.standard_normal((9, 2))
+        ok &= np.allclose(oracle.matvec(Xq, Zq, oracle.BILINEAR, M=B)[0], oracle.mahalanobis_query(Xq, Zq, B),
+                          rtol=1e-12, atol=1e-12)
+        return bool(ok)
+
     check("exact_rational", exact_rational)
+    check("even_p", even_p)
+    check("divergences", divergences)
+    check("quadratic_forms", quadratic_forms)
     check("structure", structure)
     check("lattice", lattice)
     check("rhs_columns", rhs_columns)

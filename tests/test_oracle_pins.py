@@ -423,3 +423,134 @@ def test_l3_lattice_sum_of_cubes(oracle_mod):
     i = np.arange(1, n + 1, dtype=np.float64)
     ref = (i * (i - 1) / 2) ** 2 + ((n - i) * (n - i + 1) / 2) ** 2
     assert np.array_equal(o[:, 0], ref)
+
+
+# ---------------------------------------------------------------------------
+# the sort-free family (Appendix A): even p, KL, cross entropy, Mahalanobis
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_even_p_expansion_equals_definition_exactly(p):
+    # Algorithm 5 with the binomial coefficients and weights restored
+    g = np.random.default_rng(800 + p)
+    X = g.integers(-6, 7, size=(9, 3))
+    y = g.integers(-5, 6, size=9)
+    z = oracle.even_p_query(X, y, p)
+    for k in range(9):
+        ref = sum(int(y[j]) * sum((int(X[k][i]) - int(X[j][i])) ** p for i in range(3)) for j in range(9))
+        assert z[k] == ref
+
+
+def test_even_p_two_is_algorithm_3():
+    g = np.random.default_rng(810)
+    X = [[Fraction(int(v), 7) for v in row] for row in g.integers(-20, 21, size=(8, 3))]
+    y = [Fraction(int(v), 3) for v in g.integers(-9, 10, size=8)]
+    assert oracle.even_p_query(X, y, 2) == oracle.alg3_query(X, y)
+
+
+@pytest.mark.parametrize("metric,p", [(oracle.L4, 4), (oracle.L6, 6)])
+def test_even_p_oracle_against_moment_expansion(oracle_mod, metric, p):
+    g = np.random.default_rng(820 + p)
+    X = g.integers(-40, 41, size=(30, 3)).astype(np.int64)
+    Z = g.integers(-9, 10, size=(30, 2)).astype(np.int64)
+    o, ov = oracle_mod.matvec_int(X, Z, metric)
+    assert ov == 0
+    for c in range(2):
+        assert [int(v) for v in o[:, c]] == [int(v) for v in oracle.even_p_query(X, Z[:, c], p)]
+    of, _, _ = oracle_mod.matvec(X.astype(np.float64), Z.astype(np.float64), metric)
+    assert np.array_equal(of, o.astype(np.float64))     # below 2^53 the FP64 oracle is exact too
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_even_p_lattice_faulhaber(oracle_mod, p):
+    # x_i = i on a line: sum_j (i - j)^p = F(i - 1) + F(n - i), F(N) = sum_(m<=N) m^p
+    def F(N):
+        if p == 4:
+            return N * (N + 1) * (2 * N + 1) * (3 * N * N + 3 * N - 1) // 30
+        return N * (N + 1) * (2 * N + 1) * (3 * N ** 4 + 6 * N ** 3 - 3 * N + 1) // 42
+    n = 150
+    X = np.arange(1, n + 1, dtype=np.int64)[:, None]
+    o, ov = oracle_mod.matvec_int(X, np.ones((n, 1), np.int64), oracle.L4 if p == 4 else oracle.L6)
+    assert ov == 0
+    assert [int(v) for v in o[:, 0]] == [F(i - 1) + F(n - i) for i in range(1, n + 1)]
+
+
+def _simplex(n, d, seed):
+    g = np.random.default_rng(seed)
+    P = g.random((n, d)) + 0.05
+    return P / P.sum(axis=1, keepdims=True)
+
+
+def test_kl_matches_scipy_relative_entropy(oracle_mod):
+    from scipy.stats import entropy
+    X = _simplex(12, 5, 830)
+    A = oracle_mod.explicit(X, oracle.KL)
+    ref = np.array([[entropy(X[i], X[j]) for j in range(12)] for i in range(12)])
+    assert np.allclose(A, ref, rtol=1e-12, atol=1e-15)
+    assert np.all(np.diag(A) == 0.0)                     # log(x / x) = 0
+    off = ~np.eye(12, dtype=bool)
+    assert np.all(A[off] > 0)                            # Gibbs' inequality
+    assert not np.allclose(A, A.T)                       # not symmetric
+
+
+def test_cross_entropy_is_entropy_plus_kl(oracle_mod):
+    from scipy.stats import entropy
+    X = _simplex(10, 4, 831)
+    A = oracle_mod.explicit(X, oracle.CE)
+    ref = np.array([[entropy(X[i]) + entropy(X[i], X[j]) for j in range(10)] for i in range(10)])
+    assert np.allclose(A, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_kl_algorithm_4_equals_definition(oracle_mod):
+    g = np.random.default_rng(832)
+    X = g.random((40, 6)) * 3 + 0.01                     # positive, not normalised
+    Z = g.standard_normal((40, 3))
+    Y, _, _ = oracle_mod.matvec(X, Z, oracle.KL)
+    Yq = oracle.kl_query(X, Z)
+    L = np.abs(np.log(X))
+    S = (np.abs(X) * L).sum(axis=1)[:, None] * np.abs(Z).sum(axis=0) + np.abs(X) @ (L.T @ np.abs(Z))
+    assert np.all(np.abs(Y - Yq) <= 16 * (6 + 2) * 2.0 ** -53 * S)
+    # a sign slip in either would move the result by about S
+    assert np.max(np.abs(Y - Yq) / S) < 1e-12
+
+
+def test_mahalanobis_identity_is_l2sq(oracle_mod):
+    X = _rand(30, 4, 840)
+    Z = _rand(30, 2, 841)
+    Y, _, _ = oracle_mod.matvec(X, Z, oracle.MAHA2, M=np.eye(4))
+    Y2, _, _ = oracle_mod.matvec(X, Z, L2SQ)
+    assert np.array_equal(Y, Y2)
+
+
+def test_mahalanobis_matches_scipy(oracle_mod):
+    from scipy.spatial.distance import cdist
+    g = np.random.default_rng(842)
+    X = g.standard_normal((25, 5))
+    B = g.standard_normal((5, 5))
+    M = B @ B.T + 0.5 * np.eye(5)
+    A = oracle_mod.explicit(X, oracle.MAHA2, M=M)
+    ref = cdist(X, X, "mahalanobis", VI=M) ** 2
+    assert np.allclose(A, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_mahalanobis_sees_only_the_symmetric_part(oracle_mod):
+    g = np.random.default_rng(843)
+    X = g.standard_normal((20, 4))
+    M = g.standard_normal((4, 4))
+    A = oracle_mod.explicit(X, oracle.MAHA2, M=M)
+    As = oracle_mod.explicit(X, oracle.MAHA2, M=(M + M.T) / 2)
+    assert np.allclose(A, As, rtol=1e-12, atol=1e-12)
+    assert np.allclose(A, A.T, rtol=1e-12, atol=1e-12) and np.all(np.diag(A) == 0.0)
+
+
+def test_bilinear_algorithms_8_and_9_equal_definition(oracle_mod):
+    g = np.random.default_rng(844)
+    X = g.standard_normal((30, 5))
+    Z = g.standard_normal((30, 2))
+    M = g.standard_normal((5, 5))                        # not symmetric
+    Y, _, _ = oracle_mod.matvec(X, Z, oracle.BILINEAR, M=M)
+    Yq = oracle.mahalanobis_query(X, Z, M)
+    S = np.abs(X) @ np.abs(M) @ np.abs(X).T @ np.abs(Z)
+    assert np.all(np.abs(Y - Yq) <= 64 * 2.0 ** -53 * S)
+    A = oracle_mod.explicit(X, oracle.BILINEAR, M=M)
+    assert np.allclose(A.T, oracle_mod.explicit(X, oracle.BILINEAR, M=M.T), rtol=1e-12, atol=1e-12)
+    assert np.allclose(oracle_mod.explicit(X, oracle.BILINEAR, M=np.eye(5)), X @ X.T, rtol=1e-12, atol=1e-12)
