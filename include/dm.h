@@ -18,6 +18,32 @@
  *            sort of Algorithm 1 and prefix sums of z x^t, t = 0 .. p, combined
  *            as sum_t C(p, t) (-1)^t x^(p-t) (2 P_t - T_t).  Integer data is
  *            exact under the guard ||z||_1 sum_k range_k^p < 2^62.
+ *   DM_L4    f(x, y) = sum_k (x(k) - y(k))^4     l_p^p for even p (Algorithm 5
+ *   DM_L6    f(x, y) = sum_k (x(k) - y(k))^6     and the even-p theorem of
+ *            Appendix A.1): no sort; the moments F_t(k) = sum_j z_j x~_j(k)^t
+ *            of the centred coordinates x~ = x - c (c_k the midpoint of the
+ *            coordinate's range), then per point
+ *            sum_k sum_t C(p, t) (-1)^t x~_i(k)^(p-t) F_t(k).  Float data in
+ *            FP64; integer data exact under the same guard as odd p.
+ *   DM_KL    f(x, y) = sum_k x(k) log(x(k) / y(k)), the KL divergence
+ *            D(x || y) (Algorithm 4 and the KL theorem of Appendix A):
+ *            (A z)_i = -H(x_i) sum_j z_j - sum_k x_i(k) S_k with
+ *            S_k = sum_j z_j log x_j(k).  A is not symmetric.
+ *   DM_CE    f(x, y) = -sum_k x(k) log y(k), the cross entropy (Appendix
+ *            A.3): (A z)_i = -sum_k x_i(k) S_k.  A is not symmetric.
+ *            KL and CE: float data only, every coordinate finite and > 0
+ *            (dm_prepare returns DM_ERR_ARG otherwise); the points need not
+ *            lie on the simplex.
+ *   DM_MAHA2 f(x, y) = (x - y)^T M (x - y), the squared Mahalanobis distance
+ *            for a d x d matrix M (only its symmetric part matters):
+ *            (A z)_i = q_i sum_j z_j + sum_j q_j z_j
+ *                      - x~_i^T (M + M^T) sum_j z_j x~_j,  q_i = x~_i^T M x~_i.
+ *   DM_BILINEAR f(x, y) = x^T M y, the form that the Mahalanobis paragraph of
+ *            Appendix A.2 writes down (Algorithms 8 and 9):
+ *            (A z)_i = x_i^T M (sum_j z_j x_j).
+ *            MAHA2 and BILINEAR: float data only, prepared with
+ *            dm_prepare_matrix.  The sort-free metrics accumulate in FP64
+ *            and round once to FP32.
  *
  * l1: dm_prepare sorts the n values of every coordinate once (Algorithm 1;
  * stable, ties by ascending point index) and keeps the permutations, their
@@ -57,7 +83,19 @@ extern "C" {
 
 typedef struct dm_handle dm_handle;
 
-typedef enum { DM_L1 = 1, DM_L2SQ = 2, DM_TV = 3, DM_L3 = 4, DM_L5 = 5 } dm_metric;
+typedef enum {
+    DM_L1 = 1,
+    DM_L2SQ = 2,
+    DM_TV = 3,
+    DM_L3 = 4,
+    DM_L5 = 5,
+    DM_L4 = 6,
+    DM_L6 = 7,
+    DM_KL = 8,
+    DM_CE = 9,
+    DM_MAHA2 = 10,
+    DM_BILINEAR = 11
+} dm_metric;
 typedef enum { DM_F32 = 1, DM_F64 = 2, DM_I32 = 3, DM_I64 = 4 } dm_dtype;
 typedef enum {
     DM_OK = 0,
@@ -82,11 +120,14 @@ const char* dm_status_string(int32_t status);
 dm_status dm_workspace_size(int64_t n, int32_t d, int32_t metric, int32_t dtype, size_t* bytes);
 
 /*
- * Preparation (Algorithm 1 for l1): validates X, and for l1 builds per
- * coordinate k the stable sorted order perm[k][r], its inverse rank[k][i] and
- * the sorted values xs[k][r]; for every metric the FP64 (int64 for integer
- * data) row sums s_i = sum_k x_ik and squared norms ||x_i||^2.  For l2 squared
- * it keeps a copy of X.
+ * Preparation (Algorithm 1 for l1): validates X, and for the sorted metrics
+ * (l1, TV, odd p) builds per coordinate k the stable sorted order perm[k][r],
+ * its inverse rank[k][i] and the sorted values xs[k][r]; for every metric the
+ * FP64 (int64 for integer data) row sums s_i = sum_k x_ik^p and squared norms
+ * ||x_i||^2.  For l2 squared, odd p and the sort-free metrics it keeps an FP32
+ * (int32) copy of X; for the sort-free metrics also the per-coordinate range
+ * midpoints and, for KL, the per-point values sum_k x_ik log x_ik.
+ * DM_MAHA2 and DM_BILINEAR are prepared with dm_prepare_matrix instead.
  *
  * X: device, n x d row-major of `dtype`; only read during the call.
  * workspace: device memory of at least dm_workspace_size bytes owned by the
@@ -95,10 +136,25 @@ dm_status dm_workspace_size(int64_t n, int32_t d, int32_t metric, int32_t dtype,
  * Blocking: returns after the device work finished.
  * Errors: DM_ERR_ARG, DM_ERR_DTYPE (|x| >= 2^31 in integer data),
  * DM_ERR_NONFINITE (NaN/Inf in X, or an FP64 value beyond the FP32 range),
- * DM_ERR_NOMEM, DM_ERR_DEVICE.  On error *out is NULL and nothing leaks.
+ * DM_ERR_NOMEM, DM_ERR_DEVICE.  DM_ERR_ARG also for DM_KL or DM_CE data with
+ * a coordinate <= 0 (after rounding to FP32), and for DM_MAHA2 or
+ * DM_BILINEAR.  On error *out is NULL and nothing leaks.
  */
 dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_t dtype,
                      void* workspace, size_t ws_bytes, void* stream, dm_handle** out);
+
+/*
+ * Preparation of a metric that carries a d x d matrix (DM_MAHA2,
+ * DM_BILINEAR; the preprocessing of Algorithm 8 in Appendix A.2).  M is HOST
+ * memory, d x d row-major FP64, copied during the call.  For DM_MAHA2 the
+ * per-point values q_i = (x_i - c)^T M (x_i - c) are formed here (O(n d^2)
+ * work, FP64).  Every other argument, the blocking and the errors are those of
+ * dm_prepare; additionally DM_ERR_ARG for another metric or M == NULL, and
+ * DM_ERR_NONFINITE for a NaN or Inf in M.  dm_prepare itself returns
+ * DM_ERR_ARG for these two metrics.
+ */
+dm_status dm_prepare_matrix(const void* X, int64_t n, int32_t d, int32_t metric, int32_t dtype, const double* M,
+                            void* workspace, size_t ws_bytes, void* stream, dm_handle** out);
 
 /*
  * One query: Out = A Z for b right-hand sides at once (b = 1 is the single
@@ -158,10 +214,11 @@ dm_status dm_sync(dm_handle* h);
 dm_status dm_info(const dm_handle* h, int64_t* n, int32_t* d, int32_t* metric, int32_t* dtype);
 
 /*
- * Copy the preparation results of an l1 handle into caller device buffers
+ * Copy the preparation results of a sorted-metric handle into caller device buffers
  * (any may be NULL): perm and rank are d x n uint32, xs is d x n float (float
  * data) or int32 (integer data).  Stream-ordered.  Errors: DM_ERR_ARG,
- * DM_ERR_STATE for an l2-squared handle.
+ * DM_ERR_STATE for a handle of a metric that does not sort (l2 squared and
+ * the sort-free metrics).
  */
 dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, void* xs, void* stream);
 
@@ -217,7 +274,8 @@ dm_status dm_multi_count(const dm_handle* h, int32_t* count);
  * Products with A go through dm_matvec (FP32 in and out, block columns at a
  * time: iters + 1 queries); everything else is FP64 on the device.
  *
- * h: a prepared float handle (l1 or l2 squared).  Omega: device n x block
+ * h: a prepared float handle of a symmetric metric (every metric but DM_KL,
+ * DM_CE and a DM_BILINEAR handle whose M is not symmetric).  Omega: device n x block
  * FP64, the start block, drawn by the caller (the library draws no random
  * numbers).  U: device n x rank FP64 (out), orthonormal columns (zero
  * columns only if A has fewer than `rank` independent directions in the
@@ -227,7 +285,8 @@ dm_status dm_multi_count(const dm_handle* h, int32_t* count);
  * Allocates and frees device memory (about (iters + 2) n block doubles) and
  * synchronises `stream`.
  * Errors: DM_ERR_ARG, DM_ERR_DTYPE (integer handle), DM_ERR_STATE
- * (multi-dataset handle), DM_ERR_NOMEM, DM_ERR_DEVICE, DM_ERR_NONFINITE.
+ * (multi-dataset handle, or A not symmetric), DM_ERR_NOMEM, DM_ERR_DEVICE,
+ * DM_ERR_NONFINITE.
  */
 dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, const double* Omega, double* U,
                      double* lam, void* stream, int32_t* sweeps);
@@ -260,7 +319,7 @@ dm_status dm_embed_l2(const void* X, int64_t n, int32_t d, int32_t dtype, const 
  * number of launches since profiling was last switched on.
  * Errors: DM_ERR_ARG (NULL handle, bad class), DM_ERR_DEVICE.
  */
-typedef enum { DM_K_L1_PASS = 0, DM_K_TOTALS = 1, DM_K_L2 = 2, DM_K_CLASSES = 3 } dm_kernel_class;
+typedef enum { DM_K_L1_PASS = 0, DM_K_TOTALS = 1, DM_K_L2 = 2, DM_K_SORTFREE = 3, DM_K_CLASSES = 4 } dm_kernel_class;
 dm_status dm_profile_enable(dm_handle* h, int32_t on);
 dm_status dm_profile_read(dm_handle* h, int32_t kernel_class, double* total_ms, int64_t* launches);
 

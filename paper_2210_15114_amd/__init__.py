@@ -26,6 +26,13 @@ L2SQ = 2
 TV = 3
 L3 = 4
 L5 = 5
+L4 = 6
+L6 = 7
+KL = 8
+CE = 9
+MAHA2 = 10
+BILINEAR = 11
+MATRIX_METRICS = (MAHA2, BILINEAR)
 F32, F64, I32, I64 = 1, 2, 3, 4
 
 OK = 0
@@ -62,6 +69,8 @@ def lib():
     L.dm_workspace_size.restype = i32
     L.dm_prepare.argtypes = [P, i64, i32, i32, i32, P, sz, P, ctypes.POINTER(P)]
     L.dm_prepare.restype = i32
+    L.dm_prepare_matrix.argtypes = [P, i64, i32, i32, i32, P, P, sz, P, ctypes.POINTER(P)]
+    L.dm_prepare_matrix.restype = i32
     L.dm_matvec.argtypes = [P, P, i32, i32, P, P]
     L.dm_matvec.restype = i32
     L.dm_reserve.argtypes = [P, i32]
@@ -132,7 +141,7 @@ def int_bound_ok(sum_ranges: float, z_l1: float) -> bool:
     return bool(lib().dm_int_bound_ok(float(sum_ranges), float(z_l1)))
 
 
-K_L1_PASS, K_TOTALS, K_L2 = 0, 1, 2
+K_L1_PASS, K_TOTALS, K_L2, K_SORTFREE = 0, 1, 2, 3
 
 
 def copy_probe(dst, src, stream=None):
@@ -307,8 +316,11 @@ def prepare_l2_approx(X, G, stream=None) -> "Handle":
     return h
 
 
-def prepare(X, metric: int = L1, stream=None) -> Handle:
-    """Prepare a point set X (n x d device tensor: float32/float64/int32/int64)."""
+def prepare(X, metric: int = L1, stream=None, M=None) -> Handle:
+    """Prepare a point set X (n x d device tensor: float32/float64/int32/int64).
+
+    M: the d x d matrix of MAHA2 and BILINEAR (host array-like, copied as
+    float64 row-major); must be None for the other metrics."""
     torch = _torch()
     if X.dim() != 2:
         raise ValueError("X must be n x d")
@@ -319,9 +331,18 @@ def prepare(X, metric: int = L1, stream=None) -> Handle:
     off = (-ws.data_ptr()) % 256
     wsv = ws[off:off + ws_bytes]
     h = ctypes.c_void_p(None)
-    st = lib().dm_prepare(_dev_ptr(X, "X"), n, d, metric, code, ctypes.c_void_p(wsv.data_ptr()), ws_bytes,
-                          _stream_ptr(stream), ctypes.byref(h))
-    _check(st, "dm_prepare")
+    if M is None:
+        st = lib().dm_prepare(_dev_ptr(X, "X"), n, d, metric, code, ctypes.c_void_p(wsv.data_ptr()), ws_bytes,
+                              _stream_ptr(stream), ctypes.byref(h))
+        _check(st, "dm_prepare")
+    else:
+        import numpy as np
+        Mh = np.ascontiguousarray(np.asarray(M, dtype=np.float64))
+        if Mh.shape != (d, d):
+            raise ValueError("M must be d x d")
+        st = lib().dm_prepare_matrix(_dev_ptr(X, "X"), n, d, metric, code, Mh.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.c_void_p(wsv.data_ptr()), ws_bytes, _stream_ptr(stream), ctypes.byref(h))
+        _check(st, "dm_prepare_matrix")
     return Handle(h, ws, n, d, metric, code)
 
 

@@ -21,9 +21,30 @@ namespace {
 constexpr size_t ALIGN = 256;
 inline size_t al(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-bool valid_metric(int32_t m) { return m == DM_L1 || m == DM_L2SQ || m == DM_TV || m == DM_L3 || m == DM_L5; }
-// the power p of f(x, y) = sum_k |x(k) - y(k)|^p (TV: p = 1, halved)
-int metric_power(int32_t m) { return m == DM_L2SQ ? 2 : m == DM_L3 ? 3 : m == DM_L5 ? 5 : 1; }
+bool valid_metric(int32_t m) { return m >= DM_L1 && m <= DM_BILINEAR; }
+// the power p of f(x, y) = sum_k |x(k) - y(k)|^p (TV: p = 1, halved; the
+// divergences and quadratic forms: 1, unused)
+int metric_power(int32_t m) {
+    switch (m) {
+    case DM_L2SQ: return 2;
+    case DM_L3: return 3;
+    case DM_L4: return 4;
+    case DM_L5: return 5;
+    case DM_L6: return 6;
+    default: return 1;
+    }
+}
+// metrics answered by moments and one pass over the points (Appendix A)
+bool sf_metric(int32_t m) { return m >= DM_L4 && m <= DM_BILINEAR; }
+int sf_form(int32_t m) {
+    if (m == DM_L4 || m == DM_L6) return SF_EVEN;
+    if (m == DM_KL || m == DM_CE) return SF_LOG;
+    return SF_LIN;
+}
+// metrics whose definition carries a d x d matrix (dm_prepare_matrix)
+bool matrix_metric(int32_t m) { return m == DM_MAHA2 || m == DM_BILINEAR; }
+// metrics defined on float data only
+bool float_only_metric(int32_t m) { return m == DM_TV || m == DM_KL || m == DM_CE || matrix_metric(m); }
 // metrics answered by the l1 pass (TV is half the l1 distance)
 bool l1_pass_metric(int32_t m) { return m == DM_L1 || m == DM_TV; }
 // odd p >= 3: the sorted path with p + 1 running sums
@@ -42,6 +63,7 @@ struct Layout {
     int64_t ld = 0;         // stride between coordinates of the d x n arrays
     uint32_t ntiles = 0;    // sort tiles
     size_t perm = 0, xs = 0, rank = 0, rowsum = 0, rownrm = 0, xcopy = 0, kmin = 0, kmax = 0, flags = 0;
+    size_t centre = 0, mat = 0;   // per-coordinate centre; M and W (d x d each) of the quadratic forms
     size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0;
     size_t k1 = 0, v1 = 0, counts = 0;
     size_t total = 0;
@@ -71,6 +93,8 @@ Layout make_layout(int64_t n, int32_t d, int32_t metric) {
     L.kmin = take((size_t)d * 4);
     L.kmax = take((size_t)d * 4);
     L.flags = take(16);
+    L.centre = take((size_t)d * 8);
+    if (matrix_metric(metric)) L.mat = take((size_t)d * d * 16);
     if (sorted_metric(metric)) {
         L.key_off = take((size_t)d * 8);
         L.key_len = take((size_t)d * 8);
@@ -90,7 +114,8 @@ dm_status check_shape(int64_t n, int32_t d, int32_t metric, int32_t dtype) {
     const int64_t ld = (n + 63) / 64 * 64;
     if ((uint64_t)ld * (uint64_t)d >= (1ull << 32)) return DM_ERR_ARG;   // 32-bit positions
     if (metric == DM_L2SQ && d > L2_MAX_D) return DM_ERR_ARG;
-    if (metric == DM_TV && int_dtype(dtype)) return DM_ERR_DTYPE;   // TV is defined on distributions
+    if (float_only_metric(metric) && int_dtype(dtype)) return DM_ERR_DTYPE;
+    if ((uint64_t)d * (uint64_t)d * 16 >= (1ull << 40)) return DM_ERR_ARG;
     return DM_OK;
 }
 
@@ -144,7 +169,8 @@ struct dm_handle {
     // look-back record regions, one per pass kernel shape (zeroed when created)
     struct Region { int cls; uint64_t* ptr; size_t words; };
     std::vector<Region> regions;
-    double guard_scale = 0.0;   // sum of ranges (l1) or squared ranges (l2 squared)
+    double guard_scale = 0.0;   // sum over the coordinates of range^p
+    bool symmetric = true;      // A = A^T (false for the divergences and a non-symmetric bilinear form)
     hipStream_t last = nullptr;
     // tile variant of the l1 pass per (data path, log2 of the padded block
     // width); -1 until set, tuned or found in the tuning cache (then 0)
@@ -267,7 +293,8 @@ double key_to_double(uint32_t k, bool is_int) {
 
 size_t query_scratch_bytes(const dm_handle* h, int32_t b) {
     size_t s = al(totals_scratch_bytes(h->n, b));
-    if (!sorted_metric(h->metric)) s += al(l2_scratch_bytes(h->n, h->d, b));
+    if (h->metric == DM_L2SQ) s += al(l2_scratch_bytes(h->n, h->d, b));
+    if (sf_metric(h->metric)) s += al(sf_scratch_bytes(h->n, h->d, b, sf_form(h->metric), metric_power(h->metric)));
     if (lp_metric(h->metric)) s += al(lp_moments_bytes(h->n, h->d, b, metric_power(h->metric)));
     return s;
 }
@@ -398,6 +425,63 @@ dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
     return DM_OK;
 }
 
+// The sort-free metrics (Appendix A): the per-coordinate centre, the domain
+// check and per-point weights of the divergences, and the matrices of the
+// quadratic forms.  Blocking.
+dm_status prepare_sortfree(dm_handle* h, const std::vector<uint32_t>& kmin, const std::vector<uint32_t>& kmax,
+                           const double* M, hipStream_t s) {
+    const int32_t d = h->d;
+    const int64_t n = h->n;
+    const Layout& L = h->L;
+    // centre c_k = midpoint of the coordinate's range (integer data: rounded
+    // down, so the centred values stay integers); the even-p and Mahalanobis
+    // moments of x - c are bounded by the range instead of the magnitude
+    if (h->is_int) {
+        std::vector<int64_t> c(d);
+        for (int32_t k = 0; k < d; ++k) {
+            const int64_t lo = (int32_t)(kmin[k] ^ 0x80000000u), hi = (int32_t)(kmax[k] ^ 0x80000000u);
+            c[k] = (lo + hi) >> 1;
+        }
+        DM_TRY(hipMemcpy(h->ws + L.centre, c.data(), (size_t)d * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<double> c(d);
+        for (int32_t k = 0; k < d; ++k) c[k] = 0.5 * (key_to_double(kmin[k], false) + key_to_double(kmax[k], false));
+        DM_TRY(hipMemcpy(h->ws + L.centre, c.data(), (size_t)d * 8, hipMemcpyHostToDevice));
+    }
+    const float* xc = h->at<float>(L.xcopy);
+    if (h->metric == DM_KL || h->metric == DM_CE) {
+        h->symmetric = false;
+        DM_TRY(launch_fill_u32(h->at<uint32_t>(L.flags), 0u, 4, s));
+        DM_TRY(launch_kl_weights(xc, n, d, h->at<double>(L.rowsum), h->at<uint32_t>(L.flags), FLAG_DOMAIN, s));
+        DM_TRY(hipStreamSynchronize(s));
+        uint32_t f = 0;
+        DM_TRY(hipMemcpy(&f, h->ws + L.flags, 4, hipMemcpyDeviceToHost));
+        if (f & FLAG_DOMAIN) return DM_ERR_ARG;
+    }
+    if (matrix_metric(h->metric)) {
+        const size_t dd = (size_t)d * d;
+        std::vector<double> mw(2 * dd);
+        for (size_t e = 0; e < dd; ++e) {
+            if (!std::isfinite(M[e])) return DM_ERR_NONFINITE;
+            mw[e] = M[e];
+        }
+        for (int32_t k = 0; k < d; ++k)
+            for (int32_t l = 0; l < d; ++l) {
+                const double mkl = M[(size_t)k * d + l], mlk = M[(size_t)l * d + k];
+                // Mahalanobis: sum_j z_j (x_i - x_j)^T M (x_i - x_j) carries
+                // -x_i^T (M + M^T) sum_j z_j x_j; the bilinear form carries M
+                mw[dd + (size_t)k * d + l] = h->metric == DM_MAHA2 ? -(mkl + mlk) : mkl;
+                if (h->metric == DM_BILINEAR && mkl != mlk) h->symmetric = false;
+            }
+        DM_TRY(hipMemcpy(h->ws + L.mat, mw.data(), 2 * dd * 8, hipMemcpyHostToDevice));
+        if (h->metric == DM_MAHA2)
+            DM_TRY(launch_maha_weights(xc, h->at<double>(L.centre), n, d, h->at<double>(L.mat), h->at<double>(L.rowsum),
+                                       s));
+        DM_TRY(hipStreamSynchronize(s));
+    }
+    return DM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -429,8 +513,8 @@ int dm_int_bound_ok(double sum_ranges, double z_l1) {
     return (z_l1 * sum_ranges < 4611686018427387904.0) ? 1 : 0;   // 2^62
 }
 
-dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_t dtype, void* workspace,
-                     size_t ws_bytes, void* stream, dm_handle** out) {
+static dm_status prepare_impl(const void* X, int64_t n, int32_t d, int32_t metric, int32_t dtype, const double* M,
+                              void* workspace, size_t ws_bytes, void* stream, dm_handle** out) {
     if (!out) return DM_ERR_ARG;
     *out = nullptr;
     if (!X) return DM_ERR_ARG;
@@ -506,9 +590,28 @@ dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_
         g += rp;
     }
     h->guard_scale = g;
+    if (sf_metric(metric) && (st = prepare_sortfree(h, kmin, kmax, M, s)) != DM_OK) return fail(st);
     h->last = s;
     *out = h;
     return DM_OK;
+}
+
+dm_status dm_prepare(const void* X, int64_t n, int32_t d, int32_t metric, int32_t dtype, void* workspace,
+                     size_t ws_bytes, void* stream, dm_handle** out) {
+    if (matrix_metric(metric)) {
+        if (out) *out = nullptr;
+        return DM_ERR_ARG;   // the quadratic forms need their matrix: dm_prepare_matrix
+    }
+    return prepare_impl(X, n, d, metric, dtype, nullptr, workspace, ws_bytes, stream, out);
+}
+
+dm_status dm_prepare_matrix(const void* X, int64_t n, int32_t d, int32_t metric, int32_t dtype, const double* M,
+                            void* workspace, size_t ws_bytes, void* stream, dm_handle** out) {
+    if (!matrix_metric(metric) || !M) {
+        if (out) *out = nullptr;
+        return DM_ERR_ARG;
+    }
+    return prepare_impl(X, n, d, metric, dtype, M, workspace, ws_bytes, stream, out);
 }
 
 dm_status dm_reserve(dm_handle* h, int32_t b) {
@@ -590,6 +693,48 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
             ProfScope ps(h, DM_K_L1_PASS, s);
             DM_TRY(launch_lp_pass(h->is_int, zkind, pw, b, a, s));
         }
+    } else if (sf_metric(h->metric)) {
+        {
+            ProfScope ps(h, DM_K_TOTALS, s);
+            DM_TRY(launch_totals(h->is_int, zkind, Z, h->n, b, h->ws + h->L.rowsum, h->guard_scale, tot, s));
+        }
+        SfQuery q;
+        q.X = h->ws + h->L.xcopy;
+        q.centre = h->ws + h->L.centre;
+        q.Z = Z;
+        q.n = h->n;
+        q.d = h->d;
+        q.b = b;
+        q.T0 = tot.T0;
+        q.U = nullptr;
+        q.a = nullptr;
+        q.W = nullptr;
+        q.alpha = 1.0;
+        q.Out = Out;
+        const double* weights = h->at<double>(h->L.rowsum);
+        const double* W = h->at<double>(h->L.mat + (size_t)h->d * h->d * 8);
+        switch (h->metric) {
+        case DM_KL:   // -H_i sum z - sum_k x_ik S_k (Algorithm 4)
+            q.alpha = -1.0;
+            q.a = weights;
+            break;
+        case DM_CE:   // -sum_k x_ik S_k
+            q.alpha = -1.0;
+            break;
+        case DM_MAHA2:   // q_i sum z + sum_j q_j z_j - x~_i^T (M + M^T) sum_j z_j x~_j
+            q.W = W;
+            q.a = weights;
+            q.U = (const double*)tot.U;
+            break;
+        case DM_BILINEAR:   // x_i^T M sum_j z_j x_j (Algorithms 8 and 9)
+            q.W = W;
+            q.centre = nullptr;
+            break;
+        default:
+            break;
+        }
+        ProfScope ps(h, DM_K_SORTFREE, s);
+        DM_TRY(launch_sf_query(sf_form(h->metric), metric_power(h->metric), h->is_int, zkind, q, rest, s));
     } else if (l1_pass_metric(h->metric)) {
         {
             ProfScope ps(h, DM_K_TOTALS, s);
@@ -735,6 +880,7 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     if (!h || !Omega || !U || !lam) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
     if (h->is_int) return DM_ERR_DTYPE;
+    if (!h->symmetric) return DM_ERR_STATE;   // the Rayleigh-Ritz step needs A = A^T
     if (block < 1 || block > lr_max_block() || iters < 1 || rank < 1 || rank > lr_max_block()) return DM_ERR_ARG;
     const int64_t K64 = (int64_t)block * iters;
     if (K64 > lr_max_basis() || rank > K64) return DM_ERR_ARG;

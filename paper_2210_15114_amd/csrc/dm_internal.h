@@ -11,7 +11,9 @@ namespace dm {
 enum InKind { IN_F32 = 1, IN_F64 = 2, IN_I32 = 3, IN_I64 = 4 };
 
 // prep flags written by the device
-enum PrepFlag : uint32_t { FLAG_NONFINITE = 1u, FLAG_INT_RANGE = 2u };
+// FLAG_DOMAIN: a coordinate outside the metric's domain (KL divergence and
+// cross entropy take logarithms and need every coordinate finite and > 0)
+enum PrepFlag : uint32_t { FLAG_NONFINITE = 1u, FLAG_INT_RANGE = 2u, FLAG_DOMAIN = 4u };
 
 // sticky query status bits (device side)
 // QF_STALL: a chained scan waited too long for a predecessor's record (a
@@ -199,6 +201,33 @@ hipError_t launch_lp_pass(bool is_int, int zkind, int p, int32_t b, const LpPass
 hipError_t launch_scale_f32(float* p, size_t count, float s, hipStream_t st);
 hipError_t launch_embed_l2(int kind, const void* X, int64_t n, int32_t d, const double* G, int32_t k, float* Xout,
                            hipStream_t s);
+
+// ---- the sort-free family (k_sortfree.hip) ---------------------------------
+// SF_EVEN: l_p^p for even p; SF_LOG: moments of log x (KL, cross entropy);
+// SF_LIN: moments of the centred coordinates mixed by a d x d matrix
+enum SfForm { SF_EVEN = 1, SF_LOG = 2, SF_LIN = 3 };
+struct SfQuery {
+    const void* X;          // n x d point copy (float | int32)
+    const void* centre;     // d (double | int64) subtracted from every coordinate, or NULL
+    const void* Z;          // n x b (float | int32 | int64)
+    int64_t n;
+    int32_t d, b;
+    const void* T0;         // b (double | int64): sum_j z_j
+    const double* U;        // b, added to every row, or NULL
+    const double* a;        // n: a_i T0 added to row i, or NULL
+    const double* W;        // d x d applied to the moments, or NULL
+    double alpha;           // scale of the moments when W is NULL
+    void* Out;              // n x b (float | int64)
+};
+int sf_moment_count(int form, int p);
+size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p);
+hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuery& q, void* scratch, hipStream_t s);
+// negH[i] = sum_k x_ik log x_ik; sets `bad` in *flags for a coordinate that is not finite and > 0
+hipError_t launch_kl_weights(const float* X, int64_t n, int32_t d, double* negH, uint32_t* flags, uint32_t bad,
+                             hipStream_t s);
+// q[i] = (x_i - c)^T M (x_i - c)
+hipError_t launch_maha_weights(const float* X, const double* centre, int64_t n, int32_t d, const double* M, double* q,
+                               hipStream_t s);
 
 // ---- l2 squared query ------------------------------------------------------
 size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b);

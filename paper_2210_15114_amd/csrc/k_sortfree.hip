@@ -1,0 +1,541 @@
+// k_sortfree.hip - the distance functions whose query needs no sort: per-
+// coordinate moments of the right-hand sides, then one pass over the points
+// (Appendix A: the KL divergence of Algorithm 4, l_p^p for even p of
+// Algorithm 5, the bilinear form of Algorithms 8 and 9, and the squared
+// Mahalanobis distance and cross entropy that follow the same pattern).
+//
+//  even p:     (A z)_i = sum_k sum_(t=0..p) C(p, t) (-1)^t x~_ik^(p-t) F_t(k),
+//              F_t(k) = sum_j z_j x~_jk^t,  F_0 = sum z,  x~ = x - c (a
+//              per-coordinate centre; the distance is translation invariant)
+//  linear:     (A z)_i = sum_k x~_ik V(k) + a_i sum_j z_j + U,
+//              V = alpha W F (W a d x d matrix, or the identity),
+//              F(k) = sum_j z_j phi(x_jk),  phi = log (KL, cross entropy) or
+//              the centred coordinate (Mahalanobis, bilinear form)
+//
+// Stage 1 (moments) reduces over the points: a workgroup owns a range of
+// rows and a range of coordinates and keeps per-thread sums for a few
+// coordinates of one column; stage 2 adds the row ranges in a fixed order and
+// applies the binomial coefficients (even p) or the scale alpha; an optional
+// mix applies W.  The apply stage gives every thread one column and a few
+// points, with the moments of a coordinate chunk and the points' coordinates
+// staged in LDS.  Float data accumulates in FP64 and rounds once to FP32;
+// integer data (even p) runs in wrapping int64, exact whenever the result
+// fits.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "dm_internal.h"
+
+namespace dm {
+namespace {
+
+constexpr int MSR = 32;   // rows per LDS tile of the moments stage
+constexpr int MKG = 4;    // coordinate groups per moments workgroup
+
+template <int NT>
+constexpr int moments_kpt() { return NT == 1 ? 16 : NT <= 4 ? 8 : 4; }
+
+template <typename ACC>
+__device__ __forceinline__ ACC mul_acc(ACC a, ACC b) {
+    if constexpr (std::is_same<ACC, double>::value) return a * b;
+    else return (ACC)((uint64_t)a * (uint64_t)b);
+}
+template <typename ACC>
+__device__ __forceinline__ ACC fma_acc(ACC a, ACC b, ACC c) {
+    if constexpr (std::is_same<ACC, double>::value) return fma(a, b, c);
+    else return (ACC)((uint64_t)a * (uint64_t)b + (uint64_t)c);
+}
+template <typename ACC>
+__device__ __forceinline__ ACC add_acc(ACC a, ACC b) {
+    if constexpr (std::is_same<ACC, double>::value) return a + b;
+    else return (ACC)((uint64_t)a + (uint64_t)b);
+}
+
+// feature of one coordinate value: the centred value, or its logarithm
+template <typename XT, typename ACC, bool LOG>
+__device__ __forceinline__ ACC feature(XT x, const ACC* centre, int k) {
+    if constexpr (LOG) return (ACC)log((double)x);
+    else return centre ? (ACC)((ACC)x - centre[k]) : (ACC)x;
+}
+
+// part[blk][t][k][c] = sum over the workgroup's rows of z_jc phi(x_jk)^(t+1),
+// t = 0 .. NT-1.  Threads: column c = tid % BW, coordinate group
+// (tid / BW) % MKG, row stripe tid / (BW MKG).
+template <typename XT, typename ZT, typename ACC, int NT, bool LOG, int BW>
+__global__ __launch_bounds__(256) void sf_moments_kernel(const XT* __restrict__ X, const ACC* __restrict__ centre,
+                                                         const ZT* __restrict__ Z, int64_t n, int32_t d, int32_t b,
+                                                         int64_t rows_per_blk, ACC* __restrict__ part)
+{
+    constexpr int KPT = moments_kpt<NT>();
+    constexpr int KC = MKG * KPT;
+    constexpr int RS = 256 / (BW * MKG) > 0 ? 256 / (BW * MKG) : 1;
+    constexpr int XS = KC + 1, ZS = BW + 1;
+    constexpr int STAGE = MSR * XS + MSR * ZS;
+    constexpr int RED = RS > 1 ? 256 * KPT : 0;
+    __shared__ ACC smem[STAGE > RED ? STAGE : RED];
+    ACC* sX = smem;
+    ACC* sZ = smem + MSR * XS;
+    const int tid = threadIdx.x;
+    const int c = tid % BW, kg = (tid / BW) % MKG, rs = tid / (BW * MKG);
+    const int k0 = blockIdx.y * KC;
+    const int64_t rb = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t re = rb + rows_per_blk < n ? rb + rows_per_blk : n;
+    ACC acc[KPT][NT];
+#pragma unroll
+    for (int q = 0; q < KPT; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[q][t] = ACC(0);
+    for (int64_t r0 = rb; r0 < re; r0 += MSR) {
+        const int nr = (int)(re - r0 < MSR ? re - r0 : MSR);
+        for (int e = tid; e < MSR * KC; e += 256) {
+            const int r = e / KC, kk = e % KC;
+            ACC v = ACC(0);
+            if (r < nr && k0 + kk < d) v = feature<XT, ACC, LOG>(X[(r0 + r) * d + k0 + kk], centre, k0 + kk);
+            sX[r * XS + kk] = v;
+        }
+        for (int e = tid; e < MSR * BW; e += 256) {
+            const int r = e / BW, cc = e % BW;
+            sZ[r * ZS + cc] = (r < nr && cc < b) ? (ACC)Z[(r0 + r) * b + cc] : ACC(0);
+        }
+        __syncthreads();
+        for (int r = rs; r < nr; r += RS) {
+            const ACC z = sZ[r * ZS + c];
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                const ACC x = sX[r * XS + kg * KPT + q];
+                ACC xt = x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    acc[q][t] = fma_acc(xt, z, acc[q][t]);
+                    if (t + 1 < NT) xt = mul_acc(xt, x);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // sum the row stripes (fixed order), one moment at a time
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if constexpr (RS > 1) {
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) smem[q * 256 + tid] = acc[q][t];
+            __syncthreads();
+            if (rs == 0) {
+#pragma unroll
+                for (int q = 0; q < KPT; ++q) {
+                    ACC s = ACC(0);
+                    for (int st = 0; st < RS; ++st) s = add_acc(s, smem[q * 256 + st * BW * MKG + tid]);
+                    acc[q][t] = s;
+                }
+            }
+            __syncthreads();
+        }
+        if (rs == 0 && c < b) {
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                const int k = k0 + kg * KPT + q;
+                if (k < d) part[(((size_t)blockIdx.x * NT + t) * d + k) * b + c] = acc[q][t];
+            }
+        }
+    }
+}
+
+__host__ __device__ constexpr int64_t binom_sf(int p, int t) {
+    int64_t r = 1;
+    for (int i = 0; i < t; ++i) r = r * (p - i) / (i + 1);
+    return r;
+}
+
+// G[t][k][c] = coef_t sum_blk part[blk][t][k][c]; coef_t = C(p, t + 1) (-1)^(t + 1)
+// when p > 0 (even p), alpha otherwise (float only)
+template <typename ACC>
+__global__ __launch_bounds__(256) void sf_reduce_kernel(const ACC* __restrict__ part, int nblk, int64_t per_t,
+                                                        int nt, int p, double alpha, ACC* __restrict__ G)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t count = per_t * nt;
+    if (e >= count) return;
+    ACC s = ACC(0);
+    for (int k = 0; k < nblk; ++k) s = add_acc(s, part[(size_t)k * count + e]);
+    if (p > 0) {
+        const int t = (int)(e / per_t) + 1;
+        const int64_t cf = ((t & 1) ? -1 : 1) * binom_sf(p, t);
+        G[e] = mul_acc(s, (ACC)cf);
+    } else {
+        G[e] = (ACC)(alpha * (double)s);
+    }
+}
+
+// V[k][c] = sum_l W[k][l] F[l][c]
+__global__ __launch_bounds__(256) void sf_mix_kernel(const double* __restrict__ W, const double* __restrict__ F,
+                                                     int32_t d, int32_t b, double* __restrict__ V)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)d * b) return;
+    const int k = (int)(e / b), c = (int)(e % b);
+    double s = 0.0;
+    for (int l = 0; l < d; ++l) s = fma(W[(size_t)k * d + l], F[(size_t)l * b + c], s);
+    V[e] = s;
+}
+
+template <int BW> constexpr int apply_ppt() { return BW >= 8 ? BW / 8 : 1; }
+template <int NT, int BW> constexpr int apply_kc() { return (NT <= 2 && BW >= 4) ? 32 : 16; }
+
+// Out[i][c] for every point i and column c.  Thread: column c = tid % BW,
+// point group tid / BW owning points i0 + q (256 / BW) + group, q < PPT.
+//   EVEN (NT = p):  sum_k Horner in x~_ik over G_0 = T0, G_1 .. G_p
+//   LIN  (NT = 1):  sum_k x~_ik V(k) + a_i T0 + U
+template <typename XT, typename ACC, typename OT, int NT, bool EVEN, int BW>
+__global__ __launch_bounds__(256) void sf_apply_kernel(const XT* __restrict__ X, const ACC* __restrict__ centre,
+                                                       int64_t n, int32_t d, int32_t b, const ACC* __restrict__ T0,
+                                                       const ACC* __restrict__ G, const double* __restrict__ a,
+                                                       const double* __restrict__ U, OT* __restrict__ Out)
+{
+    constexpr int PPT = apply_ppt<BW>();
+    constexpr int PG = 256 / BW;
+    constexpr int NPB = PG * PPT;
+    constexpr int KC = apply_kc<NT, BW>();
+    constexpr int XS = KC + 1;
+    __shared__ ACC sX[NPB * XS];
+    __shared__ ACC sG[NT * KC * BW];
+    const int tid = threadIdx.x;
+    const int c = tid % BW, pg = tid / BW;
+    const int64_t i0 = (int64_t)blockIdx.x * NPB;
+    const bool col_ok = c < b;
+    const ACC t0 = col_ok ? T0[c] : ACC(0);
+    ACC acc[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) acc[q] = ACC(0);
+    const size_t per_t = (size_t)d * b;
+    for (int k0 = 0; k0 < d; k0 += KC) {
+        for (int e = tid; e < NPB * KC; e += 256) {
+            const int p = e / KC, kk = e % KC;
+            const int64_t i = i0 + p;
+            ACC v = ACC(0);
+            if (i < n && k0 + kk < d) v = feature<XT, ACC, false>(X[i * d + k0 + kk], centre, k0 + kk);
+            sX[p * XS + kk] = v;
+        }
+        for (int e = tid; e < NT * KC * BW; e += 256) {
+            const int t = e / (KC * BW), rem = e % (KC * BW);
+            const int kk = rem / BW, cq = rem % BW;
+            sG[e] = (k0 + kk < d && cq < b) ? G[t * per_t + (size_t)(k0 + kk) * b + cq] : ACC(0);
+        }
+        __syncthreads();
+        const int kn = d - k0 < KC ? d - k0 : KC;
+        for (int kk = 0; kk < kn; ++kk) {
+            ACC g[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) g[t] = sG[(t * KC + kk) * BW + c];
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const ACC x = sX[(q * PG + pg) * XS + kk];
+                if constexpr (EVEN) {
+                    ACC h = t0;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) h = fma_acc(h, x, g[t]);
+                    acc[q] = add_acc(acc[q], h);
+                } else {
+                    acc[q] = fma_acc(x, g[0], acc[q]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!col_ok) return;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int64_t i = i0 + q * PG + pg;
+        if (i >= n) continue;
+        ACC s = acc[q];
+        if constexpr (!EVEN) {
+            if (a) s = fma(a[i], (double)t0, s);
+            if (U) s += U[c];
+        }
+        Out[i * b + c] = (OT)s;
+    }
+}
+
+// ---- per-point weights at preparation --------------------------------------
+// negH[i] = sum_k x_ik log x_ik; flags |= bad for a coordinate that is not
+// finite and positive (its logarithm is not finite)
+__global__ __launch_bounds__(256) void kl_weights_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                         double* __restrict__ negH, uint32_t* __restrict__ flags,
+                                                         uint32_t bad)
+{
+    constexpr int PR = 64, KC = 32;
+    __shared__ double sT[PR][KC + 1];
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * PR;
+    double s = 0.0;
+    bool fault = false;
+    for (int k0 = 0; k0 < d; k0 += KC) {
+        for (int e = tid; e < PR * KC; e += 256) {
+            const int p = e / KC, kk = e % KC;
+            const int64_t i = i0 + p;
+            double v = 0.0;
+            if (i < n && k0 + kk < d) {
+                const double x = (double)X[i * d + k0 + kk];
+                if (x > 0.0 && x <= 3.4028234663852886e38) v = x * log(x);
+                else fault = true;
+            }
+            sT[p][kk] = v;
+        }
+        __syncthreads();
+        if (tid < PR)
+            for (int kk = 0; kk < KC; ++kk) s += sT[tid][kk];
+        __syncthreads();
+    }
+    if (tid < PR && i0 + tid < n) negH[i0 + tid] = s;
+    if (fault) atomicOr(flags, bad);
+}
+
+// q[i] = x~_i^T M x~_i, x~ = x - c.  A workgroup owns 64 points and walks 64
+// rows of M at a time: P = X~ M_rows^T from LDS tiles (32 coordinates per
+// step, 4 x 4 outputs per thread), then q += sum over the rows of x~_ik P_ik.
+__global__ __launch_bounds__(256) void maha_weights_kernel(const float* __restrict__ X, const double* __restrict__ centre,
+                                                           int64_t n, int32_t d, const double* __restrict__ M,
+                                                           double* __restrict__ q)
+{
+    constexpr int PR = 64, MR = 64, LC = 32;
+    __shared__ double sX[PR][LC + 1];
+    __shared__ double sM[MR][LC + 1];
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * PR;
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double qa[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < d; m0 += MR) {
+        double acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int l0 = 0; l0 < d; l0 += LC) {
+            for (int e = tid; e < PR * LC; e += 256) {
+                const int p = e / LC, l = e % LC;
+                const int64_t i = i0 + p;
+                sX[p][l] = (i < n && l0 + l < d) ? (double)X[i * d + l0 + l] - centre[l0 + l] : 0.0;
+            }
+            for (int e = tid; e < MR * LC; e += 256) {
+                const int r = e / LC, l = e % LC;
+                sM[r][l] = (m0 + r < d && l0 + l < d) ? M[(size_t)(m0 + r) * d + l0 + l] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int l = 0; l < LC; ++l) {
+                double xa[4], ma[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    xa[i] = sX[tr + i][l];
+                    ma[i] = sM[tc + i][l];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = fma(xa[i], ma[j], acc[i][j]);
+            }
+            __syncthreads();
+        }
+        // acc[i][j] = (M x~_(tr+i))_(m0+tc+j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = i0 + tr + i;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = m0 + tc + j;
+                if (row < n && k < d) qa[i] = fma((double)X[row * d + k] - centre[k], acc[i][j], qa[i]);
+            }
+        }
+    }
+    // the 16 threads of a row group hold disjoint parts of the same 4 sums
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) qa[i] += __shfl_xor(qa[i], off, 16);
+    if (tid % 16 == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i0 + tr + i < n) q[i0 + tr + i] = qa[i];
+    }
+}
+
+// ---- host side --------------------------------------------------------------
+int pad_bw(int32_t b) {
+    int w = 1;
+    while (w < b) w <<= 1;
+    return w;
+}
+
+template <int NT>
+constexpr int moments_kc() { return MKG * moments_kpt<NT>(); }
+
+int kc_for(int nt) { return nt == 1 ? moments_kc<1>() : nt <= 4 ? moments_kc<4>() : moments_kc<6>(); }
+
+// rows per moments workgroup: about 2048 workgroups over the grid, whole tiles
+int64_t moments_rows(int64_t n, int32_t d, int kc) {
+    const int64_t kblk = (d + kc - 1) / kc;
+    int64_t want = 2048 / kblk;
+    if (want < 1) want = 1;
+    int64_t r = (n + want - 1) / want;
+    r = (r + MSR - 1) / MSR * MSR;
+    return r < MSR ? MSR : r;
+}
+
+template <typename XT, typename ZT, typename ACC, int NT, bool LOG, int BW>
+hipError_t moments_bw(const void* X, const void* centre, const void* Z, int64_t n, int32_t d, int32_t b, void* part,
+                      int64_t* nblk_out, hipStream_t s)
+{
+    constexpr int KC = moments_kc<NT>();
+    const int64_t rpb = moments_rows(n, d, KC);
+    const int64_t nblk = (n + rpb - 1) / rpb;
+    *nblk_out = nblk;
+    dim3 grid((unsigned)nblk, (unsigned)((d + KC - 1) / KC));
+    sf_moments_kernel<XT, ZT, ACC, NT, LOG, BW><<<grid, 256, 0, s>>>(
+        (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, rpb, (ACC*)part);
+    return hipGetLastError();
+}
+
+template <typename XT, typename ZT, typename ACC, int NT, bool LOG>
+hipError_t moments_t(int32_t b, const void* X, const void* centre, const void* Z, int64_t n, int32_t d, void* part,
+                     int64_t* nblk, hipStream_t s)
+{
+    switch (pad_bw(b)) {
+    case 1: return moments_bw<XT, ZT, ACC, NT, LOG, 1>(X, centre, Z, n, d, b, part, nblk, s);
+    case 2: return moments_bw<XT, ZT, ACC, NT, LOG, 2>(X, centre, Z, n, d, b, part, nblk, s);
+    case 4: return moments_bw<XT, ZT, ACC, NT, LOG, 4>(X, centre, Z, n, d, b, part, nblk, s);
+    case 8: return moments_bw<XT, ZT, ACC, NT, LOG, 8>(X, centre, Z, n, d, b, part, nblk, s);
+    case 16: return moments_bw<XT, ZT, ACC, NT, LOG, 16>(X, centre, Z, n, d, b, part, nblk, s);
+    case 32: return moments_bw<XT, ZT, ACC, NT, LOG, 32>(X, centre, Z, n, d, b, part, nblk, s);
+    case 64: return moments_bw<XT, ZT, ACC, NT, LOG, 64>(X, centre, Z, n, d, b, part, nblk, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename XT, typename ACC, typename OT, int NT, bool EVEN, int BW>
+hipError_t apply_bw(const void* X, const void* centre, int64_t n, int32_t d, int32_t b, const void* T0, const void* G,
+                    const double* a, const double* U, void* Out, hipStream_t s)
+{
+    constexpr int NPB = (256 / BW) * apply_ppt<BW>();
+    const unsigned grid = (unsigned)((n + NPB - 1) / NPB);
+    sf_apply_kernel<XT, ACC, OT, NT, EVEN, BW><<<grid, 256, 0, s>>>((const XT*)X, (const ACC*)centre, n, d, b,
+                                                                   (const ACC*)T0, (const ACC*)G, a, U, (OT*)Out);
+    return hipGetLastError();
+}
+
+template <typename XT, typename ACC, typename OT, int NT, bool EVEN>
+hipError_t apply_t(const void* X, const void* centre, int64_t n, int32_t d, int32_t b, const void* T0, const void* G,
+                   const double* a, const double* U, void* Out, hipStream_t s)
+{
+    switch (pad_bw(b)) {
+    case 1: return apply_bw<XT, ACC, OT, NT, EVEN, 1>(X, centre, n, d, b, T0, G, a, U, Out, s);
+    case 2: return apply_bw<XT, ACC, OT, NT, EVEN, 2>(X, centre, n, d, b, T0, G, a, U, Out, s);
+    case 4: return apply_bw<XT, ACC, OT, NT, EVEN, 4>(X, centre, n, d, b, T0, G, a, U, Out, s);
+    case 8: return apply_bw<XT, ACC, OT, NT, EVEN, 8>(X, centre, n, d, b, T0, G, a, U, Out, s);
+    case 16: return apply_bw<XT, ACC, OT, NT, EVEN, 16>(X, centre, n, d, b, T0, G, a, U, Out, s);
+    case 32: return apply_bw<XT, ACC, OT, NT, EVEN, 32>(X, centre, n, d, b, T0, G, a, U, Out, s);
+    case 64: return apply_bw<XT, ACC, OT, NT, EVEN, 64>(X, centre, n, d, b, T0, G, a, U, Out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename ACC>
+hipError_t reduce_launch(const void* part, int64_t nblk, int64_t per_t, int nt, int p, double alpha, void* G,
+                         hipStream_t s)
+{
+    const int64_t count = per_t * nt;
+    sf_reduce_kernel<ACC><<<(unsigned)((count + 255) / 256), 256, 0, s>>>((const ACC*)part, (int)nblk, per_t, nt, p,
+                                                                          alpha, (ACC*)G);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char* G, hipStream_t s)
+{
+    int64_t nblk = 0;
+    hipError_t e;
+    const int64_t per_t = (int64_t)q.d * q.b;
+    if (!is_int) {
+        e = moments_t<float, float, double, P, false>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+        if (e != hipSuccess) return e;
+        if ((e = reduce_launch<double>(part, nblk, per_t, P, P, 1.0, G, s)) != hipSuccess) return e;
+        return apply_t<float, double, float, P, true>(q.X, q.centre, q.n, q.d, q.b, q.T0, G, nullptr, nullptr, q.Out,
+                                                      s);
+    }
+    if (zkind == IN_I32)
+        e = moments_t<int32_t, int32_t, int64_t, P, false>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+    else
+        e = moments_t<int32_t, int64_t, int64_t, P, false>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+    if (e != hipSuccess) return e;
+    if ((e = reduce_launch<int64_t>(part, nblk, per_t, P, P, 1.0, G, s)) != hipSuccess) return e;
+    return apply_t<int32_t, int64_t, int64_t, P, true>(q.X, q.centre, q.n, q.d, q.b, q.T0, G, nullptr, nullptr,
+                                                       q.Out, s);
+}
+
+}  // namespace
+
+int sf_moment_count(int form, int p) { return form == SF_EVEN ? p : 1; }
+
+size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p) {
+    const int nt = sf_moment_count(form, p);
+    const int64_t rpb = moments_rows(n, d, kc_for(nt));
+    const int64_t nblk = (n + rpb - 1) / rpb;
+    const size_t cnt = (size_t)nt * d * b;
+    return ((size_t)nblk + 2) * cnt * 8;   // row-range partials, the moments, the mixed moments
+}
+
+hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuery& q, void* scratch, hipStream_t s)
+{
+    if (q.b < 1 || q.b > 64 || q.n < 1 || q.d < 1) return hipErrorInvalidValue;
+    const int nt = sf_moment_count(form, p);
+    const int64_t rpb = moments_rows(q.n, q.d, kc_for(nt));
+    const int64_t nblk_max = (q.n + rpb - 1) / rpb;
+    const size_t cnt = (size_t)nt * q.d * q.b;
+    char* part = (char*)scratch;
+    char* G = part + (size_t)nblk_max * cnt * 8;
+    char* V = G + cnt * 8;
+    if (form == SF_EVEN) {
+        switch (p) {
+        case 2: return even_query<2>(is_int, zkind, q, part, G, s);
+        case 4: return even_query<4>(is_int, zkind, q, part, G, s);
+        case 6: return even_query<6>(is_int, zkind, q, part, G, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (is_int) return hipErrorInvalidValue;
+    int64_t nblk = 0;
+    const int64_t per_t = (int64_t)q.d * q.b;
+    hipError_t e = (form == SF_LOG)
+                       ? moments_t<float, float, double, 1, true>(q.b, q.X, nullptr, q.Z, q.n, q.d, part, &nblk, s)
+                       : moments_t<float, float, double, 1, false>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+    if (e != hipSuccess) return e;
+    const char* Gv = G;
+    if (q.W) {
+        if ((e = reduce_launch<double>(part, nblk, per_t, 1, 0, 1.0, G, s)) != hipSuccess) return e;
+        sf_mix_kernel<<<(unsigned)((per_t + 255) / 256), 256, 0, s>>>(q.W, (const double*)G, q.d, q.b, (double*)V);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        Gv = V;
+    } else {
+        if ((e = reduce_launch<double>(part, nblk, per_t, 1, 0, q.alpha, G, s)) != hipSuccess) return e;
+    }
+    return apply_t<float, double, float, 1, false>(q.X, form == SF_LOG ? nullptr : q.centre, q.n, q.d, q.b, q.T0, Gv,
+                                                   q.a, q.U, q.Out, s);
+}
+
+hipError_t launch_kl_weights(const float* X, int64_t n, int32_t d, double* negH, uint32_t* flags, uint32_t bad,
+                             hipStream_t s)
+{
+    if (n < 1 || d < 1) return hipErrorInvalidValue;
+    kl_weights_kernel<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(X, n, d, negH, flags, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_maha_weights(const float* X, const double* centre, int64_t n, int32_t d, const double* M, double* q,
+                               hipStream_t s)
+{
+    if (n < 1 || d < 1) return hipErrorInvalidValue;
+    maha_weights_kernel<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(X, centre, n, d, M, q);
+    return hipGetLastError();
+}
+
+}  // namespace dm

@@ -77,6 +77,27 @@ def gaussian_mixture(n: int, d: int, k: int, seed: int, mean_scale: float = 5.0,
     return g.standard_normal((n, d)) + means[comp]
 
 
+def simplex_points(n: int, d: int, seed: int, alpha: float = 1.0, dtype=np.float32) -> np.ndarray:
+    """Probability vectors: Dirichlet(alpha, ..., alpha) rows, every coordinate
+    > 0 after rounding to dtype (a draw that rounds to 0 is raised to the
+    smallest normal number of dtype)."""
+    g = rng(seed)
+    P = g.dirichlet(np.full(d, float(alpha)), size=n).astype(dtype)
+    return np.maximum(P, np.finfo(dtype).tiny)
+
+
+def square_matrix(d: int, seed: int, kind: str = "spd") -> np.ndarray:
+    """A d x d FP64 matrix: "spd" = B B^T / d + I/2 (B ~ N(0,1)),
+    "general" = N(0,1) / sqrt(d) entries (neither symmetric nor definite)."""
+    g = rng(seed)
+    B = g.standard_normal((d, d))
+    if kind == "spd":
+        return B @ B.T / d + 0.5 * np.eye(d)
+    if kind == "general":
+        return B / math.sqrt(d)
+    raise ValueError(kind)
+
+
 # ----------------------------------------------------------------------------
 # right-hand sides
 # ----------------------------------------------------------------------------

@@ -43,7 +43,8 @@ def test_workspace_size_validation(L):
     f = L.dm_workspace_size
     assert f(0, 4, dm.L1, dm.F32, ctypes.byref(out)) == dm.ERR_ARG
     assert f(10, 0, dm.L1, dm.F32, ctypes.byref(out)) == dm.ERR_ARG
-    assert f(10, 4, 7, dm.F32, ctypes.byref(out)) == dm.ERR_ARG
+    assert f(10, 4, 99, dm.F32, ctypes.byref(out)) == dm.ERR_ARG
+    assert f(10, 4, 0, dm.F32, ctypes.byref(out)) == dm.ERR_ARG
     assert f(10, 4, dm.L1, 9, ctypes.byref(out)) == dm.ERR_ARG
     assert f(10, 4, dm.L1, dm.F32, None) == dm.ERR_ARG
     assert f(1 << 31, 4, dm.L1, dm.F32, ctypes.byref(out)) == dm.ERR_ARG       # 32-bit positions
@@ -62,12 +63,45 @@ def test_prepare_argument_errors_before_device(L):
     assert P(None, 10, 4, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
     assert P(fake, 0, 4, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
     assert P(fake, 10, -1, dm.L1, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
-    assert P(fake, 10, 4, 9, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, 4, 99, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
     assert P(fake, 10, 4, dm.TV, dm.I32, None, 0, None, ctypes.byref(h)) == dm.ERR_DTYPE
     assert P(fake, 10, 4, dm.L1, 0, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
     assert P(fake, 10, 4, dm.L1, dm.F32, fake, 16, None, ctypes.byref(h)) == dm.ERR_ARG   # short workspace
     assert P(fake, 10, 4, dm.L1, dm.F32, None, 0, None, None) == dm.ERR_ARG
+    for metric in (dm.KL, dm.CE):                      # logarithms: float data only
+        assert P(fake, 10, 4, metric, dm.I32, None, 0, None, ctypes.byref(h)) == dm.ERR_DTYPE
+    for metric in dm.MATRIX_METRICS:                   # the matrix comes through dm_prepare_matrix
+        assert P(fake, 10, 4, metric, dm.F32, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
     assert h.value is None
+
+
+def test_prepare_matrix_argument_errors_before_device(L):
+    import numpy as np
+    h = ctypes.c_void_p(None)
+    fake = ctypes.c_void_p(0x1000)
+    M = np.eye(4)
+    Mp = M.ctypes.data_as(ctypes.c_void_p)
+    P = L.dm_prepare_matrix
+    assert P(fake, 10, 4, dm.L1, dm.F32, Mp, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG      # no matrix metric
+    assert P(fake, 10, 4, dm.MAHA2, dm.F32, None, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG  # M missing
+    assert P(None, 10, 4, dm.MAHA2, dm.F32, Mp, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, 4, dm.MAHA2, dm.I32, Mp, None, 0, None, ctypes.byref(h)) == dm.ERR_DTYPE
+    assert P(fake, 10, 4, dm.BILINEAR, dm.I64, Mp, None, 0, None, ctypes.byref(h)) == dm.ERR_DTYPE
+    assert P(fake, 0, 4, dm.BILINEAR, dm.F32, Mp, None, 0, None, ctypes.byref(h)) == dm.ERR_ARG
+    assert P(fake, 10, 4, dm.BILINEAR, dm.F32, Mp, None, 0, None, None) == dm.ERR_ARG
+    assert h.value is None
+    if not _has_gpu():
+        assert P(fake, 10, 4, dm.MAHA2, dm.F32, Mp, None, 0, None, ctypes.byref(h)) == dm.ERR_DEVICE
+
+
+def test_workspace_of_the_sort_free_metrics(L):
+    n, d = 1000, 16
+    base = dm.workspace_size(n, d, dm.L4, dm.F32)
+    assert base >= n * d * 4                           # the point copy
+    assert dm.workspace_size(n, d, dm.L6, dm.I32) == base
+    assert dm.workspace_size(n, d, dm.KL, dm.F32) == base
+    assert dm.workspace_size(n, d, dm.MAHA2, dm.F32) >= base + 2 * d * d * 8   # M and W
+    assert dm.workspace_size(n, d, dm.L4, dm.F32) < dm.workspace_size(n, d, dm.L1, dm.F32)   # no sort arrays
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")

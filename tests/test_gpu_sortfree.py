@@ -1,0 +1,299 @@
+"""The sort-free family of Appendix A on the GPU: l_p^p for even p (Algorithm
+5 with the binomial coefficients restored), the KL divergence (Algorithm 4),
+cross entropy, the squared Mahalanobis distance and the bilinear form of
+Algorithms 8 and 9.
+
+Integer data (even p) is bit-exact against the exact oracle.  Float data is
+checked against the FP64 oracle on the same FP32 inputs: normalised error
+<= 1e-6, and per output
+
+    |y - o| <= 2 u32 |o| + (n + d + 4p + 16) u64 S,
+
+where the first term is the one rounding of the FP64 result to FP32 and S
+bounds the magnitude of every term the FP64 moments and the per-point sums
+form (for even p: sum_k sum_t C(p, t) |x~_ik|^(p-t) sum_j |z_j| |x~_jk|^t
+with x~ = x - c, c the midpoint of each coordinate's range).
+"""
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import metrics
+
+from gpu_helpers import U32, dev
+
+pytestmark = pytest.mark.gpu
+dm = pytest.importorskip("paper_2210_15114_amd")
+
+U64 = 2.0 ** -53
+EVEN = {4: oracle.L4, 6: oracle.L6}
+
+
+def _centre(X):
+    X = X.astype(np.float64)
+    return 0.5 * (X.min(axis=0) + X.max(axis=0))
+
+
+# Each scale function returns S on the given rows (m x b).
+def _scale_even(p):
+    def f(X, Z, r):
+        Xc = np.abs(X.astype(np.float64) - _centre(X))
+        Z = np.abs(Z.astype(np.float64)).reshape(X.shape[0], -1)
+        S = np.zeros((r.size, Z.shape[1]))
+        for k in range(X.shape[1]):
+            xk = Xc[:, k]
+            for t in range(p + 1):
+                S += comb(p, t) * (xk[r] ** (p - t))[:, None] * ((xk ** t) @ Z)[None, :]
+        return S
+    return f
+
+
+def _scale_log(entropy):
+    def f(X, Z, r):
+        X = X.astype(np.float64)
+        Z = np.abs(Z.astype(np.float64)).reshape(X.shape[0], -1)
+        L = np.abs(np.log(X))
+        S = X[r] @ (L.T @ Z)
+        if entropy:
+            S += (X[r] * L[r]).sum(axis=1)[:, None] * Z.sum(axis=0)[None, :]
+        return S
+    return f
+
+
+def _scale_quad(M, centred):
+    def f(X, Z, r):
+        X = X.astype(np.float64)
+        if centred:
+            X = X - _centre(X)
+        A = np.abs(X)
+        Z = np.abs(Z.astype(np.float64)).reshape(X.shape[0], -1)
+        Ma = np.abs(M)
+        S = A[r] @ ((Ma + Ma.T) @ (A.T @ Z))
+        if centred:
+            q = np.einsum("ik,kl,il->i", A, Ma, A)
+            S += q[r][:, None] * Z.sum(axis=0)[None, :] + (q @ Z)[None, :]
+        return S
+    return f
+
+
+def _sample_rows(n):
+    """Every row of a small problem; else 200 seeded rows plus the first and
+    last point of every apply workgroup size (32 .. 256 points) near the ends."""
+    if n <= 2100:
+        return np.arange(n)
+    edges = [0, n - 1]
+    for t in (32, 64, 128, 256):
+        edges += [t - 1, t, n - 1 - (n % t)]
+    return synth.subsample_rows(n, 200, 9999 + n, extra=edges)
+
+
+def _check_float(X, Z, Y, metric, scale, M=None, rows=None, p=0):
+    n, d = X.shape
+    Z64 = Z.astype(np.float64).reshape(n, -1)
+    r = _sample_rows(n) if rows is None else np.asarray(rows)
+    o, rn, ad = oracle.matvec(X.astype(np.float64), Z64, metric, r, M=M)
+    Yr = np.asarray(Y, dtype=np.float64).reshape(n, -1)[r]
+    e = metrics.errors(Yr, o, rn, ad, Z64, metrics.frob_from_rows(rn, n))
+    err = np.abs(Yr - o)
+    bound = 2 * U32 * np.abs(o) + (n + d + 4 * p + 16) * U64 * scale(X, Z, r)
+    ratio = float((err / bound).max())
+    print("metric", metric, "errors", e, "bound-ratio", ratio)
+    assert e["spec"] <= 1e-6
+    assert ratio <= 1.0
+
+
+def _query(X, Z, metric, M=None):
+    h = dm.prepare(dev(X), metric, M=M)
+    Y = h.matvec(dev(Z))
+    h.sync()
+    out = Y.cpu().numpy()
+    h.free()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# even p
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("p,b,n,d", [(4, 1, 3001, 3), (4, 5, 3001, 37), (4, 64, 2049, 3), (6, 1, 4097, 2),
+                                     (6, 8, 3001, 25), (6, 33, 1000, 3)])
+def test_even_p_integer_bit_exact(p, b, n, d):
+    g = synth.rng(9000 + 10 * p + b)
+    lim = 100 if p == 4 else 30
+    X = g.integers(-lim, lim + 1, size=(n, d)).astype(np.int32)
+    Z = np.rint((256 if p == 4 else 16) * g.standard_normal((n, b))).astype(np.int32)
+    o, ov = oracle.matvec_int(X, Z, EVEN[p])
+    assert ov == 0
+    h = dm.prepare(dev(X), EVEN[p])
+    Y = h.matvec(dev(Z))
+    h.sync()
+    assert np.array_equal(Y.cpu().numpy(), o)
+    Y64 = h.matvec(dev(Z.astype(np.int64)))
+    h.sync()
+    assert np.array_equal(Y64.cpu().numpy(), o)
+    h.free()
+
+
+def test_even_p_integer_offset_data_is_exact():
+    # large coordinates with a small spread: the moments of x - c stay small
+    g = synth.rng(9100)
+    n, d, b = 2500, 4, 3
+    X = (10 ** 9 + g.integers(0, 50, size=(n, d))).astype(np.int64)
+    Z = g.integers(-500, 501, size=(n, b)).astype(np.int64)
+    o, ov = oracle.matvec_int(X, Z, oracle.L6)
+    assert ov == 0
+    Y = _query(X, Z, oracle.L6)
+    assert np.array_equal(Y, o)
+
+
+def test_even_p_integer_overflow_guard_trips():
+    X = np.array([[0], [2 ** 16]], dtype=np.int32)
+    Z = np.array([[2 ** 20], [1]], dtype=np.int32)       # ||z||_1 range^4 >= 2^84
+    h = dm.prepare(dev(X), oracle.L4)
+    h.matvec(dev(Z))
+    with pytest.raises(dm.DMError) as ex:
+        h.sync()
+    assert ex.value.status == dm.ERR_OVERFLOW
+    h.free()
+
+
+@pytest.mark.parametrize("p,b,n,d,dist", [(4, 1, 20001, 5, "normal"), (4, 16, 4099, 37, "uniform"),
+                                          (4, 64, 4099, 3, "normal"), (6, 1, 20001, 3, "uniform"),
+                                          (6, 8, 4099, 17, "normal"), (6, 64, 2053, 5, "offset")])
+def test_even_p_float_within_bounds(p, b, n, d, dist):
+    g = synth.rng(9200 + 10 * p + b)
+    if dist == "normal":
+        X = g.standard_normal((n, d)).astype(np.float32)
+    elif dist == "uniform":
+        X = g.random((n, d)).astype(np.float32)
+    else:                                                 # far from the origin
+        X = (100.0 + g.random((n, d))).astype(np.float32)
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    Y = _query(X, Z, EVEN[p])
+    _check_float(X, Z, Y, EVEN[p], _scale_even(p), p=p)
+
+
+def test_even_p_float64_input_is_rounded_once():
+    g = synth.rng(9300)
+    X64 = g.standard_normal((3000, 4))
+    Z = g.standard_normal((3000, 2)).astype(np.float32)
+    Y = _query(X64, Z, oracle.L4)
+    X32 = X64.astype(np.float32)
+    _check_float(X32, Z, Y, oracle.L4, _scale_even(4), p=4)
+
+
+def test_single_point_and_single_coordinate():
+    for metric in (oracle.L4, oracle.L6):
+        Y = _query(np.array([[3.5]], dtype=np.float32), np.array([[2.0]], dtype=np.float32), metric)
+        assert Y.shape == (1, 1) and Y[0, 0] == 0.0
+        Yi = _query(np.array([[7]], dtype=np.int32), np.array([[5]], dtype=np.int32), metric)
+        assert Yi[0, 0] == 0
+
+
+# ---------------------------------------------------------------------------
+# KL divergence and cross entropy
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("metric", [oracle.KL, oracle.CE])
+@pytest.mark.parametrize("b,n,d,alpha", [(1, 20001, 8, 1.0), (3, 4099, 70, 0.5), (64, 2049, 16, 2.0)])
+def test_divergences_within_bounds(metric, b, n, d, alpha):
+    X = synth.simplex_points(n, d, 9400 + b + d, alpha=alpha)
+    Z = synth.rhs_normal(n, b, 9500 + b)
+    Y = _query(X, Z, metric)
+    _check_float(X, Z, Y, metric, _scale_log(metric == oracle.KL))
+
+
+def test_kl_of_unnormalised_positive_points():
+    g = synth.rng(9600)
+    X = (0.01 + 3 * g.random((5000, 6))).astype(np.float32)
+    Z = g.standard_normal((5000, 2)).astype(np.float32)
+    Y = _query(X, Z, oracle.KL)
+    _check_float(X, Z, Y, oracle.KL, _scale_log(True))
+
+
+@pytest.mark.parametrize("metric", [oracle.KL, oracle.CE])
+def test_divergence_domain_is_checked(metric):
+    X = synth.simplex_points(100, 4, 9700)
+    X[17, 2] = 0.0
+    with pytest.raises(dm.DMError) as ex:
+        dm.prepare(dev(X), metric)
+    assert ex.value.status == dm.ERR_ARG
+    X[17, 2] = -0.25
+    with pytest.raises(dm.DMError):
+        dm.prepare(dev(X), metric)
+
+
+def test_kl_handle_refuses_lowrank():
+    import torch
+    X = synth.simplex_points(500, 4, 9710)
+    h = dm.prepare(dev(X), oracle.KL)
+    om = torch.zeros((500, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(dm.DMError) as ex:
+        h.lowrank(4, om, iters=2)
+    assert ex.value.status == dm.ERR_STATE
+    h.free()
+
+
+# ---------------------------------------------------------------------------
+# squared Mahalanobis distance and the bilinear form
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("b,n,d,kind", [(1, 20001, 8, "spd"), (5, 4099, 37, "general"), (64, 2049, 70, "spd")])
+def test_mahalanobis_within_bounds(b, n, d, kind):
+    g = synth.rng(9800 + b)
+    X = (g.standard_normal((n, d)) + 3.0).astype(np.float32)
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    M = synth.square_matrix(d, 9810 + d, kind)
+    Y = _query(X, Z, oracle.MAHA2, M=M)
+    _check_float(X, Z, Y, oracle.MAHA2, _scale_quad(M, True), M=M)
+
+
+def test_mahalanobis_identity_matches_l2sq_oracle():
+    g = synth.rng(9820)
+    X = g.standard_normal((3000, 6)).astype(np.float32)
+    Z = g.standard_normal((3000, 2)).astype(np.float32)
+    Y = _query(X, Z, oracle.MAHA2, M=np.eye(6))
+    _check_float(X, Z, Y, oracle.L2SQ, _scale_quad(np.eye(6), True))
+
+
+@pytest.mark.parametrize("b,n,d", [(1, 20001, 8), (7, 4099, 37), (64, 2049, 70)])
+def test_bilinear_within_bounds(b, n, d):
+    g = synth.rng(9900 + b)
+    X = g.standard_normal((n, d)).astype(np.float32)
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    M = synth.square_matrix(d, 9910 + d, "general")
+    Y = _query(X, Z, oracle.BILINEAR, M=M)
+    _check_float(X, Z, Y, oracle.BILINEAR, _scale_quad(M, False), M=M)
+
+
+def test_matrix_metric_needs_its_matrix():
+    X = np.zeros((10, 3), dtype=np.float32)
+    with pytest.raises(dm.DMError):
+        dm.prepare(dev(X), oracle.MAHA2)
+    with pytest.raises(dm.DMError) as ex:
+        dm.prepare(dev(X), oracle.BILINEAR, M=np.full((3, 3), np.nan))
+    assert ex.value.status == dm.ERR_NONFINITE
+
+
+# ---------------------------------------------------------------------------
+# full size: n = 2^20 points, d = 64, sampled rows
+# ---------------------------------------------------------------------------
+def test_full_size_sampled_rows():
+    n, d = 1 << 20, 64
+    X = synth.uniform_points(n, d, 9950)
+    Z = synth.rhs_normal(n, 64, 9951)
+    rows = synth.subsample_rows(n, 6, 9952, extra=[0, n - 1])
+    Xd, Zd = dev(X), dev(Z)
+    h = dm.prepare(Xd, oracle.L4)
+    Y = h.matvec(Zd)
+    h.sync()
+    _check_float(X, Z, Y.cpu().numpy(), oracle.L4, _scale_even(4), rows=rows, p=4)
+    h.free()
+    del Y
+    P = synth.simplex_points(n, d, 9953)
+    z1 = Z[:, :1].copy()
+    h = dm.prepare(dev(P), oracle.KL)
+    y = h.matvec(dev(z1))
+    h.sync()
+    _check_float(P, z1, y.cpu().numpy(), oracle.KL, _scale_log(True), rows=rows)
+    h.free()
