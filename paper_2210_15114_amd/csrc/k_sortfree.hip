@@ -148,17 +148,28 @@ __host__ __device__ constexpr int64_t binom_sf(int p, int t) {
     return r;
 }
 
+template <typename ACC>
+__device__ __forceinline__ ACC shfl_xor_acc(ACC v, int off, int width) {
+    if constexpr (std::is_same<ACC, double>::value) return __shfl_xor(v, off, width);
+    else return (ACC)__shfl_xor((long long)v, off, width);
+}
+
 // G[t][k][c] = coef_t sum_blk part[blk][t][k][c]; coef_t = C(p, t + 1) (-1)^(t + 1)
-// when p > 0 (even p), alpha otherwise (float only)
+// when p > 0 (even p), alpha otherwise (float only).  One wave per entry:
+// lane l adds the partials l, l + 64, ... in order, then a fixed xor tree.
 template <typename ACC>
 __global__ __launch_bounds__(256) void sf_reduce_kernel(const ACC* __restrict__ part, int nblk, int64_t per_t,
                                                         int nt, int p, double alpha, ACC* __restrict__ G)
 {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int64_t count = per_t * nt;
-    if (e >= count) return;
+    if (e >= count) return;   // whole waves leave together
     ACC s = ACC(0);
-    for (int k = 0; k < nblk; ++k) s = add_acc(s, part[(size_t)k * count + e]);
+    for (int k = lane; k < nblk; k += 64) s = add_acc(s, part[(size_t)k * count + e]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s = add_acc(s, shfl_xor_acc(s, off, 64));
+    if (lane != 0) return;
     if (p > 0) {
         const int t = (int)(e / per_t) + 1;
         const int64_t cf = ((t & 1) ? -1 : 1) * binom_sf(p, t);
@@ -254,6 +265,183 @@ __global__ __launch_bounds__(256) void sf_apply_kernel(const XT* __restrict__ X,
             if (U) s += U[c];
         }
         Out[i * b + c] = (OT)s;
+    }
+}
+
+// ---- narrow blocks (b <= 8): no LDS staging, coordinates across the lanes ----
+constexpr int NU = 4;   // rows (moments) or points (apply) in flight per lane
+
+// part[blk][t][k][c] as sf_moments_kernel.  A workgroup owns a range of rows
+// and up to 256 coordinates; thread (row offset tid / dc, coordinate tid % dc)
+// reads its coordinate of every R-th row (R = 256 / dc) straight from the
+// row-major points, so a wave's loads are contiguous, and keeps all NT x BW
+// sums in registers; the R row offsets are added in a fixed order at the end.
+template <typename XT, typename ZT, typename ACC, int NT, bool LOG, int BW>
+__global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ X, const ACC* __restrict__ centre,
+                                                         const ZT* __restrict__ Z, int64_t n, int32_t d, int32_t b,
+                                                         int64_t rows_per_blk, ACC* __restrict__ part)
+{
+    __shared__ ACC red[256 * BW];
+    const int tid = threadIdx.x;
+    const int k0 = blockIdx.y * 256;
+    const int dc = d - k0 < 256 ? d - k0 : 256;
+    const int R = 256 / dc;
+    const int kk = tid % dc, rsub = tid / dc;
+    const bool active = rsub < R;
+    const int64_t rb = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t re = rb + rows_per_blk < n ? rb + rows_per_blk : n;
+    ACC acc[NT][BW];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < BW; ++c) acc[t][c] = ACC(0);
+    if (active) {
+        const int k = k0 + kk;
+        auto step = [&](XT xr, const ZT* zr) {
+            const ACC x = feature<XT, ACC, LOG>(xr, centre, k);
+            ACC xt = x;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                for (int c = 0; c < BW; ++c)
+                    if (c < b) acc[t][c] = fma_acc(xt, (ACC)zr[c], acc[t][c]);
+                if (t + 1 < NT) xt = mul_acc(xt, x);
+            }
+        };
+        int64_t j = rb + rsub;
+        for (; j + (int64_t)(NU - 1) * R < re; j += (int64_t)NU * R) {
+            XT xv[NU];
+            ZT zv[NU][BW];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int64_t r = j + (int64_t)u * R;
+                xv[u] = X[r * d + k];
+#pragma unroll
+                for (int c = 0; c < BW; ++c) zv[u][c] = c < b ? Z[r * b + c] : ZT(0);
+            }
+#pragma unroll
+            for (int u = 0; u < NU; ++u) step(xv[u], zv[u]);
+        }
+        for (; j < re; j += R) {
+            ZT zv[BW];
+#pragma unroll
+            for (int c = 0; c < BW; ++c) zv[c] = c < b ? Z[j * b + c] : ZT(0);
+            step(X[j * d + k], zv);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < BW; ++c) red[tid * BW + c] = acc[t][c];
+        }
+        __syncthreads();
+        if (rsub == 0) {
+#pragma unroll
+            for (int c = 0; c < BW; ++c) {
+                ACC s = ACC(0);
+                for (int r = 0; r < R; ++r) s = add_acc(s, red[(r * dc + kk) * BW + c]);
+                if (c < b) part[(((size_t)blockIdx.x * NT + t) * d + k0 + kk) * b + c] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Out as sf_apply_kernel.  Each wave takes 64 / dw points at a time (dw: d
+// rounded up to a power of two, at most 64); lane (point sub, coordinate kk)
+// forms its coordinates' terms for every column, and a fixed xor tree over
+// the dw lanes of a point adds them.  For d <= 64 the lane's moments stay in
+// registers for the whole kernel.
+template <typename XT, typename ACC, typename OT, int NT, bool EVEN, int BW>
+__global__ __launch_bounds__(256) void sf_apply_narrow(const XT* __restrict__ X, const ACC* __restrict__ centre,
+                                                       int64_t n, int32_t d, int32_t b, const ACC* __restrict__ T0,
+                                                       const ACC* __restrict__ G, const double* __restrict__ a,
+                                                       const double* __restrict__ U, OT* __restrict__ Out, int dw)
+{
+    const int lane = threadIdx.x & 63;
+    const int kk = lane & (dw - 1), sub = lane / dw;
+    const int ppw = 64 / dw;
+    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+    const size_t per_t = (size_t)d * b;
+    const bool one = d <= 64;
+    ACC t0[BW];
+#pragma unroll
+    for (int c = 0; c < BW; ++c) t0[c] = c < b ? T0[c] : ACC(0);
+    ACC g[NT][BW];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < BW; ++c) g[t][c] = (one && kk < d && c < b) ? G[t * per_t + (size_t)kk * b + c] : ACC(0);
+    // terms of one coordinate value x for every column
+    auto terms = [&](ACC x, const ACC (&gg)[NT][BW], ACC (&h)[BW]) {
+#pragma unroll
+        for (int c = 0; c < BW; ++c) {
+            if constexpr (EVEN) {
+                ACC hk = t0[c];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) hk = fma_acc(hk, x, gg[t][c]);
+                h[c] = add_acc(h[c], hk);
+            } else {
+                h[c] = fma_acc(x, gg[0][c], h[c]);
+            }
+        }
+    };
+    for (int64_t p0 = wave * ppw * NU; p0 < n; p0 += nwaves * ppw * NU) {
+        ACC h[NU][BW];
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int c = 0; c < BW; ++c) h[u][c] = ACC(0);
+        if (one) {
+            XT xv[NU];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int64_t i = p0 + (int64_t)u * ppw + sub;
+                xv[u] = (i < n && kk < d) ? X[i * d + kk] : XT(0);
+            }
+            if (kk < d) {
+#pragma unroll
+                for (int u = 0; u < NU; ++u)
+                    if (p0 + (int64_t)u * ppw + sub < n) terms(feature<XT, ACC, false>(xv[u], centre, kk), g, h[u]);
+            }
+        } else {
+            for (int k = kk; k < d; k += 64) {
+                ACC gk[NT][BW];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int c = 0; c < BW; ++c) gk[t][c] = c < b ? G[t * per_t + (size_t)k * b + c] : ACC(0);
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int64_t i = p0 + (int64_t)u * ppw + sub;
+                    if (i < n) terms(feature<XT, ACC, false>(X[i * d + k], centre, k), gk, h[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int c = 0; c < BW; ++c)
+                for (int off = dw >> 1; off >= 1; off >>= 1) h[u][c] = add_acc(h[u][c], shfl_xor_acc(h[u][c], off, 64));
+        if (kk == 0) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int64_t i = p0 + (int64_t)u * ppw + sub;
+                if (i >= n) continue;
+#pragma unroll
+                for (int c = 0; c < BW; ++c) {
+                    if (c >= b) continue;
+                    ACC v = h[u][c];
+                    if constexpr (!EVEN) {
+                        if (a) v = fma(a[i], (double)t0[c], v);
+                        if (U) v += U[c];
+                    }
+                    Out[i * b + c] = (OT)v;
+                }
+            }
+        }
     }
 }
 
@@ -372,27 +560,49 @@ constexpr int moments_kc() { return MKG * moments_kpt<NT>(); }
 
 int kc_for(int nt) { return nt == 1 ? moments_kc<1>() : nt <= 4 ? moments_kc<4>() : moments_kc<6>(); }
 
-// rows per moments workgroup: about 2048 workgroups over the grid, whole tiles
-int64_t moments_rows(int64_t n, int32_t d, int kc) {
-    const int64_t kblk = (d + kc - 1) / kc;
-    int64_t want = 2048 / kblk;
+// the narrow kernels (all sums of a thread in registers) serve b <= 8 when
+// the NT x (b rounded up) sums fit
+constexpr bool narrow_fits(int nt, int bw) { return bw <= 8 && nt * bw <= 32; }
+
+// Moments launch shape: the kernel family, rows per workgroup (about 2048
+// workgroups over the grid; the LDS kernel takes whole tiles) and the number
+// of row ranges, which sizes the partial sums.
+struct MomentsPlan {
+    bool narrow;
+    int64_t rpb, nblk;
+    unsigned kblk;
+};
+MomentsPlan moments_plan(int64_t n, int32_t d, int32_t b, int nt) {
+    MomentsPlan pl;
+    pl.narrow = narrow_fits(nt, pad_bw(b));
+    const int kc = pl.narrow ? 256 : kc_for(nt);
+    pl.kblk = (unsigned)((d + kc - 1) / kc);
+    int64_t want = 2048 / (int64_t)pl.kblk;
     if (want < 1) want = 1;
     int64_t r = (n + want - 1) / want;
-    r = (r + MSR - 1) / MSR * MSR;
-    return r < MSR ? MSR : r;
+    if (!pl.narrow) r = (r + MSR - 1) / MSR * MSR;
+    if (r < 1) r = 1;
+    pl.rpb = r;
+    pl.nblk = (n + r - 1) / r;
+    return pl;
 }
 
 template <typename XT, typename ZT, typename ACC, int NT, bool LOG, int BW>
 hipError_t moments_bw(const void* X, const void* centre, const void* Z, int64_t n, int32_t d, int32_t b, void* part,
                       int64_t* nblk_out, hipStream_t s)
 {
-    constexpr int KC = moments_kc<NT>();
-    const int64_t rpb = moments_rows(n, d, KC);
-    const int64_t nblk = (n + rpb - 1) / rpb;
-    *nblk_out = nblk;
-    dim3 grid((unsigned)nblk, (unsigned)((d + KC - 1) / KC));
+    const MomentsPlan pl = moments_plan(n, d, b, NT);
+    *nblk_out = pl.nblk;
+    dim3 grid((unsigned)pl.nblk, pl.kblk);
+    if constexpr (narrow_fits(NT, BW)) {
+        if (pl.narrow) {
+            sf_moments_narrow<XT, ZT, ACC, NT, LOG, BW><<<grid, 256, 0, s>>>(
+                (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, pl.rpb, (ACC*)part);
+            return hipGetLastError();
+        }
+    }
     sf_moments_kernel<XT, ZT, ACC, NT, LOG, BW><<<grid, 256, 0, s>>>(
-        (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, rpb, (ACC*)part);
+        (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, pl.rpb, (ACC*)part);
     return hipGetLastError();
 }
 
@@ -416,6 +626,16 @@ template <typename XT, typename ACC, typename OT, int NT, bool EVEN, int BW>
 hipError_t apply_bw(const void* X, const void* centre, int64_t n, int32_t d, int32_t b, const void* T0, const void* G,
                     const double* a, const double* U, void* Out, hipStream_t s)
 {
+    if constexpr (narrow_fits(NT, BW)) {
+        int dw = 1;
+        while (dw < d && dw < 64) dw <<= 1;
+        const int64_t waves = (n + (int64_t)(64 / dw) * NU - 1) / ((int64_t)(64 / dw) * NU);
+        int64_t blocks = (waves + 3) / 4;
+        if (blocks > 2048) blocks = 2048;
+        sf_apply_narrow<XT, ACC, OT, NT, EVEN, BW><<<(unsigned)blocks, 256, 0, s>>>(
+            (const XT*)X, (const ACC*)centre, n, d, b, (const ACC*)T0, (const ACC*)G, a, U, (OT*)Out, dw);
+        return hipGetLastError();
+    }
     constexpr int NPB = (256 / BW) * apply_ppt<BW>();
     const unsigned grid = (unsigned)((n + NPB - 1) / NPB);
     sf_apply_kernel<XT, ACC, OT, NT, EVEN, BW><<<grid, 256, 0, s>>>((const XT*)X, (const ACC*)centre, n, d, b,
@@ -444,8 +664,8 @@ hipError_t reduce_launch(const void* part, int64_t nblk, int64_t per_t, int nt, 
                          hipStream_t s)
 {
     const int64_t count = per_t * nt;
-    sf_reduce_kernel<ACC><<<(unsigned)((count + 255) / 256), 256, 0, s>>>((const ACC*)part, (int)nblk, per_t, nt, p,
-                                                                          alpha, (ACC*)G);
+    sf_reduce_kernel<ACC><<<(unsigned)((count + 3) / 4), 256, 0, s>>>((const ACC*)part, (int)nblk, per_t, nt, p,
+                                                                      alpha, (ACC*)G);
     return hipGetLastError();
 }
 
@@ -478,8 +698,7 @@ int sf_moment_count(int form, int p) { return form == SF_EVEN ? p : 1; }
 
 size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p) {
     const int nt = sf_moment_count(form, p);
-    const int64_t rpb = moments_rows(n, d, kc_for(nt));
-    const int64_t nblk = (n + rpb - 1) / rpb;
+    const int64_t nblk = moments_plan(n, d, b, nt).nblk;
     const size_t cnt = (size_t)nt * d * b;
     return ((size_t)nblk + 2) * cnt * 8;   // row-range partials, the moments, the mixed moments
 }
@@ -488,8 +707,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
 {
     if (q.b < 1 || q.b > 64 || q.n < 1 || q.d < 1) return hipErrorInvalidValue;
     const int nt = sf_moment_count(form, p);
-    const int64_t rpb = moments_rows(q.n, q.d, kc_for(nt));
-    const int64_t nblk_max = (q.n + rpb - 1) / rpb;
+    const int64_t nblk_max = moments_plan(q.n, q.d, q.b, nt).nblk;
     const size_t cnt = (size_t)nt * q.d * q.b;
     char* part = (char*)scratch;
     char* G = part + (size_t)nblk_max * cnt * 8;

@@ -297,3 +297,22 @@ def test_full_size_sampled_rows():
     h.sync()
     _check_float(P, z1, y.cpu().numpy(), oracle.KL, _scale_log(True), rows=rows)
     h.free()
+
+
+# ---------------------------------------------------------------------------
+# more coordinates than one workgroup spans (256 in the narrow moments)
+# ---------------------------------------------------------------------------
+def test_many_coordinates():
+    g = synth.rng(9960)
+    n = 3001
+    X = g.integers(-20, 21, size=(n, 260)).astype(np.int32)
+    Z = g.integers(-9, 10, size=(n, 4)).astype(np.int32)
+    o, ov = oracle.matvec_int(X, Z, oracle.L4)
+    assert ov == 0
+    assert np.array_equal(_query(X, Z, oracle.L4), o)
+    P = synth.simplex_points(n, 300, 9961)
+    Zf = synth.rhs_normal(n, 2, 9962)
+    _check_float(P, Zf, _query(P, Zf, oracle.KL), oracle.KL, _scale_log(True))
+    Xf = g.standard_normal((n, 300)).astype(np.float32)
+    Zw = synth.rhs_normal(n, 16, 9963)
+    _check_float(Xf, Zw, _query(Xf, Zw, oracle.L4), oracle.L4, _scale_even(4), p=4)
