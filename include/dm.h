@@ -33,7 +33,8 @@
  *            A.3): (A z)_i = -sum_k x_i(k) S_k.  A is not symmetric.
  *            KL and CE: float data only, every coordinate finite and > 0
  *            (dm_prepare returns DM_ERR_ARG otherwise); the points need not
- *            lie on the simplex.
+ *            lie on the simplex.  The workspace keeps log x_i(k) in FP64
+ *            (n d 8 bytes), formed once at preparation.
  *   DM_MAHA2 f(x, y) = (x - y)^T M (x - y), the squared Mahalanobis distance
  *            for a d x d matrix M (only its symmetric part matters):
  *            (A z)_i = q_i sum_j z_j + sum_j q_j z_j

@@ -64,6 +64,7 @@ struct Layout {
     uint32_t ntiles = 0;    // sort tiles
     size_t perm = 0, xs = 0, rank = 0, rowsum = 0, rownrm = 0, xcopy = 0, kmin = 0, kmax = 0, flags = 0;
     size_t centre = 0, mat = 0;   // per-coordinate centre; M and W (d x d each) of the quadratic forms
+    size_t logx = 0;              // FP64 logarithms of the points (KL divergence, cross entropy)
     size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0;
     size_t k1 = 0, v1 = 0, counts = 0;
     size_t total = 0;
@@ -95,6 +96,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t metric) {
     L.flags = take(16);
     L.centre = take((size_t)d * 8);
     if (matrix_metric(metric)) L.mat = take((size_t)d * d * 16);
+    if (metric == DM_KL || metric == DM_CE) L.logx = take((size_t)n * d * 8);
     if (sorted_metric(metric)) {
         L.key_off = take((size_t)d * 8);
         L.key_len = take((size_t)d * 8);
@@ -452,7 +454,8 @@ dm_status prepare_sortfree(dm_handle* h, const std::vector<uint32_t>& kmin, cons
     if (h->metric == DM_KL || h->metric == DM_CE) {
         h->symmetric = false;
         DM_TRY(launch_fill_u32(h->at<uint32_t>(L.flags), 0u, 4, s));
-        DM_TRY(launch_kl_weights(xc, n, d, h->at<double>(L.rowsum), h->at<uint32_t>(L.flags), FLAG_DOMAIN, s));
+        DM_TRY(launch_kl_weights(xc, n, d, h->at<double>(L.rowsum), h->at<double>(L.logx), h->at<uint32_t>(L.flags),
+                                 FLAG_DOMAIN, s));
         DM_TRY(hipStreamSynchronize(s));
         uint32_t f = 0;
         DM_TRY(hipMemcpy(&f, h->ws + L.flags, 4, hipMemcpyDeviceToHost));
@@ -700,6 +703,7 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         }
         SfQuery q;
         q.X = h->ws + h->L.xcopy;
+        q.LX = (h->metric == DM_KL || h->metric == DM_CE) ? h->at<double>(h->L.logx) : nullptr;
         q.centre = h->ws + h->L.centre;
         q.Z = Z;
         q.n = h->n;

@@ -208,6 +208,7 @@ hipError_t launch_embed_l2(int kind, const void* X, int64_t n, int32_t d, const 
 enum SfForm { SF_EVEN = 1, SF_LOG = 2, SF_LIN = 3 };
 struct SfQuery {
     const void* X;          // n x d point copy (float | int32)
+    const double* LX;       // n x d logarithms of X (SF_LOG) or NULL
     const void* centre;     // d (double | int64) subtracted from every coordinate, or NULL
     const void* Z;          // n x b (float | int32 | int64)
     int64_t n;
@@ -222,9 +223,10 @@ struct SfQuery {
 int sf_moment_count(int form, int p);
 size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p);
 hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuery& q, void* scratch, hipStream_t s);
-// negH[i] = sum_k x_ik log x_ik; sets `bad` in *flags for a coordinate that is not finite and > 0
-hipError_t launch_kl_weights(const float* X, int64_t n, int32_t d, double* negH, uint32_t* flags, uint32_t bad,
-                             hipStream_t s);
+// negH[i] = sum_k x_ik log x_ik, LX (n x d) = log X; sets `bad` in *flags for a
+// coordinate that is not finite and > 0
+hipError_t launch_kl_weights(const float* X, int64_t n, int32_t d, double* negH, double* LX, uint32_t* flags,
+                             uint32_t bad, hipStream_t s);
 // q[i] = (x_i - c)^T M (x_i - c)
 hipError_t launch_maha_weights(const float* X, const double* centre, int64_t n, int32_t d, const double* M, double* q,
                                hipStream_t s);

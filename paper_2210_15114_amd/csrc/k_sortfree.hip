@@ -53,17 +53,16 @@ __device__ __forceinline__ ACC add_acc(ACC a, ACC b) {
     else return (ACC)((uint64_t)a + (uint64_t)b);
 }
 
-// feature of one coordinate value: the centred value, or its logarithm
-template <typename XT, typename ACC, bool LOG>
+// a coordinate value less its centre (none: the value itself)
+template <typename XT, typename ACC>
 __device__ __forceinline__ ACC feature(XT x, const ACC* centre, int k) {
-    if constexpr (LOG) return (ACC)log((double)x);
-    else return centre ? (ACC)((ACC)x - centre[k]) : (ACC)x;
+    return centre ? (ACC)((ACC)x - centre[k]) : (ACC)x;
 }
 
 // part[blk][t][k][c] = sum over the workgroup's rows of z_jc phi(x_jk)^(t+1),
 // t = 0 .. NT-1.  Threads: column c = tid % BW, coordinate group
 // (tid / BW) % MKG, row stripe tid / (BW MKG).
-template <typename XT, typename ZT, typename ACC, int NT, bool LOG, int BW>
+template <typename XT, typename ZT, typename ACC, int NT, int BW>
 __global__ __launch_bounds__(256) void sf_moments_kernel(const XT* __restrict__ X, const ACC* __restrict__ centre,
                                                          const ZT* __restrict__ Z, int64_t n, int32_t d, int32_t b,
                                                          int64_t rows_per_blk, ACC* __restrict__ part)
@@ -92,7 +91,7 @@ __global__ __launch_bounds__(256) void sf_moments_kernel(const XT* __restrict__ 
         for (int e = tid; e < MSR * KC; e += 256) {
             const int r = e / KC, kk = e % KC;
             ACC v = ACC(0);
-            if (r < nr && k0 + kk < d) v = feature<XT, ACC, LOG>(X[(r0 + r) * d + k0 + kk], centre, k0 + kk);
+            if (r < nr && k0 + kk < d) v = feature<XT, ACC>(X[(r0 + r) * d + k0 + kk], centre, k0 + kk);
             sX[r * XS + kk] = v;
         }
         for (int e = tid; e < MSR * BW; e += 256) {
@@ -192,7 +191,7 @@ __global__ __launch_bounds__(256) void sf_mix_kernel(const double* __restrict__ 
 }
 
 template <int BW> constexpr int apply_ppt() { return BW >= 8 ? BW / 8 : 1; }
-template <int NT, int BW> constexpr int apply_kc() { return (NT <= 2 && BW >= 4) ? 32 : 16; }
+template <int NT, int BW> constexpr int apply_kc() { return (BW <= 8 || NT <= 2) ? 32 : 16; }
 
 // Out[i][c] for every point i and column c.  Thread: column c = tid % BW,
 // point group tid / BW owning points i0 + q (256 / BW) + group, q < PPT.
@@ -209,7 +208,8 @@ __global__ __launch_bounds__(256) void sf_apply_kernel(const XT* __restrict__ X,
     constexpr int NPB = PG * PPT;
     constexpr int KC = apply_kc<NT, BW>();
     constexpr int XS = KC + 1;
-    __shared__ ACC sX[NPB * XS];
+    __shared__ XT sX[NPB * XS];          // raw coordinates; the centre is taken off at use
+    __shared__ ACC sC[KC];
     __shared__ ACC sG[NT * KC * BW];
     const int tid = threadIdx.x;
     const int c = tid % BW, pg = tid / BW;
@@ -224,10 +224,9 @@ __global__ __launch_bounds__(256) void sf_apply_kernel(const XT* __restrict__ X,
         for (int e = tid; e < NPB * KC; e += 256) {
             const int p = e / KC, kk = e % KC;
             const int64_t i = i0 + p;
-            ACC v = ACC(0);
-            if (i < n && k0 + kk < d) v = feature<XT, ACC, false>(X[i * d + k0 + kk], centre, k0 + kk);
-            sX[p * XS + kk] = v;
+            sX[p * XS + kk] = (i < n && k0 + kk < d) ? X[i * d + k0 + kk] : XT(0);
         }
+        if (tid < KC) sC[tid] = (centre && k0 + tid < d) ? centre[k0 + tid] : ACC(0);
         for (int e = tid; e < NT * KC * BW; e += 256) {
             const int t = e / (KC * BW), rem = e % (KC * BW);
             const int kk = rem / BW, cq = rem % BW;
@@ -239,9 +238,10 @@ __global__ __launch_bounds__(256) void sf_apply_kernel(const XT* __restrict__ X,
             ACC g[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) g[t] = sG[(t * KC + kk) * BW + c];
+            const ACC ck = sC[kk];
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
-                const ACC x = sX[(q * PG + pg) * XS + kk];
+                const ACC x = (ACC)((ACC)sX[(q * PG + pg) * XS + kk] - ck);
                 if constexpr (EVEN) {
                     ACC h = t0;
 #pragma unroll
@@ -268,15 +268,15 @@ __global__ __launch_bounds__(256) void sf_apply_kernel(const XT* __restrict__ X,
     }
 }
 
-// ---- narrow blocks (b <= 8): no LDS staging, coordinates across the lanes ----
-constexpr int NU = 4;   // rows (moments) or points (apply) in flight per lane
+// ---- narrow blocks (b <= 8): moments without LDS staging ---------------------
+constexpr int NU = 4;   // rows in flight per thread
 
 // part[blk][t][k][c] as sf_moments_kernel.  A workgroup owns a range of rows
 // and up to 256 coordinates; thread (row offset tid / dc, coordinate tid % dc)
 // reads its coordinate of every R-th row (R = 256 / dc) straight from the
 // row-major points, so a wave's loads are contiguous, and keeps all NT x BW
 // sums in registers; the R row offsets are added in a fixed order at the end.
-template <typename XT, typename ZT, typename ACC, int NT, bool LOG, int BW>
+template <typename XT, typename ZT, typename ACC, int NT, int BW>
 __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ X, const ACC* __restrict__ centre,
                                                          const ZT* __restrict__ Z, int64_t n, int32_t d, int32_t b,
                                                          int64_t rows_per_blk, ACC* __restrict__ part)
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ 
     if (active) {
         const int k = k0 + kk;
         auto step = [&](XT xr, const ZT* zr) {
-            const ACC x = feature<XT, ACC, LOG>(xr, centre, k);
+            const ACC x = feature<XT, ACC>(xr, centre, k);
             ACC xt = x;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -348,109 +348,12 @@ __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ 
     }
 }
 
-// Out as sf_apply_kernel.  Each wave takes 64 / dw points at a time (dw: d
-// rounded up to a power of two, at most 64); lane (point sub, coordinate kk)
-// forms its coordinates' terms for every column, and a fixed xor tree over
-// the dw lanes of a point adds them.  For d <= 64 the lane's moments stay in
-// registers for the whole kernel.
-template <typename XT, typename ACC, typename OT, int NT, bool EVEN, int BW>
-__global__ __launch_bounds__(256) void sf_apply_narrow(const XT* __restrict__ X, const ACC* __restrict__ centre,
-                                                       int64_t n, int32_t d, int32_t b, const ACC* __restrict__ T0,
-                                                       const ACC* __restrict__ G, const double* __restrict__ a,
-                                                       const double* __restrict__ U, OT* __restrict__ Out, int dw)
-{
-    const int lane = threadIdx.x & 63;
-    const int kk = lane & (dw - 1), sub = lane / dw;
-    const int ppw = 64 / dw;
-    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
-    const size_t per_t = (size_t)d * b;
-    const bool one = d <= 64;
-    ACC t0[BW];
-#pragma unroll
-    for (int c = 0; c < BW; ++c) t0[c] = c < b ? T0[c] : ACC(0);
-    ACC g[NT][BW];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int c = 0; c < BW; ++c) g[t][c] = (one && kk < d && c < b) ? G[t * per_t + (size_t)kk * b + c] : ACC(0);
-    // terms of one coordinate value x for every column
-    auto terms = [&](ACC x, const ACC (&gg)[NT][BW], ACC (&h)[BW]) {
-#pragma unroll
-        for (int c = 0; c < BW; ++c) {
-            if constexpr (EVEN) {
-                ACC hk = t0[c];
-#pragma unroll
-                for (int t = 0; t < NT; ++t) hk = fma_acc(hk, x, gg[t][c]);
-                h[c] = add_acc(h[c], hk);
-            } else {
-                h[c] = fma_acc(x, gg[0][c], h[c]);
-            }
-        }
-    };
-    for (int64_t p0 = wave * ppw * NU; p0 < n; p0 += nwaves * ppw * NU) {
-        ACC h[NU][BW];
-#pragma unroll
-        for (int u = 0; u < NU; ++u)
-#pragma unroll
-            for (int c = 0; c < BW; ++c) h[u][c] = ACC(0);
-        if (one) {
-            XT xv[NU];
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                const int64_t i = p0 + (int64_t)u * ppw + sub;
-                xv[u] = (i < n && kk < d) ? X[i * d + kk] : XT(0);
-            }
-            if (kk < d) {
-#pragma unroll
-                for (int u = 0; u < NU; ++u)
-                    if (p0 + (int64_t)u * ppw + sub < n) terms(feature<XT, ACC, false>(xv[u], centre, kk), g, h[u]);
-            }
-        } else {
-            for (int k = kk; k < d; k += 64) {
-                ACC gk[NT][BW];
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int c = 0; c < BW; ++c) gk[t][c] = c < b ? G[t * per_t + (size_t)k * b + c] : ACC(0);
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const int64_t i = p0 + (int64_t)u * ppw + sub;
-                    if (i < n) terms(feature<XT, ACC, false>(X[i * d + k], centre, k), gk, h[u]);
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < NU; ++u)
-#pragma unroll
-            for (int c = 0; c < BW; ++c)
-                for (int off = dw >> 1; off >= 1; off >>= 1) h[u][c] = add_acc(h[u][c], shfl_xor_acc(h[u][c], off, 64));
-        if (kk == 0) {
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                const int64_t i = p0 + (int64_t)u * ppw + sub;
-                if (i >= n) continue;
-#pragma unroll
-                for (int c = 0; c < BW; ++c) {
-                    if (c >= b) continue;
-                    ACC v = h[u][c];
-                    if constexpr (!EVEN) {
-                        if (a) v = fma(a[i], (double)t0[c], v);
-                        if (U) v += U[c];
-                    }
-                    Out[i * b + c] = (OT)v;
-                }
-            }
-        }
-    }
-}
-
 // ---- per-point weights at preparation --------------------------------------
-// negH[i] = sum_k x_ik log x_ik; flags |= bad for a coordinate that is not
-// finite and positive (its logarithm is not finite)
+// negH[i] = sum_k x_ik log x_ik and LX[i][k] = log x_ik (FP64); flags |= bad
+// for a coordinate that is not finite and positive (its logarithm is not finite)
 __global__ __launch_bounds__(256) void kl_weights_kernel(const float* __restrict__ X, int64_t n, int32_t d,
-                                                         double* __restrict__ negH, uint32_t* __restrict__ flags,
-                                                         uint32_t bad)
+                                                         double* __restrict__ negH, double* __restrict__ LX,
+                                                         uint32_t* __restrict__ flags, uint32_t bad)
 {
     constexpr int PR = 64, KC = 32;
     __shared__ double sT[PR][KC + 1];
@@ -465,8 +368,13 @@ __global__ __launch_bounds__(256) void kl_weights_kernel(const float* __restrict
             double v = 0.0;
             if (i < n && k0 + kk < d) {
                 const double x = (double)X[i * d + k0 + kk];
-                if (x > 0.0 && x <= 3.4028234663852886e38) v = x * log(x);
-                else fault = true;
+                if (x > 0.0 && x <= 3.4028234663852886e38) {
+                    const double lx = log(x);
+                    LX[i * d + k0 + kk] = lx;
+                    v = x * lx;
+                } else {
+                    fault = true;
+                }
             }
             sT[p][kk] = v;
         }
@@ -587,7 +495,7 @@ MomentsPlan moments_plan(int64_t n, int32_t d, int32_t b, int nt) {
     return pl;
 }
 
-template <typename XT, typename ZT, typename ACC, int NT, bool LOG, int BW>
+template <typename XT, typename ZT, typename ACC, int NT, int BW>
 hipError_t moments_bw(const void* X, const void* centre, const void* Z, int64_t n, int32_t d, int32_t b, void* part,
                       int64_t* nblk_out, hipStream_t s)
 {
@@ -596,28 +504,28 @@ hipError_t moments_bw(const void* X, const void* centre, const void* Z, int64_t 
     dim3 grid((unsigned)pl.nblk, pl.kblk);
     if constexpr (narrow_fits(NT, BW)) {
         if (pl.narrow) {
-            sf_moments_narrow<XT, ZT, ACC, NT, LOG, BW><<<grid, 256, 0, s>>>(
+            sf_moments_narrow<XT, ZT, ACC, NT, BW><<<grid, 256, 0, s>>>(
                 (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, pl.rpb, (ACC*)part);
             return hipGetLastError();
         }
     }
-    sf_moments_kernel<XT, ZT, ACC, NT, LOG, BW><<<grid, 256, 0, s>>>(
+    sf_moments_kernel<XT, ZT, ACC, NT, BW><<<grid, 256, 0, s>>>(
         (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, pl.rpb, (ACC*)part);
     return hipGetLastError();
 }
 
-template <typename XT, typename ZT, typename ACC, int NT, bool LOG>
+template <typename XT, typename ZT, typename ACC, int NT>
 hipError_t moments_t(int32_t b, const void* X, const void* centre, const void* Z, int64_t n, int32_t d, void* part,
                      int64_t* nblk, hipStream_t s)
 {
     switch (pad_bw(b)) {
-    case 1: return moments_bw<XT, ZT, ACC, NT, LOG, 1>(X, centre, Z, n, d, b, part, nblk, s);
-    case 2: return moments_bw<XT, ZT, ACC, NT, LOG, 2>(X, centre, Z, n, d, b, part, nblk, s);
-    case 4: return moments_bw<XT, ZT, ACC, NT, LOG, 4>(X, centre, Z, n, d, b, part, nblk, s);
-    case 8: return moments_bw<XT, ZT, ACC, NT, LOG, 8>(X, centre, Z, n, d, b, part, nblk, s);
-    case 16: return moments_bw<XT, ZT, ACC, NT, LOG, 16>(X, centre, Z, n, d, b, part, nblk, s);
-    case 32: return moments_bw<XT, ZT, ACC, NT, LOG, 32>(X, centre, Z, n, d, b, part, nblk, s);
-    case 64: return moments_bw<XT, ZT, ACC, NT, LOG, 64>(X, centre, Z, n, d, b, part, nblk, s);
+    case 1: return moments_bw<XT, ZT, ACC, NT, 1>(X, centre, Z, n, d, b, part, nblk, s);
+    case 2: return moments_bw<XT, ZT, ACC, NT, 2>(X, centre, Z, n, d, b, part, nblk, s);
+    case 4: return moments_bw<XT, ZT, ACC, NT, 4>(X, centre, Z, n, d, b, part, nblk, s);
+    case 8: return moments_bw<XT, ZT, ACC, NT, 8>(X, centre, Z, n, d, b, part, nblk, s);
+    case 16: return moments_bw<XT, ZT, ACC, NT, 16>(X, centre, Z, n, d, b, part, nblk, s);
+    case 32: return moments_bw<XT, ZT, ACC, NT, 32>(X, centre, Z, n, d, b, part, nblk, s);
+    case 64: return moments_bw<XT, ZT, ACC, NT, 64>(X, centre, Z, n, d, b, part, nblk, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -626,16 +534,6 @@ template <typename XT, typename ACC, typename OT, int NT, bool EVEN, int BW>
 hipError_t apply_bw(const void* X, const void* centre, int64_t n, int32_t d, int32_t b, const void* T0, const void* G,
                     const double* a, const double* U, void* Out, hipStream_t s)
 {
-    if constexpr (narrow_fits(NT, BW)) {
-        int dw = 1;
-        while (dw < d && dw < 64) dw <<= 1;
-        const int64_t waves = (n + (int64_t)(64 / dw) * NU - 1) / ((int64_t)(64 / dw) * NU);
-        int64_t blocks = (waves + 3) / 4;
-        if (blocks > 2048) blocks = 2048;
-        sf_apply_narrow<XT, ACC, OT, NT, EVEN, BW><<<(unsigned)blocks, 256, 0, s>>>(
-            (const XT*)X, (const ACC*)centre, n, d, b, (const ACC*)T0, (const ACC*)G, a, U, (OT*)Out, dw);
-        return hipGetLastError();
-    }
     constexpr int NPB = (256 / BW) * apply_ppt<BW>();
     const unsigned grid = (unsigned)((n + NPB - 1) / NPB);
     sf_apply_kernel<XT, ACC, OT, NT, EVEN, BW><<<grid, 256, 0, s>>>((const XT*)X, (const ACC*)centre, n, d, b,
@@ -676,16 +574,16 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
     hipError_t e;
     const int64_t per_t = (int64_t)q.d * q.b;
     if (!is_int) {
-        e = moments_t<float, float, double, P, false>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+        e = moments_t<float, float, double, P>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
         if (e != hipSuccess) return e;
         if ((e = reduce_launch<double>(part, nblk, per_t, P, P, 1.0, G, s)) != hipSuccess) return e;
         return apply_t<float, double, float, P, true>(q.X, q.centre, q.n, q.d, q.b, q.T0, G, nullptr, nullptr, q.Out,
                                                       s);
     }
     if (zkind == IN_I32)
-        e = moments_t<int32_t, int32_t, int64_t, P, false>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+        e = moments_t<int32_t, int32_t, int64_t, P>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
     else
-        e = moments_t<int32_t, int64_t, int64_t, P, false>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+        e = moments_t<int32_t, int64_t, int64_t, P>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
     if (e != hipSuccess) return e;
     if ((e = reduce_launch<int64_t>(part, nblk, per_t, P, P, 1.0, G, s)) != hipSuccess) return e;
     return apply_t<int32_t, int64_t, int64_t, P, true>(q.X, q.centre, q.n, q.d, q.b, q.T0, G, nullptr, nullptr,
@@ -723,9 +621,10 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     if (is_int) return hipErrorInvalidValue;
     int64_t nblk = 0;
     const int64_t per_t = (int64_t)q.d * q.b;
+    // KL and cross entropy: moments of the logarithms kept since preparation
     hipError_t e = (form == SF_LOG)
-                       ? moments_t<float, float, double, 1, true>(q.b, q.X, nullptr, q.Z, q.n, q.d, part, &nblk, s)
-                       : moments_t<float, float, double, 1, false>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+                       ? moments_t<double, float, double, 1>(q.b, q.LX, nullptr, q.Z, q.n, q.d, part, &nblk, s)
+                       : moments_t<float, float, double, 1>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
     if (e != hipSuccess) return e;
     const char* Gv = G;
     if (q.W) {
@@ -740,11 +639,11 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
                                                    q.a, q.U, q.Out, s);
 }
 
-hipError_t launch_kl_weights(const float* X, int64_t n, int32_t d, double* negH, uint32_t* flags, uint32_t bad,
-                             hipStream_t s)
+hipError_t launch_kl_weights(const float* X, int64_t n, int32_t d, double* negH, double* LX, uint32_t* flags,
+                             uint32_t bad, hipStream_t s)
 {
     if (n < 1 || d < 1) return hipErrorInvalidValue;
-    kl_weights_kernel<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(X, n, d, negH, flags, bad);
+    kl_weights_kernel<<<(unsigned)((n + 63) / 64), 256, 0, s>>>(X, n, d, negH, LX, flags, bad);
     return hipGetLastError();
 }
 

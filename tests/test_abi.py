@@ -99,7 +99,8 @@ def test_workspace_of_the_sort_free_metrics(L):
     base = dm.workspace_size(n, d, dm.L4, dm.F32)
     assert base >= n * d * 4                           # the point copy
     assert dm.workspace_size(n, d, dm.L6, dm.I32) == base
-    assert dm.workspace_size(n, d, dm.KL, dm.F32) == base
+    assert dm.workspace_size(n, d, dm.CE, dm.F32) >= base + n * d * 8          # FP64 logarithms
+    assert dm.workspace_size(n, d, dm.KL, dm.F32) == dm.workspace_size(n, d, dm.CE, dm.F32)
     assert dm.workspace_size(n, d, dm.MAHA2, dm.F32) >= base + 2 * d * d * 8   # M and W
     assert dm.workspace_size(n, d, dm.L4, dm.F32) < dm.workspace_size(n, d, dm.L1, dm.F32)   # no sort arrays
 
