@@ -217,6 +217,67 @@ def run_approx_l2(args, dm, synth, np, torch, dev, stream):
             "relative_frobenius_sampled_rows": rel, "expected_spread": float(np.sqrt(np.pi / 2 - 1) / np.sqrt(k))}
 
 
+def run_sortfree(args, dm, synth, np, torch, dev, stream):
+    """The sort-free family (Appendix A) on n = 2^20 points, d = 64: l_4^4 and
+    l_6^6 on the 32-component mixture, KL divergence and cross entropy on
+    Dirichlet(1) probability vectors, the squared Mahalanobis distance and the
+    bilinear form with a seeded SPD matrix.  Single vector (b = 1) and a block
+    of b = 64; 3 warm-up and 10 timed queries each (median).  Reported per
+    query: time, the algorithmic HBM bytes (moments read X, or its FP64
+    logarithms for KL and cross entropy, plus Z; the point pass reads X and
+    writes Out; the totals read Z) and their rate, and the FP64 operation
+    rate; errors against the oracle on 4 sampled rows for l_4^4 and KL."""
+    import oracle
+    from oracle import metrics
+    n, d = 1 << 20, 64
+    Xm, _ = synth.workload2(n, d, 1)
+    P = synth.simplex_points(n, d, synth.seeds(2)["X"] + 11)
+    M = synth.square_matrix(d, synth.seeds(2)["X"] + 12, "spd")
+    rows = synth.subsample_rows(n, 4, synth.seeds(2)["sub"] + 3)
+    cases = (("l4", dm.L4, Xm, None, 4), ("l6", dm.L6, Xm, None, 6), ("kl", dm.KL, P, None, 1),
+             ("ce", dm.CE, P, None, 1), ("maha2", dm.MAHA2, Xm, M, 1), ("bilinear", dm.BILINEAR, Xm, M, 1))
+    res = {"n": n, "d": d}
+    for b in (1, 64):
+        Z = synth.rhs_normal(n, b, synth.seeds(2)["Z"] + 20 + b, np.float32)
+        Zd = torch.from_numpy(Z).to(dev)
+        out = torch.empty((n, b), dtype=torch.float32, device=dev)
+        for name, metric, X, Mm, nt in cases:
+            Xd = torch.from_numpy(X).to(dev)
+            h = dm.prepare(Xd, metric, M=Mm)
+            for _ in range(3):
+                h.matvec(Zd, out=out)
+            h.sync()
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(20)]
+            for q in range(10):
+                evs[2 * q].record(stream)
+                h.matvec(Zd, out=out)
+                evs[2 * q + 1].record(stream)
+            torch.cuda.synchronize()
+            h.sync()
+            ms = pct(sorted(evs[2 * q].elapsed_time(evs[2 * q + 1]) for q in range(10)), 0.5)
+            xb = n * d * (8 if metric in (dm.KL, dm.CE) else 4)
+            nbytes = xb + n * d * 4 + 3 * n * b * 4
+            # FP64 operations per (point, coordinate, column): even p takes NT
+            # FMAs and NT - 1 products for the moments and a Horner step of NT
+            # FMAs plus an add per point; the linear forms one FMA in each stage
+            flops = float(n) * d * b * (5 * nt if nt > 1 else 4)
+            ent = {"ms": round(ms, 4), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                   "fp64_TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2)}
+            if name in ("l4", "kl") and b == 1:
+                y = out.cpu().numpy().astype(np.float64)
+                o, rn, ad = oracle.matvec(X.astype(np.float64), Z.astype(np.float64),
+                                          oracle.L4 if name == "l4" else oracle.KL, rows)
+                ent["error_spec"] = metrics.errors(y[rows], o, rn, ad, Z.astype(np.float64),
+                                                   metrics.frob_from_rows(rn, n))["spec"]
+            res["%s_b%d" % (name, b)] = ent
+            log("sort-free %s b=%d: %.3f ms/query, %.0f GB/s, %.2f FP64 TFLOP/s" %
+                (name, b, ms, ent["GBps"], ent["fp64_TFLOPs"]))
+            h.free()
+            del Xd
+        del Zd, out
+    return res
+
+
 def pass_kernel_name(variant, b):
     """Kernel of a float l1 pass variant: 0/1 the keep kernel, 2/3 the
     re-gathering kernel; odd variants halve the ranks per slot."""
@@ -300,6 +361,7 @@ def main():
     ap.add_argument("--no-lowrank", action="store_true", help="skip the block-Krylov low-rank leg")
     ap.add_argument("--no-mixture", action="store_true", help="skip the single-vector mixture leg")
     ap.add_argument("--no-approx-l2", action="store_true", help="skip the approximate l2 leg")
+    ap.add_argument("--no-sortfree", action="store_true", help="skip the sort-free family leg")
     ap.add_argument("--multi-count", type=int, default=512)
     args = ap.parse_args()
 
@@ -458,6 +520,11 @@ def main():
     if not args.no_approx_l2:
         approx = run_approx_l2(args, dm, synth, np, torch, dev, stream)
 
+    # ---- the sort-free family ----
+    sortfree = None
+    if not args.no_sortfree:
+        sortfree = run_sortfree(args, dm, synth, np, torch, dev, stream)
+
     # ---- block-Krylov low rank ----
     lowrank = None
     if not args.no_lowrank:
@@ -524,6 +591,7 @@ def main():
         "lowrank": lowrank,
         "single_vector_mixture": mixture,
         "approx_l2": approx,
+        "sortfree": sortfree,
         "errors": errors,
     }
     print(json.dumps(result), flush=True)
