@@ -53,6 +53,13 @@ __device__ __forceinline__ ACC add_acc(ACC a, ACC b) {
     else return (ACC)((uint64_t)a + (uint64_t)b);
 }
 
+// V consecutive values loaded as one vector (16 bytes for V = 4 floats or
+// V = 2 doubles); the address must be a multiple of the vector size
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Vec {
+    T v[V];
+};
+
 // a coordinate value less its centre (none: the value itself)
 template <typename XT, typename ACC>
 __device__ __forceinline__ ACC feature(XT x, const ACC* centre, int k) {
@@ -221,10 +228,21 @@ __global__ __launch_bounds__(256) void sf_apply_kernel(const XT* __restrict__ X,
     for (int q = 0; q < PPT; ++q) acc[q] = ACC(0);
     const size_t per_t = (size_t)d * b;
     for (int k0 = 0; k0 < d; k0 += KC) {
-        for (int e = tid; e < NPB * KC; e += 256) {
-            const int p = e / KC, kk = e % KC;
-            const int64_t i = i0 + p;
-            sX[p * XS + kk] = (i < n && k0 + kk < d) ? X[i * d + k0 + kk] : XT(0);
+        if (d % 4 == 0) {   // 16-byte loads; a group of 4 lies wholly inside or outside the row
+            for (int e = tid; e < NPB * (KC / 4); e += 256) {
+                const int p = e / (KC / 4), kk = 4 * (e % (KC / 4));
+                const int64_t i = i0 + p;
+                Vec<XT, 4> v = {};
+                if (i < n && k0 + kk < d) v = *reinterpret_cast<const Vec<XT, 4>*>(X + i * d + k0 + kk);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sX[p * XS + kk + j] = v.v[j];
+            }
+        } else {
+            for (int e = tid; e < NPB * KC; e += 256) {
+                const int p = e / KC, kk = e % KC;
+                const int64_t i = i0 + p;
+                sX[p * XS + kk] = (i < n && k0 + kk < d) ? X[i * d + k0 + kk] : XT(0);
+            }
         }
         if (tid < KC) sC[tid] = (centre && k0 + tid < d) ? centre[k0 + tid] : ACC(0);
         for (int e = tid; e < NT * KC * BW; e += 256) {
@@ -272,79 +290,92 @@ __global__ __launch_bounds__(256) void sf_apply_kernel(const XT* __restrict__ X,
 constexpr int NU = 4;   // rows in flight per thread
 
 // part[blk][t][k][c] as sf_moments_kernel.  A workgroup owns a range of rows
-// and up to 256 coordinates; thread (row offset tid / dc, coordinate tid % dc)
-// reads its coordinate of every R-th row (R = 256 / dc) straight from the
-// row-major points, so a wave's loads are contiguous, and keeps all NT x BW
-// sums in registers; the R row offsets are added in a fixed order at the end.
-template <typename XT, typename ZT, typename ACC, int NT, int BW>
+// and up to 256 V coordinates; thread (row offset tid / dcv, coordinate group
+// tid % dcv) reads V adjacent coordinates of every R-th row (R = 256 / dcv)
+// straight from the row-major points, so a wave's loads are contiguous, and
+// keeps all NT x BW x V sums in registers; the R row offsets are added in a
+// fixed order at the end.  V > 1 needs d to be a multiple of V.
+template <typename XT, typename ZT, typename ACC, int NT, int BW, int V>
 __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ X, const ACC* __restrict__ centre,
                                                          const ZT* __restrict__ Z, int64_t n, int32_t d, int32_t b,
                                                          int64_t rows_per_blk, ACC* __restrict__ part)
 {
     __shared__ ACC red[256 * BW];
     const int tid = threadIdx.x;
-    const int k0 = blockIdx.y * 256;
-    const int dc = d - k0 < 256 ? d - k0 : 256;
-    const int R = 256 / dc;
-    const int kk = tid % dc, rsub = tid / dc;
+    const int k0 = blockIdx.y * 256 * V;
+    const int dc = d - k0 < 256 * V ? d - k0 : 256 * V;
+    const int dcv = dc / V;
+    const int R = 256 / dcv;
+    const int kv = tid % dcv, rsub = tid / dcv;
     const bool active = rsub < R;
+    const int k = k0 + kv * V;
     const int64_t rb = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t re = rb + rows_per_blk < n ? rb + rows_per_blk : n;
-    ACC acc[NT][BW];
+    ACC acc[NT][BW][V];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int c = 0; c < BW; ++c) acc[t][c] = ACC(0);
+        for (int c = 0; c < BW; ++c)
+#pragma unroll
+            for (int j = 0; j < V; ++j) acc[t][c][j] = ACC(0);
     if (active) {
-        const int k = k0 + kk;
-        auto step = [&](XT xr, const ZT* zr) {
-            const ACC x = feature<XT, ACC>(xr, centre, k);
-            ACC xt = x;
+        ACC cen[V];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
+        for (int j = 0; j < V; ++j) cen[j] = centre ? centre[k + j] : ACC(0);
+        auto step = [&](const Vec<XT, V>& xr, const ZT* zr) {
 #pragma unroll
-                for (int c = 0; c < BW; ++c)
-                    if (c < b) acc[t][c] = fma_acc(xt, (ACC)zr[c], acc[t][c]);
-                if (t + 1 < NT) xt = mul_acc(xt, x);
+            for (int j = 0; j < V; ++j) {
+                const ACC x = (ACC)((ACC)xr.v[j] - cen[j]);
+                ACC xt = x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                    for (int c = 0; c < BW; ++c)
+                        if (c < b) acc[t][c][j] = fma_acc(xt, (ACC)zr[c], acc[t][c][j]);
+                    if (t + 1 < NT) xt = mul_acc(xt, x);
+                }
             }
         };
-        int64_t j = rb + rsub;
-        for (; j + (int64_t)(NU - 1) * R < re; j += (int64_t)NU * R) {
-            XT xv[NU];
+        int64_t r = rb + rsub;
+        for (; r + (int64_t)(NU - 1) * R < re; r += (int64_t)NU * R) {
+            Vec<XT, V> xv[NU];
             ZT zv[NU][BW];
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                const int64_t r = j + (int64_t)u * R;
-                xv[u] = X[r * d + k];
+                const int64_t row = r + (int64_t)u * R;
+                xv[u] = *reinterpret_cast<const Vec<XT, V>*>(X + row * d + k);
 #pragma unroll
-                for (int c = 0; c < BW; ++c) zv[u][c] = c < b ? Z[r * b + c] : ZT(0);
+                for (int c = 0; c < BW; ++c) zv[u][c] = c < b ? Z[row * b + c] : ZT(0);
             }
 #pragma unroll
             for (int u = 0; u < NU; ++u) step(xv[u], zv[u]);
         }
-        for (; j < re; j += R) {
+        for (; r < re; r += R) {
             ZT zv[BW];
 #pragma unroll
-            for (int c = 0; c < BW; ++c) zv[c] = c < b ? Z[j * b + c] : ZT(0);
-            step(X[j * d + k], zv);
+            for (int c = 0; c < BW; ++c) zv[c] = c < b ? Z[r * b + c] : ZT(0);
+            step(*reinterpret_cast<const Vec<XT, V>*>(X + r * d + k), zv);
         }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        if (active) {
 #pragma unroll
-            for (int c = 0; c < BW; ++c) red[tid * BW + c] = acc[t][c];
-        }
-        __syncthreads();
-        if (rsub == 0) {
+        for (int j = 0; j < V; ++j) {
+            if (active) {
 #pragma unroll
-            for (int c = 0; c < BW; ++c) {
-                ACC s = ACC(0);
-                for (int r = 0; r < R; ++r) s = add_acc(s, red[(r * dc + kk) * BW + c]);
-                if (c < b) part[(((size_t)blockIdx.x * NT + t) * d + k0 + kk) * b + c] = s;
+                for (int c = 0; c < BW; ++c) red[tid * BW + c] = acc[t][c][j];
             }
+            __syncthreads();
+            if (rsub == 0) {
+#pragma unroll
+                for (int c = 0; c < BW; ++c) {
+                    ACC sum = ACC(0);
+                    for (int q = 0; q < R; ++q) sum = add_acc(sum, red[(q * dcv + kv) * BW + c]);
+                    if (c < b) part[(((size_t)blockIdx.x * NT + t) * d + k + j) * b + c] = sum;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -468,22 +499,34 @@ constexpr int moments_kc() { return MKG * moments_kpt<NT>(); }
 
 int kc_for(int nt) { return nt == 1 ? moments_kc<1>() : nt <= 4 ? moments_kc<4>() : moments_kc<6>(); }
 
-// the narrow kernels (all sums of a thread in registers) serve b <= 8 when
-// the NT x (b rounded up) sums fit
-constexpr bool narrow_fits(int nt, int bw) { return bw <= 8 && nt * bw <= 32; }
+// the narrow moments kernel (all sums of a thread in registers) serves b <= 8
+// when the NT x (b rounded up) x V sums fit
+constexpr bool narrow_fits(int nt, int bw, int v = 1) { return bw <= 8 && nt * bw * v <= 32; }
+
+// coordinates per thread of the narrow moments kernel: 16-byte loads when d
+// allows and the sums fit
+int narrow_vec(int nt, int32_t b, int32_t d, int xbytes) {
+    const int bw = pad_bw(b);
+    const int vmax = 16 / xbytes;
+    for (int v = vmax; v > 1; v >>= 1)
+        if (d % v == 0 && narrow_fits(nt, bw, v)) return v;
+    return 1;
+}
 
 // Moments launch shape: the kernel family, rows per workgroup (about 2048
 // workgroups over the grid; the LDS kernel takes whole tiles) and the number
 // of row ranges, which sizes the partial sums.
 struct MomentsPlan {
     bool narrow;
+    int vec;   // coordinates per thread of the narrow kernel
     int64_t rpb, nblk;
     unsigned kblk;
 };
-MomentsPlan moments_plan(int64_t n, int32_t d, int32_t b, int nt) {
+MomentsPlan moments_plan(int64_t n, int32_t d, int32_t b, int nt, int xbytes) {
     MomentsPlan pl;
     pl.narrow = narrow_fits(nt, pad_bw(b));
-    const int kc = pl.narrow ? 256 : kc_for(nt);
+    pl.vec = pl.narrow ? narrow_vec(nt, b, d, xbytes) : 1;
+    const int kc = pl.narrow ? 256 * pl.vec : kc_for(nt);
     pl.kblk = (unsigned)((d + kc - 1) / kc);
     int64_t want = 2048 / (int64_t)pl.kblk;
     if (want < 1) want = 1;
@@ -499,12 +542,27 @@ template <typename XT, typename ZT, typename ACC, int NT, int BW>
 hipError_t moments_bw(const void* X, const void* centre, const void* Z, int64_t n, int32_t d, int32_t b, void* part,
                       int64_t* nblk_out, hipStream_t s)
 {
-    const MomentsPlan pl = moments_plan(n, d, b, NT);
+    const MomentsPlan pl = moments_plan(n, d, b, NT, (int)sizeof(XT));
     *nblk_out = pl.nblk;
     dim3 grid((unsigned)pl.nblk, pl.kblk);
     if constexpr (narrow_fits(NT, BW)) {
         if (pl.narrow) {
-            sf_moments_narrow<XT, ZT, ACC, NT, BW><<<grid, 256, 0, s>>>(
+            constexpr int V4 = 16 / (int)sizeof(XT);
+            if constexpr (V4 >= 4 && narrow_fits(NT, BW, 4)) {
+                if (pl.vec == 4) {
+                    sf_moments_narrow<XT, ZT, ACC, NT, BW, 4><<<grid, 256, 0, s>>>(
+                        (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, pl.rpb, (ACC*)part);
+                    return hipGetLastError();
+                }
+            }
+            if constexpr (V4 >= 2 && narrow_fits(NT, BW, 2)) {
+                if (pl.vec == 2) {
+                    sf_moments_narrow<XT, ZT, ACC, NT, BW, 2><<<grid, 256, 0, s>>>(
+                        (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, pl.rpb, (ACC*)part);
+                    return hipGetLastError();
+                }
+            }
+            sf_moments_narrow<XT, ZT, ACC, NT, BW, 1><<<grid, 256, 0, s>>>(
                 (const XT*)X, (const ACC*)centre, (const ZT*)Z, n, d, b, pl.rpb, (ACC*)part);
             return hipGetLastError();
         }
@@ -596,7 +654,7 @@ int sf_moment_count(int form, int p) { return form == SF_EVEN ? p : 1; }
 
 size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p) {
     const int nt = sf_moment_count(form, p);
-    const int64_t nblk = moments_plan(n, d, b, nt).nblk;
+    const int64_t nblk = moments_plan(n, d, b, nt, form == SF_LOG ? 8 : 4).nblk;
     const size_t cnt = (size_t)nt * d * b;
     return ((size_t)nblk + 2) * cnt * 8;   // row-range partials, the moments, the mixed moments
 }
@@ -605,7 +663,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
 {
     if (q.b < 1 || q.b > 64 || q.n < 1 || q.d < 1) return hipErrorInvalidValue;
     const int nt = sf_moment_count(form, p);
-    const int64_t nblk_max = moments_plan(q.n, q.d, q.b, nt).nblk;
+    const int64_t nblk_max = moments_plan(q.n, q.d, q.b, nt, form == SF_LOG ? 8 : 4).nblk;
     const size_t cnt = (size_t)nt * q.d * q.b;
     char* part = (char*)scratch;
     char* G = part + (size_t)nblk_max * cnt * 8;
