@@ -23,6 +23,7 @@
 // fits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -379,6 +380,195 @@ __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ 
     }
 }
 
+// ---- FP64 matrix cores for the single-moment forms (b > 32) ----------------
+// v_mfma_f64_16x16x4f64 lane layout on gfx950 (checked on the GPU with a
+// probe): A (16 x 4): lane l holds A[l % 16][l / 16]; B (4 x 16): lane l holds
+// B[l / 16][l % 16]; D (16 x 16): lane l, element r holds D[4r + l / 16][l % 16].
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <typename XT>
+__device__ __forceinline__ void load4(const XT* p, double (&v)[4]) {
+    if constexpr (sizeof(XT) == 4) {
+        const Vec<XT, 4> q = *reinterpret_cast<const Vec<XT, 4>*>(p);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = (double)q.v[t];
+    } else {
+        const Vec<XT, 2> q0 = *reinterpret_cast<const Vec<XT, 2>*>(p);
+        const Vec<XT, 2> q1 = *reinterpret_cast<const Vec<XT, 2>*>(p + 2);
+        v[0] = (double)q0.v[0];
+        v[1] = (double)q0.v[1];
+        v[2] = (double)q1.v[0];
+        v[3] = (double)q1.v[1];
+    }
+}
+
+// part[wave][k][c] = sum over the wave's rows j of phi(x_jk) z_jc (phi: the
+// centred coordinate, or the stored logarithm).  A wave owns 64 coordinates
+// (workgroup column blockIdx.y) and 64 columns: 4 x 4 tiles of 16 x 16.  Each
+// step takes 4 rows; lane (m, g) = (l % 16, l / 16) loads coordinates
+// k0 + 4m .. +3 and columns 4m .. +3 of row j + g with one 16-byte load each,
+// so tile t of the coordinates holds k = k0 + 4 i + t at tile row i and tile u
+// of the columns holds c = 4 n + u at tile column n.  Needs d % 4 == 0 and
+// b % 4 == 0.
+template <typename XT>
+__global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X, const double* __restrict__ centre,
+                                                       const float* __restrict__ Z, int64_t n, int32_t d, int32_t b,
+                                                       int64_t rows_per_wave, double* __restrict__ part)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int64_t xw = (int64_t)blockIdx.x * 4 + w;
+    const int k0 = blockIdx.y * 64;
+    const int kq = k0 + 4 * m, cq = 4 * m;
+    const bool kin = kq < d, cin = cq < b;
+    double cen[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cen[t] = (centre && kin) ? centre[kq + t] : 0.0;
+    d4v acc[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int64_t r0 = xw * rows_per_wave;
+    const int64_t r1 = r0 + rows_per_wave < n ? r0 + rows_per_wave : n;
+    for (int64_t j0 = r0; j0 < r1; j0 += 4) {   // the same trip count on every lane
+        const int64_t j = j0 + g;
+        double a[4] = {0.0, 0.0, 0.0, 0.0}, z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (j < r1) {
+            if (kin) {
+                load4<XT>(X + j * d + kq, a);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[t] -= cen[t];
+            }
+            if (cin) load4<float>(Z + j * b + cq, z);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], z[u], acc[t][u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = k0 + 4 * (4 * r + g) + t, c = 4 * m + u;
+                if (k < d && c < b) part[((size_t)xw * d + k) * b + c] = acc[t][u][r];
+            }
+}
+
+// Out[i][c] = sum_k x~_ik V[k][c] + a_i T0_c + U_c on matrix cores.  A wave
+// takes NTL tiles of 16 points at a time and every column (CT tiles of 16);
+// per chunk of 16 coordinates lane (m, g) loads coordinates k0 + 4g .. +3 of
+// point m of each tile (one 16-byte load when d % 4 == 0; the next chunk's
+// loads are issued before the current chunk's products), and step s of the
+// chunk multiplies the A column g = coordinate k0 + 4g + s.  V (d x b FP64) is
+// staged once per workgroup in dynamic LDS when it fits (LDS_V), else read
+// through the caches; each V operand serves all NTL tiles.
+constexpr int NTL = 1;   // 4 tiles per step measured slower (occupancy 1) than 1
+template <int CT, bool LDS_V>
+__global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X, const double* __restrict__ centre,
+                                                     int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
+                                                     const double* __restrict__ V, const double* __restrict__ a,
+                                                     const double* __restrict__ U, float* __restrict__ Out)
+{
+    extern __shared__ double sV[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int wpb = blockDim.x >> 6;   // waves per workgroup (8 share one LDS copy of V)
+    if constexpr (LDS_V) {
+        for (int e = threadIdx.x; e < d * b; e += blockDim.x) sV[e] = V[e];
+        __syncthreads();
+    }
+    const double* Vs = LDS_V ? sV : V;
+    const int64_t ngroup = (n + 16 * NTL - 1) / (16 * NTL);
+    const int64_t wave = (int64_t)blockIdx.x * wpb + w, nwaves = (int64_t)gridDim.x * wpb;
+    const bool vec = d % 4 == 0;
+    double t0[CT], uu[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+        const int c = 16 * u + m;
+        t0[u] = c < b ? T0[c] : 0.0;
+        uu[u] = (U && c < b) ? U[c] : 0.0;
+    }
+    // coordinates k0 + 4g .. +3 of point ia, zero outside the data
+    auto load_chunk = [&](int64_t ia, int k0, float (&xv)[4]) {
+        const int kq = k0 + 4 * g;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) xv[s] = 0.0f;
+        if (ia >= n) return;
+        if (vec) {
+            if (kq < d) {
+                const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(X + ia * d + kq);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) xv[s] = q.v[s];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if (kq + s < d) xv[s] = X[ia * d + kq + s];
+        }
+    };
+    for (int64_t grp = wave; grp < ngroup; grp += nwaves) {
+        const int64_t i0 = grp * 16 * NTL;
+        d4v acc[NTL][CT];
+#pragma unroll
+        for (int q = 0; q < NTL; ++q)
+#pragma unroll
+            for (int u = 0; u < CT; ++u) acc[q][u] = d4v{0.0, 0.0, 0.0, 0.0};
+        float xn[NTL][4];
+#pragma unroll
+        for (int q = 0; q < NTL; ++q) load_chunk(i0 + 16 * q + m, 0, xn[q]);
+        for (int k0 = 0; k0 < d; k0 += 16) {
+            float xv[NTL][4];
+#pragma unroll
+            for (int q = 0; q < NTL; ++q)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) xv[q][s] = xn[q][s];
+            if (k0 + 16 < d) {
+#pragma unroll
+                for (int q = 0; q < NTL; ++q) load_chunk(i0 + 16 * q + m, k0 + 16, xn[q]);
+            }
+            const int kq = k0 + 4 * g;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = kq + s;
+                const bool kin = k < d;
+                const double ck = (kin && centre) ? centre[k] : 0.0;
+                double vb[CT];
+#pragma unroll
+                for (int u = 0; u < CT; ++u) {
+                    const int c = 16 * u + m;
+                    vb[u] = (kin && c < b) ? Vs[(size_t)k * b + c] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < NTL; ++q) {
+                    const double xa = kin ? (double)xv[q][s] - ck : 0.0;   // zero for points past n
+#pragma unroll
+                    for (int u = 0; u < CT; ++u)
+                        acc[q][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, vb[u], acc[q][u], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NTL; ++q)
+#pragma unroll
+            for (int u = 0; u < CT; ++u) {
+                const int c = 16 * u + m;
+                if (c >= b) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = i0 + 16 * q + 4 * r + g;
+                    if (i >= n) continue;
+                    double v = acc[q][u][r] + uu[u];
+                    if (a) v = fma(a[i], t0[u], v);
+                    Out[i * b + c] = (float)v;
+                }
+            }
+    }
+}
+
 // ---- per-point weights at preparation --------------------------------------
 // negH[i] = sum_k x_ik log x_ik and LX[i][k] = log x_ik (FP64); flags |= bad
 // for a coordinate that is not finite and positive (its logarithm is not finite)
@@ -652,9 +842,33 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
 
 int sf_moment_count(int form, int p) { return form == SF_EVEN ? p : 1; }
 
+namespace {
+
+// The matrix-core moments serve the single-moment forms at b > 32 with d and b
+// multiples of 4 (16-byte loads of X and Z; Z must also be 16-byte aligned).
+bool mfma_moments_fit(int form, int32_t d, int32_t b) {
+    return form != SF_EVEN && pad_bw(b) == 64 && d % 4 == 0 && b % 4 == 0;
+}
+// waves of the matrix-core moments along the rows: about 2048 over the grid
+int64_t mfma_row_waves(int64_t n, int32_t d) {
+    const int64_t ky = (d + 63) / 64;
+    int64_t w = 2048 / ky;
+    const int64_t steps = (n + 3) / 4;
+    if (w > steps) w = steps;
+    return w < 4 ? 4 : (w + 3) / 4 * 4;
+}
+// row-range partials the moments stage may write
+int64_t partial_count(int64_t n, int32_t d, int32_t b, int form, int nt) {
+    int64_t nb = moments_plan(n, d, b, nt, form == SF_LOG ? 8 : 4).nblk;
+    if (mfma_moments_fit(form, d, b)) nb = std::max(nb, mfma_row_waves(n, d));
+    return nb;
+}
+
+}  // namespace
+
 size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p) {
     const int nt = sf_moment_count(form, p);
-    const int64_t nblk = moments_plan(n, d, b, nt, form == SF_LOG ? 8 : 4).nblk;
+    const int64_t nblk = partial_count(n, d, b, form, nt);
     const size_t cnt = (size_t)nt * d * b;
     return ((size_t)nblk + 2) * cnt * 8;   // row-range partials, the moments, the mixed moments
 }
@@ -663,7 +877,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
 {
     if (q.b < 1 || q.b > 64 || q.n < 1 || q.d < 1) return hipErrorInvalidValue;
     const int nt = sf_moment_count(form, p);
-    const int64_t nblk_max = moments_plan(q.n, q.d, q.b, nt, form == SF_LOG ? 8 : 4).nblk;
+    const int64_t nblk_max = partial_count(q.n, q.d, q.b, form, nt);
     const size_t cnt = (size_t)nt * q.d * q.b;
     char* part = (char*)scratch;
     char* G = part + (size_t)nblk_max * cnt * 8;
@@ -680,9 +894,24 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     int64_t nblk = 0;
     const int64_t per_t = (int64_t)q.d * q.b;
     // KL and cross entropy: moments of the logarithms kept since preparation
-    hipError_t e = (form == SF_LOG)
-                       ? moments_t<double, float, double, 1>(q.b, q.LX, nullptr, q.Z, q.n, q.d, part, &nblk, s)
-                       : moments_t<float, float, double, 1>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+    hipError_t e;
+    if (mfma_moments_fit(form, q.d, q.b) && (uintptr_t)q.Z % 16 == 0) {
+        const int64_t waves = mfma_row_waves(q.n, q.d);
+        const int64_t rpw = ((q.n + waves - 1) / waves + 3) / 4 * 4;
+        dim3 grid((unsigned)(waves / 4), (unsigned)((q.d + 63) / 64));
+        if (form == SF_LOG)
+            sf_moments_mfma<double><<<grid, 256, 0, s>>>(q.LX, nullptr, (const float*)q.Z, q.n, q.d, q.b, rpw,
+                                                         (double*)part);
+        else
+            sf_moments_mfma<float><<<grid, 256, 0, s>>>((const float*)q.X, (const double*)q.centre,
+                                                        (const float*)q.Z, q.n, q.d, q.b, rpw, (double*)part);
+        e = hipGetLastError();
+        nblk = waves;
+    } else {
+        e = (form == SF_LOG)
+                ? moments_t<double, float, double, 1>(q.b, q.LX, nullptr, q.Z, q.n, q.d, part, &nblk, s)
+                : moments_t<float, float, double, 1>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+    }
     if (e != hipSuccess) return e;
     const char* Gv = G;
     if (q.W) {
@@ -693,8 +922,36 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     } else {
         if ((e = reduce_launch<double>(part, nblk, per_t, 1, 0, q.alpha, G, s)) != hipSuccess) return e;
     }
-    return apply_t<float, double, float, 1, false>(q.X, form == SF_LOG ? nullptr : q.centre, q.n, q.d, q.b, q.T0, Gv,
-                                                   q.a, q.U, q.Out, s);
+    const double* cen = form == SF_LOG ? nullptr : (const double*)q.centre;
+    if (q.b >= 16) {   // matrix cores: 16 points x every column per wave
+        const int64_t groups = (q.n + 16 * NTL - 1) / (16 * NTL);
+        int64_t blocks = (groups + 7) / 8;
+        if (blocks > 1024) blocks = 1024;
+        const unsigned gb = (unsigned)blocks;
+        const float* Xf = (const float*)q.X;
+        const double* T0 = (const double*)q.T0;
+        const double* Vd = (const double*)Gv;
+        float* O = (float*)q.Out;
+        const size_t vbytes = (size_t)q.d * q.b * 8;
+        const bool lds = vbytes <= 65536;
+        const size_t shm = lds ? vbytes : 0;
+#define SF_APPLY_MFMA(CT)                                                                                           \
+    do {                                                                                                            \
+        if (lds)                                                                                                    \
+            sf_apply_mfma<CT, true><<<gb, 512, shm, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, q.U, O);              \
+        else                                                                                                        \
+            sf_apply_mfma<CT, false><<<2 * gb, 256, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, q.U, O);           \
+    } while (0)
+        switch ((q.b + 15) / 16) {
+        case 1: SF_APPLY_MFMA(1); break;
+        case 2: SF_APPLY_MFMA(2); break;
+        case 3: SF_APPLY_MFMA(3); break;
+        default: SF_APPLY_MFMA(4); break;
+        }
+#undef SF_APPLY_MFMA
+        return hipGetLastError();
+    }
+    return apply_t<float, double, float, 1, false>(q.X, cen, q.n, q.d, q.b, q.T0, Gv, q.a, q.U, q.Out, s);
 }
 
 hipError_t launch_kl_weights(const float* X, int64_t n, int32_t d, double* negH, double* LX, uint32_t* flags,

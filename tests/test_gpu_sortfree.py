@@ -316,3 +316,41 @@ def test_many_coordinates():
     Xf = g.standard_normal((n, 300)).astype(np.float32)
     Zw = synth.rhs_normal(n, 16, 9963)
     _check_float(Xf, Zw, _query(Xf, Zw, oracle.L4), oracle.L4, _scale_even(4), p=4)
+
+
+# ---------------------------------------------------------------------------
+# the matrix-core kernels of the single-moment forms: moments at b > 32 with d,
+# b multiples of 4 and an aligned Z; the point pass at b >= 16
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("metric,b,n,d", [(oracle.KL, 20, 3001, 12), (oracle.MAHA2, 33, 2501, 37),
+                                          (oracle.BILINEAR, 48, 4099, 64), (oracle.CE, 64, 2049, 70),
+                                          (oracle.MAHA2, 64, 4099, 132), (oracle.KL, 40, 2053, 8)])
+def test_matrix_core_shapes(metric, b, n, d):
+    g = synth.rng(9970 + b + d)
+    M = None
+    if metric in (oracle.KL, oracle.CE):
+        X = synth.simplex_points(n, d, 9971 + d)
+        scale = _scale_log(metric == oracle.KL)
+    else:
+        X = (g.standard_normal((n, d)) + 2.0).astype(np.float32)
+        M = synth.square_matrix(d, 9972 + d, "spd" if metric == oracle.MAHA2 else "general")
+        scale = _scale_quad(M, metric == oracle.MAHA2)
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    Y = _query(X, Z, metric, M=M)
+    _check_float(X, Z, Y, metric, scale, M=M)
+
+
+def test_matrix_core_moments_with_unaligned_z():
+    import torch
+    n, d, b = 3001, 16, 64
+    X = synth.simplex_points(n, d, 9980)
+    Z = synth.rhs_normal(n, b, 9981)
+    flat = torch.empty(n * b + 1, dtype=torch.float32, device="cuda")
+    Zd = flat[1:].view(n, b)                     # 4 bytes past a 16-byte boundary
+    Zd.copy_(torch.from_numpy(Z))
+    assert Zd.data_ptr() % 16 != 0
+    h = dm.prepare(dev(X), oracle.KL)
+    Y = h.matvec(Zd)
+    h.sync()
+    _check_float(X, Z, Y.cpu().numpy(), oracle.KL, _scale_log(True))
+    h.free()
