@@ -17,59 +17,113 @@ namespace {
 constexpr int TOT_ROWS = 4096;  // rows per stage-1 block
 constexpr int TOT_MAXB = 1024;
 
-template <bool INT, typename ZT, typename WT>
+// V adjacent columns per thread, loaded as one vector when V > 1
+template <typename T, int V>
+struct alignas(sizeof(T) * V) ZVec {
+    T v[V];
+};
+
+// thread layout: column group (tid % bpc) of V adjacent columns, row lane
+// tid / bpc; rows are taken 4 at a time so that 4 loads are in flight
+template <bool INT, typename ZT, typename WT, int V>
 __global__ __launch_bounds__(256) void totals_stage1(const ZT* __restrict__ Z, int64_t n, int32_t b,
                                                      const WT* __restrict__ wgt, void* __restrict__ partials,
                                                      uint32_t* __restrict__ status)
 {
-    // thread layout: column c = tid % BPc, row lane = tid / BPc
+    const int ng = (b + V - 1) / V;   // column groups
     int bpc = 1;
-    while (bpc < b && bpc < 256) bpc <<= 1;
+    while (bpc < ng && bpc < 256) bpc <<= 1;
     const int rl = threadIdx.x / bpc, rs = 256 / bpc;
     const int64_t j0 = (int64_t)blockIdx.x * TOT_ROWS;
     const int64_t j1 = min(n, j0 + TOT_ROWS);
-    __shared__ double s_f[3][256];
-    __shared__ int64_t s_i[2][256];
+    __shared__ double s_f[3][V][256];
+    __shared__ int64_t s_i[2][V][256];
     uint32_t bad = 0;
-    for (int cbase = 0; cbase < b; cbase += bpc) {
-        const int c = cbase + (int)(threadIdx.x % bpc);
-        double f0 = 0.0, f1 = 0.0, fl = 0.0;
-        uint64_t i0 = 0, i1 = 0;
-        if (c < b) {
-            for (int64_t j = j0 + rl; j < j1; j += rs) {
-                const ZT z = Z[j * b + c];
+    for (int gbase = 0; gbase < ng; gbase += bpc) {
+        const int grp = gbase + (int)(threadIdx.x % bpc);
+        const int c0 = grp * V;
+        double f0[V], f1[V], fl[V];
+        uint64_t i0[V], i1[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            f0[v] = f1[v] = fl[v] = 0.0;
+            i0[v] = i1[v] = 0;
+        }
+        auto add = [&](const ZVec<ZT, V>& zr, WT wj) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const ZT z = zr.v[v];
                 if constexpr (INT) {
-                    i0 += (uint64_t)(int64_t)z;
-                    i1 += (uint64_t)(int64_t)wgt[j] * (uint64_t)(int64_t)z;
-                    fl += fabs((double)z);
+                    i0[v] += (uint64_t)(int64_t)z;
+                    i1[v] += (uint64_t)(int64_t)wj * (uint64_t)(int64_t)z;
+                    fl[v] += fabs((double)z);
                 } else {
                     if (!isfinite(z)) bad = 1;
-                    f0 += (double)z;
-                    f1 += (double)wgt[j] * (double)z;
-                    fl += fabs((double)z);
+                    f0[v] += (double)z;
+                    f1[v] += (double)wj * (double)z;
+                    fl[v] += fabs((double)z);
                 }
             }
+        };
+        if (grp < ng) {
+            int64_t j = j0 + rl;
+            for (; j + 3 * (int64_t)rs < j1; j += 4 * (int64_t)rs) {
+                ZVec<ZT, V> zr[4];
+                WT wj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t r = j + u * (int64_t)rs;
+                    if (V > 1) {
+                        zr[u] = *reinterpret_cast<const ZVec<ZT, V>*>(Z + r * b + c0);
+                    } else {
+                        zr[u].v[0] = Z[r * b + c0];
+                    }
+                    wj[u] = wgt[r];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) add(zr[u], wj[u]);
+            }
+            for (; j < j1; j += rs) {
+                ZVec<ZT, V> zr;
+                if (V > 1) {
+                    zr = *reinterpret_cast<const ZVec<ZT, V>*>(Z + j * b + c0);
+                } else {
+                    zr.v[0] = Z[j * b + c0];
+                }
+                add(zr, wgt[j]);
+            }
         }
-        s_f[0][threadIdx.x] = f0; s_f[1][threadIdx.x] = f1; s_f[2][threadIdx.x] = fl;
-        s_i[0][threadIdx.x] = (int64_t)i0; s_i[1][threadIdx.x] = (int64_t)i1;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            s_f[0][v][threadIdx.x] = f0[v];
+            s_f[1][v][threadIdx.x] = f1[v];
+            s_f[2][v][threadIdx.x] = fl[v];
+            s_i[0][v][threadIdx.x] = (int64_t)i0[v];
+            s_i[1][v][threadIdx.x] = (int64_t)i1[v];
+        }
         __syncthreads();
-        if ((int)threadIdx.x < bpc && c < b) {
-            double a0 = 0, a1 = 0, al = 0;
-            uint64_t b0 = 0, b1 = 0;
-            for (int r = 0; r < rs; ++r) {
-                const int t = r * bpc + threadIdx.x;
-                a0 += s_f[0][t]; a1 += s_f[1][t]; al += s_f[2][t];
-                b0 += (uint64_t)s_i[0][t]; b1 += (uint64_t)s_i[1][t];
+        if ((int)threadIdx.x < bpc && grp < ng) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int c = c0 + v;
+                if (c >= b) continue;
+                double a0 = 0, a1 = 0, al = 0;
+                uint64_t b0 = 0, b1 = 0;
+                for (int r = 0; r < rs; ++r) {
+                    const int t = r * bpc + threadIdx.x;
+                    a0 += s_f[0][v][t]; a1 += s_f[1][v][t]; al += s_f[2][v][t];
+                    b0 += (uint64_t)s_i[0][v][t]; b1 += (uint64_t)s_i[1][v][t];
+                }
+                double* pf = (double*)partials + ((size_t)blockIdx.x * b + c) * 3;
+                if constexpr (INT) {
+                    pf[0] = __longlong_as_double((long long)b0);
+                    pf[1] = __longlong_as_double((long long)b1);
+                } else {
+                    pf[0] = a0;
+                    pf[1] = a1;
+                }
+                pf[2] = al;
             }
-            double* pf = (double*)partials + ((size_t)blockIdx.x * b + c) * 3;
-            if constexpr (INT) {
-                pf[0] = __longlong_as_double((long long)b0);
-                pf[1] = __longlong_as_double((long long)b1);
-            } else {
-                pf[0] = a0;
-                pf[1] = a1;
-            }
-            pf[2] = al;
         }
         __syncthreads();
     }
@@ -140,15 +194,31 @@ hipError_t launch_totals(bool is_int, int zkind, const void* Z, int64_t n, int32
 {
     if (b < 1 || b > TOT_MAXB) return hipErrorInvalidValue;
     const int nblk = totals_partial_blocks(n);
+    // 16-byte row loads when every row of Z starts on a 16-byte boundary
+    const size_t zb = (!is_int || zkind == IN_I32) ? 4 : 8;
+    const int vw = (int)(16 / zb);
+    const bool vec = b % vw == 0 && (uintptr_t)Z % 16 == 0;
     if (!is_int) {
-        totals_stage1<false, float, double><<<nblk, 256, 0, s>>>((const float*)Z, n, b, (const double*)w,
-                                                                 o.partials, o.status);
+        if (vec)
+            totals_stage1<false, float, double, 4><<<nblk, 256, 0, s>>>((const float*)Z, n, b, (const double*)w,
+                                                                        o.partials, o.status);
+        else
+            totals_stage1<false, float, double, 1><<<nblk, 256, 0, s>>>((const float*)Z, n, b, (const double*)w,
+                                                                        o.partials, o.status);
     } else if (zkind == IN_I32) {
-        totals_stage1<true, int32_t, int64_t><<<nblk, 256, 0, s>>>((const int32_t*)Z, n, b, (const int64_t*)w,
-                                                                   o.partials, o.status);
+        if (vec)
+            totals_stage1<true, int32_t, int64_t, 4><<<nblk, 256, 0, s>>>((const int32_t*)Z, n, b,
+                                                                          (const int64_t*)w, o.partials, o.status);
+        else
+            totals_stage1<true, int32_t, int64_t, 1><<<nblk, 256, 0, s>>>((const int32_t*)Z, n, b,
+                                                                          (const int64_t*)w, o.partials, o.status);
     } else {
-        totals_stage1<true, int64_t, int64_t><<<nblk, 256, 0, s>>>((const int64_t*)Z, n, b, (const int64_t*)w,
-                                                                   o.partials, o.status);
+        if (vec)
+            totals_stage1<true, int64_t, int64_t, 2><<<nblk, 256, 0, s>>>((const int64_t*)Z, n, b,
+                                                                          (const int64_t*)w, o.partials, o.status);
+        else
+            totals_stage1<true, int64_t, int64_t, 1><<<nblk, 256, 0, s>>>((const int64_t*)Z, n, b,
+                                                                          (const int64_t*)w, o.partials, o.status);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

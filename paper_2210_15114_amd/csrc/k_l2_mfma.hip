@@ -157,8 +157,9 @@ __global__ __launch_bounds__(256) void xtz_reduce_kernel(const double* __restric
 
 // ---------------------------------------------------------------------------
 // Out = nrm_i S0_c + R_c - 2 (X V)_ic; each wave computes 32 rows x all b
-// columns per step, loading the block's X values for every k-step first;
-// V is split into BF16 hi/lo once per workgroup in LDS.
+// columns per step, with the next k-step's X values in flight during the
+// current step's products; V is split into BF16 hi/lo once per workgroup in
+// LDS.
 // ---------------------------------------------------------------------------
 template <int KS, bool VEC>
 __global__ __launch_bounds__(256) void l2_apply_mfma_kernel(const float* __restrict__ X, int64_t n, int32_t d,
@@ -188,37 +189,43 @@ __global__ __launch_bounds__(256) void l2_apply_mfma_kernel(const float* __restr
         s0[ct] = (ct < ct_n && c < b) ? S0[c] : 0.0;
         rr[ct] = (ct < ct_n && c < b) ? R[c] : 0.0;
     }
+    // X of one k-step (8 values of the lane's A row); the next step's values
+    // are loaded before this step's products
+    auto load_step = [&](int64_t ir, int ks, float (&xv)[8]) {
+        const int kb = ks * 16 + 8 * (lane / 32);
+        if (VEC) {
+            if (ir < n && kb < d) {
+                const float4 a = *reinterpret_cast<const float4*>(X + ir * d + kb);
+                const float4 c = *reinterpret_cast<const float4*>(X + ir * d + kb + 4);
+                xv[0] = a.x; xv[1] = a.y; xv[2] = a.z; xv[3] = a.w;
+                xv[4] = c.x; xv[5] = c.y; xv[6] = c.z; xv[7] = c.w;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) xv[t] = 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) xv[t] = (ir < n && kb + t < d) ? X[ir * d + kb + t] : 0.0f;
+        }
+    };
     for (int64_t blk = (int64_t)blockIdx.x * 4 + w; blk < nblk; blk += (int64_t)gridDim.x * 4) {
         const int64_t i0 = blk * 32;
         const int64_t ir = i0 + lane % 32;       // the A row this lane loads
-        float xv[KS][8];
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int kb = ks * 16 + 8 * (lane / 32);
-            if (VEC) {
-                if (ir < n && kb < d) {
-                    const float4 a = *reinterpret_cast<const float4*>(X + ir * d + kb);
-                    const float4 c = *reinterpret_cast<const float4*>(X + ir * d + kb + 4);
-                    xv[ks][0] = a.x; xv[ks][1] = a.y; xv[ks][2] = a.z; xv[ks][3] = a.w;
-                    xv[ks][4] = c.x; xv[ks][5] = c.y; xv[ks][6] = c.z; xv[ks][7] = c.w;
-                } else {
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) xv[ks][t] = 0.0f;
-                }
-            } else {
-#pragma unroll
-                for (int t = 0; t < 8; ++t) xv[ks][t] = (ir < n && kb + t < d) ? X[ir * d + kb + t] : 0.0f;
-            }
-        }
+        float xn[8];
+        load_step(ir, 0, xn);
         f32x16 acc0 = {}, acc1 = {};
-#pragma unroll
+#pragma unroll 1
         for (int ks = 0; ks < KS; ++ks) {
             const int kb = ks * 16 + 8 * (lane / 32);
+            float xv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) xv[t] = xn[t];
+            if (ks + 1 < KS) load_step(ir, ks + 1, xn);
             bf16x8 ah, al;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 __bf16 h, l;
-                split(xv[ks][t], h, l);
+                split(xv[t], h, l);
                 ah[t] = h;
                 al[t] = l;
             }
