@@ -569,6 +569,147 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
     }
 }
 
+// Even-p moments on matrix cores: part[blk][t][k][c] = sum over the
+// workgroup's rows j of x~_jk^(t+1) z_jc, t = 0 .. NT-1.  A workgroup owns a
+// row range and 64 coordinates; wave w owns the 16 coordinates
+// k0 + 16w .. +15 (tile row m is coordinate k0 + 16w + m) and all 64 columns
+// (tile u holds column 4n + u at tile column n, from one 16-byte load of Z
+// per lane and step); the powers of x~ are formed once per lane and feed NT
+// products.  Needs b % 4 == 0 and a 16-byte aligned Z.
+template <int NT>
+__global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restrict__ X,
+                                                            const double* __restrict__ centre,
+                                                            const float* __restrict__ Z, int64_t n, int32_t d,
+                                                            int32_t b, int64_t rows_per_blk, double* __restrict__ part)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int kt0 = blockIdx.y * 64 + 16 * w;   // the wave's first coordinate
+    const int k = kt0 + m;
+    const bool kin = k < d, cin = 4 * m < b;
+    const double ck = kin ? centre[k] : 0.0;
+    d4v acc[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
+    // two 4-row steps per iteration: both steps' loads are issued before the products
+    for (int64_t j0 = r0; j0 < r1; j0 += 8) {   // the same trip count on every lane
+        double x[2] = {0.0, 0.0}, z[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t j = j0 + 4 * h + g;
+            if (j < r1) {
+                if (kin) x[h] = (double)X[j * d + k];
+                if (cin) load4<float>(Z + j * b + 4 * m, z[h]);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double xh = (j0 + 4 * h + g < r1 && kin) ? x[h] - ck : 0.0;
+            double xt = xh;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xt, z[h][u], acc[t][u], 0, 0, 0);
+                xt *= xh;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int kk = kt0 + 4 * r + g, c = 4 * m + u;
+                if (kk < d && c < b) part[(((size_t)blockIdx.x * NT + t) * d + kk) * b + c] = acc[t][u][r];
+            }
+}
+
+// Even-p point pass on matrix cores: Out[i][c] = sum_k sum_(t=0..P)
+// x~_ik^(P-t) G_t[k][c], with G_0[k][c] = T0[c] and G_t (t >= 1) the scaled
+// moments.  A workgroup of 8 waves takes 128 points at a time (16 per wave,
+// every column in CT tiles of 16); the moments of a chunk of 16 coordinates
+// are staged in LDS for all 8 waves between two barriers.  Within a chunk
+// lane (m, g) holds coordinates k0 + 4g .. +3 of point i0 + m, and step s
+// multiplies the A column g = coordinate k0 + 4g + s, once per power.
+template <int P, int CT>
+__global__ __launch_bounds__(512) void sf_apply_even_mfma(const float* __restrict__ X,
+                                                          const double* __restrict__ centre, int64_t n, int32_t d,
+                                                          int32_t b, const double* __restrict__ T0,
+                                                          const double* __restrict__ G, float* __restrict__ Out)
+{
+    __shared__ double sG[P][16][16 * CT];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const size_t per_t = (size_t)d * b;
+    const bool vec = d % 4 == 0;
+    double t0[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) t0[u] = 16 * u + m < b ? T0[16 * u + m] : 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 128; base < n; base += (int64_t)gridDim.x * 128) {   // uniform
+        const int64_t i0 = base + 16 * w, ia = i0 + m;
+        d4v acc[CT];
+#pragma unroll
+        for (int u = 0; u < CT; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < d; k0 += 16) {
+            __syncthreads();   // every wave is done with the previous chunk
+            for (int e = threadIdx.x; e < P * 16 * 16 * CT; e += 512) {
+                const int t = e / (16 * 16 * CT), rem = e % (16 * 16 * CT);
+                const int kk = rem / (16 * CT), c = rem % (16 * CT);
+                sG[t][kk][c] = (k0 + kk < d && c < b) ? G[t * per_t + (size_t)(k0 + kk) * b + c] : 0.0;
+            }
+            __syncthreads();
+            const int kq = k0 + 4 * g;
+            float xv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (ia < n) {
+                if (vec) {
+                    if (kq < d) {
+                        const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(X + ia * d + kq);
+#pragma unroll
+                        for (int s2 = 0; s2 < 4; ++s2) xv[s2] = q.v[s2];
+                    }
+                } else {
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; ++s2)
+                        if (kq + s2 < d) xv[s2] = X[ia * d + kq + s2];
+                }
+            }
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int kk = kq + st;
+                const double xa = kk < d ? (double)xv[st] - centre[kk] : 0.0;
+                double pw[P + 1];   // pw[e] = xa^e
+                pw[0] = 1.0;
+#pragma unroll
+                for (int e = 1; e <= P; ++e) pw[e] = pw[e - 1] * xa;
+#pragma unroll
+                for (int u = 0; u < CT; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(pw[P], t0[u], acc[u], 0, 0, 0);
+#pragma unroll
+                for (int t = 1; t <= P; ++t)
+#pragma unroll
+                    for (int u = 0; u < CT; ++u)
+                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(pw[P - t], sG[t - 1][4 * g + st][16 * u + m],
+                                                                      acc[u], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CT; ++u) {
+            const int c = 16 * u + m;
+            if (c >= b) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + 4 * r + g;
+                if (i < n) Out[i * b + c] = (float)acc[u][r];
+            }
+        }
+    }
+}
+
 // ---- per-point weights at preparation --------------------------------------
 // negH[i] = sum_k x_ik log x_ik and LX[i][k] = log x_ik (FP64); flags |= bad
 // for a coordinate that is not finite and positive (its logarithm is not finite)
@@ -815,6 +956,29 @@ hipError_t reduce_launch(const void* part, int64_t nblk, int64_t per_t, int nt, 
     return hipGetLastError();
 }
 
+// The matrix-core moments serve the single-moment forms at b > 32 with d and b
+// multiples of 4 (16-byte loads of X and Z; Z must also be 16-byte aligned).
+bool mfma_moments_fit(int form, int32_t d, int32_t b) {
+    return form != SF_EVEN && pad_bw(b) == 64 && d % 4 == 0 && b % 4 == 0;
+}
+// even p (float data) on matrix cores: b > 32 and b % 4 == 0 (16-byte loads of Z)
+bool even_mfma_fit(int32_t b) { return pad_bw(b) == 64 && b % 4 == 0; }
+// row ranges of the even-p matrix-core moments: about 2048 workgroups
+int64_t even_mfma_blocks(int64_t n, int32_t d) {
+    const int64_t ky = (d + 63) / 64;
+    int64_t blk = 2048 / ky;
+    const int64_t steps = (n + 3) / 4;
+    if (blk > steps) blk = steps;
+    return blk < 1 ? 1 : blk;
+}
+// waves of the matrix-core moments along the rows: about 2048 over the grid
+int64_t mfma_row_waves(int64_t n, int32_t d) {
+    const int64_t ky = (d + 63) / 64;
+    int64_t w = 2048 / ky;
+    const int64_t steps = (n + 3) / 4;
+    if (w > steps) w = steps;
+    return w < 4 ? 4 : (w + 3) / 4 * 4;
+}
 template <int P>
 hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char* G, hipStream_t s)
 {
@@ -822,9 +986,37 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
     hipError_t e;
     const int64_t per_t = (int64_t)q.d * q.b;
     if (!is_int) {
-        e = moments_t<float, float, double, P>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+        if (even_mfma_fit(q.b) && (uintptr_t)q.Z % 16 == 0) {
+            const int64_t blk = even_mfma_blocks(q.n, q.d);
+            const int64_t rpb = ((q.n + blk - 1) / blk + 3) / 4 * 4;
+            const int64_t nb = (q.n + rpb - 1) / rpb;
+            dim3 grid((unsigned)nb, (unsigned)((q.d + 63) / 64));
+            sf_moments_even_mfma<P><<<grid, 256, 0, s>>>((const float*)q.X, (const double*)q.centre,
+                                                         (const float*)q.Z, q.n, q.d, q.b, rpb, (double*)part);
+            e = hipGetLastError();
+            nblk = nb;
+        } else {
+            e = moments_t<float, float, double, P>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
+        }
         if (e != hipSuccess) return e;
         if ((e = reduce_launch<double>(part, nblk, per_t, P, P, 1.0, G, s)) != hipSuccess) return e;
+        if (q.b >= 16) {   // matrix cores for the point pass
+            int64_t blocks = (q.n + 127) / 128;
+            if (blocks > 1024) blocks = 1024;
+            const unsigned gb = (unsigned)blocks;
+            const float* Xf = (const float*)q.X;
+            const double* cen = (const double*)q.centre;
+            const double* T0 = (const double*)q.T0;
+            const double* Gd = (const double*)G;
+            float* O = (float*)q.Out;
+            switch ((q.b + 15) / 16) {
+            case 1: sf_apply_even_mfma<P, 1><<<gb, 512, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Gd, O); break;
+            case 2: sf_apply_even_mfma<P, 2><<<gb, 512, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Gd, O); break;
+            case 3: sf_apply_even_mfma<P, 3><<<gb, 512, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Gd, O); break;
+            default: sf_apply_even_mfma<P, 4><<<gb, 512, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Gd, O); break;
+            }
+            return hipGetLastError();
+        }
         return apply_t<float, double, float, P, true>(q.X, q.centre, q.n, q.d, q.b, q.T0, G, nullptr, nullptr, q.Out,
                                                       s);
     }
@@ -844,23 +1036,11 @@ int sf_moment_count(int form, int p) { return form == SF_EVEN ? p : 1; }
 
 namespace {
 
-// The matrix-core moments serve the single-moment forms at b > 32 with d and b
-// multiples of 4 (16-byte loads of X and Z; Z must also be 16-byte aligned).
-bool mfma_moments_fit(int form, int32_t d, int32_t b) {
-    return form != SF_EVEN && pad_bw(b) == 64 && d % 4 == 0 && b % 4 == 0;
-}
-// waves of the matrix-core moments along the rows: about 2048 over the grid
-int64_t mfma_row_waves(int64_t n, int32_t d) {
-    const int64_t ky = (d + 63) / 64;
-    int64_t w = 2048 / ky;
-    const int64_t steps = (n + 3) / 4;
-    if (w > steps) w = steps;
-    return w < 4 ? 4 : (w + 3) / 4 * 4;
-}
 // row-range partials the moments stage may write
 int64_t partial_count(int64_t n, int32_t d, int32_t b, int form, int nt) {
     int64_t nb = moments_plan(n, d, b, nt, form == SF_LOG ? 8 : 4).nblk;
     if (mfma_moments_fit(form, d, b)) nb = std::max(nb, mfma_row_waves(n, d));
+    if (form == SF_EVEN && even_mfma_fit(b)) nb = std::max(nb, even_mfma_blocks(n, d));
     return nb;
 }
 

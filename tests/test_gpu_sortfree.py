@@ -354,3 +354,24 @@ def test_matrix_core_moments_with_unaligned_z():
     h.sync()
     _check_float(X, Z, Y.cpu().numpy(), oracle.KL, _scale_log(True))
     h.free()
+
+
+@pytest.mark.parametrize("p,b,n,d,aligned", [(4, 40, 3001, 70, True), (6, 48, 2053, 9, True),
+                                              (4, 64, 3001, 33, False), (6, 20, 4099, 64, True)])
+def test_even_p_matrix_core_shapes(p, b, n, d, aligned):
+    import torch
+    g = synth.rng(9990 + p + b + d)
+    X = (g.standard_normal((n, d)) + 5.0).astype(np.float32)
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    if aligned:
+        Zd = dev(Z)
+    else:
+        flat = torch.empty(n * b + 1, dtype=torch.float32, device="cuda")
+        Zd = flat[1:].view(n, b)
+        Zd.copy_(torch.from_numpy(Z))
+        assert Zd.data_ptr() % 16 != 0
+    h = dm.prepare(dev(X), EVEN[p])
+    Y = h.matvec(Zd)
+    h.sync()
+    _check_float(X, Z, Y.cpu().numpy(), EVEN[p], _scale_even(p), p=p)
+    h.free()
