@@ -375,3 +375,33 @@ def test_even_p_matrix_core_shapes(p, b, n, d, aligned):
     h.sync()
     _check_float(X, Z, Y.cpu().numpy(), EVEN[p], _scale_even(p), p=p)
     h.free()
+
+
+@pytest.mark.parametrize("n", [1, 5, 17, 130])
+@pytest.mark.parametrize("metric", [oracle.L4, oracle.L6, oracle.KL, oracle.MAHA2])
+def test_matrix_core_paths_at_tiny_n(metric, n):
+    # fewer points than one 4-row step, one 16-point tile or one 128-point workgroup
+    g = synth.rng(9995 + n + metric)
+    d, b = 8, 64
+    M = None
+    if metric == oracle.KL:
+        X = synth.simplex_points(n, d, 9996 + n)
+        scale = _scale_log(True)
+    else:
+        X = (g.standard_normal((n, d)) + 1.0).astype(np.float32)
+        if metric == oracle.MAHA2:
+            M = synth.square_matrix(d, 9997, "spd")
+            scale = _scale_quad(M, True)
+        else:
+            scale = _scale_even(4 if metric == oracle.L4 else 6)
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    Y = _query(X, Z, metric, M=M)
+    p = {oracle.L4: 4, oracle.L6: 6}.get(metric, 0)
+    if n == 1 and metric == oracle.KL:
+        # D(x || x) = 0, reached through -H(x) sum z - sum_k x(k) log x(k) z: FP64 cancellation only
+        r = np.arange(1)
+        assert np.all(np.abs(Y) <= (d + 16) * U64 * scale(X, Z, r))
+    elif n == 1:
+        assert np.all(Y == 0.0)                     # the centred coordinates are exactly 0
+    else:
+        _check_float(X, Z, Y, metric, scale, M=M, p=p)
