@@ -84,3 +84,34 @@ def test_lowrank_rejects_bad_arguments():
     with pytest.raises(dm.DMError):
         hi.lowrank(2, torch.zeros((300, 4), dtype=torch.float64, device="cuda"), 2)
     hi.free()
+
+
+@pytest.mark.parametrize("metric,d,rank", [(oracle.MAHA2, 3, 5), (oracle.L4, 1, 5), (oracle.BILINEAR, 4, 4)])
+def test_exact_low_rank_of_the_sort_free_metrics(metric, d, rank):
+    # the expansions have rank at most d + 2 (Mahalanobis), p + 1 per coordinate
+    # (even p; d = 1 here) and d (the bilinear form), so the rank-r
+    # approximation from a large enough Krylov basis is A itself
+    g = synth.rng(5252 + metric)
+    n = 2500
+    X = g.standard_normal((n, d)).astype(np.float32)
+    M = synth.square_matrix(d, 5253, "spd") if metric in oracle.MATRIX_METRICS else None
+    omega = g.standard_normal((n, 8))
+    h = dm.prepare(dev(X), metric, M=M)
+    U, lam, _ = h.lowrank(rank, dev(omega), 2)
+    U, lam = U.cpu().numpy(), lam.cpu().numpy()
+    h.free()
+    A = oracle.explicit(X, metric, M=M)
+    rel = olr.approx_error(A, U, lam) / np.linalg.norm(A)
+    print("metric", metric, "relative error", rel)
+    assert rel <= 1e-5
+
+
+def test_lowrank_refuses_a_non_symmetric_bilinear_form():
+    import torch
+    X = synth.rng(5254).standard_normal((300, 3)).astype(np.float32)
+    h = dm.prepare(dev(X), oracle.BILINEAR, M=synth.square_matrix(3, 5255, "general"))
+    om = torch.zeros((300, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(dm.DMError) as ex:
+        h.lowrank(2, om, 1)
+    assert ex.value.status == dm.ERR_STATE
+    h.free()
