@@ -911,7 +911,7 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     const size_t o_w = take((size_t)K * sizeof(double));
     const size_t o_G = take((size_t)B * B * sizeof(double));
     const size_t o_X = take((size_t)B * B * sizeof(double));
-    const size_t o_C = take((size_t)B * B * sizeof(double));
+    const size_t o_C = take((size_t)K * B * sizeof(double));
     const size_t o_Vk = take((size_t)K * rank * sizeof(double));
     const size_t o_sw = take(sizeof(int));
     char* mem = nullptr;
@@ -945,20 +945,22 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
             const dm_status ms = dm_matvec(h, Zf, DM_F32, B, Yf, s);
             if (ms != DM_OK) return ms;
             DM_TRY(lr_cvt(Yf, Y, nb, s));
-            // Block Gram-Schmidt against Q_0 .. Q_{j-1}, twice.  The first
-            // pass's coefficients Q_i^T (A Q_{j-1}) are the Rayleigh-Ritz blocks
-            // T[i][j-1] (the earlier subtractions change them only by the
-            // rounding-level overlap of the orthonormal blocks), so they are
-            // written straight into T.
+            // Block classical Gram-Schmidt against Q_0 .. Q_{j-1}, twice: every
+            // coefficient block Q_i^T Y first, then one update
+            // Y -= sum_i Q_i C_i that moves Y once.  The first pass's
+            // coefficients Q_i^T (A Q_{j-1}) are exactly the Rayleigh-Ritz
+            // blocks T[i][j-1], so they are written straight into T (rows
+            // i B .. of column block j - 1, leading dimension K).
             for (int i = 0; i < j; ++i) {
                 double* Tij = T + (size_t)i * B * K + (size_t)(j - 1) * B;
                 DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, Tij, K, 1.0, s));
-                if (j < iters) DM_TRY(lr_update_rows(Y, B, Qb(i), B, Tij, K, -1.0, 1.0, n, s));
             }
             if (j == iters) break;
-            for (int i = 0; i < j; ++i) {
-                DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, C, B, 1.0, s));
-                DM_TRY(lr_update_rows(Y, B, Qb(i), B, C, B, -1.0, 1.0, n, s));
+            if (j > 0) {
+                DM_TRY(lr_update_blocks(Y, B, Qb(0), nb, j, B, T + (size_t)(j - 1) * B, K, -1.0, 1.0, n, s));
+                for (int i = 0; i < j; ++i)
+                    DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, C + (size_t)i * B * B, B, 1.0, s));
+                DM_TRY(lr_update_blocks(Y, B, Qb(0), nb, j, B, C, B, -1.0, 1.0, n, s));
             }
             // Cholesky QR, twice
             for (int pass = 0; pass < 2; ++pass) {
@@ -973,9 +975,8 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
         DM_TRY(lr_eig(T, T2, V, w, K, 60, 1e-14, d_sweeps, &sw_host, s));
         sw_used = sw_host;
         DM_TRY(lr_topk(w, V, K, rank, lam, Vk, s));
-        // U = Q Vk, block by block
-        for (int i = 0; i < iters; ++i)
-            DM_TRY(lr_update_rows(U, rank, Qb(i), B, Vk + (size_t)i * B * rank, rank, 1.0, i == 0 ? 0.0 : 1.0, n, s));
+        // U = Q Vk = sum_i Q_i Vk_i in one pass over U
+        DM_TRY(lr_update_blocks(U, rank, Qb(0), nb, iters, B, Vk, rank, 1.0, 0.0, n, s));
         return DM_OK;
     };
     dm_status st = run();

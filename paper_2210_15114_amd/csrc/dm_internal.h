@@ -157,6 +157,10 @@ hipError_t lr_gram(const double* A, int ma, const double* B, int mb, int64_t n, 
 // Y = beta Y + alpha Q C; Y n x mb, Q n x ma, C ma x ldc (Y may be Q when beta is 0)
 hipError_t lr_update_rows(double* Y, int mb, const double* Q, int ma, const double* C, int ldc, double alpha,
                           double beta, int64_t n, hipStream_t s);
+// Y = beta Y + alpha sum_(i < nq) Q_i C_i with Q_i = Q + i qstride (n x ma) and
+// C_i rows i ma .. of C (leading dimension ldc); Y must not be any Q_i unless nq = 1
+hipError_t lr_update_blocks(double* Y, int mb, const double* Q, size_t qstride, int nq, int ma, const double* C,
+                            int ldc, double alpha, double beta, int64_t n, hipStream_t s);
 hipError_t lr_cholinv(const double* G, int m, double rel, double* X, uint32_t* status, hipStream_t s);
 hipError_t lr_symm(double* T, int m, int bw, hipStream_t s);
 hipError_t lr_cvt(const double* a, float* b, size_t n, hipStream_t s);

@@ -8,8 +8,8 @@
 //   * lr_gram_partial / lr_reduce - C = A^T B of two n x m blocks, split over
 //     rows into fixed per-block partial sums and reduced in a fixed order
 //     (bit-reproducible run to run);
-//   * lr_update   - Y = beta Y + alpha Q C, row by row (block Gram-Schmidt updates,
-//     Y R^-1 of Cholesky QR, and U = Q V of the final step);
+//   * lr_update   - Y = beta Y + alpha sum_i Q_i C_i, row by row on FP64 matrix
+//     cores (block Gram-Schmidt updates, Y R^-1 of Cholesky QR, U = Q V);
 //   * lr_chol     - the orthonormalising factor of Cholesky QR for a small
 //     Gram matrix (column-equilibrated), dropping dependent columns;
 //   * lr_jacobi_step - eigenvalues and eigenvectors of the symmetric T by the
@@ -154,62 +154,67 @@ __global__ __launch_bounds__(256) void lr_reduce(const double* __restrict__ part
 }
 
 // ---------------------------------------------------------------------------
-// Y = beta Y + alpha Q C, row by row: Y n x mb (leading dimension mb), Q n x
-// ma, C ma x ldc.  A workgroup owns GT rows: it reads its Q rows flat into
-// LDS, forms the products there, and writes its Y rows flat, so Y may be Q
-// (in-place right multiplication, beta = 0).  LDS is sized by the launch to
-// ma and mb (dynamic), so narrow blocks leave room for more workgroups.
+// Y = beta Y + alpha sum_(i < nq) Q_i C_i, row by row, on FP64 matrix cores.
+// Y is n x mb (leading dimension mb); Q_i = Q + i qstride is n x ma
+// row-major; C_i is rows i ma .. i ma + ma - 1 of C (leading dimension ldc).
+// A workgroup takes GT rows at a time; for each i it stages the Q_i rows
+// (a flat, coalesced copy) and alpha C_i in LDS, and wave w multiplies rows
+// 16w .. 16w + 15 by every column with v_mfma_f64_16x16x4f64 (gfx950 lane
+// layout: A lane l holds A[l % 16][l / 16], B lane l holds B[l / 16][l % 16],
+// D lane l element r holds D[4r + l / 16][l % 16]).  A tile's Q rows are all
+// read before its Y rows are written, so Y may be Q when nq = 1 and beta = 0
+// (in-place right multiplication).  One call with nq blocks moves Y once,
+// where nq single-block calls would move it nq times.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void lr_update(double* Y, int mb, const double* Q, int ma,
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void lr_update(double* Y, int mb, const double* Q, size_t qstride, int nq, int ma,
                                                  const double* __restrict__ C, int ldc, double alpha, double beta,
                                                  int64_t n)
 {
     extern __shared__ double lds[];
-    const int lq = (ma > mb ? ma : mb) + 1;   // row stride of the Q / result tile
-    const int lc = mb + 1;                    // row stride of C
-    double* sQ = lds;                         // GT x lq
-    double* sC = lds + GT * lq;               // ma x lc
-    const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * GT;
-    const int nr = (int)(n - r0 < GT ? n - r0 : GT);
-    for (int i = tid; i < ma * mb; i += 256) sC[(i / mb) * lc + (i % mb)] = alpha * C[(size_t)(i / mb) * ldc + (i % mb)];
-    {
-        const double* q0 = Q + r0 * ma;
-        const int nq = nr * ma;
+    const int lq = ma + 1;   // row stride of the Q tile
+    double* sQ = lds;        // GT x lq
+    double* sC = lds + GT * lq;   // ma x mb
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int ct_n = (mb + 15) / 16;
+    for (int64_t r0 = (int64_t)blockIdx.x * GT; r0 < n; r0 += (int64_t)gridDim.x * GT) {   // uniform
+        const int nr = (int)(n - r0 < GT ? n - r0 : GT);
+        d4v acc[MAXM / 16];
 #pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            const int i = tid + 256 * k;
-            if (i < nq) sQ[(i / ma) * lq + (i % ma)] = q0[i];
+        for (int u = 0; u < MAXM / 16; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < nq; ++i) {
+            __syncthreads();   // the previous block's tiles are no longer read
+            const double* q0 = Q + (size_t)i * qstride + r0 * ma;
+            for (int e = tid; e < GT * ma; e += 256) sQ[(e / ma) * lq + (e % ma)] = e < nr * ma ? q0[e] : 0.0;
+            for (int e = tid; e < ma * mb; e += 256)
+                sC[e] = alpha * C[(size_t)(i * ma + e / mb) * ldc + (e % mb)];
+            __syncthreads();
+            for (int k0 = 0; k0 < ma; k0 += 4) {
+                const int kk = k0 + g;
+                const double av = kk < ma ? sQ[(16 * w + m) * lq + kk] : 0.0;
+#pragma unroll
+                for (int u = 0; u < MAXM / 16; ++u) {
+                    if (u < ct_n) {   // the same on every lane
+                        const int c = 16 * u + m;
+                        const double bv = (kk < ma && c < mb) ? sC[kk * mb + c] : 0.0;
+                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+                    }
+                }
+            }
         }
-    }
-    __syncthreads();
-    const int rr = tid >> 2, cg = tid & 3;
-    double out[MAXM / 4];
 #pragma unroll
-    for (int k = 0; k < MAXM / 4; ++k) out[k] = 0.0;
-    if (rr < nr) {
-        for (int p = 0; p < ma; ++p) {
-            const double qv = sQ[rr * lq + p];
+        for (int u = 0; u < MAXM / 16; ++u) {
+            const int c = 16 * u + m;
+            if (u >= ct_n || c >= mb) continue;
 #pragma unroll
-            for (int k = 0; k < MAXM / 4; ++k)
-                if (cg + 4 * k < mb) out[k] = fma(qv, sC[p * lc + cg + 4 * k], out[k]);
-        }
-    }
-    __syncthreads();   // all reads of sQ are done: it now holds the results
-    if (rr < nr) {
-#pragma unroll
-        for (int k = 0; k < MAXM / 4; ++k)
-            if (cg + 4 * k < mb) sQ[rr * lq + cg + 4 * k] = out[k];
-    }
-    __syncthreads();
-    double* y0 = Y + r0 * mb;
-    const int ny = nr * mb;
-#pragma unroll
-    for (int k = 0; k < TPT; ++k) {
-        const int i = tid + 256 * k;
-        if (i < ny) {
-            const double v = sQ[(i / mb) * lq + (i % mb)];
-            y0[i] = beta == 0.0 ? v : fma(beta, y0[i], v);
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + 16 * w + 4 * r + g;
+                if (row >= n) continue;
+                double* y = Y + row * mb + c;
+                *y = beta == 0.0 ? acc[u][r] : fma(beta, *y, acc[u][r]);
+            }
         }
     }
 }
@@ -484,14 +489,21 @@ hipError_t lr_gram(const double* A, int ma, const double* B, int mb, int64_t n, 
     return hipGetLastError();
 }
 
+hipError_t lr_update_blocks(double* Y, int mb, const double* Q, size_t qstride, int nq, int ma, const double* C,
+                            int ldc, double alpha, double beta, int64_t n, hipStream_t s)
+{
+    if (ma < 1 || mb < 1 || ma > MAXM || mb > MAXM || n < 1 || nq < 1) return hipErrorInvalidValue;
+    const size_t lds = ((size_t)GT * (ma + 1) + (size_t)ma * mb) * sizeof(double);
+    int64_t blocks = (n + GT - 1) / GT;
+    if (blocks > 2048) blocks = 2048;
+    lr_update<<<(unsigned)blocks, 256, lds, s>>>(Y, mb, Q, qstride, nq, ma, C, ldc, alpha, beta, n);
+    return hipGetLastError();
+}
+
 hipError_t lr_update_rows(double* Y, int mb, const double* Q, int ma, const double* C, int ldc, double alpha,
                           double beta, int64_t n, hipStream_t s)
 {
-    if (ma < 1 || mb < 1 || ma > MAXM || mb > MAXM || n < 1) return hipErrorInvalidValue;
-    const int lq = (ma > mb ? ma : mb) + 1;
-    const size_t lds = ((size_t)GT * lq + (size_t)ma * (mb + 1)) * sizeof(double);
-    lr_update<<<(unsigned)((n + GT - 1) / GT), 256, lds, s>>>(Y, mb, Q, ma, C, ldc, alpha, beta, n);
-    return hipGetLastError();
+    return lr_update_blocks(Y, mb, Q, 0, 1, ma, C, ldc, alpha, beta, n, s);
 }
 
 hipError_t lr_cholinv(const double* G, int m, double rel, double* X, uint32_t* status, hipStream_t s)
