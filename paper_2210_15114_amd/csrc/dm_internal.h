@@ -166,8 +166,8 @@ hipError_t lr_symm(double* T, int m, int bw, hipStream_t s);
 hipError_t lr_cvt(const double* a, float* b, size_t n, hipStream_t s);
 hipError_t lr_cvt(const float* a, double* b, size_t n, hipStream_t s);
 // eigen-decomposition of the symmetric m x m T (destroyed; T2 is a second
-// m x m buffer): V (m x m) and w (m); *sweeps = sweeps used (host value);
-// synchronises s once per sweep
+// m x m buffer): eigenvalues w (m) and eigenvectors as the rows of V (m x m);
+// *sweeps = sweeps used (host value); synchronises s once per sweep
 hipError_t lr_eig(double* T, double* T2, double* V, double* w, int m, int max_sweeps, double tol, int* d_done,
                   int* sweeps, hipStream_t s);
 hipError_t lr_topk(const double* w, const double* V, int m, int k, double* lam, double* Vk, hipStream_t s);

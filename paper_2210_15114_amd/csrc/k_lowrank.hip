@@ -378,15 +378,18 @@ __global__ __launch_bounds__(256) void lr_jacobi_step(const double* __restrict__
     const int pj = sp[j], qj = sq[j];
     const double cj = sc[j], sj = ss[j];
     const bool qv = qj < m;
+    // T is symmetric (to rounding), so the block of rows (pi, qi) and columns
+    // (pj, qj) is read from, and its rotated values written to, rows pj and qj:
+    // a workgroup touches only its own two rows
     for (int i = tid; i < half; i += 256) {
         const int pi = sp[i], qi = sq[i];
         const double ci = sc[i], si = ss[i];
         const bool rv = qi < m;
         // the block [[a, b], [c, d]] = rows (pi, qi) x columns (pj, qj)
-        double a = Tin[pi * m + pj];
-        double b = qv ? Tin[pi * m + qj] : 0.0;
-        double c = rv ? Tin[qi * m + pj] : 0.0;
-        double d = (rv && qv) ? Tin[qi * m + qj] : 0.0;
+        double a = Tin[pj * m + pi];
+        double b = qv ? Tin[qj * m + pi] : 0.0;
+        double c = rv ? Tin[pj * m + qi] : 0.0;
+        double d = (rv && qv) ? Tin[qj * m + qi] : 0.0;
         // rows: J_i^T
         const double a1 = ci * a - si * c, c1 = si * a + ci * c;
         const double b1 = ci * b - si * d, d1 = si * b + ci * d;
@@ -395,16 +398,17 @@ __global__ __launch_bounds__(256) void lr_jacobi_step(const double* __restrict__
         b = sj * a1 + cj * b1;
         c = cj * c1 - sj * d1;
         d = sj * c1 + cj * d1;
-        Tout[pi * m + pj] = a;
-        if (qv) Tout[pi * m + qj] = b;
-        if (rv) Tout[qi * m + pj] = c;
-        if (rv && qv) Tout[qi * m + qj] = d;
+        Tout[pj * m + pi] = a;
+        if (qv) Tout[qj * m + pi] = b;
+        if (rv) Tout[pj * m + qi] = c;
+        if (rv && qv) Tout[qj * m + qi] = d;
     }
+    // V is kept transposed (row j is eigenvector j): rotate rows pj and qj
     if (qv) {
         for (int r = tid; r < m; r += 256) {
-            const double va = V[r * m + pj], vb = V[r * m + qj];
-            V[r * m + pj] = cj * va - sj * vb;
-            V[r * m + qj] = sj * va + cj * vb;
+            const double va = V[pj * m + r], vb = V[qj * m + r];
+            V[pj * m + r] = cj * va - sj * vb;
+            V[qj * m + r] = sj * va + cj * vb;
         }
     }
 }
@@ -463,7 +467,7 @@ __global__ __launch_bounds__(1024) void lr_select(const double* __restrict__ w, 
     __syncthreads();
     for (int e = threadIdx.x; e < m * k; e += 1024) {
         const int r = e / k, t = e % k;
-        Vk[e] = V[r * m + sidx[t]];
+        Vk[e] = V[sidx[t] * m + r];   // V holds the eigenvectors as rows
     }
 }
 
