@@ -8,9 +8,11 @@
 // split-K reduction over the points: stage 1 writes one FP64 partial of
 // X^T Z per block of rows, stage 2 adds the partials in block order.  The
 // apply stage forms <x_i, V> per row and combines the rank-one terms in FP64.
-// For float data with at least 16 right-hand sides both contractions run on
-// the matrix cores (k_l2_mfma.hip); this file is the vector path used for
-// narrow blocks and for integer data (wrapping int64, exact modulo 2^64).
+// For float data with at least 16 right-hand sides and d <= 128 both
+// contractions run on the BF16 matrix cores (k_l2_mfma.hip).  Other float
+// shapes are the linear form of the sort-free kernels (k_sortfree.hip) with
+// V = -2 X^T z, weights a_i = ||x_i||^2 on S0 and U = R, all in FP64.  This
+// file's vector path serves integer data (wrapping int64, exact modulo 2^64).
 #include "dm_device.h"
 #include "dm_internal.h"
 
@@ -135,7 +137,9 @@ __global__ __launch_bounds__(256) void l2_apply_vec(const typename L2T<INT>::X* 
 
 size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b) {
     const size_t nblk = (size_t)((n + VROWS - 1) / VROWS);
-    return (nblk + 1) * (size_t)d * (size_t)b * 8 + 256;
+    const size_t vec = (nblk + 1) * (size_t)d * (size_t)b * 8 + 256;
+    const size_t lin = sf_scratch_bytes(n, d, b, SF_LIN, 1);
+    return vec > lin ? vec : lin;
 }
 
 hipError_t launch_l2sq_mfma(const float* Xc, const double* nrm, int64_t n, int32_t d, const float* Z, int32_t b,
@@ -153,6 +157,22 @@ hipError_t launch_l2sq(bool is_int, int zkind, const void* Xc, const void* nrm, 
         e = launch_l2sq_mfma((const float*)Xc, (const double*)nrm, n, d, (const float*)Z, b, (float*)Out, scratch,
                              tot, s, &used);
         if (e != hipSuccess || used) return e;
+        // (A z)_i = <x_i, -2 X^T z> + ||x_i||^2 S0 + R: the linear sort-free form
+        SfQuery q;
+        q.X = Xc;
+        q.LX = nullptr;
+        q.centre = nullptr;
+        q.Z = Z;
+        q.n = n;
+        q.d = d;
+        q.b = b;
+        q.T0 = tot.T0;
+        q.U = (const double*)tot.U;
+        q.a = (const double*)nrm;
+        q.W = nullptr;
+        q.alpha = -2.0;
+        q.Out = Out;
+        return launch_sf_query(SF_LIN, 1, false, zkind, q, scratch, s);
     }
     const int nblk = (int)((n + VROWS - 1) / VROWS);
     const int ent = d * b;
