@@ -337,6 +337,25 @@ __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ 
                 }
             }
         };
+        // a Z row as 16-byte vectors when b and the alignment allow
+        constexpr int ZV = 16 / (int)sizeof(ZT);
+        const bool zvec = BW >= ZV && b % ZV == 0 && (uintptr_t)Z % 16 == 0;
+        auto load_z = [&](int64_t row, ZT (&zr)[BW]) {
+            if constexpr (BW >= ZV) {
+                if (zvec) {
+#pragma unroll
+                    for (int c0 = 0; c0 < BW; c0 += ZV) {
+                        Vec<ZT, ZV> q = {};
+                        if (c0 < b) q = *reinterpret_cast<const Vec<ZT, ZV>*>(Z + row * b + c0);
+#pragma unroll
+                        for (int v = 0; v < ZV; ++v) zr[c0 + v] = q.v[v];
+                    }
+                    return;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < BW; ++c) zr[c] = c < b ? Z[row * b + c] : ZT(0);
+        };
         int64_t r = rb + rsub;
         for (; r + (int64_t)(NU - 1) * R < re; r += (int64_t)NU * R) {
             Vec<XT, V> xv[NU];
@@ -345,16 +364,14 @@ __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ 
             for (int u = 0; u < NU; ++u) {
                 const int64_t row = r + (int64_t)u * R;
                 xv[u] = *reinterpret_cast<const Vec<XT, V>*>(X + row * d + k);
-#pragma unroll
-                for (int c = 0; c < BW; ++c) zv[u][c] = c < b ? Z[row * b + c] : ZT(0);
+                load_z(row, zv[u]);
             }
 #pragma unroll
             for (int u = 0; u < NU; ++u) step(xv[u], zv[u]);
         }
         for (; r < re; r += R) {
             ZT zv[BW];
-#pragma unroll
-            for (int c = 0; c < BW; ++c) zv[c] = c < b ? Z[r * b + c] : ZT(0);
+            load_z(r, zv);
             step(*reinterpret_cast<const Vec<XT, V>*>(X + r * d + k), zv);
         }
     }
@@ -831,7 +848,8 @@ constexpr int moments_kc() { return MKG * moments_kpt<NT>(); }
 int kc_for(int nt) { return nt == 1 ? moments_kc<1>() : nt <= 4 ? moments_kc<4>() : moments_kc<6>(); }
 
 // the narrow moments kernel (all sums of a thread in registers) serves b <= 8
-// when the NT x (b rounded up) x V sums fit
+// when the NT x (b rounded up) x V sums fit (b = 16 measured no faster than
+// the LDS-tiled kernel)
 constexpr bool narrow_fits(int nt, int bw, int v = 1) { return bw <= 8 && nt * bw * v <= 32; }
 
 // coordinates per thread of the narrow moments kernel: 16-byte loads when d
@@ -1103,7 +1121,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
         if ((e = reduce_launch<double>(part, nblk, per_t, 1, 0, q.alpha, G, s)) != hipSuccess) return e;
     }
     const double* cen = form == SF_LOG ? nullptr : (const double*)q.centre;
-    if (q.b >= 16) {   // matrix cores: 16 points x every column per wave
+    if (q.b >= 4) {   // matrix cores: 16 points x every column per wave (masked past b)
         const int64_t groups = (q.n + 16 * NTL - 1) / (16 * NTL);
         int64_t blocks = (groups + 7) / 8;
         if (blocks > 1024) blocks = 1024;
