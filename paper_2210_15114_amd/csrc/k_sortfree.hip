@@ -155,18 +155,26 @@ __host__ __device__ constexpr int64_t binom_sf(int p, int t) {
     return r;
 }
 
+// The row-range partials part[blk][e] (e = (t, k, c), count entries) are added
+// in a fixed order.  Many entries: two passes; slice s sums blocks [s ks, (s + 1) ks) for every
+// entry (threads over consecutive entries, so every load is coalesced), then
+// G[e] = coef_t sum over the slices in order, with coef_t = C(p, t + 1)
+// (-1)^(t + 1) when p > 0 (even p) and alpha otherwise (float only).
+constexpr int SF_SLICES = 32;
+
 template <typename ACC>
 __device__ __forceinline__ ACC shfl_xor_acc(ACC v, int off, int width) {
     if constexpr (std::is_same<ACC, double>::value) return __shfl_xor(v, off, width);
     else return (ACC)__shfl_xor((long long)v, off, width);
 }
 
-// G[t][k][c] = coef_t sum_blk part[blk][t][k][c]; coef_t = C(p, t + 1) (-1)^(t + 1)
-// when p > 0 (even p), alpha otherwise (float only).  One wave per entry:
-// lane l adds the partials l, l + 64, ... in order, then a fixed xor tree.
+__device__ __forceinline__ int64_t even_coef(int p, int t) { return ((t & 1) ? -1 : 1) * binom_sf(p, t); }
+
+// Few entries (narrow blocks): one launch, one wave per entry; lane l adds
+// the partials l, l + 64, ... in order, then a fixed xor tree.
 template <typename ACC>
-__global__ __launch_bounds__(256) void sf_reduce_kernel(const ACC* __restrict__ part, int nblk, int64_t per_t,
-                                                        int nt, int p, double alpha, ACC* __restrict__ G)
+__global__ __launch_bounds__(256) void sf_reduce_waves(const ACC* __restrict__ part, int nblk, int64_t per_t, int nt,
+                                                       int p, double alpha, ACC* __restrict__ G)
 {
     const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -177,13 +185,34 @@ __global__ __launch_bounds__(256) void sf_reduce_kernel(const ACC* __restrict__ 
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s = add_acc(s, shfl_xor_acc(s, off, 64));
     if (lane != 0) return;
-    if (p > 0) {
-        const int t = (int)(e / per_t) + 1;
-        const int64_t cf = ((t & 1) ? -1 : 1) * binom_sf(p, t);
-        G[e] = mul_acc(s, (ACC)cf);
-    } else {
-        G[e] = (ACC)(alpha * (double)s);
-    }
+    if (p > 0) G[e] = mul_acc(s, (ACC)even_coef(p, (int)(e / per_t) + 1));
+    else G[e] = (ACC)(alpha * (double)s);
+}
+
+template <typename ACC>
+__global__ __launch_bounds__(256) void sf_reduce_slices(const ACC* __restrict__ part, int nblk, int64_t count, int ks,
+                                                        ACC* __restrict__ slices)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    const int k0 = blockIdx.y * ks;
+    const int k1 = k0 + ks < nblk ? k0 + ks : nblk;
+    ACC acc = ACC(0);
+    for (int k = k0; k < k1; ++k) acc = add_acc(acc, part[(size_t)k * count + e]);
+    slices[(size_t)blockIdx.y * count + e] = acc;
+}
+
+template <typename ACC>
+__global__ __launch_bounds__(256) void sf_reduce_kernel(const ACC* __restrict__ slices, int nslice, int64_t per_t,
+                                                        int nt, int p, double alpha, ACC* __restrict__ G)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t count = per_t * nt;
+    if (e >= count) return;
+    ACC s = ACC(0);
+    for (int k = 0; k < nslice; ++k) s = add_acc(s, slices[(size_t)k * count + e]);
+    if (p > 0) G[e] = mul_acc(s, (ACC)even_coef(p, (int)(e / per_t) + 1));
+    else G[e] = (ACC)(alpha * (double)s);
 }
 
 // V[k][c] = sum_l W[k][l] F[l][c]
@@ -966,11 +995,22 @@ hipError_t apply_t(const void* X, const void* centre, int64_t n, int32_t d, int3
 
 template <typename ACC>
 hipError_t reduce_launch(const void* part, int64_t nblk, int64_t per_t, int nt, int p, double alpha, void* G,
-                         hipStream_t s)
+                         void* slices, hipStream_t s)
 {
     const int64_t count = per_t * nt;
-    sf_reduce_kernel<ACC><<<(unsigned)((count + 3) / 4), 256, 0, s>>>((const ACC*)part, (int)nblk, per_t, nt, p,
-                                                                      alpha, (ACC*)G);
+    if (count < 2048) {   // narrow blocks: one launch
+        sf_reduce_waves<ACC><<<(unsigned)((count + 3) / 4), 256, 0, s>>>((const ACC*)part, (int)nblk, per_t, nt, p,
+                                                                         alpha, (ACC*)G);
+        return hipGetLastError();
+    }
+    const int nsl = (int)(nblk < SF_SLICES ? nblk : SF_SLICES);
+    const int ks = (int)((nblk + nsl - 1) / nsl);
+    dim3 g1((unsigned)((count + 255) / 256), (unsigned)nsl);
+    sf_reduce_slices<ACC><<<g1, 256, 0, s>>>((const ACC*)part, (int)nblk, count, ks, (ACC*)slices);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sf_reduce_kernel<ACC><<<(unsigned)((count + 255) / 256), 256, 0, s>>>((const ACC*)slices, nsl, per_t, nt, p,
+                                                                          alpha, (ACC*)G);
     return hipGetLastError();
 }
 
@@ -998,7 +1038,7 @@ int64_t mfma_row_waves(int64_t n, int32_t d) {
     return w < 4 ? 4 : (w + 3) / 4 * 4;
 }
 template <int P>
-hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char* G, hipStream_t s)
+hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char* G, char* SL, hipStream_t s)
 {
     int64_t nblk = 0;
     hipError_t e;
@@ -1017,7 +1057,7 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
             e = moments_t<float, float, double, P>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
         }
         if (e != hipSuccess) return e;
-        if ((e = reduce_launch<double>(part, nblk, per_t, P, P, 1.0, G, s)) != hipSuccess) return e;
+        if ((e = reduce_launch<double>(part, nblk, per_t, P, P, 1.0, G, SL, s)) != hipSuccess) return e;
         if (q.b >= 16) {   // matrix cores for the point pass
             int64_t blocks = (q.n + 127) / 128;
             if (blocks > 1024) blocks = 1024;
@@ -1043,7 +1083,7 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
     else
         e = moments_t<int32_t, int64_t, int64_t, P>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
     if (e != hipSuccess) return e;
-    if ((e = reduce_launch<int64_t>(part, nblk, per_t, P, P, 1.0, G, s)) != hipSuccess) return e;
+    if ((e = reduce_launch<int64_t>(part, nblk, per_t, P, P, 1.0, G, SL, s)) != hipSuccess) return e;
     return apply_t<int32_t, int64_t, int64_t, P, true>(q.X, q.centre, q.n, q.d, q.b, q.T0, G, nullptr, nullptr,
                                                        q.Out, s);
 }
@@ -1068,7 +1108,7 @@ size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p) {
     const int nt = sf_moment_count(form, p);
     const int64_t nblk = partial_count(n, d, b, form, nt);
     const size_t cnt = (size_t)nt * d * b;
-    return ((size_t)nblk + 2) * cnt * 8;   // row-range partials, the moments, the mixed moments
+    return ((size_t)nblk + 2 + SF_SLICES) * cnt * 8;   // row-range partials, the moments, the mixed moments, slices
 }
 
 hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuery& q, void* scratch, hipStream_t s)
@@ -1080,11 +1120,12 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     char* part = (char*)scratch;
     char* G = part + (size_t)nblk_max * cnt * 8;
     char* V = G + cnt * 8;
+    char* SL = V + cnt * 8;
     if (form == SF_EVEN) {
         switch (p) {
-        case 2: return even_query<2>(is_int, zkind, q, part, G, s);
-        case 4: return even_query<4>(is_int, zkind, q, part, G, s);
-        case 6: return even_query<6>(is_int, zkind, q, part, G, s);
+        case 2: return even_query<2>(is_int, zkind, q, part, G, SL, s);
+        case 4: return even_query<4>(is_int, zkind, q, part, G, SL, s);
+        case 6: return even_query<6>(is_int, zkind, q, part, G, SL, s);
         default: return hipErrorInvalidValue;
         }
     }
@@ -1113,12 +1154,12 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     if (e != hipSuccess) return e;
     const char* Gv = G;
     if (q.W) {
-        if ((e = reduce_launch<double>(part, nblk, per_t, 1, 0, 1.0, G, s)) != hipSuccess) return e;
+        if ((e = reduce_launch<double>(part, nblk, per_t, 1, 0, 1.0, G, SL, s)) != hipSuccess) return e;
         sf_mix_kernel<<<(unsigned)((per_t + 255) / 256), 256, 0, s>>>(q.W, (const double*)G, q.d, q.b, (double*)V);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         Gv = V;
     } else {
-        if ((e = reduce_launch<double>(part, nblk, per_t, 1, 0, q.alpha, G, s)) != hipSuccess) return e;
+        if ((e = reduce_launch<double>(part, nblk, per_t, 1, 0, q.alpha, G, SL, s)) != hipSuccess) return e;
     }
     const double* cen = form == SF_LOG ? nullptr : (const double*)q.centre;
     if (q.b >= 4) {   // matrix cores: 16 points x every column per wave (masked past b)
