@@ -405,3 +405,23 @@ def test_matrix_core_paths_at_tiny_n(metric, n):
         assert np.all(Y == 0.0)                     # the centred coordinates are exactly 0
     else:
         _check_float(X, Z, Y, metric, scale, M=M, p=p)
+
+
+def test_full_size_wide_blocks_sampled_rows():
+    # the benchmark's sort-free shapes at b = 64: n = 2^20 points, d = 64
+    n, d, b = 1 << 20, 64, 64
+    Xm, _ = synth.workload2(n, d, 1)
+    P = synth.simplex_points(n, d, synth.seeds(2)["X"] + 11)
+    M = synth.square_matrix(d, synth.seeds(2)["X"] + 12, "spd")
+    Z = synth.rhs_normal(n, b, synth.seeds(2)["Z"] + 20 + b)
+    rows = synth.subsample_rows(n, 3, 9998, extra=[0, n - 1])
+    Zd = dev(Z)
+    for metric, X, Mm, scale, p in ((oracle.L6, Xm, None, _scale_even(6), 6),
+                                    (oracle.KL, P, None, _scale_log(True), 0),
+                                    (oracle.MAHA2, Xm, M, _scale_quad(M, True), 0)):
+        h = dm.prepare(dev(X), metric, M=Mm)
+        Y = h.matvec(Zd)
+        h.sync()
+        _check_float(X, Z, Y.cpu().numpy(), metric, scale, M=Mm, rows=rows, p=p)
+        h.free()
+        del Y
