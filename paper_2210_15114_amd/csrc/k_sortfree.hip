@@ -512,7 +512,7 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
 // chunk multiplies the A column g = coordinate k0 + 4g + s.  V (d x b FP64) is
 // staged once per workgroup in dynamic LDS when it fits (LDS_V), else read
 // through the caches; each V operand serves all NTL tiles.
-constexpr int NTL = 1;   // 4 tiles per step measured slower (occupancy 1) than 1
+constexpr int NTL = 1;   // 2 or 4 tiles per step measured slower (fewer waves per SIMD) than 1
 template <int CT, bool LDS_V>
 __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X, const double* __restrict__ centre,
                                                      int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
