@@ -168,6 +168,10 @@ struct dm_handle {
     Ctl* ctl = nullptr;
     char* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // single-column l1 queries: each coordinate's values in sorted order
+    // (d x ld, FP32 or int64), gathered per point after the passes
+    char* sorted_buf = nullptr;
+    size_t sorted_bytes = 0;
     // look-back record regions, one per pass kernel shape (zeroed when created)
     struct Region { int cls; uint64_t* ptr; size_t words; };
     std::vector<Region> regions;
@@ -202,6 +206,7 @@ void release(dm_handle* h) {
         if (e.b) (void)hipEventDestroy(e.b);
     }
     if (h->scratch) (void)hipFree(h->scratch);
+    if (h->sorted_buf) (void)hipFree(h->sorted_buf);
     for (auto& r : h->regions) (void)hipFree(r.ptr);
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
@@ -349,6 +354,21 @@ dm_status ensure_scratch(dm_handle* h, int32_t b, hipStream_t s) {
     h->scratch = (char*)p;
     h->scratch_bytes = need;
     DM_TRY(launch_fill_u32((uint32_t*)p, 0u, need / 4, s));
+    return DM_OK;
+}
+
+// The sorted-order buffer of single-column l1 queries (created on first use).
+dm_status ensure_sorted_buf(dm_handle* h) {
+    const size_t need = (size_t)h->d * (size_t)h->L.ld * (h->is_int ? 8 : 4);
+    if (h->sorted_bytes >= need) return DM_OK;
+    void* p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) {
+        (void)hipGetLastError();   // the caller falls back; keep later launch checks clean
+        return DM_ERR_NOMEM;
+    }
+    if (h->sorted_buf) (void)hipFree(h->sorted_buf);
+    h->sorted_buf = (char*)p;
+    h->sorted_bytes = need;
     return DM_OK;
 }
 
@@ -632,7 +652,12 @@ dm_status dm_reserve(dm_handle* h, int32_t b) {
             }
             const int v = variant_for(h, kind_index(h->is_int, kinds[ki]), log2_pad(b));
             if ((st = region_for(h, l1_shape(h->n, b, h->is_int, kinds[ki], v), h->last, &r)) != DM_OK) return st;
+            // single-column queries use the sorted passes
+            const int v1 = variant_for(h, kind_index(h->is_int, kinds[ki]), 0);
+            if ((st = region_for(h, l1_sorted_shape(h->n, h->is_int, kinds[ki], v1), h->last, &r)) != DM_OK)
+                return st;
         }
+        if (l1_pass_metric(h->metric) && (st = ensure_sorted_buf(h)) != DM_OK) return st;
     }
     return hipStreamSynchronize(h->last) == hipSuccess ? DM_OK : DM_ERR_DEVICE;
 }
@@ -762,13 +787,31 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
             a.variant = v;
         }
         const size_t vsz = 4;
+        // one column: every pass writes its values in sorted order, then one
+        // gather per point adds them through the rank arrays (Algorithm 2's
+        // arrays and lookups); falls back to the scattering passes when the
+        // d x n buffer cannot be allocated
+        const bool sorted = b == 1 && ensure_sorted_buf(h) == DM_OK;
+        const size_t osz = h->is_int ? 8 : 4;
+        if (sorted) {
+            const L1Shape sh = l1_sorted_shape(h->n, h->is_int, zkind, a.variant);
+            dm_status rs = region_for(h, sh, s, &a.records);
+            if (rs != DM_OK) return rs;
+            a.record_words = sh.record_words;
+            a.cls = sh.cls;
+            a.sorted = 1;
+        }
         for (int32_t k = 0; k < h->d; ++k) {
             a.perm = h->at<uint32_t>(h->L.perm) + (size_t)k * h->L.ld;
             a.xs = h->ws + h->L.xs + (size_t)k * h->L.ld * vsz;
             a.first = k == 0;
+            if (sorted) a.Out = h->sorted_buf + (size_t)k * h->L.ld * osz;
             ProfScope ps(h, DM_K_L1_PASS, s);
             DM_TRY(launch_l1_pass(h->is_int, zkind, b, a, s));
         }
+        if (sorted)
+            DM_TRY(launch_l1_gather_sorted(h->is_int, h->at<uint32_t>(h->L.rank), h->L.ld, h->sorted_buf, h->n, h->d,
+                                           tot.U, Out, s));
         // TV(x, y) = l1(x, y) / 2 (the TV theorem of Appendix A.3); the
         // halving is exact in floating point
         if (h->metric == DM_TV) DM_TRY(launch_scale_f32((float*)Out, (size_t)h->n * b, 0.5f, s));

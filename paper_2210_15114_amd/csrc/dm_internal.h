@@ -31,7 +31,9 @@ constexpr int SORT_THREADS = 256;
 // is created and never reset; the host never reads them.
 constexpr int L1_VARIANTS = 4;      // tile variants per l1 pass configuration (tuned per handle)
 constexpr int L1_CLASSES = 96;      // 3 data paths x 8 block widths x L1_VARIANTS
-constexpr int CHAIN_CLASSES = L1_CLASSES + 48;   // plus odd p: 3 data paths x 8 block widths x (p = 3, 5)
+constexpr int LP_CLASSES = 48;      // odd p: 3 data paths x 8 block widths x (p = 3, 5)
+constexpr int SORTED_CLASSES = 12;  // single-column passes in sorted order: 3 data paths x L1_VARIANTS
+constexpr int CHAIN_CLASSES = L1_CLASSES + LP_CLASSES + SORTED_CLASSES;
 struct ChainState {
     uint64_t ticket[CHAIN_CLASSES];
 };
@@ -96,6 +98,7 @@ struct L1PassArgs {
     int cls;                // the shape's ticket class (l1_shape)
     int variant;            // tile variant, 0 .. L1_VARIANTS-1
     uint32_t* status;       // sticky query flags (QF_STALL on a stuck chain)
+    int sorted = 0;         // b = 1 only: write each rank's value at its rank in Out (n values), add no U
 };
 int l1_tile_ranks(int32_t b, bool is_int, int zkind, int variant);
 size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind, int variant);
@@ -113,6 +116,12 @@ struct L1Shape {
     size_t record_words;
 };
 L1Shape l1_shape(int64_t n, int32_t b, bool is_int, int zkind, int variant);
+// the single-column pass that writes in sorted order (its own ticket class)
+L1Shape l1_sorted_shape(int64_t n, bool is_int, int zkind, int variant);
+// Out[i] = U + sum_k Cs[k * ld + rank[k * ld + i]], b = 1: the lookup step that
+// follows the sorted passes (float data: FP64 sum rounded once; integers: int64)
+hipError_t launch_l1_gather_sorted(bool is_int, const uint32_t* rank, int64_t ld, const void* Cs, int64_t n, int32_t d,
+                                   const void* U, void* Out, hipStream_t s);
 hipError_t launch_l1_pass(bool is_int, int zkind, int32_t b, const L1PassArgs& a, hipStream_t s);
 
 // ---- many datasets in one query --------------------------------------------

@@ -13,11 +13,14 @@
 // to Out[perm[r]] and the first pass also adds U.
 //
 // Algorithm 2 materialises the prefix arrays B_i and C_i and looks positions
-// up per point; here the two loops are fused into one pass per coordinate:
-// the sorted order is walked once, the prefixes live in registers, and each
-// result is scattered to its point's row.  Every pass visits each row of Out
-// exactly once (perm is a permutation), so passes are stream-ordered and a
-// pass needs no atomics on Out.
+// up per point; for blocks of columns the two loops are fused into one pass
+// per coordinate: the sorted order is walked once, the prefixes live in
+// registers, and each result is scattered to its point's row.  Every pass
+// visits each row of Out exactly once (perm is a permutation), so passes are
+// stream-ordered and a pass needs no atomics on Out.  For a single column
+// (SORTED) the pass instead writes each rank's value in sorted order, and one
+// later gather per point adds its d values through the rank arrays (the
+// lookup step of Algorithm 2): two random accesses per rank instead of three.
 //
 // One pass = one launch, one tile of TILE consecutive ranks per workgroup.
 // Tiles take indices from a ticket counter in dispatch order and chain their
@@ -40,7 +43,7 @@ namespace {
 
 using namespace l1;
 
-template <typename P, int BP, int R, int SUB, int OC, bool VEC>
+template <typename P, int BP, int R, int SUB, int OC, bool VEC, bool SORTED = false>
 __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
                 if (c < b) {
                     const C b0 = P::caddl(s_wexcl[w][0][c], e0[j]);
                     const C b1 = P::caddl(s_wexcl[w][1][c], e1[j]);
-                    f[j] = P::fin(b0, b1, T0[c], first ? U[c] : typename P::T(0));
+                    f[j] = P::fin(b0, b1, T0[c], (first && !SORTED) ? U[c] : typename P::T(0));
                 } else {
                     f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
                 }
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
                 typename P::O o[OC][CPL];
 #pragma unroll
                 for (int i = 0; i < OC; ++i) {
-                    if (!first) {
+                    if (!first && !SORTED) {
                         load_row<CPL, VEC>(Out + (size_t)p[i0 + i] * b, col0, b, r0 + i0 + i < n, o[i]);
                     } else {
 #pragma unroll
@@ -245,7 +248,10 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
                         l1[j] = P::lmac(l1[j], x[i0 + i], g[i0 + i][j]);
                         res[j] = P::oadd(o[i][j], P::out(l0[j], l1[j], x[i0 + i], f[j]));
                     }
-                    if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + (size_t)p[i0 + i] * b, col0, b, res);
+                    // SORTED: the value at its rank (Algorithm 2's per-coordinate array),
+                    // else added into the point's row
+                    const size_t orow = SORTED ? (size_t)(r0 + i0 + i) : (size_t)p[i0 + i];
+                    if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + orow * b, col0, b, res);
                 }
             }
         }
@@ -259,7 +265,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
 // Variant that keeps the whole tile on chip: a tile is two sub-chunks; the
 // first is staged in LDS (as per-thread storage) and the second stays in
 // registers, so phase 2 reads no Z row twice.  Used where the staging fits.
-template <typename P, int BP, int R, int OC, bool VEC>
+template <typename P, int BP, int R, int OC, bool VEC, bool SORTED = false>
 __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
@@ -446,7 +452,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
                 if (c < b) {
                     const C b0 = P::caddl(s_wexcl[w][0][c], e0[j]);
                     const C b1 = P::caddl(s_wexcl[w][1][c], e1[j]);
-                    f[j] = P::fin(b0, b1, T0[c], first ? U[c] : typename P::T(0));
+                    f[j] = P::fin(b0, b1, T0[c], (first && !SORTED) ? U[c] : typename P::T(0));
                 } else {
                     f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
                 }
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
                 typename P::O o[OC][CPL];
 #pragma unroll
                 for (int i = 0; i < OC; ++i) {
-                    if (!first) {
+                    if (!first && !SORTED) {
                         load_row<CPL, VEC>(Out + (size_t)getp(i0 + i) * b, col0, b, r0 + i0 + i < n, o[i]);
                     } else {
 #pragma unroll
@@ -475,7 +481,8 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
                         l1[j] = P::lmac(l1[j], getx(i0 + i), getg(i0 + i, j));
                         res[j] = P::oadd(o[i][j], P::out(l0[j], l1[j], getx(i0 + i), f[j]));
                     }
-                    if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + (size_t)getp(i0 + i) * b, col0, b, res);
+                    const size_t orow = SORTED ? (size_t)(r0 + i0 + i) : (size_t)getp(i0 + i);
+                    if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + orow * b, col0, b, res);
                 }
             }
         };
@@ -573,7 +580,30 @@ hipError_t launch_shape(const L1PassArgs& a, int32_t b, hipStream_t s) {
     // 16-byte row accesses: whole 4-column groups, 16-byte aligned rows
     const bool vec = (b % 4 == 0) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
     // one grid size per tile shape: every pass of a shape must use the same
-    // grid, since the ticket count of a pass is ntiles + grid
+    // grid, since the ticket count of a pass is ntiles + grid (the sorted
+    // passes are shapes of their own, with their own ticket class)
+    if constexpr (BP == 1) {
+        if (a.sorted) {
+            if constexpr (S::KEEP) {
+                const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_keep_kernel<P, BP, R, OC, false, true>,
+                                                    (const void*)l1_pass_keep_kernel<P, BP, R, OC, false, true>);
+                l1_pass_keep_kernel<P, BP, R, OC, false, true><<<grid, 256, 0, s>>>(
+                    a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+                    (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat,
+                    a.status);
+            } else {
+                const int grid = persistent_grid_of(
+                    ntiles, (const void*)l1_pass_kernel<P, BP, R, SUB, OC, false, true>,
+                    (const void*)l1_pass_kernel<P, BP, R, SUB, OC, false, true>);
+                l1_pass_kernel<P, BP, R, SUB, OC, false, true><<<grid, 256, 0, s>>>(
+                    a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+                    (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat,
+                    a.status);
+            }
+            return hipGetLastError();
+        }
+    }
+    if (a.sorted) return hipErrorInvalidValue;   // single columns only
     if constexpr (S::KEEP) {
         const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_keep_kernel<P, BP, R, OC, false>,
                                             (const void*)l1_pass_keep_kernel<P, BP, R, OC, true>);

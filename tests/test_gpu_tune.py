@@ -45,17 +45,18 @@ def test_every_variant_bit_exact_on_integers(b):
     h.free()
 
 
-def test_every_variant_bit_exact_int64_rhs():
-    X, Z = _int_data(5003, 2, 16, 950, wide=True)
+@pytest.mark.parametrize("b", [1, 16])
+def test_every_variant_bit_exact_int64_rhs(b):
+    X, Z = _int_data(5003, 2, b, 950 + b, wide=True)
     o, ov = oracle.matvec_int(X, Z, L1)
     assert ov == 0
     h = dm.prepare(dev(X), L1)
     import torch
     for v in range(dm.lib().dm_variant_count()):
-        h.set_variant(16, v, torch.int64)
+        h.set_variant(b, v, torch.int64)
         Y = h.matvec(dev(Z))
         h.sync()
-        assert np.array_equal(Y.cpu().numpy(), o), "variant %d" % v
+        assert np.array_equal(Y.cpu().numpy(), o), "variant %d, b=%d" % (v, b)
     h.free()
 
 
