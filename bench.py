@@ -443,7 +443,10 @@ def main():
     log("batched: %.2f ms/step (wall %.2f ms), %.1f columns/s, pass %.3f ms x %d" %
         (ms_step, wall * 1e3 / args.steps, cols_s, avg_pass_ms, pass_n // max(args.steps, 1)))
 
-    bytes_pass = 12.0 * n * b + 8.0 * n
+    # per launch, averaged over the d passes of a query: each pass reads perm
+    # and xs (8n), the Z rows (4nb) and the Out rows (4nb) and writes Out (4nb);
+    # the first pass reads no Out
+    bytes_pass = 12.0 * n * b + 8.0 * n - 4.0 * n * b / d
     achieved = bytes_pass / (avg_pass_ms * 1e-3) / 1e9
     traffic = read_traffic(vb)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -325,8 +325,9 @@ dm_status dm_profile_enable(dm_handle* h, int32_t on);
 dm_status dm_profile_read(dm_handle* h, int32_t kernel_class, double* total_ms, int64_t* launches);
 
 /*
- * Streaming copy of `bytes` bytes from src to dst (device pointers, 16-byte
- * aligned, not overlapping), used to calibrate achievable HBM bandwidth and
+ * Streaming copy of `bytes` bytes (a nonzero multiple of 16) from src to dst
+ * (device pointers, 16-byte aligned, not overlapping), one 16-byte element per
+ * lane, used to calibrate achievable HBM bandwidth and
  * hardware byte counters.  Stream-ordered.  Errors: DM_ERR_ARG, DM_ERR_DEVICE.
  */
 dm_status dm_copy_probe(void* dst, const void* src, size_t bytes, void* stream);

@@ -168,10 +168,10 @@ struct dm_handle {
     Ctl* ctl = nullptr;
     char* scratch = nullptr;
     size_t scratch_bytes = 0;
-    // single-column l1 queries: each coordinate's values in sorted order
-    // (d x ld, FP32 or int64), gathered per point after the passes
-    char* sorted_buf = nullptr;
-    size_t sorted_bytes = 0;
+    // single-column l1 queries: the values of a group of coordinates, each in
+    // point order (group x ld, FP32 or int64), summed after the group's passes
+    char* single_buf = nullptr;
+    size_t single_bytes = 0;
     // look-back record regions, one per pass kernel shape (zeroed when created)
     struct Region { int cls; uint64_t* ptr; size_t words; };
     std::vector<Region> regions;
@@ -206,7 +206,7 @@ void release(dm_handle* h) {
         if (e.b) (void)hipEventDestroy(e.b);
     }
     if (h->scratch) (void)hipFree(h->scratch);
-    if (h->sorted_buf) (void)hipFree(h->sorted_buf);
+    if (h->single_buf) (void)hipFree(h->single_buf);
     for (auto& r : h->regions) (void)hipFree(r.ptr);
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
@@ -357,18 +357,26 @@ dm_status ensure_scratch(dm_handle* h, int32_t b, hipStream_t s) {
     return DM_OK;
 }
 
-// The sorted-order buffer of single-column l1 queries (created on first use).
-dm_status ensure_sorted_buf(dm_handle* h) {
-    const size_t need = (size_t)h->d * (size_t)h->L.ld * (h->is_int ? 8 : 4);
-    if (h->sorted_bytes >= need) return DM_OK;
+// Coordinates per group of a single-column l1 query (group x ld values of
+// FP32 or int64 in the buffer).
+int32_t single_group(const dm_handle* h) {
+    const size_t per = (size_t)h->L.ld * (h->is_int ? 8 : 4);
+    const size_t g = SINGLE_GROUP_BYTES / per;
+    return (int32_t)(g < 1 ? 1 : g > (size_t)h->d ? (size_t)h->d : g);
+}
+
+// The group buffer of single-column l1 queries (created on first use).
+dm_status ensure_single_buf(dm_handle* h) {
+    const size_t need = (size_t)single_group(h) * (size_t)h->L.ld * (h->is_int ? 8 : 4);
+    if (h->single_bytes >= need) return DM_OK;
     void* p = nullptr;
     if (hipMalloc(&p, need) != hipSuccess) {
         (void)hipGetLastError();   // the caller falls back; keep later launch checks clean
         return DM_ERR_NOMEM;
     }
-    if (h->sorted_buf) (void)hipFree(h->sorted_buf);
-    h->sorted_buf = (char*)p;
-    h->sorted_bytes = need;
+    if (h->single_buf) (void)hipFree(h->single_buf);
+    h->single_buf = (char*)p;
+    h->single_bytes = need;
     return DM_OK;
 }
 
@@ -652,12 +660,12 @@ dm_status dm_reserve(dm_handle* h, int32_t b) {
             }
             const int v = variant_for(h, kind_index(h->is_int, kinds[ki]), log2_pad(b));
             if ((st = region_for(h, l1_shape(h->n, b, h->is_int, kinds[ki], v), h->last, &r)) != DM_OK) return st;
-            // single-column queries use the sorted passes
+            // single-column queries use the OUT_FRESH passes
             const int v1 = variant_for(h, kind_index(h->is_int, kinds[ki]), 0);
-            if ((st = region_for(h, l1_sorted_shape(h->n, h->is_int, kinds[ki], v1), h->last, &r)) != DM_OK)
+            if ((st = region_for(h, l1_single_shape(h->n, h->is_int, kinds[ki], v1), h->last, &r)) != DM_OK)
                 return st;
         }
-        if (l1_pass_metric(h->metric) && (st = ensure_sorted_buf(h)) != DM_OK) return st;
+        if (l1_pass_metric(h->metric) && (st = ensure_single_buf(h)) != DM_OK) return st;
     }
     return hipStreamSynchronize(h->last) == hipSuccess ? DM_OK : DM_ERR_DEVICE;
 }
@@ -787,31 +795,35 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
             a.variant = v;
         }
         const size_t vsz = 4;
-        // one column: every pass writes its values in sorted order, then one
-        // gather per point adds them through the rank arrays (Algorithm 2's
-        // arrays and lookups); falls back to the scattering passes when the
-        // d x n buffer cannot be allocated
-        const bool sorted = b == 1 && ensure_sorted_buf(h) == DM_OK;
+        // one column: each pass writes its values in point order to a buffer
+        // of its own, and after each group of G coordinates one coalesced sweep
+        // adds the group's buffers into Out; falls back to the adding passes
+        // when the G x n buffer cannot be allocated
+        const bool single = b == 1 && ensure_single_buf(h) == DM_OK;
+        const int32_t G = single ? single_group(h) : 1;
         const size_t osz = h->is_int ? 8 : 4;
-        if (sorted) {
-            const L1Shape sh = l1_sorted_shape(h->n, h->is_int, zkind, a.variant);
+        if (single) {
+            const L1Shape sh = l1_single_shape(h->n, h->is_int, zkind, a.variant);
             dm_status rs = region_for(h, sh, s, &a.records);
             if (rs != DM_OK) return rs;
             a.record_words = sh.record_words;
             a.cls = sh.cls;
-            a.sorted = 1;
+            a.out_mode = OUT_FRESH;
         }
         for (int32_t k = 0; k < h->d; ++k) {
             a.perm = h->at<uint32_t>(h->L.perm) + (size_t)k * h->L.ld;
             a.xs = h->ws + h->L.xs + (size_t)k * h->L.ld * vsz;
             a.first = k == 0;
-            if (sorted) a.Out = h->sorted_buf + (size_t)k * h->L.ld * osz;
-            ProfScope ps(h, DM_K_L1_PASS, s);
-            DM_TRY(launch_l1_pass(h->is_int, zkind, b, a, s));
+            if (single) a.Out = h->single_buf + (size_t)(k % G) * h->L.ld * osz;
+            {
+                ProfScope ps(h, DM_K_L1_PASS, s);
+                DM_TRY(launch_l1_pass(h->is_int, zkind, b, a, s));
+            }
+            if (single && (k % G == G - 1 || k == h->d - 1)) {
+                const int32_t k0 = k - k % G;
+                DM_TRY(launch_l1_combine(h->is_int, h->L.ld, h->single_buf, h->n, k - k0 + 1, k0 == 0, tot.U, Out, s));
+            }
         }
-        if (sorted)
-            DM_TRY(launch_l1_gather_sorted(h->is_int, h->at<uint32_t>(h->L.rank), h->L.ld, h->sorted_buf, h->n, h->d,
-                                           tot.U, Out, s));
         // TV(x, y) = l1(x, y) / 2 (the TV theorem of Appendix A.3); the
         // halving is exact in floating point
         if (h->metric == DM_TV) DM_TRY(launch_scale_f32((float*)Out, (size_t)h->n * b, 0.5f, s));
@@ -1109,7 +1121,7 @@ dm_status dm_profile_read(dm_handle* h, int32_t kernel_class, double* total_ms, 
 }
 
 dm_status dm_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
-    if (!dst || !src || bytes == 0) return DM_ERR_ARG;
+    if (!dst || !src || bytes == 0 || bytes % 16 != 0) return DM_ERR_ARG;
     if (((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return DM_ERR_ARG;
     const char* d = (const char*)dst;
     const char* s = (const char*)src;

@@ -32,8 +32,8 @@ constexpr int SORT_THREADS = 256;
 constexpr int L1_VARIANTS = 4;      // tile variants per l1 pass configuration (tuned per handle)
 constexpr int L1_CLASSES = 96;      // 3 data paths x 8 block widths x L1_VARIANTS
 constexpr int LP_CLASSES = 48;      // odd p: 3 data paths x 8 block widths x (p = 3, 5)
-constexpr int SORTED_CLASSES = 12;  // single-column passes in sorted order: 3 data paths x L1_VARIANTS
-constexpr int CHAIN_CLASSES = L1_CLASSES + LP_CLASSES + SORTED_CLASSES;
+constexpr int SINGLE_CLASSES = 12;  // single-column OUT_FRESH passes: 3 data paths x L1_VARIANTS
+constexpr int CHAIN_CLASSES = L1_CLASSES + LP_CLASSES + SINGLE_CLASSES;
 struct ChainState {
     uint64_t ticket[CHAIN_CLASSES];
 };
@@ -83,6 +83,9 @@ size_t totals_scratch_bytes(int64_t n, int32_t b);
 hipError_t launch_totals(bool is_int, int zkind, const void* Z, int64_t n, int32_t b, const void* w,
                          double guard_scale, const TotalsOut& o, hipStream_t s);
 
+// How a pass stores its values: add them into Out[perm[r]] (and, on the
+// first pass, U), or write them to Out[perm[r]] without reading Out.
+enum { OUT_ADD = 0, OUT_FRESH = 1 };
 struct L1PassArgs {
     const uint32_t* perm;   // n (this coordinate)
     const void* xs;         // n (float | int32)
@@ -98,7 +101,7 @@ struct L1PassArgs {
     int cls;                // the shape's ticket class (l1_shape)
     int variant;            // tile variant, 0 .. L1_VARIANTS-1
     uint32_t* status;       // sticky query flags (QF_STALL on a stuck chain)
-    int sorted = 0;         // b = 1 only: write each rank's value at its rank in Out (n values), add no U
+    int out_mode = OUT_ADD; // OUT_FRESH (b = 1 only): write the values, add no U
 };
 int l1_tile_ranks(int32_t b, bool is_int, int zkind, int variant);
 size_t l1_record_words(int64_t n, int32_t b, bool is_int, int zkind, int variant);
@@ -116,12 +119,15 @@ struct L1Shape {
     size_t record_words;
 };
 L1Shape l1_shape(int64_t n, int32_t b, bool is_int, int zkind, int variant);
-// the single-column pass that writes in sorted order (its own ticket class)
-L1Shape l1_sorted_shape(int64_t n, bool is_int, int zkind, int variant);
-// Out[i] = U + sum_k Cs[k * ld + rank[k * ld + i]], b = 1: the lookup step that
-// follows the sorted passes (float data: FP64 sum rounded once; integers: int64)
-hipError_t launch_l1_gather_sorted(bool is_int, const uint32_t* rank, int64_t ld, const void* Cs, int64_t n, int32_t d,
-                                   const void* U, void* Out, hipStream_t s);
+// the single-column OUT_FRESH pass (its own ticket class)
+L1Shape l1_single_shape(int64_t n, bool is_int, int zkind, int variant);
+// Out[i] = (first ? U : Out[i]) + sum_{k < g} Cs[k * ld + i], b = 1: the sum of
+// a group of g passes written in point order (float data: FP64 sum rounded
+// once per group; integers: wrapping int64)
+hipError_t launch_l1_combine(bool is_int, int64_t ld, const void* Cs, int64_t n, int32_t g, bool first,
+                             const void* U, void* Out, hipStream_t s);
+// bytes of per-coordinate values per group of a single-column query
+constexpr size_t SINGLE_GROUP_BYTES = (size_t)64 << 20;
 hipError_t launch_l1_pass(bool is_int, int zkind, int32_t b, const L1PassArgs& a, hipStream_t s);
 
 // ---- many datasets in one query --------------------------------------------

@@ -264,7 +264,7 @@ L1Shape l1_shape(int64_t n, int32_t b, bool is_int, int zkind, int variant) {
     return sh;
 }
 
-L1Shape l1_sorted_shape(int64_t n, bool is_int, int zkind, int variant) {
+L1Shape l1_single_shape(int64_t n, bool is_int, int zkind, int variant) {
     L1Shape sh;
     sh.cls = L1_CLASSES + LP_CLASSES + kind_of(is_int, zkind) * L1_VARIANTS + variant;
     sh.record_words = l1_record_words(n, 1, is_int, zkind, variant);
@@ -273,60 +273,38 @@ L1Shape l1_sorted_shape(int64_t n, bool is_int, int zkind, int variant) {
 
 namespace {
 
-// Out[i] = U + sum_k Cs[k][rank[k][i]] (b = 1).  A thread owns one point; the
-// ranks of 8 coordinates are read (coalesced over the points) before their 8
-// values are gathered, so 8 random loads are in flight per thread.
+// Out[i] = (first ? U : Out[i]) + sum_k Cs[k][i] over the g coordinates of a
+// group (b = 1), coalesced over the points.
 template <bool INT>
-__global__ __launch_bounds__(256) void l1_gather_sorted(const uint32_t* __restrict__ rank, int64_t ld,
-                                                        const void* __restrict__ Cs, int64_t n, int32_t d,
-                                                        const void* __restrict__ U, void* __restrict__ Out)
+__global__ __launch_bounds__(256) void l1_combine(int64_t ld, const void* __restrict__ Cs, int64_t n, int32_t g,
+                                                  int first, const void* __restrict__ U, void* __restrict__ Out)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    constexpr int G = 8;
     if constexpr (INT) {
-        const int64_t* C = (const int64_t*)Cs;
-        uint64_t acc = (uint64_t)((const int64_t*)U)[0];
-        int k = 0;
-        for (; k + G <= d; k += G) {
-            uint32_t r[G];
-#pragma unroll
-            for (int q = 0; q < G; ++q) r[q] = rank[(int64_t)(k + q) * ld + i];
-#pragma unroll
-            for (int q = 0; q < G; ++q) acc += (uint64_t)C[(int64_t)(k + q) * ld + r[q]];
-        }
-        for (; k < d; ++k) acc += (uint64_t)C[(int64_t)k * ld + rank[(int64_t)k * ld + i]];
+        const int64_t* C = (const int64_t*)Cs + i;
+        uint64_t acc = (uint64_t)(first ? ((const int64_t*)U)[0] : ((const int64_t*)Out)[i]);
+        for (int32_t k = 0; k < g; ++k) acc += (uint64_t)C[(int64_t)k * ld];
         ((int64_t*)Out)[i] = (int64_t)acc;
     } else {
-        const float* C = (const float*)Cs;
-        double acc = ((const double*)U)[0];
-        int k = 0;
-        for (; k + G <= d; k += G) {
-            uint32_t r[G];
-#pragma unroll
-            for (int q = 0; q < G; ++q) r[q] = rank[(int64_t)(k + q) * ld + i];
-            float v[G];
-#pragma unroll
-            for (int q = 0; q < G; ++q) v[q] = C[(int64_t)(k + q) * ld + r[q]];
-#pragma unroll
-            for (int q = 0; q < G; ++q) acc += (double)v[q];
-        }
-        for (; k < d; ++k) acc += (double)C[(int64_t)k * ld + rank[(int64_t)k * ld + i]];
+        const float* C = (const float*)Cs + i;
+        double acc = first ? ((const double*)U)[0] : (double)((const float*)Out)[i];
+        for (int32_t k = 0; k < g; ++k) acc += (double)C[(int64_t)k * ld];
         ((float*)Out)[i] = (float)acc;
     }
 }
 
 }  // namespace
 
-hipError_t launch_l1_gather_sorted(bool is_int, const uint32_t* rank, int64_t ld, const void* Cs, int64_t n, int32_t d,
-                                   const void* U, void* Out, hipStream_t s)
+hipError_t launch_l1_combine(bool is_int, int64_t ld, const void* Cs, int64_t n, int32_t g, bool first,
+                             const void* U, void* Out, hipStream_t s)
 {
-    if (n < 1 || d < 1) return hipErrorInvalidValue;
+    if (n < 1 || g < 1 || ld < n) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)((n + 255) / 256);
     if (is_int)
-        l1_gather_sorted<true><<<grid, 256, 0, s>>>(rank, ld, Cs, n, d, U, Out);
+        l1_combine<true><<<grid, 256, 0, s>>>(ld, Cs, n, g, first ? 1 : 0, U, Out);
     else
-        l1_gather_sorted<false><<<grid, 256, 0, s>>>(rank, ld, Cs, n, d, U, Out);
+        l1_combine<false><<<grid, 256, 0, s>>>(ld, Cs, n, g, first ? 1 : 0, U, Out);
     return hipGetLastError();
 }
 

@@ -142,12 +142,12 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t count) {
     for (; i < count; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// plain streaming copy, 16 bytes per lane per iteration
+// plain streaming copy, one 16-byte element per lane (a grid-stride loop over
+// a capped grid reaches about a quarter less bandwidth on gfx950)
 __global__ __launch_bounds__(256) void copy_probe_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
                                                          size_t n16) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n16; i += stride) dst[i] = src[i];
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) dst[i] = src[i];
 }
 
 // p[i] *= s
@@ -171,10 +171,12 @@ hipError_t launch_scale_f32(float* p, size_t count, float s, hipStream_t st)
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s)
 {
     const size_t n16 = bytes / 16;
-    if (n16 == 0) return hipSuccess;
-    size_t blocks = (n16 + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;
-    copy_probe_kernel<<<(unsigned)blocks, 256, 0, s>>>((uint4*)dst, (const uint4*)src, n16);
+    // grids of at most 2^30 lanes (16 GiB per launch)
+    constexpr size_t CHUNK = (size_t)1 << 30;
+    for (size_t at = 0; at < n16; at += CHUNK) {
+        const size_t cnt = n16 - at < CHUNK ? n16 - at : CHUNK;
+        copy_probe_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>((uint4*)dst + at, (const uint4*)src + at, cnt);
+    }
     return hipGetLastError();
 }
 

@@ -13,14 +13,15 @@
 // to Out[perm[r]] and the first pass also adds U.
 //
 // Algorithm 2 materialises the prefix arrays B_i and C_i and looks positions
-// up per point; for blocks of columns the two loops are fused into one pass
-// per coordinate: the sorted order is walked once, the prefixes live in
-// registers, and each result is scattered to its point's row.  Every pass
-// visits each row of Out exactly once (perm is a permutation), so passes are
-// stream-ordered and a pass needs no atomics on Out.  For a single column
-// (SORTED) the pass instead writes each rank's value in sorted order, and one
-// later gather per point adds its d values through the rank arrays (the
-// lookup step of Algorithm 2): two random accesses per rank instead of three.
+// up per point; here the two loops are fused into one pass per coordinate:
+// the sorted order is walked once, the prefixes live in registers, and each
+// result is scattered to its point's row.  Every pass visits each row of Out
+// exactly once (perm is a permutation), so passes are stream-ordered and a
+// pass needs no atomics on Out.  For a single column (OUT_FRESH) a pass writes
+// its values to a buffer of its own in point order instead of adding them into
+// Out, and the buffers of a group of coordinates are summed afterwards in one
+// coalesced sweep: two scattered accesses per rank (the Z gather and the
+// store) instead of three, and no scattered load whose latency is exposed.
 //
 // One pass = one launch, one tile of TILE consecutive ranks per workgroup.
 // Tiles take indices from a ticket counter in dispatch order and chain their
@@ -43,7 +44,7 @@ namespace {
 
 using namespace l1;
 
-template <typename P, int BP, int R, int SUB, int OC, bool VEC, bool SORTED = false>
+template <typename P, int BP, int R, int SUB, int OC, bool VEC, int OM = OUT_ADD>
 __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
                 if (c < b) {
                     const C b0 = P::caddl(s_wexcl[w][0][c], e0[j]);
                     const C b1 = P::caddl(s_wexcl[w][1][c], e1[j]);
-                    f[j] = P::fin(b0, b1, T0[c], (first && !SORTED) ? U[c] : typename P::T(0));
+                    f[j] = P::fin(b0, b1, T0[c], (first && OM == OUT_ADD) ? U[c] : typename P::T(0));
                 } else {
                     f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
                 }
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
                 typename P::O o[OC][CPL];
 #pragma unroll
                 for (int i = 0; i < OC; ++i) {
-                    if (!first && !SORTED) {
+                    if (!first && OM == OUT_ADD) {
                         load_row<CPL, VEC>(Out + (size_t)p[i0 + i] * b, col0, b, r0 + i0 + i < n, o[i]);
                     } else {
 #pragma unroll
@@ -248,9 +249,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
                         l1[j] = P::lmac(l1[j], x[i0 + i], g[i0 + i][j]);
                         res[j] = P::oadd(o[i][j], P::out(l0[j], l1[j], x[i0 + i], f[j]));
                     }
-                    // SORTED: the value at its rank (Algorithm 2's per-coordinate array),
-                    // else added into the point's row
-                    const size_t orow = SORTED ? (size_t)(r0 + i0 + i) : (size_t)p[i0 + i];
+                    const size_t orow = (size_t)p[i0 + i];
                     if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + orow * b, col0, b, res);
                 }
             }
@@ -265,7 +264,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_kernel(
 // Variant that keeps the whole tile on chip: a tile is two sub-chunks; the
 // first is staged in LDS (as per-thread storage) and the second stays in
 // registers, so phase 2 reads no Z row twice.  Used where the staging fits.
-template <typename P, int BP, int R, int OC, bool VEC, bool SORTED = false>
+template <typename P, int BP, int R, int OC, bool VEC, int OM = OUT_ADD>
 __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
@@ -452,7 +451,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
                 if (c < b) {
                     const C b0 = P::caddl(s_wexcl[w][0][c], e0[j]);
                     const C b1 = P::caddl(s_wexcl[w][1][c], e1[j]);
-                    f[j] = P::fin(b0, b1, T0[c], (first && !SORTED) ? U[c] : typename P::T(0));
+                    f[j] = P::fin(b0, b1, T0[c], (first && OM == OUT_ADD) ? U[c] : typename P::T(0));
                 } else {
                     f[j] = P::fin(P::czero(), P::czero(), typename P::T(0), typename P::T(0));
                 }
@@ -465,7 +464,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
                 typename P::O o[OC][CPL];
 #pragma unroll
                 for (int i = 0; i < OC; ++i) {
-                    if (!first && !SORTED) {
+                    if (!first && OM == OUT_ADD) {
                         load_row<CPL, VEC>(Out + (size_t)getp(i0 + i) * b, col0, b, r0 + i0 + i < n, o[i]);
                     } else {
 #pragma unroll
@@ -481,7 +480,7 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
                         l1[j] = P::lmac(l1[j], getx(i0 + i), getg(i0 + i, j));
                         res[j] = P::oadd(o[i][j], P::out(l0[j], l1[j], getx(i0 + i), f[j]));
                     }
-                    const size_t orow = SORTED ? (size_t)(r0 + i0 + i) : (size_t)getp(i0 + i);
+                    const size_t orow = (size_t)getp(i0 + i);
                     if (r0 + i0 + i < n) store_row<CPL, VEC>(Out + orow * b, col0, b, res);
                 }
             }
@@ -568,6 +567,29 @@ static int persistent_grid_of(int64_t ntiles, const void* fn, const void* fn2) {
     return (int)g;
 }
 
+// single-column passes that write rather than add (OUT_FRESH): a kernel shape
+// of its own with its own ticket class
+template <typename P, int BP, int R, int SUB, int OC, bool KEEP, int OM>
+hipError_t launch_single(const L1PassArgs& a, int32_t b, hipStream_t s, uint64_t* ctr, int64_t ntiles,
+                         uint64_t* stat) {
+    if constexpr (KEEP) {
+        const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_keep_kernel<P, BP, R, OC, false, OM>,
+                                            (const void*)l1_pass_keep_kernel<P, BP, R, OC, false, OM>);
+        l1_pass_keep_kernel<P, BP, R, OC, false, OM><<<grid, 256, 0, s>>>(
+            a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat,
+            a.status);
+    } else {
+        const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_kernel<P, BP, R, SUB, OC, false, OM>,
+                                            (const void*)l1_pass_kernel<P, BP, R, SUB, OC, false, OM>);
+        l1_pass_kernel<P, BP, R, SUB, OC, false, OM><<<grid, 256, 0, s>>>(
+            a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
+            (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat,
+            a.status);
+    }
+    return hipGetLastError();
+}
+
 template <typename P, int BP, int V>
 hipError_t launch_shape(const L1PassArgs& a, int32_t b, hipStream_t s) {
     using S = Shape<P, BP, V>;
@@ -580,30 +602,12 @@ hipError_t launch_shape(const L1PassArgs& a, int32_t b, hipStream_t s) {
     // 16-byte row accesses: whole 4-column groups, 16-byte aligned rows
     const bool vec = (b % 4 == 0) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
     // one grid size per tile shape: every pass of a shape must use the same
-    // grid, since the ticket count of a pass is ntiles + grid (the sorted
+    // grid, since the ticket count of a pass is ntiles + grid (the OUT_FRESH
     // passes are shapes of their own, with their own ticket class)
     if constexpr (BP == 1) {
-        if (a.sorted) {
-            if constexpr (S::KEEP) {
-                const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_keep_kernel<P, BP, R, OC, false, true>,
-                                                    (const void*)l1_pass_keep_kernel<P, BP, R, OC, false, true>);
-                l1_pass_keep_kernel<P, BP, R, OC, false, true><<<grid, 256, 0, s>>>(
-                    a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-                    (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat,
-                    a.status);
-            } else {
-                const int grid = persistent_grid_of(
-                    ntiles, (const void*)l1_pass_kernel<P, BP, R, SUB, OC, false, true>,
-                    (const void*)l1_pass_kernel<P, BP, R, SUB, OC, false, true>);
-                l1_pass_kernel<P, BP, R, SUB, OC, false, true><<<grid, 256, 0, s>>>(
-                    a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-                    (const typename P::T*)a.T0, (const typename P::T*)a.U, a.first, ctr, a.cls, ntiles, a.records, stat,
-                    a.status);
-            }
-            return hipGetLastError();
-        }
+        if (a.out_mode == OUT_FRESH) return launch_single<P, BP, R, SUB, OC, S::KEEP, OUT_FRESH>(a, b, s, ctr, ntiles, stat);
     }
-    if (a.sorted) return hipErrorInvalidValue;   // single columns only
+    if (a.out_mode != OUT_ADD) return hipErrorInvalidValue;   // single columns only
     if constexpr (S::KEEP) {
         const int grid = persistent_grid_of(ntiles, (const void*)l1_pass_keep_kernel<P, BP, R, OC, false>,
                                             (const void*)l1_pass_keep_kernel<P, BP, R, OC, true>);

@@ -138,6 +138,15 @@ def test_embed_argument_errors_before_device(L):
     L.dm_free(None)
 
 
+def test_copy_probe_argument_errors_before_device(L):
+    A, B = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x90000)
+    assert L.dm_copy_probe(A, B, 0, None) == dm.ERR_ARG            # empty
+    assert L.dm_copy_probe(A, B, 24, None) == dm.ERR_ARG           # not a multiple of 16
+    assert L.dm_copy_probe(ctypes.c_void_p(0x10008), B, 32, None) == dm.ERR_ARG   # misaligned
+    assert L.dm_copy_probe(A, ctypes.c_void_p(0x10010), 32, None) == dm.ERR_ARG   # overlap
+    assert L.dm_copy_probe(None, B, 32, None) == dm.ERR_ARG
+
+
 def test_variant_count(L):
     assert L.dm_variant_count() == 4
 

@@ -143,6 +143,38 @@ def test_columns_equal_single_vector_queries():
     h.sync()
 
 
+@pytest.mark.parametrize("zdtype", [np.int32, np.int64])
+def test_single_column_in_several_coordinate_groups(zdtype):
+    # a single column runs the passes in groups of coordinates whose values fit
+    # a 64 MiB buffer: at n = 2^20 + 37 that is 7 coordinates of int64 values,
+    # so d = 20 takes 3 groups, the last ragged
+    g = synth.rng(710)
+    n, d = (1 << 20) + 37, 20
+    X = g.integers(-2 ** 15, 2 ** 15, size=(n, d)).astype(np.int32)
+    Z = g.integers(-4096, 4096, size=(n, 2)).astype(zdtype)
+    import paper_2210_15114_amd as dmm
+    h = dmm.prepare(dev(X), L1)
+    y1 = h.matvec(dev(np.ascontiguousarray(Z[:, 0]))).cpu().numpy().reshape(n)
+    y2 = h.matvec(dev(Z)).cpu().numpy()
+    h.sync()
+    # every row against the two-column query, which adds in place
+    assert np.array_equal(y1, y2[:, 0])
+    rows = np.concatenate([np.arange(4), g.choice(n, 40, replace=False), np.arange(n - 4, n)])
+    o, ov = oracle.matvec_int(X, Z[:, :1], L1, rows)
+    assert ov == 0
+    assert np.array_equal(y1[rows], o[:, 0])
+
+
+def test_single_column_float_in_several_coordinate_groups():
+    g = synth.rng(720)
+    n, d = (1 << 20) + 11, 24      # 15 FP32 coordinates per group at this n: 2 groups
+    X = g.random((n, d), dtype=np.float32)
+    Z = g.standard_normal(n, dtype=np.float32)
+    Y, _ = run(X, Z, L1)
+    rows = np.concatenate([np.arange(3), g.choice(n, 30, replace=False), np.arange(n - 3, n)])
+    _check_float(X, Z, Y, rows=rows)
+
+
 def test_integer_runs_are_deterministic():
     g = synth.rng(600)
     X = g.integers(-100, 100, size=(20000, 4)).astype(np.int32)
