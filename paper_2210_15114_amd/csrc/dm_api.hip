@@ -893,8 +893,11 @@ dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* 
         a.chain = &h->ctl->chain;
         a.status = &h->ctl->status;
         a.first = 0;
+        // a single column runs the OUT_FRESH passes
+        a.out_mode = b == 1 ? OUT_FRESH : OUT_ADD;
         for (int v = 0; v < L1_VARIANTS; ++v) {
-            const L1Shape sh = l1_shape(h->n, b, h->is_int, zkind, v);
+            const L1Shape sh =
+                b == 1 ? l1_single_shape(h->n, h->is_int, zkind, v) : l1_shape(h->n, b, h->is_int, zkind, v);
             const dm_status rs = region_for(h, sh, s, &a.records);
             if (rs != DM_OK) return rs;
             a.record_words = sh.record_words;
