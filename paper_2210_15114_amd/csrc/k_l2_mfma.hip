@@ -137,22 +137,29 @@ __global__ __launch_bounds__(256) void xtz_mfma_kernel(const float* __restrict__
     }
 }
 
-// fixed-order sum of the partials: V[e] = sum_g part[g][e]; one block per
-// entry group, each thread a strided slice, then a fixed tree in LDS
+// fixed-order sum of the partials: V[e] = sum_g part[g][e].  A block takes 32
+// consecutive entries; its 8 row groups each sum the partials g = q, q + 8, ...
+// in ascending order (32 lanes read 256 contiguous bytes per load), and the 8
+// group sums are added in group order.
 __global__ __launch_bounds__(256) void xtz_reduce_kernel(const double* __restrict__ part, int nblk, int ent,
                                                          double* __restrict__ V)
 {
-    __shared__ double s[256];
-    const int e = blockIdx.x;
+    __shared__ double s[8][32];
+    const int el = threadIdx.x % 32, q = threadIdx.x / 32;
+    const int e = blockIdx.x * 32 + el;
     double acc = 0.0;
-    for (int g = threadIdx.x; g < nblk; g += 256) acc += part[(size_t)g * ent + e];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
-        __syncthreads();
+    if (e < ent) {
+#pragma unroll 8
+        for (int g = q; g < nblk; g += 8) acc += part[(size_t)g * ent + e];
     }
-    if (threadIdx.x == 0) V[e] = s[0];
+    s[q][el] = acc;
+    __syncthreads();
+    if (q == 0 && e < ent) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v += s[r][el];
+        V[e] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -282,7 +289,7 @@ hipError_t launch_l2sq_mfma(const float* Xc, const double* nrm, int64_t n, int32
     xtz_mfma_kernel<<<nblk, 256, 0, s>>>(Xc, n, d, Z, b, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    xtz_reduce_kernel<<<ent, 256, 0, s>>>(part, nblk, ent, V);
+    xtz_reduce_kernel<<<(ent + 31) / 32, 256, 0, s>>>(part, nblk, ent, V);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t blocks = (n + 127) / 128;
     const unsigned grid = (unsigned)(blocks < 256 * 8 ? blocks : 256 * 8);

@@ -31,7 +31,10 @@ def _mscale(X32, Z32):
     return nrm[:, None] * zl1[None, :] + (nrm @ Z)[None, :] + 2 * np.abs(X) @ t
 
 
-@pytest.mark.parametrize("n,d,b", [(1, 3, 1), (2048, 16, 1), (3001, 7, 4), (5000, 64, 16), (4099, 128, 64)])
+# matrix-core shapes: d <= 32 (4 waves split the points), 33..64 (2), 65..96
+# (one wave idle), 97..128; b up to 32 (one column tile) and beyond
+@pytest.mark.parametrize("n,d,b", [(1, 3, 1), (2048, 16, 1), (3001, 7, 4), (5000, 64, 16), (4099, 128, 64),
+                                   (3000, 20, 24), (257, 33, 17), (4500, 96, 40), (9001, 128, 33)])
 def test_float(n, d, b):
     g = synth.rng(700 + n + b)
     X = g.standard_normal((n, d), dtype=np.float32)
@@ -64,3 +67,19 @@ def test_identical_points_give_zero():
     Z = synth.rng(9).standard_normal((500, 2)).astype(np.float32)
     Y, _ = run(X, Z, L2SQ)
     assert np.abs(Y).max() <= 1e-3 * np.abs(Z).sum()
+
+
+@pytest.mark.parametrize("b", [1, 16, 64])
+def test_nonfinite_rhs_flagged(b):
+    g = synth.rng(850 + b)
+    X = g.standard_normal((700, 8)).astype(np.float32)
+    Z = g.standard_normal((700, b)).astype(np.float32)
+    Z[333, b - 1] = np.inf
+    h = dm.prepare(dev(X), L2SQ)
+    h.matvec(dev(Z))
+    with pytest.raises(dm.DMError) as ei:
+        h.sync()
+    assert ei.value.status == dm.ERR_NONFINITE
+    Z[333, b - 1] = 0.0
+    h.matvec(dev(Z))
+    h.sync()
