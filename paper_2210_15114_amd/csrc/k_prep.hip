@@ -98,42 +98,61 @@ __global__ __launch_bounds__(256) void prep_transpose_kernel(
     }
 }
 
-// Row statistics s_i = sum_k x_ik and ||x_i||^2, one thread per row, k
-// ascending (fixed order, so the FP64 sums are reproducible).
+// Row statistics: rowsum[i] = sum_k x_ik^p (p = 1: the row sum; p odd >= 3:
+// the weights of the l_p^p query's constant term), rownrm[i] = sum_k x_ik^2.
+// G = 2^lg lanes share a row: lane l takes k = l, l + G, ... in ascending order
+// (each load instruction reads G consecutive values of the row), and the G
+// partial sums are then added by a fixed xor butterfly, so every FP64 sum is
+// reproducible.  Integer data runs in wrapping int64 (exact modulo 2^64).
 template <int KIND>
-// rowsum[i] = sum_k x_ik^p (p = 1: the row sum; p odd >= 3: the weights of
-// the l_p^p query's constant term), rownrm[i] = sum_k x_ik^2
 __global__ __launch_bounds__(256) void row_stats_kernel(
-    const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d, int p, void* rowsum, void* rownrm)
+    const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d, int p, int lg, void* rowsum, void* rownrm)
 {
     using I = In<KIND>;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const typename I::T* xi = X + i * d;
+    const int G = 1 << lg;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lg;
+    const int l = (int)(threadIdx.x & (G - 1));
+    const bool valid = i < n;   // every lane takes part in the butterfly
+    const typename I::T* xi = X + (valid ? i : 0) * d;
     uint32_t bad = 0;
     if constexpr (KIND == IN_F32 || KIND == IN_F64) {
         double s = 0.0, q = 0.0;
-        for (int32_t k = 0; k < d; ++k) {
-            double v = (double)I::conv(xi[k], bad);
-            double vp = v;
-            for (int e = 1; e < p; ++e) vp *= v;
-            s += vp;
-            q += v * v;
+        if (valid) {
+            for (int32_t k = l; k < d; k += G) {
+                const double v = (double)I::conv(xi[k], bad);
+                double vp = v;
+                for (int e = 1; e < p; ++e) vp *= v;
+                s += vp;
+                q += v * v;
+            }
         }
-        ((double*)rowsum)[i] = s;
-        ((double*)rownrm)[i] = q;
+        for (int off = 1; off < G; off <<= 1) {
+            s += __shfl_xor(s, off);
+            q += __shfl_xor(q, off);
+        }
+        if (valid && l == 0) {
+            ((double*)rowsum)[i] = s;
+            ((double*)rownrm)[i] = q;
+        }
     } else {
-        // wrapping int64: exact modulo 2^64
         uint64_t s = 0, q = 0;
-        for (int32_t k = 0; k < d; ++k) {
-            int64_t v = (int64_t)I::conv(xi[k], bad);
-            uint64_t vp = (uint64_t)v;
-            for (int e = 1; e < p; ++e) vp *= (uint64_t)v;
-            s += vp;
-            q += (uint64_t)v * (uint64_t)v;
+        if (valid) {
+            for (int32_t k = l; k < d; k += G) {
+                const int64_t v = (int64_t)I::conv(xi[k], bad);
+                uint64_t vp = (uint64_t)v;
+                for (int e = 1; e < p; ++e) vp *= (uint64_t)v;
+                s += vp;
+                q += (uint64_t)v * (uint64_t)v;
+            }
         }
-        ((int64_t*)rowsum)[i] = (int64_t)s;
-        ((int64_t*)rownrm)[i] = (int64_t)q;
+        for (int off = 1; off < G; off <<= 1) {
+            s += (uint64_t)__shfl_xor((unsigned long long)s, off);
+            q += (uint64_t)__shfl_xor((unsigned long long)q, off);
+        }
+        if (valid && l == 0) {
+            ((int64_t*)rowsum)[i] = (int64_t)s;
+            ((int64_t*)rownrm)[i] = (int64_t)q;
+        }
     }
 }
 
@@ -211,12 +230,17 @@ hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d, 
 hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d, void* rowsum, void* rownrm,
                             hipStream_t s, int p)
 {
-    unsigned grid = (unsigned)((n + 255) / 256);
+    if (n < 1 || d < 1) return hipErrorInvalidValue;
+    // lanes per row: the power of two nearest above d / 4, at most 64
+    int lg = 0;
+    while ((1 << lg) < 64 && (int64_t)(1 << lg) * 4 < d) ++lg;
+    const int64_t threads = n << lg;
+    const unsigned grid = (unsigned)((threads + 255) / 256);
     switch (kind) {
-    case IN_F32: row_stats_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, p, rowsum, rownrm); break;
-    case IN_F64: row_stats_kernel<IN_F64><<<grid, 256, 0, s>>>((const double*)X, n, d, p, rowsum, rownrm); break;
-    case IN_I32: row_stats_kernel<IN_I32><<<grid, 256, 0, s>>>((const int32_t*)X, n, d, p, rowsum, rownrm); break;
-    case IN_I64: row_stats_kernel<IN_I64><<<grid, 256, 0, s>>>((const int64_t*)X, n, d, p, rowsum, rownrm); break;
+    case IN_F32: row_stats_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, p, lg, rowsum, rownrm); break;
+    case IN_F64: row_stats_kernel<IN_F64><<<grid, 256, 0, s>>>((const double*)X, n, d, p, lg, rowsum, rownrm); break;
+    case IN_I32: row_stats_kernel<IN_I32><<<grid, 256, 0, s>>>((const int32_t*)X, n, d, p, lg, rowsum, rownrm); break;
+    case IN_I64: row_stats_kernel<IN_I64><<<grid, 256, 0, s>>>((const int64_t*)X, n, d, p, lg, rowsum, rownrm); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
