@@ -67,8 +67,17 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_count_kernel(
     __syncthreads();
     TileRange r = tile_range(tb, blockIdx.x);
     const uint32_t* k = keys + r.base;
-    for (int i = threadIdx.x; i < r.count; i += SORT_THREADS)
-        atomicAdd(&h[w][(k[i] >> shift) & 255u], 1u);
+    if (r.count == SORT_TILE) {
+        // a full tile: all KPT keys of the thread are loaded before any count
+        uint32_t kv[KPT];
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) kv[q] = k[q * SORT_THREADS + threadIdx.x];
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) atomicAdd(&h[w][(kv[q] >> shift) & 255u], 1u);
+    } else {
+        for (int i = threadIdx.x; i < r.count; i += SORT_THREADS)
+            atomicAdd(&h[w][(k[i] >> shift) & 255u], 1u);
+    }
     __syncthreads();
     const int v = threadIdx.x;
     counts[(size_t)blockIdx.x * 256 + v] = h[0][v] + h[1][v] + h[2][v] + h[3][v];
@@ -82,11 +91,31 @@ __global__ __launch_bounds__(256) void sort_scan_kernel(uint32_t* __restrict__ c
     const uint32_t s = blockIdx.x;
     const uint32_t t0 = tb.tile_off[s], t1 = tb.tile_off[s + 1];
     const int v = threadIdx.x;
+    // batches of 8 tiles: 8 independent loads in flight per thread
+    constexpr uint32_t B = 8;
     uint32_t total = 0;
-    for (uint32_t t = t0; t < t1; ++t) total += counts[(size_t)t * 256 + v];
+    uint32_t t = t0;
+    for (; t + B <= t1; t += B) {
+        uint32_t c[B];
+#pragma unroll
+        for (uint32_t q = 0; q < B; ++q) c[q] = counts[(size_t)(t + q) * 256 + v];
+#pragma unroll
+        for (uint32_t q = 0; q < B; ++q) total += c[q];
+    }
+    for (; t < t1; ++t) total += counts[(size_t)t * 256 + v];
     uint32_t run = (uint32_t)tb.key_off[s] + block_excl_scan_256(total, s_wave);
-    for (uint32_t t = t0; t < t1; ++t) {
-        uint32_t c = counts[(size_t)t * 256 + v];
+    for (t = t0; t + B <= t1; t += B) {
+        uint32_t c[B];
+#pragma unroll
+        for (uint32_t q = 0; q < B; ++q) c[q] = counts[(size_t)(t + q) * 256 + v];
+#pragma unroll
+        for (uint32_t q = 0; q < B; ++q) {
+            counts[(size_t)(t + q) * 256 + v] = run;
+            run += c[q];
+        }
+    }
+    for (; t < t1; ++t) {
+        const uint32_t c = counts[(size_t)t * 256 + v];
         counts[(size_t)t * 256 + v] = run;
         run += c;
     }
