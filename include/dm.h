@@ -217,7 +217,10 @@ dm_status dm_info(const dm_handle* h, int64_t* n, int32_t* d, int32_t* metric, i
 /*
  * Copy the preparation results of a sorted-metric handle into caller device buffers
  * (any may be NULL): perm and rank are d x n uint32, xs is d x n float (float
- * data) or int32 (integer data).  Stream-ordered.  Errors: DM_ERR_ARG,
+ * data) or int32 (integer data).  perm[k][r] is the point at rank r of
+ * coordinate k (ties by ascending point id, Algorithm 1); rank[k][i] is the
+ * rank of point i (the positions Algorithm 2 looks up), formed from perm by a
+ * kernel on this call, since queries never read it.  Stream-ordered.  Errors: DM_ERR_ARG,
  * DM_ERR_STATE for a handle of a metric that does not sort (l2 squared and
  * the sort-free metrics).
  */

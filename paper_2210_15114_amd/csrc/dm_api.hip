@@ -62,7 +62,7 @@ constexpr int32_t MAX_B = 64;
 struct Layout {
     int64_t ld = 0;         // stride between coordinates of the d x n arrays
     uint32_t ntiles = 0;    // sort tiles
-    size_t perm = 0, xs = 0, rank = 0, rowsum = 0, rownrm = 0, xcopy = 0, kmin = 0, kmax = 0, flags = 0;
+    size_t perm = 0, xs = 0, ids = 0, rowsum = 0, rownrm = 0, xcopy = 0, kmin = 0, kmax = 0, flags = 0;
     size_t centre = 0, mat = 0;   // per-coordinate centre; M and W (d x d each) of the quadratic forms
     size_t logx = 0;              // FP64 logarithms of the points (KL divergence, cross entropy)
     size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0;
@@ -84,7 +84,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t metric) {
         L.ntiles = (uint32_t)((size_t)d * (size_t)((n + SORT_TILE - 1) / SORT_TILE));
         L.perm = take(arr);
         L.xs = take(arr);
-        L.rank = take(arr);
+        L.ids = take(arr);   // point ids of the middle sort passes
     }
     // a row-major FP32 / int32 copy of X: for the l2-squared products and for
     // the per-coordinate moments of odd p
@@ -431,7 +431,7 @@ dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
     tb.ntiles = L.ntiles;
 
     uint32_t* K0 = h->at<uint32_t>(L.xs);     // keys after transposition; becomes xs
-    uint32_t* V0 = h->at<uint32_t>(L.rank);   // ids after pass 1; becomes rank
+    uint32_t* V0 = h->at<uint32_t>(L.ids);   // point ids after pass 2
     uint32_t* K1 = h->at<uint32_t>(L.k1);
     uint32_t* V1 = h->at<uint32_t>(L.v1);
     uint32_t* perm = h->at<uint32_t>(L.perm);
@@ -449,8 +449,8 @@ dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
         const int shift = 8 * pass;
         DM_TRY(launch_sort_count(kin[pass], counts, tb, shift, s));
         DM_TRY(launch_sort_scan(counts, tb, s));
-        DM_TRY(launch_sort_scatter(kin[pass], vin[pass], kout[pass], vout[pass], pass == 3 ? V0 : nullptr, counts,
-                                   tb, shift, pass == 0, pass == 3, h->is_int, s));
+        DM_TRY(launch_sort_scatter(kin[pass], vin[pass], kout[pass], vout[pass], counts, tb, shift, pass == 0,
+                                   pass == 3, h->is_int, s));
     }
     return DM_OK;
 }
@@ -1091,7 +1091,8 @@ dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, voi
     hipStream_t s = (hipStream_t)stream;
     const size_t w = (size_t)h->n * 4, sp = (size_t)h->L.ld * 4;
     if (perm) DM_TRY(hipMemcpy2DAsync(perm, w, h->ws + h->L.perm, sp, w, h->d, hipMemcpyDeviceToDevice, s));
-    if (rank) DM_TRY(hipMemcpy2DAsync(rank, w, h->ws + h->L.rank, sp, w, h->d, hipMemcpyDeviceToDevice, s));
+    // the inverse permutations are formed on request (no query reads them)
+    if (rank) DM_TRY(launch_rank_invert(h->at<uint32_t>(h->L.perm), h->L.ld, h->n, h->d, rank, h->n, s));
     if (xs) DM_TRY(hipMemcpy2DAsync(xs, w, h->ws + h->L.xs, sp, w, h->d, hipMemcpyDeviceToDevice, s));
     return DM_OK;
 }
@@ -1170,7 +1171,7 @@ struct MultiPlan {
 };
 
 struct MultiLayout {
-    size_t perm = 0, xs = 0, rank = 0, k1 = 0, v1 = 0, counts = 0, flags = 0;
+    size_t perm = 0, xs = 0, ids = 0, k1 = 0, v1 = 0, counts = 0, flags = 0;
     size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0, seg_int = 0;
     int64_t total_keys = 0;
     uint32_t ntiles = 0;
@@ -1234,7 +1235,7 @@ dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSe
     const size_t arr = (size_t)keys * 4;
     M.perm = take(arr);
     M.xs = take(arr);
-    M.rank = take(arr);
+    M.ids = take(arr);
     int32_t nseg = 0;
     uint32_t ntiles = 0;
     for (auto& m : v) {
@@ -1472,7 +1473,7 @@ dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspac
         tb.nseg = L.nseg;
         tb.ntiles = L.ntiles;
         uint32_t* K0 = h->at<uint32_t>(L.xs);
-        uint32_t* V0 = h->at<uint32_t>(L.rank);
+        uint32_t* V0 = h->at<uint32_t>(L.ids);
         uint32_t* K1 = h->at<uint32_t>(L.k1);
         uint32_t* V1 = h->at<uint32_t>(L.v1);
         uint32_t* perm = h->at<uint32_t>(L.perm);
@@ -1485,8 +1486,8 @@ dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspac
             const int shift = 8 * pass;
             if (launch_sort_count(kin[pass], counts, tb, shift, s) != hipSuccess ||
                 launch_sort_scan(counts, tb, s) != hipSuccess ||
-                launch_sort_scatter(kin[pass], vin[pass], kout[pass], vout[pass], pass == 3 ? V0 : nullptr, counts,
-                                    tb, shift, pass == 0, pass == 3, false, s) != hipSuccess)
+                launch_sort_scatter(kin[pass], vin[pass], kout[pass], vout[pass], counts, tb, shift, pass == 0,
+                                    pass == 3, false, s) != hipSuccess)
                 return fail(DM_ERR_DEVICE);
         }
     }

@@ -66,8 +66,11 @@ hipError_t launch_sort_count(const uint32_t* keys, uint32_t* counts, const SegTa
                              hipStream_t s);
 hipError_t launch_sort_scan(uint32_t* counts, const SegTables& t, hipStream_t s);
 hipError_t launch_sort_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                               uint32_t* rank_out, const uint32_t* offs, const SegTables& t, int shift,
-                               bool first, bool last, bool is_int, hipStream_t s);
+                               const uint32_t* offs, const SegTables& t, int shift, bool first, bool last,
+                               bool is_int, hipStream_t s);
+// rank[k * pitch + perm[k * ld + r]] = r for r < n, k < d (the inverse permutations)
+hipError_t launch_rank_invert(const uint32_t* perm, int64_t ld, int64_t n, int32_t d, uint32_t* rank, int64_t pitch,
+                              hipStream_t s);
 
 // ---- l1 query --------------------------------------------------------------
 // totals: T0[c] = sum_j z_jc, U[c] = sum_j w_j z_jc, |z_c|_1; with guards.

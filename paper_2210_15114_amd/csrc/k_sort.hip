@@ -10,8 +10,9 @@
 //             (keys of one wave that share a digit find each other with 8
 //             ballots; their order inside the group is the lane order), the
 //             tile reordered in LDS, then written out in digit runs.
-// The final pass writes the sorted values, the permutation and its inverse
-// (the rank array Algorithm 2 looks positions up in) directly.
+// The final pass writes the sorted values and the permutation.  Its inverse
+// (the rank array Algorithm 2 looks positions up in) is formed on request by
+// rank_invert_kernel: the query scatters through perm and never reads it.
 #include "dm_device.h"
 #include "dm_internal.h"
 
@@ -121,11 +122,22 @@ __global__ __launch_bounds__(256) void sort_scan_kernel(uint32_t* __restrict__ c
     }
 }
 
+// rank[k][perm[k][r]] = r: the position of each point in coordinate k's sorted
+// order (the inverse permutation), one coordinate per grid row
+__global__ __launch_bounds__(256) void rank_invert_kernel(const uint32_t* __restrict__ perm, int64_t ld, int64_t n,
+                                                          uint32_t* __restrict__ rank, int64_t pitch)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const int64_t k = blockIdx.y;
+    rank[k * pitch + perm[k * ld + r]] = (uint32_t)r;
+}
+
 template <bool FIRST, bool LAST, bool IS_INT>
 __global__ __launch_bounds__(SORT_THREADS) void sort_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t* __restrict__ rank_out,
-    const uint32_t* __restrict__ offs, SegTables tb, int shift)
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ offs, SegTables tb,
+    int shift)
 {
     __shared__ uint32_t s_keys[SORT_TILE];
     __shared__ uint32_t s_vals[SORT_TILE];
@@ -198,9 +210,8 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_scatter_kernel(
         if (LAST) {
             const bool as_int = tb.seg_int ? tb.seg_int[r.seg] != 0 : IS_INT;
             uint32_t bits = as_int ? (uint32_t)key_i32(k) : __float_as_uint(key_f32(k));
-            kout[gpos] = bits;                                        // sorted values
-            vout[gpos] = v;                                           // permutation
-            rank_out[r.seg_base + v] = gpos - (uint32_t)r.seg_base;   // its inverse
+            kout[gpos] = bits;   // sorted values
+            vout[gpos] = v;      // permutation
         } else {
             kout[gpos] = k;
             vout[gpos] = v;
@@ -224,18 +235,26 @@ hipError_t launch_sort_scan(uint32_t* counts, const SegTables& t, hipStream_t s)
 }
 
 hipError_t launch_sort_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                               uint32_t* rank_out, const uint32_t* offs, const SegTables& t, int shift,
-                               bool first, bool last, bool is_int, hipStream_t s)
+                               const uint32_t* offs, const SegTables& t, int shift, bool first, bool last,
+                               bool is_int, hipStream_t s)
 {
-#define DM_SCATTER(F, L, I)                                                                          \
-    sort_scatter_kernel<F, L, I><<<t.ntiles, SORT_THREADS, 0, s>>>(kin, vin, kout, vout, rank_out, offs, \
-                                                                 t, shift)
+#define DM_SCATTER(F, L, I) \
+    sort_scatter_kernel<F, L, I><<<t.ntiles, SORT_THREADS, 0, s>>>(kin, vin, kout, vout, offs, t, shift)
     if (first && last) return hipErrorInvalidValue;   // four passes always
     if (first) DM_SCATTER(true, false, false);
     else if (!last) DM_SCATTER(false, false, false);
     else if (is_int) DM_SCATTER(false, true, true);
     else DM_SCATTER(false, true, false);
 #undef DM_SCATTER
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_invert(const uint32_t* perm, int64_t ld, int64_t n, int32_t d, uint32_t* rank, int64_t pitch,
+                              hipStream_t s)
+{
+    if (n < 1 || d < 1 || ld < n || pitch < n) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)d);
+    rank_invert_kernel<<<grid, 256, 0, s>>>(perm, ld, n, rank, pitch);
     return hipGetLastError();
 }
 
