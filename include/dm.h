@@ -167,14 +167,17 @@ dm_status dm_prepare_matrix(const void* X, int64_t n, int32_t d, int32_t metric,
  * integer data).  Out: device n x b, float or int64.  Z and Out must not
  * overlap.  1 <= b <= 64.
  * Stream-ordered and asynchronous.  The library may grow per-handle scratch
- * memory on the first call with a larger b (see dm_reserve).
+ * memory on the first call with a larger b, and allocates the group buffer of
+ * single-column l1 / TV queries (per-coordinate values of up to 64 MiB worth of
+ * coordinates, at least one) on the first such query (see dm_reserve).
  * Errors (synchronous): DM_ERR_ARG, DM_ERR_DTYPE, DM_ERR_NOMEM, DM_ERR_DEVICE.
  * Errors (sticky, via dm_sync): DM_ERR_NONFINITE, DM_ERR_OVERFLOW.
  */
 dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream);
 
-/* Pre-size the per-handle query scratch for right-hand-side counts up to b, so
- * that later dm_matvec calls allocate nothing.  Errors: DM_ERR_ARG, DM_ERR_NOMEM. */
+/* Pre-size the per-handle query scratch for right-hand-side counts up to b
+ * (and, for l1 and TV, the single-column group buffer), so that later
+ * dm_matvec calls allocate nothing.  Errors: DM_ERR_ARG, DM_ERR_NOMEM. */
 dm_status dm_reserve(dm_handle* h, int32_t b);
 
 /*
