@@ -467,9 +467,11 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
     const int k0 = blockIdx.y * 64;
     const int kq = k0 + 4 * m, cq = 4 * m;
     const bool kin = kq < d, cin = cq < b;
+    // centres apply to FP32 coordinates only (the stored logarithms have none)
+    constexpr bool CEN = sizeof(XT) == 4;
     double cen[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) cen[t] = (centre && kin) ? centre[kq + t] : 0.0;
+    for (int t = 0; t < 4; ++t) cen[t] = (CEN && centre && kin) ? centre[kq + t] : 0.0;
     d4v acc[4][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -477,17 +479,42 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
         for (int u = 0; u < 4; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
     const int64_t r0 = xw * rows_per_wave;
     const int64_t r1 = r0 + rows_per_wave < n ? r0 + rows_per_wave : n;
-    for (int64_t j0 = r0; j0 < r1; j0 += 4) {   // the same trip count on every lane
-        const int64_t j = j0 + g;
-        double a[4] = {0.0, 0.0, 0.0, 0.0}, z[4] = {0.0, 0.0, 0.0, 0.0};
+    // raw values of one row step; the next step's are loaded before this
+    // step's products
+    XT xn[4] = {XT(0), XT(0), XT(0), XT(0)};
+    float zn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto fetch = [&](int64_t j) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) { xn[t] = XT(0); zn[t] = 0.0f; }
         if (j < r1) {
             if (kin) {
-                load4<XT>(X + j * d + kq, a);
+                if constexpr (sizeof(XT) == 4) {
+                    const Vec<XT, 4> q = *reinterpret_cast<const Vec<XT, 4>*>(X + j * d + kq);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) a[t] -= cen[t];
+                    for (int t = 0; t < 4; ++t) xn[t] = q.v[t];
+                } else {
+                    const Vec<XT, 2> q0 = *reinterpret_cast<const Vec<XT, 2>*>(X + j * d + kq);
+                    const Vec<XT, 2> q1 = *reinterpret_cast<const Vec<XT, 2>*>(X + j * d + kq + 2);
+                    xn[0] = q0.v[0]; xn[1] = q0.v[1]; xn[2] = q1.v[0]; xn[3] = q1.v[1];
+                }
             }
-            if (cin) load4<float>(Z + j * b + cq, z);
+            if (cin) {
+                const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(Z + j * b + cq);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) zn[t] = q.v[t];
+            }
         }
+    };
+    fetch(r0 + g);
+    for (int64_t j0 = r0; j0 < r1; j0 += 4) {   // the same trip count on every lane
+        const int64_t j = j0 + g;
+        double a[4], z[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            a[t] = (j < r1 && kin) ? (CEN ? (double)xn[t] - cen[t] : (double)xn[t]) : 0.0;
+            z[t] = (double)zn[t];
+        }
+        if (j0 + 4 < r1) fetch(j + 4);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
