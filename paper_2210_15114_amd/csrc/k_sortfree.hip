@@ -668,17 +668,36 @@ __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restr
         for (int u = 0; u < 4; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
-    // two 4-row steps per iteration: both steps' loads are issued before the products
-    for (int64_t j0 = r0; j0 < r1; j0 += 8) {   // the same trip count on every lane
-        double x[2] = {0.0, 0.0}, z[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    // two 4-row steps per iteration; the next iteration's raw values are
+    // loaded before this iteration's products
+    float xn[2], zn[2][4];
+    auto fetch = [&](int64_t j0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t j = j0 + 4 * h + g;
+            xn[h] = 0.0f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) zn[h][u] = 0.0f;
             if (j < r1) {
-                if (kin) x[h] = (double)X[j * d + k];
-                if (cin) load4<float>(Z + j * b + 4 * m, z[h]);
+                if (kin) xn[h] = X[j * d + k];
+                if (cin) {
+                    const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(Z + j * b + 4 * m);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) zn[h][u] = q.v[u];
+                }
             }
         }
+    };
+    fetch(r0);
+    for (int64_t j0 = r0; j0 < r1; j0 += 8) {   // the same trip count on every lane
+        double x[2], z[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            x[h] = (double)xn[h];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) z[h][u] = (double)zn[h][u];
+        }
+        if (j0 + 8 < r1) fetch(j0 + 8);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const double xh = (j0 + 4 * h + g < r1 && kin) ? x[h] - ck : 0.0;
