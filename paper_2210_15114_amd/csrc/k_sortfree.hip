@@ -591,24 +591,37 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
 #pragma unroll
             for (int u = 0; u < CT; ++u) acc[q][u] = d4v{0.0, 0.0, 0.0, 0.0};
         float xn[NTL][4];
+        double cn[4];   // centres of the lane's 4 coordinates of the chunk, fetched with X
+        auto load_centre = [&](int k0) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + 4 * g + s;
+                cn[s] = (centre && k < d) ? centre[k] : 0.0;
+            }
+        };
 #pragma unroll
         for (int q = 0; q < NTL; ++q) load_chunk(i0 + 16 * q + m, 0, xn[q]);
+        load_centre(0);
         for (int k0 = 0; k0 < d; k0 += 16) {
             float xv[NTL][4];
+            double cv[4];
 #pragma unroll
             for (int q = 0; q < NTL; ++q)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) xv[q][s] = xn[q][s];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) cv[s] = cn[s];
             if (k0 + 16 < d) {
 #pragma unroll
                 for (int q = 0; q < NTL; ++q) load_chunk(i0 + 16 * q + m, k0 + 16, xn[q]);
+                load_centre(k0 + 16);
             }
             const int kq = k0 + 4 * g;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int k = kq + s;
                 const bool kin = k < d;
-                const double ck = (kin && centre) ? centre[k] : 0.0;
+                const double ck = cv[s];
                 double vb[CT];
 #pragma unroll
                 for (int u = 0; u < CT; ++u) {
