@@ -142,7 +142,7 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_scatter_kernel(
     __shared__ uint32_t s_keys[SORT_TILE];
     __shared__ uint32_t s_vals[SORT_TILE];
     __shared__ uint32_t s_wcnt[WAVES][256];
-    __shared__ uint32_t s_start[256];
+    __shared__ uint32_t s_base[256];   // output position of tile index 0 for each digit (mod 2^32)
     __shared__ uint32_t s_wave[4];
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -183,7 +183,8 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_scatter_kernel(
         const int v = threadIdx.x;
         const uint32_t c0 = s_wcnt[0][v], c1 = s_wcnt[1][v], c2 = s_wcnt[2][v], c3 = s_wcnt[3][v];
         const uint32_t start = block_excl_scan_256(c0 + c1 + c2 + c3, s_wave);
-        s_start[v] = start;
+        // the tile's keys of digit v sit at start .. in LDS and go to offs[v] ..
+        s_base[v] = offs[(size_t)blockIdx.x * 256 + v] - start;
         s_wcnt[0][v] = start;
         s_wcnt[1][v] = start + c0;
         s_wcnt[2][v] = start + c0 + c1;
@@ -201,14 +202,13 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_scatter_kernel(
         }
     }
     __syncthreads();
-    const uint32_t* o = offs + (size_t)blockIdx.x * 256;
+    const bool as_int = LAST && (tb.seg_int ? tb.seg_int[r.seg] != 0 : IS_INT);
     for (int i = threadIdx.x; i < r.count; i += SORT_THREADS) {
         const uint32_t k = s_keys[i];
         const uint32_t v = s_vals[i];
         const uint32_t dig = (k >> shift) & 255u;
-        const uint32_t gpos = o[dig] + (uint32_t)i - s_start[dig];
+        const uint32_t gpos = s_base[dig] + (uint32_t)i;
         if (LAST) {
-            const bool as_int = tb.seg_int ? tb.seg_int[r.seg] != 0 : IS_INT;
             uint32_t bits = as_int ? (uint32_t)key_i32(k) : __float_as_uint(key_f32(k));
             kout[gpos] = bits;   // sorted values
             vout[gpos] = v;      // permutation
