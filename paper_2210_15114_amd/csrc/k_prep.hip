@@ -50,9 +50,12 @@ template <> struct In<IN_I64> {
 
 constexpr int TT = 64;  // transpose tile: 64 rows x 64 coordinates
 
-// One 64 x 64 tile of X: validates it, writes its keys coordinate-major
-// (coalesced both ways through LDS), its FP32/int32 copy row-major, and folds
-// the tile's per-coordinate min/max keys into kmin/kmax.
+// RT consecutive 64 x 64 tiles of X (rows r0 .., coordinates c0 .. +63) per
+// workgroup: validates them, writes their keys coordinate-major (coalesced
+// both ways through LDS) and their FP32/int32 copy row-major, and folds the
+// per-coordinate min/max keys of all RT tiles into kmin/kmax with one atomic
+// per coordinate (one per tile contended heavily on the d addresses).
+constexpr int RT = 16;
 template <int KIND>
 __global__ __launch_bounds__(256) void prep_transpose_kernel(
     const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d,
@@ -62,22 +65,34 @@ __global__ __launch_bounds__(256) void prep_transpose_kernel(
     using I = In<KIND>;
     __shared__ uint32_t tile[TT][TT + 1];
     __shared__ uint32_t smin[4][TT], smax[4][TT];
-    const int64_t r0 = (int64_t)blockIdx.x * TT;
     const int32_t c0 = blockIdx.y * TT;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int32_t col = c0 + tx;
     uint32_t bad = 0, lo = 0xffffffffu, hi = 0u;
-    for (int rr = ty; rr < TT; rr += 4) {
-        int64_t row = r0 + rr;
-        uint32_t k = 0;
-        if (row < n && col < d) {
-            typename I::V v = I::conv(X[row * d + col], bad);
-            if (xcopy) xcopy[row * d + col] = v;
-            k = I::key(v);
-            lo = min(lo, k);
-            hi = max(hi, k);
+    for (int q = 0; q < RT; ++q) {
+        const int64_t r0 = ((int64_t)blockIdx.x * RT + q) * TT;
+        if (r0 >= n) break;   // the same on every thread
+        __syncthreads();      // the previous tile has been written out
+        for (int rr = ty; rr < TT; rr += 4) {
+            int64_t row = r0 + rr;
+            uint32_t k = 0;
+            if (row < n && col < d) {
+                typename I::V v = I::conv(X[row * d + col], bad);
+                if (xcopy) xcopy[row * d + col] = v;
+                k = I::key(v);
+                lo = min(lo, k);
+                hi = max(hi, k);
+            }
+            tile[rr][tx] = k;
         }
-        tile[rr][tx] = k;
+        __syncthreads();
+        if (keys) {
+            for (int cc = ty; cc < TT; cc += 4) {
+                int32_t c = c0 + cc;
+                int64_t row = r0 + tx;
+                if (c < d && row < n) keys[(int64_t)c * ld + row] = tile[tx][cc];
+            }
+        }
     }
     smin[ty][tx] = lo;
     smax[ty][tx] = hi;
@@ -88,13 +103,6 @@ __global__ __launch_bounds__(256) void prep_transpose_kernel(
         uint32_t b = max(max(smax[0][tx], smax[1][tx]), max(smax[2][tx], smax[3][tx]));
         atomicMin(kmin + col, a);
         atomicMax(kmax + col, b);
-    }
-    if (keys) {
-        for (int cc = ty; cc < TT; cc += 4) {
-            int32_t c = c0 + cc;
-            int64_t row = r0 + tx;
-            if (c < d && row < n) keys[(int64_t)c * ld + row] = tile[tx][cc];
-        }
     }
 }
 
@@ -203,7 +211,7 @@ hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d, 
                                  int64_t ld, void* xcopy, uint32_t* kmin, uint32_t* kmax, uint32_t* flags,
                                  hipStream_t s)
 {
-    dim3 grid((unsigned)((n + TT - 1) / TT), (unsigned)((d + TT - 1) / TT));
+    dim3 grid((unsigned)((n + (int64_t)TT * RT - 1) / ((int64_t)TT * RT)), (unsigned)((d + TT - 1) / TT));
     switch (kind) {
     case IN_F32:
         prep_transpose_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, keys, ld, (float*)xcopy,
