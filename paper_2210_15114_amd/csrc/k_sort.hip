@@ -73,8 +73,26 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_count_kernel(
         uint32_t kv[KPT];
 #pragma unroll
         for (int q = 0; q < KPT; ++q) kv[q] = k[q * SORT_THREADS + threadIdx.x];
+        if (shift == 24) {
+            // the top digit (sign and exponent bits of float keys) takes few
+            // values, so the lanes of a wave that share a digit find each
+            // other with 8 ballots and only the first adds their count
 #pragma unroll
-        for (int q = 0; q < KPT; ++q) atomicAdd(&h[w][(kv[q] >> shift) & 255u], 1u);
+            for (int q = 0; q < KPT; ++q) {
+                const uint32_t dig = (kv[q] >> shift) & 255u;
+                uint64_t peers = ~0ull;   // a full tile: every lane holds a key
+#pragma unroll
+                for (int bit = 0; bit < 8; ++bit) {
+                    const bool on = (dig >> bit) & 1u;
+                    const uint64_t bb = __ballot(on);
+                    peers &= on ? bb : ~bb;
+                }
+                if (mask_rank(peers) == 0) atomicAdd(&h[w][dig], (uint32_t)__popcll(peers));
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) atomicAdd(&h[w][(kv[q] >> shift) & 255u], 1u);
+        }
     } else {
         for (int i = threadIdx.x; i < r.count; i += SORT_THREADS)
             atomicAdd(&h[w][(k[i] >> shift) & 255u], 1u);
