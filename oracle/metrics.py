@@ -24,9 +24,13 @@ def frob_l2sq(X) -> float:
 
     With a_i = ||x_i||^2 and G = X X^T, A = a 1^T + 1 a^T - 2G, so
     ||A||_F^2 = 2n sum a_i^2 + 2 (sum a_i)^2 + 4 ||X^T X||_F^2 - 8 a^T X (X^T 1).
-    (The decomposition is the one of Section 1.2.)
+    (The decomposition is the one of Section 1.2.)  A is unchanged by a
+    translation of the points, so the sums are formed on X minus its column
+    means: their cancellation then scales with the spread of the points, not
+    with their distance from the origin.
     """
     X = np.asarray(X, dtype=np.float64)
+    X = X - X.mean(axis=0)[None, :]
     n = X.shape[0]
     a = np.einsum("ij,ij->i", X, X)
     g = X.T @ X

@@ -63,7 +63,8 @@ struct Layout {
     int64_t ld = 0;         // stride between coordinates of the d x n arrays
     uint32_t ntiles = 0;    // sort tiles
     size_t perm = 0, xs = 0, ids = 0, rowsum = 0, rownrm = 0, xcopy = 0, kmin = 0, kmax = 0, flags = 0;
-    size_t centre = 0, mat = 0;   // per-coordinate centre; M and W (d x d each) of the quadratic forms
+    size_t centre = 0, mat = 0;   // per-coordinate centre (FP64); M and W (d x d each) of the quadratic forms
+    size_t c32 = 0;               // per-coordinate FP32 centre of the sorted metrics and l2 squared
     size_t logx = 0;              // FP64 logarithms of the points (KL divergence, cross entropy)
     size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0;
     size_t k1 = 0, v1 = 0, counts = 0;
@@ -95,6 +96,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t metric) {
     L.kmax = take((size_t)d * 4);
     L.flags = take(16);
     L.centre = take((size_t)d * 8);
+    L.c32 = take((size_t)d * 4);
     if (matrix_metric(metric)) L.mat = take((size_t)d * d * 16);
     if (metric == DM_KL || metric == DM_CE) L.logx = take((size_t)n * d * 8);
     if (sorted_metric(metric)) {
@@ -427,6 +429,7 @@ dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
     tb.tile_off = h->at<uint32_t>(L.tile_off);
     tb.tile_seg = h->at<uint32_t>(L.tile_seg);
     tb.seg_int = nullptr;
+    tb.centre = h->is_int ? nullptr : h->at<float>(L.c32);
     tb.nseg = d;
     tb.ntiles = L.ntiles;
 
@@ -437,9 +440,13 @@ dm_status prepare_l1(dm_handle* h, const void* X, hipStream_t s) {
     uint32_t* perm = h->at<uint32_t>(L.perm);
     uint32_t* counts = h->at<uint32_t>(L.counts);
 
-    DM_TRY(launch_prep_transpose(h->dtype, X, n, d, K0, L.ld, lp_metric(h->metric) ? h->ws + L.xcopy : nullptr,
-                                 h->at<uint32_t>(L.kmin), h->at<uint32_t>(L.kmax), h->at<uint32_t>(L.flags), s));
-    DM_TRY(launch_row_stats(h->dtype, X, n, d, h->ws + L.rowsum, h->ws + L.rownrm, s, metric_power(h->metric)));
+    DM_TRY(launch_prep_transpose(h->dtype, X, n, d, K0, L.ld, nullptr, h->at<uint32_t>(L.kmin),
+                                 h->at<uint32_t>(L.kmax), h->at<uint32_t>(L.flags), s));
+    // float coordinates are shifted by their centres (exact) before anything
+    // is formed from them: sorted values, row statistics, the point copy
+    if (!h->is_int) DM_TRY(launch_centre(h->at<uint32_t>(L.kmin), h->at<uint32_t>(L.kmax), d, h->at<float>(L.c32), s));
+    DM_TRY(launch_row_stats(h->dtype, X, n, d, h->ws + L.rowsum, h->ws + L.rownrm, s, metric_power(h->metric),
+                            tb.centre, lp_metric(h->metric) ? h->ws + L.xcopy : nullptr));
 
     const uint32_t* kin[4] = {K0, K1, K0, K1};
     const uint32_t* vin[4] = {nullptr, V1, V0, V1};
@@ -597,7 +604,19 @@ static dm_status prepare_impl(const void* X, int64_t n, int32_t d, int32_t metri
 
     if (sorted_metric(metric)) {
         if ((st = prepare_l1(h, X, s)) != DM_OK) return fail(st);
+    } else if (metric == DM_L2SQ) {
+        // the point copy, squared norms and (float data) centres as for the
+        // sorted metrics; the l2-squared query sees only centred points
+        const float* c = h->is_int ? nullptr : h->at<float>(L.c32);
+        if (launch_prep_transpose(dtype, X, n, d, nullptr, 0, nullptr, h->at<uint32_t>(L.kmin),
+                                  h->at<uint32_t>(L.kmax), h->at<uint32_t>(L.flags), s) != hipSuccess ||
+            (c && launch_centre(h->at<uint32_t>(L.kmin), h->at<uint32_t>(L.kmax), d, h->at<float>(L.c32), s) !=
+                      hipSuccess) ||
+            launch_row_stats(dtype, X, n, d, h->ws + L.rowsum, h->ws + L.rownrm, s, 1, c, h->ws + L.xcopy) !=
+                hipSuccess)
+            return fail(DM_ERR_DEVICE);
     } else {
+        // the sort-free metrics keep the raw point copy (they centre in FP64 at use)
         if (launch_prep_transpose(dtype, X, n, d, nullptr, 0, h->ws + L.xcopy, h->at<uint32_t>(L.kmin),
                                   h->at<uint32_t>(L.kmax), h->at<uint32_t>(L.flags), s) != hipSuccess)
             return fail(DM_ERR_DEVICE);
@@ -1093,7 +1112,11 @@ dm_status dm_copy_sorted(const dm_handle* h, uint32_t* perm, uint32_t* rank, voi
     if (perm) DM_TRY(hipMemcpy2DAsync(perm, w, h->ws + h->L.perm, sp, w, h->d, hipMemcpyDeviceToDevice, s));
     // the inverse permutations are formed on request (no query reads them)
     if (rank) DM_TRY(launch_rank_invert(h->at<uint32_t>(h->L.perm), h->L.ld, h->n, h->d, rank, h->n, s));
-    if (xs) DM_TRY(hipMemcpy2DAsync(xs, w, h->ws + h->L.xs, sp, w, h->d, hipMemcpyDeviceToDevice, s));
+    if (xs) {
+        DM_TRY(hipMemcpy2DAsync(xs, w, h->ws + h->L.xs, sp, w, h->d, hipMemcpyDeviceToDevice, s));
+        // float values are kept relative to their coordinate's centre
+        if (!h->is_int) DM_TRY(launch_add_centre((float*)xs, h->n, h->d, h->n, h->at<float>(h->L.c32), s));
+    }
     return DM_OK;
 }
 
@@ -1150,6 +1173,7 @@ namespace {
 struct MultiSet {
     int64_t n = 0, ld = 0, base = 0;   // base: first key of the dataset in the concatenated arrays
     int32_t d = 0, dtype = 0;
+    int32_t seg0 = 0;                  // its first segment (coordinate 0) of the segmented sort
     bool is_int = false;
     size_t rowsum = 0, rownrm = 0, kmin = 0, kmax = 0;
     double guard = 0.0;
@@ -1173,6 +1197,7 @@ struct MultiPlan {
 struct MultiLayout {
     size_t perm = 0, xs = 0, ids = 0, k1 = 0, v1 = 0, counts = 0, flags = 0;
     size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0, seg_int = 0;
+    size_t centre = 0;             // per segment: FP32 centre of a float coordinate
     int64_t total_keys = 0;
     uint32_t ntiles = 0;
     int32_t nseg = 0;
@@ -1243,6 +1268,7 @@ dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSe
         m.rownrm = take((size_t)m.n * 8);
         m.kmin = take((size_t)m.d * 4);
         m.kmax = take((size_t)m.d * 4);
+        m.seg0 = nseg;
         nseg += m.d;
         ntiles += (uint32_t)m.d * (uint32_t)((m.n + SORT_TILE - 1) / SORT_TILE);
     }
@@ -1254,6 +1280,7 @@ dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSe
     M.tile_off = take((size_t)(nseg + 1) * 4);
     M.tile_seg = take((size_t)ntiles * 4);
     M.seg_int = take((size_t)nseg);
+    M.centre = take((size_t)nseg * 4);
     M.k1 = take(arr);
     M.v1 = take(arr);
     M.counts = take((size_t)ntiles * 256 * 4);
@@ -1432,10 +1459,15 @@ dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspac
         if (launch_fill_u32(h->at<uint32_t>(q.kmin), 0xffffffffu, (size_t)q.d, s) != hipSuccess ||
             launch_fill_u32(h->at<uint32_t>(q.kmax), 0u, (size_t)q.d, s) != hipSuccess)
             return fail(DM_ERR_DEVICE);
+        // float coordinates are shifted by their centres (exact) before the
+        // row sums and sorted values are formed from them
+        float* c = q.is_int ? nullptr : h->at<float>(L.centre) + q.seg0;
         if (launch_prep_transpose(q.dtype, sets[i].X, q.n, q.d, h->at<uint32_t>(L.xs) + q.base, q.ld, nullptr,
                                   h->at<uint32_t>(q.kmin), h->at<uint32_t>(q.kmax), h->at<uint32_t>(L.flags),
                                   s) != hipSuccess ||
-            launch_row_stats(q.dtype, sets[i].X, q.n, q.d, h->ws + q.rowsum, h->ws + q.rownrm, s) != hipSuccess)
+            (c && launch_centre(h->at<uint32_t>(q.kmin), h->at<uint32_t>(q.kmax), q.d, c, s) != hipSuccess) ||
+            launch_row_stats(q.dtype, sets[i].X, q.n, q.d, h->ws + q.rowsum, h->ws + q.rownrm, s, 1, c) !=
+                hipSuccess)
             return fail(DM_ERR_DEVICE);
     }
     // one segmented sort over every (dataset, coordinate) segment
@@ -1470,6 +1502,7 @@ dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspac
         tb.tile_off = h->at<uint32_t>(L.tile_off);
         tb.tile_seg = h->at<uint32_t>(L.tile_seg);
         tb.seg_int = h->at<uint8_t>(L.seg_int);
+        tb.centre = h->at<float>(L.centre);
         tb.nseg = L.nseg;
         tb.ntiles = L.ntiles;
         uint32_t* K0 = h->at<uint32_t>(L.xs);

@@ -46,6 +46,7 @@ struct SegTables {
     const uint32_t* tile_off;  // S + 1
     const uint32_t* tile_seg;  // T
     const uint8_t* seg_int;    // S (integer keys?) or NULL: all segments of one kind
+    const float* centre;       // S: subtracted from the sorted float values of a segment, or NULL
     int32_t nseg;
     uint32_t ntiles;
 };
@@ -56,8 +57,17 @@ hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d,
                                  void* xcopy /* n x d (4-byte) or NULL */,
                                  uint32_t* kmin, uint32_t* kmax, uint32_t* flags,
                                  hipStream_t s);
+// row sums of x~^p and squared norms of x~ (x~ = x - centre, float data with
+// centre != NULL; x otherwise); with xcopy != NULL also the values x~ as an
+// n x d FP32 (int32) copy
 hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d,
-                            void* rowsum /* n x 8B */, void* rownrm /* n x 8B */, hipStream_t s, int p = 1);
+                            void* rowsum /* n x 8B */, void* rownrm /* n x 8B */, hipStream_t s, int p = 1,
+                            const float* centre = nullptr, void* xcopy = nullptr);
+// centre[k] for float coordinates from their min/max keys: the FP32 midpoint
+// when x - c is exact for the whole range, else 0
+hipError_t launch_centre(const uint32_t* kmin, const uint32_t* kmax, int32_t d, float* centre, hipStream_t s);
+// xs[k * pitch + r] += centre[k], r < n, k < d
+hipError_t launch_add_centre(float* xs, int64_t n, int32_t d, int64_t pitch, const float* centre, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s);
 

@@ -106,15 +106,19 @@ __global__ __launch_bounds__(256) void prep_transpose_kernel(
     }
 }
 
-// Row statistics: rowsum[i] = sum_k x_ik^p (p = 1: the row sum; p odd >= 3:
-// the weights of the l_p^p query's constant term), rownrm[i] = sum_k x_ik^2.
+// Row statistics: rowsum[i] = sum_k x~_ik^p (p = 1: the row sum; p odd >= 3:
+// the weights of the l_p^p query's constant term), rownrm[i] = sum_k x~_ik^2,
+// where x~_ik = x_ik - c_k for float data with per-coordinate centres c (exact
+// in FP32, see centre_kernel) and x~ = x otherwise.  With xcopy set, the
+// FP32 (int32) values x~ are also written row-major (n x d).
 // G = 2^lg lanes share a row: lane l takes k = l, l + G, ... in ascending order
 // (each load instruction reads G consecutive values of the row), and the G
 // partial sums are then added by a fixed xor butterfly, so every FP64 sum is
 // reproducible.  Integer data runs in wrapping int64 (exact modulo 2^64).
 template <int KIND>
 __global__ __launch_bounds__(256) void row_stats_kernel(
-    const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d, int p, int lg, void* rowsum, void* rownrm)
+    const typename In<KIND>::T* __restrict__ X, int64_t n, int32_t d, int p, int lg, void* rowsum, void* rownrm,
+    const float* __restrict__ centre, typename In<KIND>::V* __restrict__ xcopy)
 {
     using I = In<KIND>;
     const int G = 1 << lg;
@@ -127,7 +131,10 @@ __global__ __launch_bounds__(256) void row_stats_kernel(
         double s = 0.0, q = 0.0;
         if (valid) {
             for (int32_t k = l; k < d; k += G) {
-                const double v = (double)I::conv(xi[k], bad);
+                float t = I::conv(xi[k], bad);
+                if (centre) t = t - centre[k];   // exact (Sterbenz)
+                if (xcopy) xcopy[i * d + k] = t;
+                const double v = (double)t;
                 double vp = v;
                 for (int e = 1; e < p; ++e) vp *= v;
                 s += vp;
@@ -146,7 +153,9 @@ __global__ __launch_bounds__(256) void row_stats_kernel(
         uint64_t s = 0, q = 0;
         if (valid) {
             for (int32_t k = l; k < d; k += G) {
-                const int64_t v = (int64_t)I::conv(xi[k], bad);
+                const int32_t t = I::conv(xi[k], bad);
+                if (xcopy) xcopy[i * d + k] = t;
+                const int64_t v = (int64_t)t;
                 uint64_t vp = (uint64_t)v;
                 for (int e = 1; e < p; ++e) vp *= (uint64_t)v;
                 s += vp;
@@ -162,6 +171,39 @@ __global__ __launch_bounds__(256) void row_stats_kernel(
             ((int64_t*)rownrm)[i] = (int64_t)q;
         }
     }
+}
+
+// Centres of float coordinates.  The terms the sorted query forms (x times a
+// prefix of z, prefix sums of x z, their totals) grow with |x|, while the
+// result only depends on differences of coordinates; for points far from the
+// origin (say 10^4 + U[0, 1)) FP32 would lose the differences to cancellation.
+// Every metric of the sorted path and l2 squared is invariant under
+// translating a coordinate, so the coordinate is shifted by c_k and nothing
+// else changes, provided x - c_k is exact for every x of the coordinate.  By
+// Sterbenz's lemma it is whenever c_k / 2 <= x <= 2 c_k (or the mirror image
+// for negative values): c_k is the FP32 midpoint of [min_k, max_k] when the
+// whole range satisfies that, else 0 (a range that reaches zero or spans a
+// factor of about three or more: there |x| <= 1.5 (max_k - min_k) already).
+__global__ void centre_kernel(const uint32_t* __restrict__ kmin, const uint32_t* __restrict__ kmax, int32_t d,
+                              float* __restrict__ centre)
+{
+    const int32_t k = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= d) return;
+    const float lo = key_f32(kmin[k]), hi = key_f32(kmax[k]);
+    const float m = 0.5f * lo + 0.5f * hi;
+    float c = 0.0f;
+    if (lo > 0.0f && m <= 2.0f * lo && hi <= 2.0f * m) c = m;
+    if (hi < 0.0f && m >= 2.0f * hi && lo >= 2.0f * m) c = m;
+    centre[k] = c;
+}
+
+// xs[k * pitch + r] += centre[k] for r < n: the sorted values of coordinate k
+// back in the caller's frame (exact: the stored value is x - c_k exactly)
+__global__ __launch_bounds__(256) void add_centre_kernel(float* __restrict__ xs, int64_t n, int64_t pitch,
+                                                         const float* __restrict__ centre)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r < n) xs[(int64_t)blockIdx.y * pitch + r] += centre[blockIdx.y];
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t count) {
@@ -236,7 +278,7 @@ hipError_t launch_prep_transpose(int kind, const void* X, int64_t n, int32_t d, 
 }
 
 hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d, void* rowsum, void* rownrm,
-                            hipStream_t s, int p)
+                            hipStream_t s, int p, const float* centre, void* xcopy)
 {
     if (n < 1 || d < 1) return hipErrorInvalidValue;
     // lanes per row: the power of two nearest above d / 4, at most 64
@@ -245,12 +287,39 @@ hipError_t launch_row_stats(int kind, const void* X, int64_t n, int32_t d, void*
     const int64_t threads = n << lg;
     const unsigned grid = (unsigned)((threads + 255) / 256);
     switch (kind) {
-    case IN_F32: row_stats_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, p, lg, rowsum, rownrm); break;
-    case IN_F64: row_stats_kernel<IN_F64><<<grid, 256, 0, s>>>((const double*)X, n, d, p, lg, rowsum, rownrm); break;
-    case IN_I32: row_stats_kernel<IN_I32><<<grid, 256, 0, s>>>((const int32_t*)X, n, d, p, lg, rowsum, rownrm); break;
-    case IN_I64: row_stats_kernel<IN_I64><<<grid, 256, 0, s>>>((const int64_t*)X, n, d, p, lg, rowsum, rownrm); break;
+    case IN_F32:
+        row_stats_kernel<IN_F32><<<grid, 256, 0, s>>>((const float*)X, n, d, p, lg, rowsum, rownrm, centre,
+                                                      (float*)xcopy);
+        break;
+    case IN_F64:
+        row_stats_kernel<IN_F64><<<grid, 256, 0, s>>>((const double*)X, n, d, p, lg, rowsum, rownrm, centre,
+                                                      (float*)xcopy);
+        break;
+    case IN_I32:
+        row_stats_kernel<IN_I32><<<grid, 256, 0, s>>>((const int32_t*)X, n, d, p, lg, rowsum, rownrm, nullptr,
+                                                      (int32_t*)xcopy);
+        break;
+    case IN_I64:
+        row_stats_kernel<IN_I64><<<grid, 256, 0, s>>>((const int64_t*)X, n, d, p, lg, rowsum, rownrm, nullptr,
+                                                      (int32_t*)xcopy);
+        break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_centre(const uint32_t* kmin, const uint32_t* kmax, int32_t d, float* centre, hipStream_t s)
+{
+    if (d < 1) return hipErrorInvalidValue;
+    centre_kernel<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(kmin, kmax, d, centre);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_centre(float* xs, int64_t n, int32_t d, int64_t pitch, const float* centre, hipStream_t s)
+{
+    if (n < 1 || d < 1 || pitch < n) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)d);
+    add_centre_kernel<<<grid, 256, 0, s>>>(xs, n, pitch, centre);
     return hipGetLastError();
 }
 

@@ -221,13 +221,15 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_scatter_kernel(
     }
     __syncthreads();
     const bool as_int = LAST && (tb.seg_int ? tb.seg_int[r.seg] != 0 : IS_INT);
+    // float segments are stored relative to their centre (exact, see centre_kernel)
+    const float cen = (LAST && !as_int && tb.centre) ? tb.centre[r.seg] : 0.0f;
     for (int i = threadIdx.x; i < r.count; i += SORT_THREADS) {
         const uint32_t k = s_keys[i];
         const uint32_t v = s_vals[i];
         const uint32_t dig = (k >> shift) & 255u;
         const uint32_t gpos = s_base[dig] + (uint32_t)i;
         if (LAST) {
-            uint32_t bits = as_int ? (uint32_t)key_i32(k) : __float_as_uint(key_f32(k));
+            uint32_t bits = as_int ? (uint32_t)key_i32(k) : __float_as_uint(key_f32(k) - cen);
             kout[gpos] = bits;   // sorted values
             vout[gpos] = v;      // permutation
         } else {

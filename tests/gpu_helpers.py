@@ -47,10 +47,43 @@ def float_errors(Xf32, Zf32, Y, metric, rows=None):
     return metrics.errors(Yr, o, rn, ad, Z64, frob), o
 
 
+def bound_ratio(err, bound):
+    """max(err / bound) over all entries, where a zero error against a zero
+    bound counts as 0 and a nonzero error against a zero bound as infinity
+    (a single point, or a constant coordinate, has an exact zero result)."""
+    err = np.abs(np.asarray(err, dtype=np.float64))
+    bound = np.broadcast_to(np.asarray(bound, dtype=np.float64), err.shape)
+    pos = bound > 0
+    r = np.where(pos, err / np.where(pos, bound, 1.0), np.where(err == 0, 0.0, np.inf))
+    return float(r.max()) if r.size else 0.0
+
+
+def centres(Xf32):
+    """The per-coordinate shift the library applies to float points before the
+    sorted and l2-squared queries form anything from them (its documented
+    rule): the FP32 midpoint m of [min, max] when every value x of the
+    coordinate has m/2 <= x <= 2m (or the mirror image for negative values),
+    so that x - m is exact in FP32 (Sterbenz), else 0."""
+    X = np.asarray(Xf32, dtype=np.float32)
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    half = np.float32(0.5)
+    m = half * lo + half * hi
+    two = np.float32(2.0)
+    ok = ((lo > 0) & (m <= two * lo) & (hi <= two * m)) | ((hi < 0) & (m >= two * hi) & (lo >= two * m))
+    return np.where(ok, m, np.float32(0.0)).astype(np.float32)
+
+
+def centred(Xf32):
+    """X - c (exact in FP32 by the choice of c)."""
+    X = np.asarray(Xf32, dtype=np.float32)
+    return X - centres(X)[None, :]
+
+
 def method_scale_l1(Xf32, Zf32, rows):
-    """sum_k (|x_ik| sum_j |z_j| + sum_j |x_jk z_j|): size of the terms the l1
-    method forms for row i (used to state its FP32 error bound)."""
-    X = np.abs(Xf32.astype(np.float64))
+    """sum_k (|x~_ik| sum_j |z_j| + sum_j |x~_jk z_j|): size of the terms the l1
+    method forms for row i (used to state its FP32 error bound), with x~ the
+    centred coordinates the method works on."""
+    X = np.abs(centred(Xf32).astype(np.float64))
     Z = np.abs(Zf32.astype(np.float64))
     if Z.ndim == 1:
         Z = Z[:, None]

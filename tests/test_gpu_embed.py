@@ -20,7 +20,7 @@ import synth
 from oracle import L1
 from oracle import approx_l2
 
-from gpu_helpers import U32, dev, float_errors, method_scale_l1
+from gpu_helpers import U32, bound_ratio, dev, float_errors, method_scale_l1
 
 pytestmark = pytest.mark.gpu
 dm = pytest.importorskip("paper_2210_15114_amd")
@@ -58,7 +58,7 @@ def test_approximate_l2_query():
     # (1) the query is the l1 path on the embedded points
     e, o = float_errors(Xe, Z, Y, L1)
     S = method_scale_l1(Xe, Z, np.arange(n))
-    ratio = float((np.abs(Y.astype(np.float64) - o) / ((8 + 3 * k) * U32 * S)).max())
+    ratio = bound_ratio(np.abs(Y.astype(np.float64) - o), ((8 + 3 * k) * U32 * S))
     print("l1 errors on X'", e, "bound-ratio", ratio)
     assert e["spec"] <= 1e-6 and ratio <= 1.0
     # (2) B approximates the Euclidean distance matrix A

@@ -4,7 +4,8 @@ benchmark times, on sampled rows that the FP64 oracle computes one by one.
 * single vector, n = 2^20 points, d = 64, 32-component Gaussian mixture, one
   z ~ N(0,1): l1 and l2-squared;
 * block of b = 64 columns, n = 2^22 points, d = 128, uniform [0,1) FP32:
-  l1 (the benchmarked pass) and l2-squared (matrix-core path);
+  l1 (the benchmarked pass) and l2-squared (matrix-core path; 256 rows
+  including the 16 points of largest norm);
 * 512 datasets of uneven n and d, float and integer, b = 8, one graph
   launch: every dataset checked (4 rows; all rows of the 16 smallest),
   integer datasets bit-exact, float datasets within the bounds.
@@ -21,7 +22,7 @@ import oracle
 import synth
 from oracle import L1, L2SQ
 
-from gpu_helpers import U32, dev, float_errors, method_scale_l1
+from gpu_helpers import U32, bound_ratio, centred, dev, float_errors, method_scale_l1
 
 pytestmark = pytest.mark.gpu
 dm = pytest.importorskip("paper_2210_15114_amd")
@@ -41,8 +42,9 @@ def _rows(X, m, seed):
 
 
 def _l2_scale(X32, Z32, rows):
-    """M_i of the l2-squared bound, for the given rows only."""
-    X = X32.astype(np.float64)
+    """M_i of the l2-squared bound, for the given rows only (on the centred
+    coordinates the method works with)."""
+    X = centred(X32).astype(np.float64)
     Z = np.abs(Z32.astype(np.float64)).reshape(X.shape[0], -1)
     nrm = np.einsum("ij,ij->i", X, X)
     t = np.abs(X).T @ Z
@@ -55,7 +57,7 @@ def _check_l1(X32, Z32, Y, rows):
     d = X32.shape[1]
     S = method_scale_l1(X32, Z32, rows)
     err = np.abs(Y.reshape(X32.shape[0], -1)[rows].astype(np.float64) - o)
-    ratio = float((err / ((8 + 3 * d) * U32 * S)).max())
+    ratio = bound_ratio(err, ((8 + 3 * d) * U32 * S))
     print("l1 errors", e, "bound-ratio", ratio)
     assert e["spec"] <= 1e-6 and e["per_row"] <= 1e-6
     assert ratio <= 1.0
@@ -65,7 +67,7 @@ def _check_l2(X32, Z32, Y, rows, tol):
     e, o = float_errors(X32, Z32, Y, L2SQ, rows)
     M = _l2_scale(X32, Z32, rows)
     err = np.abs(Y.reshape(X32.shape[0], -1)[rows].astype(np.float64) - o)
-    ratio = float((err / (tol * M)).max())
+    ratio = bound_ratio(err, (tol * M))
     print("l2sq errors", e, "bound-ratio", ratio)
     assert e["spec"] <= 1e-6
     assert ratio <= 1.0
@@ -107,7 +109,12 @@ def test_uniform_block_of_64_l1_and_l2sq():
     h2.free()
     del Xd, Zd, Y2
     _check_l1(X, Z, Yl1, rows)
-    _check_l2(X, Z, Yl2, rows[:8], 2.0 ** -13)
+    # l2 squared: 240 seeded rows and the 16 points of largest norm (the
+    # largest terms of the expansion)
+    nrm = np.einsum("ij,ij->i", X.astype(np.float64), X.astype(np.float64))
+    far = np.argsort(nrm, kind="stable")[-16:]
+    rows2 = synth.subsample_rows(X.shape[0], 240, s["sub"] + 1, extra=far)
+    _check_l2(X, Z, Yl2, rows2, 2.0 ** -13)
 
 
 def test_uneven_512_datasets_one_graph():

@@ -16,7 +16,7 @@ import oracle
 import synth
 from oracle import L1
 
-from gpu_helpers import U32, dev, float_errors, method_scale_l1, run
+from gpu_helpers import U32, bound_ratio, dev, float_errors, method_scale_l1, run
 
 pytestmark = pytest.mark.gpu
 dm = pytest.importorskip("paper_2210_15114_amd")
@@ -28,7 +28,7 @@ def _check_float(X32, Z32, Y, rows=None, spec=1e-6):
     r = np.arange(n) if rows is None else np.asarray(rows)
     S = method_scale_l1(X32, Z32, r)
     err = np.abs(Y.reshape(n, -1)[r].astype(np.float64) - o)
-    worst = float((err / ((8 + 3 * d) * U32 * S)).max())
+    worst = bound_ratio(err, ((8 + 3 * d) * U32 * S))
     print("errors", e, "bound-ratio", worst)
     assert e["spec"] <= spec
     assert e["per_row"] <= spec

@@ -16,14 +16,14 @@ import oracle
 import synth
 from oracle import L2SQ
 
-from gpu_helpers import U32, dev, float_errors, run
+from gpu_helpers import U32, bound_ratio, centred, dev, float_errors, run
 
 pytestmark = pytest.mark.gpu
 dm = pytest.importorskip("paper_2210_15114_amd")
 
 
 def _mscale(X32, Z32):
-    X = X32.astype(np.float64)
+    X = (centred(X32) if X32.dtype.kind == "f" else X32).astype(np.float64)
     Z = np.abs(Z32.astype(np.float64))
     nrm = (X * X).sum(axis=1)
     zl1 = Z.sum(axis=0)
@@ -44,7 +44,7 @@ def test_float(n, d, b):
     M = _mscale(X, Z)
     err = np.abs(Y.astype(np.float64) - o)
     tol = 2.0 ** -13 if b >= 16 else 4 * U32
-    ratio = float((err / (tol * M)).max())
+    ratio = bound_ratio(err, (tol * M))
     print("errors", e, "bound-ratio", ratio)
     assert e["spec"] <= 1e-6
     assert ratio <= 1.0

@@ -14,7 +14,7 @@ import pytest
 import oracle
 import synth
 
-from gpu_helpers import U32, dev, float_errors
+from gpu_helpers import U32, bound_ratio, centred, dev, float_errors
 
 pytestmark = pytest.mark.gpu
 dm = pytest.importorskip("paper_2210_15114_amd")
@@ -23,7 +23,9 @@ METRIC = {3: 4, 5: 5}
 
 
 def _scale(X, Z, p):
-    X = np.abs(X.astype(np.float64))
+    """Size of the terms the odd-p method forms, on the centred coordinates
+    it works with (integer data is not shifted)."""
+    X = np.abs((centred(X) if X.dtype.kind == "f" else X).astype(np.float64))
     Z = np.abs(Z.astype(np.float64)).reshape(X.shape[0], -1)
     S = np.zeros((X.shape[0], Z.shape[1]))
     for k in range(X.shape[1]):
@@ -66,7 +68,7 @@ def test_float_within_bounds(p, b, dist):
     h.free()
     e, o = float_errors(X, Z, Y, METRIC[p])
     S = _scale(X, Z, p)
-    ratio = float((np.abs(Y.reshape(n, -1).astype(np.float64) - o) / ((4 * p + 8 + 3 * d) * U32 * S)).max())
+    ratio = bound_ratio(np.abs(Y.reshape(n, -1).astype(np.float64) - o), ((4 * p + 8 + 3 * d) * U32 * S))
     print("p", p, "errors", e, "bound-ratio", ratio)
     assert e["spec"] <= 1e-6
     assert ratio <= 1.0

@@ -23,7 +23,7 @@ import oracle
 import synth
 from oracle import metrics
 
-from gpu_helpers import U32, dev
+from gpu_helpers import U32, bound_ratio, dev
 
 pytestmark = pytest.mark.gpu
 dm = pytest.importorskip("paper_2210_15114_amd")
@@ -99,7 +99,7 @@ def _check_float(X, Z, Y, metric, scale, M=None, rows=None, p=0):
     e = metrics.errors(Yr, o, rn, ad, Z64, metrics.frob_from_rows(rn, n))
     err = np.abs(Yr - o)
     bound = 2 * U32 * np.abs(o) + (n + d + 4 * p + 16) * U64 * scale(X, Z, r)
-    ratio = float((err / bound).max())
+    ratio = bound_ratio(err, bound)
     print("metric", metric, "errors", e, "bound-ratio", ratio)
     assert e["spec"] <= 1e-6
     assert ratio <= 1.0

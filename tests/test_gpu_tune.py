@@ -16,7 +16,7 @@ import oracle
 import synth
 from oracle import L1
 
-from gpu_helpers import U32, dev, float_errors, method_scale_l1
+from gpu_helpers import U32, bound_ratio, dev, float_errors, method_scale_l1
 
 pytestmark = pytest.mark.gpu
 dm = pytest.importorskip("paper_2210_15114_amd")
@@ -75,7 +75,7 @@ def test_every_variant_within_float_bounds(b):
         Y = h.matvec(Zd).cpu().numpy()
         h.sync()
         e, o = float_errors(X, Z, Y, L1)
-        ratio = float((np.abs(Y.astype(np.float64) - o) / ((8 + 3 * d) * U32 * S)).max())
+        ratio = bound_ratio(np.abs(Y.astype(np.float64) - o), ((8 + 3 * d) * U32 * S))
         print("variant", v, e, ratio)
         assert e["spec"] <= 1e-6 and e["per_row"] <= 1e-6, "variant %d" % v
         assert ratio <= 1.0, "variant %d" % v

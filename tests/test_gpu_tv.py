@@ -8,7 +8,7 @@ import pytest
 import oracle
 import synth
 
-from gpu_helpers import U32, dev, float_errors, method_scale_l1
+from gpu_helpers import U32, bound_ratio, dev, float_errors, method_scale_l1
 
 pytestmark = pytest.mark.gpu
 dm = pytest.importorskip("paper_2210_15114_amd")
@@ -26,7 +26,7 @@ def test_tv_matches_oracle(b):
     h.free()
     e, o = float_errors(X, Z, Y, oracle.TV)
     S = method_scale_l1(X, Z, np.arange(n))
-    ratio = float((np.abs(Y.reshape(n, -1).astype(np.float64) - o) / (0.5 * (8 + 3 * d) * U32 * S)).max())
+    ratio = bound_ratio(np.abs(Y.reshape(n, -1).astype(np.float64) - o), (0.5 * (8 + 3 * d) * U32 * S))
     print("tv errors", e, "bound-ratio", ratio)
     assert e["spec"] <= 1e-6 and ratio <= 1.0
 

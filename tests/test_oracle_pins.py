@@ -240,6 +240,15 @@ def test_l2sq_rank_and_frobenius(oracle_mod):
     assert np.linalg.svd(A1, compute_uv=False)[20] > 1e-6 * np.linalg.norm(A1)   # l1 is not low rank
 
 
+def test_frob_l2sq_far_from_origin(oracle_mod):
+    """The closed form on points 10^4 + U[0,1): the explicit A's norm, which
+    is the same as that of the points moved back to the origin."""
+    X = 1.0e4 + synth.rng(93).random((300, 4))
+    A = oracle.explicit(X, L2SQ)
+    assert metrics.frob_l2sq(X) == pytest.approx(np.linalg.norm(A), rel=1e-9)
+    assert metrics.frob_l2sq(X) == pytest.approx(metrics.frob_l2sq(X - 1.0e4), rel=1e-9)
+
+
 def test_frob_from_rows(oracle_mod):
     X = _rand(200, 3, 92)
     Y, rn, ad = oracle.matvec(X, np.ones((200, 1)), L1)
