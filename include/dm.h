@@ -113,8 +113,14 @@ typedef enum {
 const char* dm_status_string(int32_t status);
 
 /*
- * Bytes of device workspace dm_prepare needs for one dataset (persistent
- * arrays plus the sort's temporary buffers).  Pure host function.
+ * Bytes of device workspace dm_prepare needs for one dataset: the persistent
+ * arrays, the sort's temporary buffers, and everything a later query of any
+ * b <= 64 uses (the control block with the sticky status and the chained-scan
+ * ticket counters, the query scratch, the look-back record regions of every
+ * pass shape and tile variant, and for l1 / TV the single-column group
+ * buffer).  The matrix-vector query model of Section 1 prepares once and then
+ * answers products only, so with a caller workspace no query allocates.
+ * Pure host function.
  * Errors: DM_ERR_ARG for n < 1, d < 1, n * d >= 2^32, bad metric or dtype,
  * bytes == NULL.
  */
@@ -128,12 +134,20 @@ dm_status dm_workspace_size(int64_t n, int32_t d, int32_t metric, int32_t dtype,
  * ||x_i||^2.  For l2 squared, odd p and the sort-free metrics it keeps an FP32
  * (int32) copy of X; for the sort-free metrics also the per-coordinate range
  * midpoints and, for KL, the per-point values sum_k x_ik log x_ik.
+ * Float data of the sorted metrics and l2 squared is kept relative to a
+ * per-coordinate centre c_k (every such metric is translation invariant): the
+ * FP32 midpoint of the coordinate's range when x - c_k is exact for every x of
+ * the coordinate (Sterbenz's lemma: all x within a factor two of c_k), else 0.
+ * The sorted values, row statistics and the point copy are those of x - c, so
+ * the FP32 query keeps its accuracy on points far from the origin.
  * DM_MAHA2 and DM_BILINEAR are prepared with dm_prepare_matrix instead.
  *
  * X: device, n x d row-major of `dtype`; only read during the call.
- * workspace: device memory of at least dm_workspace_size bytes owned by the
- *   caller, which must outlive the handle; NULL lets the library allocate
- *   (and dm_free release) it.
+ * workspace: device memory of at least dm_workspace_size bytes, 256-byte
+ *   aligned, owned by the caller, which must outlive the handle; NULL lets the
+ *   library allocate (and dm_free release) it.  Either way the handle's device
+ *   memory is this one block: dm_matvec, dm_matvec_multi and dm_reserve never
+ *   allocate or free device memory.
  * Blocking: returns after the device work finished.
  * Errors: DM_ERR_ARG, DM_ERR_DTYPE (|x| >= 2^31 in integer data),
  * DM_ERR_NONFINITE (NaN/Inf in X, or an FP64 value beyond the FP32 range),
@@ -166,18 +180,17 @@ dm_status dm_prepare_matrix(const void* X, int64_t n, int32_t d, int32_t metric,
  * Z: device n x b of `z_dtype` (DM_F32 for float data; DM_I32 or DM_I64 for
  * integer data).  Out: device n x b, float or int64.  Z and Out must not
  * overlap.  1 <= b <= 64.
- * Stream-ordered and asynchronous.  The library may grow per-handle scratch
- * memory on the first call with a larger b, and allocates the group buffer of
- * single-column l1 / TV queries (per-coordinate values of up to 64 MiB worth of
- * coordinates, at least one) on the first such query (see dm_reserve).
- * Errors (synchronous): DM_ERR_ARG, DM_ERR_DTYPE, DM_ERR_NOMEM, DM_ERR_DEVICE.
+ * Stream-ordered and asynchronous: it only enqueues kernels on `stream`, in
+ * the handle's workspace; it neither allocates device memory nor waits.
+ * Errors (synchronous): DM_ERR_ARG, DM_ERR_DTYPE, DM_ERR_DEVICE.
  * Errors (sticky, via dm_sync): DM_ERR_NONFINITE, DM_ERR_OVERFLOW.
  */
 dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream);
 
-/* Pre-size the per-handle query scratch for right-hand-side counts up to b
- * (and, for l1 and TV, the single-column group buffer), so that later
- * dm_matvec calls allocate nothing.  Errors: DM_ERR_ARG, DM_ERR_NOMEM. */
+/* Kept for callers that reserved query memory before the workspace held it:
+ * checks b (1..64) and does nothing else, since the workspace already holds
+ * every query's memory.  Errors: DM_ERR_ARG, DM_ERR_STATE (multi-dataset
+ * handle). */
 dm_status dm_reserve(dm_handle* h, int32_t b);
 
 /*
@@ -250,7 +263,11 @@ int dm_int_bound_ok(double sum_ranges, double z_l1);
  * Out[s]: device n_s x b, float or int64.  Z and Out are host arrays of
  * count device pointers.  1 <= b <= 64.
  * A call that changes any Z/Out pointer waits for the previous call's upload
- * of the pointer table to have run.  Errors as for dm_prepare / dm_matvec;
+ * of the pointer table to have run.  The first call with a new b (or with a
+ * new choice of 16-byte row access) lays out that b's tile tables and record
+ * regions in the workspace's plan area, which dm_workspace_size_multi sizes
+ * for every b <= 64, and captures its graph; this synchronises the call's
+ * stream.  No call allocates device memory.  Errors as for dm_prepare / dm_matvec;
  * a non-l1 metric is DM_ERR_ARG; dm_matvec_multi on a single-dataset handle
  * (or dm_matvec on a multi-dataset handle) is DM_ERR_STATE.
  */

@@ -56,9 +56,29 @@ bool int_dtype(int32_t t) { return t == DM_I32 || t == DM_I64; }
 size_t dtype_size(int32_t t) { return (t == DM_F64 || t == DM_I64) ? 8 : 4; }
 
 constexpr int32_t L2_MAX_D = 512;   // LDS staging bound of the l2-squared kernels
-constexpr int32_t MAX_B = 64;
 
-// Byte layout of one dataset's workspace.
+// Control block owned by a handle: sticky status, chained-scan state, totals.
+struct Ctl {
+    uint32_t status;
+    uint32_t pad[63];
+    ChainState chain;
+    double T0[1024];
+    double U[1024];
+    double zl1[1024];
+};
+
+// A look-back record region of one pass kernel shape (its ticket class).
+struct RegionSpec {
+    int cls;
+    size_t off;     // byte offset in the workspace
+    size_t words;   // 64-bit words
+};
+
+// Byte layout of one dataset's workspace: the preparation results, the sort's
+// temporaries and everything a query needs (control block, scratch for
+// b <= MAX_B, the record regions of every pass shape the handle can launch,
+// the single-column group buffer), so that a caller who passes the workspace
+// owns all device memory the handle uses.
 struct Layout {
     int64_t ld = 0;         // stride between coordinates of the d x n arrays
     uint32_t ntiles = 0;    // sort tiles
@@ -68,10 +88,50 @@ struct Layout {
     size_t logx = 0;              // FP64 logarithms of the points (KL divergence, cross entropy)
     size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0;
     size_t k1 = 0, v1 = 0, counts = 0;
+    size_t ctl = 0;                       // Ctl
+    size_t qscratch = 0, qscratch_bytes = 0;   // query scratch (totals partials, moments, l2 partials)
+    size_t single = 0, single_bytes = 0;  // single-column group buffer (l1, TV)
+    int32_t single_group = 0;             // coordinates per group of that buffer
+    size_t regions_begin = 0, regions_end = 0;
+    std::vector<RegionSpec> regions;
     size_t total = 0;
 };
 
-Layout make_layout(int64_t n, int32_t d, int32_t metric) {
+constexpr int32_t MAX_B = 64;
+
+size_t query_scratch_bytes(int64_t n, int32_t d, int32_t metric, int32_t b) {
+    size_t s = al(totals_scratch_bytes(n, b));
+    if (metric == DM_L2SQ) s += al(l2_scratch_bytes(n, d, b));
+    if (sf_metric(metric)) s += al(sf_scratch_bytes(n, d, b, sf_form(metric), metric_power(metric)));
+    if (lp_metric(metric)) s += al(lp_moments_bytes(n, d, b, metric_power(metric)));
+    return s;
+}
+
+int kind_index(bool is_int, int zkind) { return !is_int ? 0 : zkind == IN_I32 ? 1 : 2; }
+
+int log2_pad(int32_t b) {
+    int lg = 0;
+    while ((1 << lg) < b) ++lg;
+    return lg;
+}
+
+// the ticket class and record region size of an odd-p pass
+L1Shape lp_shape_of(int64_t n, int p, bool is_int, int32_t b, int zkind) {
+    L1Shape sh;
+    sh.cls = L1_CLASSES + (kind_index(is_int, zkind) * 8 + log2_pad(b)) * 2 + (p == 5 ? 1 : 0);
+    sh.record_words = lp_record_words(n, b, is_int, p);
+    return sh;
+}
+
+// Coordinates per group of a single-column l1 query (group x ld values of
+// FP32 or int64 in the buffer).
+int32_t single_group_of(int64_t ld, int32_t d, bool is_int) {
+    const size_t per = (size_t)ld * (is_int ? 8 : 4);
+    const size_t g = SINGLE_GROUP_BYTES / per;
+    return (int32_t)(g < 1 ? 1 : g > (size_t)d ? (size_t)d : g);
+}
+
+Layout make_layout(int64_t n, int32_t d, int32_t metric, int32_t dtype) {
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -108,6 +168,37 @@ Layout make_layout(int64_t n, int32_t d, int32_t metric) {
         L.v1 = take(arr);
         L.counts = take((size_t)L.ntiles * 256 * 4);
     }
+    // ---- what queries use ----
+    const bool is_int = int_dtype(dtype);
+    L.ctl = take(sizeof(Ctl));
+    for (int32_t b = 1; b <= MAX_B; ++b) L.qscratch_bytes = std::max(L.qscratch_bytes, query_scratch_bytes(n, d, metric, b));
+    L.qscratch = take(L.qscratch_bytes);
+    if (l1_pass_metric(metric)) {
+        L.single_group = single_group_of(L.ld, d, is_int);
+        L.single_bytes = (size_t)L.single_group * (size_t)L.ld * (is_int ? 8 : 4);
+        L.single = take(L.single_bytes);
+    }
+    // record regions of every pass shape reachable with b <= MAX_B, any tile
+    // variant and (integer data) either right-hand-side type
+    L.regions_begin = o;
+    auto region = [&](const L1Shape& sh) {
+        for (auto& r : L.regions)
+            if (r.cls == sh.cls) return;
+        L.regions.push_back(RegionSpec{sh.cls, take(sh.record_words * 8), sh.record_words});
+    };
+    const int kinds[2] = {is_int ? IN_I32 : IN_F32, IN_I64};
+    for (int ki = 0; ki < (is_int ? 2 : 1); ++ki)
+        for (int32_t bp = 1; bp <= MAX_B; bp <<= 1) {
+            if (l1_pass_metric(metric)) {
+                for (int v = 0; v < L1_VARIANTS; ++v) {
+                    region(l1_shape(n, bp, is_int, kinds[ki], v));
+                    if (bp == 1) region(l1_single_shape(n, is_int, kinds[ki], v));
+                }
+            } else if (lp_metric(metric)) {
+                region(lp_shape_of(n, metric_power(metric), is_int, bp, kinds[ki]));
+            }
+        }
+    L.regions_end = o;
     L.total = o;
     return L;
 }
@@ -142,16 +233,6 @@ dm_status device_ready(int* dev) {
     return DM_OK;
 }
 
-// Control block owned by a handle: sticky status, chained-scan state, totals.
-struct Ctl {
-    uint32_t status;
-    uint32_t pad[63];
-    ChainState chain;
-    double T0[1024];
-    double U[1024];
-    double zl1[1024];
-};
-
 }  // namespace
 
 struct MultiState;
@@ -167,16 +248,7 @@ struct dm_handle {
     Layout L;
     char* ws = nullptr;
     bool owns_ws = false;
-    Ctl* ctl = nullptr;
-    char* scratch = nullptr;
-    size_t scratch_bytes = 0;
-    // single-column l1 queries: the values of a group of coordinates, each in
-    // point order (group x ld, FP32 or int64), summed after the group's passes
-    char* single_buf = nullptr;
-    size_t single_bytes = 0;
-    // look-back record regions, one per pass kernel shape (zeroed when created)
-    struct Region { int cls; uint64_t* ptr; size_t words; };
-    std::vector<Region> regions;
+    Ctl* ctl = nullptr;   // in the workspace
     double guard_scale = 0.0;   // sum over the coordinates of range^p
     bool symmetric = true;      // A = A^T (false for the divergences and a non-symmetric bilinear form)
     hipStream_t last = nullptr;
@@ -207,10 +279,6 @@ void release(dm_handle* h) {
         if (e.a) (void)hipEventDestroy(e.a);
         if (e.b) (void)hipEventDestroy(e.b);
     }
-    if (h->scratch) (void)hipFree(h->scratch);
-    if (h->single_buf) (void)hipFree(h->single_buf);
-    for (auto& r : h->regions) (void)hipFree(r.ptr);
-    if (h->ctl) (void)hipFree(h->ctl);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
     delete h;
 }
@@ -225,18 +293,11 @@ void arch_name(int dev, char* out) {
     out[i] = 0;
 }
 
-int log2_pad(int32_t b) {
-    int lg = 0;
-    while ((1 << lg) < b) ++lg;
-    return lg;
-}
 int floor_log2(int64_t n) {
     int lg = 0;
     while ((int64_t(1) << (lg + 1)) <= n) ++lg;
     return lg;
 }
-int kind_index(bool is_int, int zkind) { return !is_int ? 0 : zkind == IN_I32 ? 1 : 2; }
-
 // the pass data path of a right-hand-side type on this handle
 dm_status zkind_of(const dm_handle* h, int32_t z_dtype, int* zkind) {
     if (!valid_dtype(z_dtype)) return DM_ERR_ARG;
@@ -300,86 +361,20 @@ double key_to_double(uint32_t k, bool is_int) {
     return (double)f;
 }
 
-size_t query_scratch_bytes(const dm_handle* h, int32_t b) {
-    size_t s = al(totals_scratch_bytes(h->n, b));
-    if (h->metric == DM_L2SQ) s += al(l2_scratch_bytes(h->n, h->d, b));
-    if (sf_metric(h->metric)) s += al(sf_scratch_bytes(h->n, h->d, b, sf_form(h->metric), metric_power(h->metric)));
-    if (lp_metric(h->metric)) s += al(lp_moments_bytes(h->n, h->d, b, metric_power(h->metric)));
-    return s;
-}
-
 // the ticket class and record region size of an odd-p pass
 L1Shape lp_shape(const dm_handle* h, int32_t b, int zkind) {
-    L1Shape sh;
-    const int pw = metric_power(h->metric);
-    sh.cls = L1_CLASSES + (kind_index(h->is_int, zkind) * 8 + log2_pad(b)) * 2 + (pw == 5 ? 1 : 0);
-    sh.record_words = lp_record_words(h->n, b, h->is_int, pw);
-    return sh;
+    return lp_shape_of(h->n, metric_power(h->metric), h->is_int, b, zkind);
 }
 
-// the record region of one pass shape, created (and zeroed) on first use
-dm_status region_for(dm_handle* h, const L1Shape& sh, hipStream_t s, uint64_t** out) {
-    for (auto& r : h->regions)
+// the record region of one pass shape (carved from the workspace at
+// preparation and zeroed there)
+dm_status region_for(dm_handle* h, const L1Shape& sh, uint64_t** out) {
+    for (auto& r : h->L.regions)
         if (r.cls == sh.cls && r.words >= sh.record_words) {
-            *out = r.ptr;
+            *out = h->at<uint64_t>(r.off);
             return DM_OK;
         }
-    for (auto it = h->regions.begin(); it != h->regions.end(); ++it)
-        if (it->cls == sh.cls) {   // too small (cannot happen for a fixed n): replace
-            DM_TRY(hipStreamSynchronize(h->last));
-            DM_TRY(hipFree(it->ptr));
-            h->regions.erase(it);
-            break;
-        }
-    void* p = nullptr;
-    DM_TRY(hipMalloc(&p, sh.record_words * 8));
-    DM_TRY(launch_fill_u32((uint32_t*)p, 0u, sh.record_words * 2, s));
-    h->regions.push_back(dm_handle::Region{sh.cls, (uint64_t*)p, sh.record_words});
-    *out = (uint64_t*)p;
-    return DM_OK;
-}
-
-dm_status ensure_scratch(dm_handle* h, int32_t b, hipStream_t s) {
-    size_t need = 0;
-    // record size depends on the rounded-up b and (for integers) not on the z type
-    for (int32_t bb = 1; bb <= b; bb <<= 1) need = std::max(need, query_scratch_bytes(h, bb));
-    need = std::max(need, query_scratch_bytes(h, b));
-    if (need <= h->scratch_bytes) return DM_OK;
-    if (h->scratch) {
-        DM_TRY(hipStreamSynchronize(h->last));
-        DM_TRY(hipFree(h->scratch));
-        h->scratch = nullptr;
-        h->scratch_bytes = 0;
-    }
-    void* p = nullptr;
-    DM_TRY(hipMalloc(&p, need));
-    h->scratch = (char*)p;
-    h->scratch_bytes = need;
-    DM_TRY(launch_fill_u32((uint32_t*)p, 0u, need / 4, s));
-    return DM_OK;
-}
-
-// Coordinates per group of a single-column l1 query (group x ld values of
-// FP32 or int64 in the buffer).
-int32_t single_group(const dm_handle* h) {
-    const size_t per = (size_t)h->L.ld * (h->is_int ? 8 : 4);
-    const size_t g = SINGLE_GROUP_BYTES / per;
-    return (int32_t)(g < 1 ? 1 : g > (size_t)h->d ? (size_t)h->d : g);
-}
-
-// The group buffer of single-column l1 queries (created on first use).
-dm_status ensure_single_buf(dm_handle* h) {
-    const size_t need = (size_t)single_group(h) * (size_t)h->L.ld * (h->is_int ? 8 : 4);
-    if (h->single_bytes >= need) return DM_OK;
-    void* p = nullptr;
-    if (hipMalloc(&p, need) != hipSuccess) {
-        (void)hipGetLastError();   // the caller falls back; keep later launch checks clean
-        return DM_ERR_NOMEM;
-    }
-    if (h->single_buf) (void)hipFree(h->single_buf);
-    h->single_buf = (char*)p;
-    h->single_bytes = need;
-    return DM_OK;
+    return DM_ERR_STATE;   // not a shape this handle was laid out for
 }
 
 // Bracket one launch with events when profiling is on.
@@ -542,7 +537,7 @@ dm_status dm_workspace_size(int64_t n, int32_t d, int32_t metric, int32_t dtype,
     if (!bytes) return DM_ERR_ARG;
     dm_status st = check_shape(n, d, metric, dtype);
     if (st != DM_OK) return st;
-    *bytes = make_layout(n, d, metric).total;
+    *bytes = make_layout(n, d, metric, dtype).total;
     return DM_OK;
 }
 
@@ -558,7 +553,7 @@ static dm_status prepare_impl(const void* X, int64_t n, int32_t d, int32_t metri
     if (!X) return DM_ERR_ARG;
     dm_status st = check_shape(n, d, metric, dtype);
     if (st != DM_OK) return st;
-    const Layout L = make_layout(n, d, metric);
+    const Layout L = make_layout(n, d, metric, dtype);
     if (workspace && ws_bytes < L.total) return DM_ERR_ARG;
     if (workspace && ((uintptr_t)workspace % ALIGN) != 0) return DM_ERR_ARG;
     int dev = 0;
@@ -588,14 +583,16 @@ static dm_status prepare_impl(const void* X, int64_t n, int32_t d, int32_t metri
         h->ws = (char*)p;
         h->owns_ws = true;
     }
-    {
-        void* p = nullptr;
-        if (hipMalloc(&p, sizeof(Ctl)) != hipSuccess) return fail(DM_ERR_NOMEM);
-        h->ctl = (Ctl*)p;
-    }
+    h->ctl = h->at<Ctl>(L.ctl);
     Ctl init;
     std::memset(&init, 0, sizeof(init));
     if (hipMemcpyAsync(h->ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(DM_ERR_DEVICE);
+    // query scratch and the look-back record regions start at zero (a zero
+    // word carries no pass tag)
+    if (launch_fill_u32(h->at<uint32_t>(L.qscratch), 0u, L.qscratch_bytes / 4, s) != hipSuccess ||
+        launch_fill_u32(h->at<uint32_t>(L.regions_begin), 0u, (L.regions_end - L.regions_begin) / 4, s) !=
+            hipSuccess)
         return fail(DM_ERR_DEVICE);
     if (launch_fill_u32(h->at<uint32_t>(L.kmin), 0xffffffffu, (size_t)d, s) != hipSuccess ||
         launch_fill_u32(h->at<uint32_t>(L.kmax), 0u, (size_t)d, s) != hipSuccess ||
@@ -667,34 +664,27 @@ dm_status dm_prepare_matrix(const void* X, int64_t n, int32_t d, int32_t metric,
 dm_status dm_reserve(dm_handle* h, int32_t b) {
     if (!h || b < 1 || b > MAX_B) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    dm_status st = ensure_scratch(h, b, h->last);
-    if (st != DM_OK) return st;
-    if (sorted_metric(h->metric)) {
-        const int kinds[2] = {h->is_int ? IN_I32 : IN_F32, IN_I64};
-        for (int ki = 0; ki < (h->is_int ? 2 : 1); ++ki) {
-            uint64_t* r = nullptr;
-            if (lp_metric(h->metric)) {
-                if ((st = region_for(h, lp_shape(h, b, kinds[ki]), h->last, &r)) != DM_OK) return st;
-                continue;
-            }
-            const int v = variant_for(h, kind_index(h->is_int, kinds[ki]), log2_pad(b));
-            if ((st = region_for(h, l1_shape(h->n, b, h->is_int, kinds[ki], v), h->last, &r)) != DM_OK) return st;
-            // single-column queries use the OUT_FRESH passes
-            const int v1 = variant_for(h, kind_index(h->is_int, kinds[ki]), 0);
-            if ((st = region_for(h, l1_single_shape(h->n, h->is_int, kinds[ki], v1), h->last, &r)) != DM_OK)
-                return st;
-        }
-        if (l1_pass_metric(h->metric) && (st = ensure_single_buf(h)) != DM_OK) return st;
-    }
-    return hipStreamSynchronize(h->last) == hipSuccess ? DM_OK : DM_ERR_DEVICE;
+    return DM_OK;   // the workspace already holds what any query needs
 }
 
-dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Where a query's scratch lives (the handle's workspace for dm_matvec).
+struct QueryMem {
+    char* scratch = nullptr;       // totals partials, then the metric's scratch
+    uint64_t* records = nullptr;   // one record block for the call's pass shape, or NULL: the workspace regions
+    size_t record_words = 0;
+    char* single = nullptr;        // b = 1 group buffer (NULL: single columns take the adding passes)
+    int32_t single_group = 0;
+};
+
+dm_status query_args(const dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, const void* Out, int* zkind) {
     if (!h || !Z || !Out || b < 1 || b > MAX_B) return DM_ERR_ARG;
     if (h->multi) return DM_ERR_STATE;
-    int zkind = 0;
     {
-        const dm_status zs = zkind_of(h, z_dtype, &zkind);
+        const dm_status zs = zkind_of(h, z_dtype, zkind);
         if (zs != DM_OK) return zs;
     }
     const size_t zbytes = (size_t)h->n * b * dtype_size(z_dtype);
@@ -702,10 +692,20 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
     const char* zp = (const char*)Z;
     const char* op = (const char*)Out;
     if (zp < op + obytes && op < zp + zbytes) return DM_ERR_ARG;   // overlap
-    hipStream_t s = (hipStream_t)stream;
-    dm_status st = ensure_scratch(h, b, s);
-    if (st != DM_OK) return st;
-    char* sc = h->scratch;
+    return DM_OK;
+}
+
+// the record block of the call's pass shape
+dm_status records_for(dm_handle* h, const QueryMem& q, const L1Shape& sh, uint64_t** out) {
+    if (!q.records) return region_for(h, sh, out);
+    if (sh.record_words > q.record_words) return DM_ERR_ARG;
+    *out = q.records;
+    return DM_OK;
+}
+
+dm_status matvec_impl(dm_handle* h, const void* Z, int zkind, int32_t b, void* Out, hipStream_t s,
+                      const QueryMem& q) {
+    char* sc = q.scratch;
     TotalsOut tot;
     tot.T0 = h->ctl->T0;
     tot.U = h->ctl->U;
@@ -735,7 +735,7 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         a.status = &h->ctl->status;
         {
             const L1Shape sh = lp_shape(h, b, zkind);
-            dm_status rs = region_for(h, sh, s, &a.records);
+            dm_status rs = records_for(h, q, sh, &a.records);
             if (rs != DM_OK) return rs;
             a.record_words = sh.record_words;
             a.cls = sh.cls;
@@ -807,7 +807,7 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         {
             const int v = variant_for(h, kind_index(h->is_int, zkind), log2_pad(b));
             const L1Shape sh = l1_shape(h->n, b, h->is_int, zkind, v);
-            dm_status rs = region_for(h, sh, s, &a.records);
+            dm_status rs = records_for(h, q, sh, &a.records);
             if (rs != DM_OK) return rs;
             a.record_words = sh.record_words;
             a.cls = sh.cls;
@@ -815,15 +815,15 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         }
         const size_t vsz = 4;
         // one column: each pass writes its values in point order to a buffer
-        // of its own, and after each group of G coordinates one coalesced sweep
-        // adds the group's buffers into Out; falls back to the adding passes
-        // when the G x n buffer cannot be allocated
-        const bool single = b == 1 && ensure_single_buf(h) == DM_OK;
-        const int32_t G = single ? single_group(h) : 1;
+        // of its own (the workspace's group buffer), and after each group of G
+        // coordinates one coalesced sweep adds the group's buffers into Out
+        const bool single = b == 1 && q.single;
+        const int32_t G = single ? q.single_group : 1;
+        char* single_buf = q.single;
         const size_t osz = h->is_int ? 8 : 4;
         if (single) {
             const L1Shape sh = l1_single_shape(h->n, h->is_int, zkind, a.variant);
-            dm_status rs = region_for(h, sh, s, &a.records);
+            dm_status rs = records_for(h, q, sh, &a.records);
             if (rs != DM_OK) return rs;
             a.record_words = sh.record_words;
             a.cls = sh.cls;
@@ -833,14 +833,14 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
             a.perm = h->at<uint32_t>(h->L.perm) + (size_t)k * h->L.ld;
             a.xs = h->ws + h->L.xs + (size_t)k * h->L.ld * vsz;
             a.first = k == 0;
-            if (single) a.Out = h->single_buf + (size_t)(k % G) * h->L.ld * osz;
+            if (single) a.Out = single_buf + (size_t)(k % G) * h->L.ld * osz;
             {
                 ProfScope ps(h, DM_K_L1_PASS, s);
                 DM_TRY(launch_l1_pass(h->is_int, zkind, b, a, s));
             }
             if (single && (k % G == G - 1 || k == h->d - 1)) {
                 const int32_t k0 = k - k % G;
-                DM_TRY(launch_l1_combine(h->is_int, h->L.ld, h->single_buf, h->n, k - k0 + 1, k0 == 0, tot.U, Out, s));
+                DM_TRY(launch_l1_combine(h->is_int, h->L.ld, single_buf, h->n, k - k0 + 1, k0 == 0, tot.U, Out, s));
             }
         }
         // TV(x, y) = l1(x, y) / 2 (the TV theorem of Appendix A.3); the
@@ -852,6 +852,23 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
                            tot, h->guard_scale, s));
     }
     return DM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream) {
+    int zkind = 0;
+    const dm_status st = query_args(h, Z, z_dtype, b, Out, &zkind);
+    if (st != DM_OK) return st;
+    QueryMem q;
+    q.scratch = h->ws + h->L.qscratch;
+    if (h->L.single_bytes) {
+        q.single = h->ws + h->L.single;
+        q.single_group = h->L.single_group;
+    }
+    return matvec_impl(h, Z, zkind, b, Out, (hipStream_t)stream, q);
 }
 
 dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t variant) {
@@ -917,7 +934,7 @@ dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* 
         for (int v = 0; v < L1_VARIANTS; ++v) {
             const L1Shape sh =
                 b == 1 ? l1_single_shape(h->n, h->is_int, zkind, v) : l1_shape(h->n, b, h->is_int, zkind, v);
-            const dm_status rs = region_for(h, sh, s, &a.records);
+            const dm_status rs = region_for(h, sh, &a.records);
             if (rs != DM_OK) return rs;
             a.record_words = sh.record_words;
             a.cls = sh.cls;
@@ -1198,6 +1215,12 @@ struct MultiLayout {
     size_t perm = 0, xs = 0, ids = 0, k1 = 0, v1 = 0, counts = 0, flags = 0;
     size_t key_off = 0, key_len = 0, tile_off = 0, tile_seg = 0, seg_int = 0;
     size_t centre = 0;             // per segment: FP32 centre of a float coordinate
+    // what queries use: control block, descriptors, totals block table, and
+    // the plan area (sized for the largest b), all in the workspace
+    size_t ctl = 0, ds = 0, blk = 0;
+    size_t tickets = 0, tot = 0, partials = 0;
+    size_t plan = 0, plan_bytes = 0;
+    int nblk = 0;
     int64_t total_keys = 0;
     uint32_t ntiles = 0;
     int32_t nseg = 0;
@@ -1225,11 +1248,6 @@ namespace {
 void free_plan(MultiPlan& p) {
     if (p.exec) (void)hipGraphExecDestroy(p.exec);
     if (p.graph) (void)hipGraphDestroy(p.graph);
-    for (auto* t : p.tiles) if (t) (void)hipFree(t);
-    for (auto* r : p.records) if (r) (void)hipFree(r);
-    if (p.tickets) (void)hipFree(p.tickets);
-    if (p.partials) (void)hipFree(p.partials);
-    if (p.tot) (void)hipFree(p.tot);
     p = MultiPlan();
 }
 
@@ -1284,6 +1302,33 @@ dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSe
     M.k1 = take(arr);
     M.v1 = take(arr);
     M.counts = take((size_t)ntiles * 256 * 4);
+    int maxd = 0;
+    for (auto& m : v) {
+        M.nblk += (int)((m.n + multi_totals_rows() - 1) / multi_totals_rows());
+        maxd = std::max(maxd, m.d);
+    }
+    M.ctl = take(sizeof(Ctl));
+    M.ds = take((size_t)count * sizeof(MultiDs));
+    M.blk = take((size_t)M.nblk * 4);
+    M.tickets = take((size_t)maxd * 2 * 8);
+    M.tot = take((size_t)count * 2 * MAX_B * 8);
+    M.partials = take((size_t)M.nblk * MAX_B * 3 * 8 + 8);
+    // per (round, kind): the tile table and the record region of that
+    // round's launch; both depend on b through the tile size
+    for (int32_t b = 1; b <= MAX_B; ++b) {
+        size_t bytes = 0;
+        for (int k = 0; k < maxd; ++k)
+            for (int kind = 0; kind < 2; ++kind) {
+                const int tr = multi_tile_ranks(b, kind == 1);
+                int64_t nt = 0;
+                for (auto& m : v)
+                    if (m.is_int == (kind == 1) && m.d > k) nt += (m.n + tr - 1) / tr;
+                if (nt == 0) continue;
+                bytes += al((size_t)nt * sizeof(MultiTile)) + al(multi_record_words(nt, b, kind == 1) * 8);
+            }
+        M.plan_bytes = std::max(M.plan_bytes, bytes);
+    }
+    M.plan = take(M.plan_bytes);
     M.total = o;
     if (out) *out = std::move(v);
     if (L) *L = M;
@@ -1302,15 +1347,12 @@ dm_status build_plan(dm_handle* h, int32_t b, bool vec) {
     const int nsets = (int)m->sets.size();
     // per-dataset totals storage and descriptors
     {
-        void* q = nullptr;
-        DM_TRY(hipMalloc(&q, (size_t)nsets * 2 * b * 8));
-        p.tot = (double*)q;
-        DM_TRY(hipMalloc(&q, (size_t)m->nblk * b * 3 * 8 + 8));
-        p.partials = (double*)q;
-        DM_TRY(hipMalloc(&q, (size_t)p.rounds * 2 * 8));
-        p.tickets = (uint64_t*)q;
-        DM_TRY(launch_fill_u32((uint32_t*)q, 0u, (size_t)p.rounds * 4, m->cap));
+        p.tot = h->at<double>(m->L.tot);
+        p.partials = h->at<double>(m->L.partials);
+        p.tickets = h->at<uint64_t>(m->L.tickets);
+        DM_TRY(launch_fill_u32((uint32_t*)p.tickets, 0u, (size_t)p.rounds * 4, m->cap));
     }
+    size_t at = m->L.plan;   // tile tables and record regions, carved in order
     for (int s = 0; s < nsets; ++s) {
         m->h_ds[s].T0 = p.tot + (size_t)s * 2 * b;
         m->h_ds[s].U = p.tot + (size_t)s * 2 * b + b;
@@ -1336,12 +1378,15 @@ dm_status build_plan(dm_handle* h, int32_t b, bool vec) {
             const size_t ix = (size_t)k * 2 + kind;
             p.ntiles[ix] = (int64_t)t.size();
             if (t.empty()) continue;
-            void* q = nullptr;
-            DM_TRY(hipMalloc(&q, t.size() * sizeof(MultiTile)));
+            const size_t words = multi_record_words((int64_t)t.size(), b, kind == 1);
+            if (at + al(t.size() * sizeof(MultiTile)) + al(words * 8) > m->L.plan + m->L.plan_bytes)
+                return DM_ERR_STATE;   // cannot happen: the plan area is sized for every b
+            void* q = h->ws + at;
+            at += al(t.size() * sizeof(MultiTile));
             p.tiles[ix] = (MultiTile*)q;
             DM_TRY(hipMemcpyAsync(q, t.data(), t.size() * sizeof(MultiTile), hipMemcpyHostToDevice, m->cap));
-            const size_t words = multi_record_words((int64_t)t.size(), b, kind == 1);
-            DM_TRY(hipMalloc(&q, words * 8));
+            q = h->ws + at;
+            at += al(words * 8);
             p.records[ix] = (uint64_t*)q;
             DM_TRY(launch_fill_u32((uint32_t*)q, 0u, words * 2, m->cap));
             p.grids[ix] = multi_grid((int64_t)t.size(), b, kind == 1);
@@ -1374,9 +1419,7 @@ void release_multi(MultiState* m) {
     if (!m) return;
     if (m->launched) (void)hipEventSynchronize(m->done);
     free_plan(m->plan);
-    if (m->d_ds) (void)hipFree(m->d_ds);
     if (m->h_ds) (void)hipHostFree(m->h_ds);
-    if (m->d_blk) (void)hipFree(m->d_blk);
     if (m->done) (void)hipEventDestroy(m->done);
     if (m->cap) (void)hipStreamDestroy(m->cap);
     delete m;
@@ -1440,11 +1483,7 @@ dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspac
         h->ws = (char*)p;
         h->owns_ws = true;
     }
-    {
-        void* p = nullptr;
-        if (hipMalloc(&p, sizeof(Ctl)) != hipSuccess) return fail(DM_ERR_NOMEM);
-        h->ctl = (Ctl*)p;
-    }
+    h->ctl = h->at<Ctl>(L.ctl);
     if (hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess)
         return fail(DM_ERR_DEVICE);
@@ -1531,9 +1570,9 @@ dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspac
     if (flags & FLAG_INT_RANGE) return fail(DM_ERR_DTYPE);
     // descriptors (pinned mirror and device copy) and the totals block table
     const int nsets = count;
-    if (hipHostMalloc((void**)&m->h_ds, (size_t)nsets * sizeof(MultiDs), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&m->d_ds, (size_t)nsets * sizeof(MultiDs)) != hipSuccess)
+    if (hipHostMalloc((void**)&m->h_ds, (size_t)nsets * sizeof(MultiDs), hipHostMallocDefault) != hipSuccess)
         return fail(DM_ERR_NOMEM);
+    m->d_ds = h->at<MultiDs>(L.ds);
     std::vector<uint32_t> blk;
     for (int32_t i = 0; i < nsets; ++i) {
         MultiSet& q = m->sets[i];
@@ -1560,7 +1599,8 @@ dm_status dm_prepare_multi(const dm_dataset* sets, int32_t count, void* workspac
         for (int j = 0; j < nb; ++j) blk.push_back((uint32_t)i);
     }
     m->nblk = (int)blk.size();
-    if (hipMalloc((void**)&m->d_blk, blk.size() * 4) != hipSuccess) return fail(DM_ERR_NOMEM);
+    if (m->nblk != L.nblk) return fail(DM_ERR_STATE);   // the layout counted the same blocks
+    m->d_blk = h->at<uint32_t>(L.blk);
     if (hipMemcpy(m->d_blk, blk.data(), blk.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
         return fail(DM_ERR_DEVICE);
     h->last = s;

@@ -82,6 +82,13 @@ hipError_t launch_sort_scatter(const uint32_t* kin, const uint32_t* vin, uint32_
 hipError_t launch_rank_invert(const uint32_t* perm, int64_t ld, int64_t n, int32_t d, uint32_t* rank, int64_t pitch,
                               hipStream_t s);
 
+// Workgroups of a persistent launch of `fn` on the current device: the
+// smaller occupancy of fn and fn2 (two variants of one kernel shape, which
+// must share a grid) times the device's compute units, at most ntiles.  The
+// occupancy is cached per (device, kernel) under a lock, so concurrent callers
+// with distinct handles and devices are safe.
+int persistent_grid(const void* fn, const void* fn2, int64_t ntiles);
+
 // ---- l1 query --------------------------------------------------------------
 // totals: T0[c] = sum_j z_jc, U[c] = sum_j w_j z_jc, |z_c|_1; with guards.
 struct TotalsOut {

@@ -1,12 +1,44 @@
 // k_l1.hip - per-query totals of the l1 query (T0, U and the guard sums)
 // and the dispatch of the coordinate passes (l1_pass.h) by data path, block
 // width and tuned variant.
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "dm_device.h"
 #include "dm_internal.h"
 
 namespace dm {
+
+int persistent_grid(const void* fn, const void* fn2, int64_t ntiles) {
+    struct Entry { int dev; const void* fn; int per_cu; int cus; };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int per_cu = 0, cus = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (const Entry& e : cache)
+            if (e.dev == dev && e.fn == fn) {
+                per_cu = e.per_cu;
+                cus = e.cus;
+            }
+        if (per_cu == 0) {
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            int nb = 0, nb2 = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, fn2, 256, 0) != hipSuccess || nb2 < 1) nb2 = 1;
+            per_cu = nb < nb2 ? nb : nb2;
+            cache.push_back(Entry{dev, fn, per_cu, cus});
+        }
+    }
+    int64_t g = (int64_t)per_cu * cus;
+    if (g > ntiles) g = ntiles;
+    if (g < 1) g = 1;
+    return (int)g;
+}
 namespace {
 
 // ---------------------------------------------------------------------------

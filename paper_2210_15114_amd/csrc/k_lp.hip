@@ -356,19 +356,8 @@ hipError_t lp_launch_bp(const LpPassArgs& a, int32_t b, hipStream_t s) {
     const int64_t ntiles = (a.n + TILE - 1) / TILE;
     if ((size_t)ntiles * (2 * (size_t)NM * P::WPV * BP + 1) > a.record_words) return hipErrorInvalidValue;
     uint64_t* stat = a.records + (size_t)ntiles * 2 * NM * P::WPV * BP;
-    static int per_cu = 0, cus = 0;
-    if (per_cu == 0) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)lp_pass_kernel<P, BP, NM, R>, 256, 0) !=
-                hipSuccess || nb < 1)
-            nb = 1;
-        per_cu = nb;
-    }
-    int64_t grid = (int64_t)per_cu * cus;
-    if (grid > ntiles) grid = ntiles;
+    const int64_t grid = persistent_grid((const void*)lp_pass_kernel<P, BP, NM, R>,
+                                         (const void*)lp_pass_kernel<P, BP, NM, R>, ntiles);
     lp_pass_kernel<P, BP, NM, R><<<(unsigned)grid, 256, 0, s>>>(
         a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
         (const typename P::T*)a.T0, (const typename P::T*)a.Mk, a.mstride, (const typename P::T*)a.U, a.first,

@@ -323,11 +323,8 @@ static hipError_t launch_bp(const MultiDs* ds, const MultiTile* tiles, int64_t n
     return hipGetLastError();
 }
 
-template <typename P, int BP> static int occ2() {
-    int a = 0, c = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kfn<P, BP, false>(), 256, 0) != hipSuccess || a < 1) a = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, kfn<P, BP, true>(), 256, 0) != hipSuccess || c < 1) c = 1;
-    return a < c ? a : c;
+template <typename P, int BP> static int grid2(int64_t ntiles) {
+    return persistent_grid(kfn<P, BP, false>(), kfn<P, BP, true>(), ntiles);
 }
 
 }  // namespace
@@ -349,29 +346,18 @@ size_t multi_record_words(int64_t ntiles, int32_t b, bool is_int) {
     return (size_t)ntiles * (2 * 2 * wpv * (size_t)bpad2(b) + 1);
 }
 
+// the smaller occupancy of the two row-access variants, so that a plan's grid
+// does not depend on which one it launches
 int multi_grid(int64_t ntiles, int32_t b, bool is_int) {
-    static int cus = -1;
-    if (cus < 0) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-    }
-    // the smaller occupancy of the two row-access variants, so that a plan's
-    // grid does not depend on which one it launches
-    int nb = 1;
     switch (bpad2(b)) {
-    case 1: nb = is_int ? occ2<IntPath<int32_t>, 1>() : occ2<FloatPath, 1>(); break;
-    case 2: nb = is_int ? occ2<IntPath<int32_t>, 2>() : occ2<FloatPath, 2>(); break;
-    case 4: nb = is_int ? occ2<IntPath<int32_t>, 4>() : occ2<FloatPath, 4>(); break;
-    case 8: nb = is_int ? occ2<IntPath<int32_t>, 8>() : occ2<FloatPath, 8>(); break;
-    case 16: nb = is_int ? occ2<IntPath<int32_t>, 16>() : occ2<FloatPath, 16>(); break;
-    case 32: nb = is_int ? occ2<IntPath<int32_t>, 32>() : occ2<FloatPath, 32>(); break;
-    default: nb = is_int ? occ2<IntPath<int32_t>, 64>() : occ2<FloatPath, 64>(); break;
+    case 1: return is_int ? grid2<IntPath<int32_t>, 1>(ntiles) : grid2<FloatPath, 1>(ntiles);
+    case 2: return is_int ? grid2<IntPath<int32_t>, 2>(ntiles) : grid2<FloatPath, 2>(ntiles);
+    case 4: return is_int ? grid2<IntPath<int32_t>, 4>(ntiles) : grid2<FloatPath, 4>(ntiles);
+    case 8: return is_int ? grid2<IntPath<int32_t>, 8>(ntiles) : grid2<FloatPath, 8>(ntiles);
+    case 16: return is_int ? grid2<IntPath<int32_t>, 16>(ntiles) : grid2<FloatPath, 16>(ntiles);
+    case 32: return is_int ? grid2<IntPath<int32_t>, 32>(ntiles) : grid2<FloatPath, 32>(ntiles);
+    default: return is_int ? grid2<IntPath<int32_t>, 64>(ntiles) : grid2<FloatPath, 64>(ntiles);
     }
-    int64_t g = (int64_t)nb * cus;
-    if (g > ntiles) g = ntiles;
-    if (g < 1) g = 1;
-    return (int)g;
 }
 
 int multi_totals_rows() { return MT_ROWS; }

@@ -539,32 +539,10 @@ template <typename P, int BP, int V> struct Shape {
 template <int BP> constexpr int log2c() { return BP <= 1 ? 0 : 1 + log2c<BP / 2>(); }
 
 // Persistent grid: as many workgroups as fit on the device at once (never more
-// than one per tile).  Cached per kernel; every pass of one kernel shape gets
-// the same grid, which the ticket arithmetic relies on.
+// than one per tile), the same for every pass of one kernel shape on a device,
+// which the ticket arithmetic relies on (persistent_grid).
 static int persistent_grid_of(int64_t ntiles, const void* fn, const void* fn2) {
-    struct Entry { const void* fn; int per_cu; };
-    static Entry cache[64];
-    static int cached = 0, cus = -1;
-    if (cus < 0) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-    }
-    // the smaller occupancy of the two variants (vector and scalar row access)
-    // of one shape, so that every pass of the shape uses the same grid
-    int per_cu = 0;
-    for (int i = 0; i < cached; ++i)
-        if (cache[i].fn == fn) per_cu = cache[i].per_cu;
-    if (per_cu == 0) {
-        int nb = 0, nb2 = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, fn2, 256, 0) != hipSuccess || nb2 < 1) nb2 = 1;
-        per_cu = nb < nb2 ? nb : nb2;
-        if (cached < 64) cache[cached++] = Entry{fn, per_cu};
-    }
-    int64_t g = (int64_t)per_cu * cus;
-    if (g > ntiles) g = ntiles;
-    return (int)g;
+    return persistent_grid(fn, fn2, ntiles);
 }
 
 // single-column passes that write rather than add (OUT_FRESH): a kernel shape

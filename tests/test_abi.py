@@ -96,13 +96,25 @@ def test_prepare_matrix_argument_errors_before_device(L):
 
 def test_workspace_of_the_sort_free_metrics(L):
     n, d = 1000, 16
-    base = dm.workspace_size(n, d, dm.L4, dm.F32)
-    assert base >= n * d * 4                           # the point copy
-    assert dm.workspace_size(n, d, dm.L6, dm.I32) == base
-    assert dm.workspace_size(n, d, dm.CE, dm.F32) >= base + n * d * 8          # FP64 logarithms
+    # the workspace holds the point copy (and, for the divergences, the FP64
+    # logarithms; for the quadratic forms M and W) besides the query scratch
+    # of b <= 64, which depends on the metric's number of moments
+    assert dm.workspace_size(n, d, dm.L4, dm.F32) >= n * d * 4
+    assert dm.workspace_size(n, d, dm.L6, dm.I32) >= dm.workspace_size(n, d, dm.L4, dm.F32)
+    assert dm.workspace_size(n, d, dm.CE, dm.F32) >= n * d * (4 + 8)
     assert dm.workspace_size(n, d, dm.KL, dm.F32) == dm.workspace_size(n, d, dm.CE, dm.F32)
-    assert dm.workspace_size(n, d, dm.MAHA2, dm.F32) >= base + 2 * d * d * 8   # M and W
-    assert dm.workspace_size(n, d, dm.L4, dm.F32) < dm.workspace_size(n, d, dm.L1, dm.F32)   # no sort arrays
+    assert dm.workspace_size(n, d, dm.MAHA2, dm.F32) >= n * d * 4 + 2 * d * d * 8
+    big = 1 << 20   # no sort arrays: far smaller than l1's at a size where arrays dominate
+    assert dm.workspace_size(big, d, dm.L4, dm.F32) < dm.workspace_size(big, d, dm.L1, dm.F32) / 2
+
+
+def test_workspace_holds_the_query_memory(L):
+    """Everything a query of any b <= 64 needs lives in the workspace: it
+    grows linearly in n with no per-b part left to allocate later."""
+    for metric, dtype in ((dm.L1, dm.F32), (dm.L1, dm.I32), (dm.L3, dm.F32), (dm.L2SQ, dm.F32)):
+        a = dm.workspace_size(100000, 8, metric, dtype)
+        b = dm.workspace_size(200000, 8, metric, dtype)
+        assert b > a
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
