@@ -187,6 +187,26 @@ dm_status dm_prepare_matrix(const void* X, int64_t n, int32_t d, int32_t metric,
  */
 dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream);
 
+/*
+ * The same query as dm_matvec, for callers that cannot allocate device memory
+ * or do not want to hold the query part of the workspace busy: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  Its
+ * scratch (totals partials, the metric's scratch, the look-back records of the
+ * pass, and for a single l1 / TV column as many coordinates of the group
+ * buffer as fit) comes from the library's static device array of 32 MiB per
+ * GPU (held by every GPU the library runs on until the process ends) instead
+ * of the workspace.  Z, Out, the stream and the results are exactly those of
+ * dm_matvec (same kernels); the handle's workspace still holds the prepared
+ * data and the sticky status.  Allocates nothing.
+ * The array is shared by every call on a GPU and keeps the last call's
+ * contents (each call clears what must start at zero), so calls that overlap
+ * in time on one GPU, from any handle or stream, race: serialise them.
+ * The handle's device must be the current device.
+ * Errors: those of dm_matvec, and DM_ERR_ARG when the call's scratch exceeds
+ * the 32 MiB (large n x b shapes: use dm_matvec) or another device is current.
+ */
+dm_status dm_matvec_static(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream);
+
 /* Kept for callers that reserved query memory before the workspace held it:
  * checks b (1..64) and does nothing else, since the workspace already holds
  * every query's memory.  Errors: DM_ERR_ARG, DM_ERR_STATE (multi-dataset

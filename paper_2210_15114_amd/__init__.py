@@ -73,6 +73,8 @@ def lib():
     L.dm_prepare_matrix.restype = i32
     L.dm_matvec.argtypes = [P, P, i32, i32, P, P]
     L.dm_matvec.restype = i32
+    L.dm_matvec_static.argtypes = [P, P, i32, i32, P, P]
+    L.dm_matvec_static.restype = i32
     L.dm_reserve.argtypes = [P, i32]
     L.dm_reserve.restype = i32
     L.dm_sync.argtypes = [P]
@@ -209,6 +211,21 @@ class Handle:
                              _stream_ptr(stream))
         _check(st, "dm_matvec")
         return out.view(self.n) if squeeze and out.dim() == 2 else out
+
+    def matvec_static(self, Z, out, stream=None):
+        """Out = A Z through dm_matvec_static (scratch in the library's static
+        device array; allocates nothing).  out must be given (n x b)."""
+        squeeze = Z.dim() == 1
+        Zm = Z.unsqueeze(1) if squeeze else Z
+        if Zm.dim() != 2 or Zm.shape[0] != self.n:
+            raise ValueError("Z must be n x b")
+        b = Zm.shape[1]
+        if out.numel() != self.n * b:
+            raise ValueError("out has the wrong shape")
+        st = lib().dm_matvec_static(self._ptr, _dev_ptr(Zm, "Z"), _dtype_code(Zm.dtype), b, _dev_ptr(out, "out"),
+                                    _stream_ptr(stream))
+        _check(st, "dm_matvec_static")
+        return out
 
     def reserve(self, b: int):
         _check(lib().dm_reserve(self._ptr, b), "dm_reserve")

@@ -671,7 +671,8 @@ dm_status dm_reserve(dm_handle* h, int32_t b) {
 
 namespace {
 
-// Where a query's scratch lives (the handle's workspace for dm_matvec).
+// Where a query's scratch lives: the handle's workspace (dm_matvec) or the
+// library's static device array (dm_matvec_static).
 struct QueryMem {
     char* scratch = nullptr;       // totals partials, then the metric's scratch
     uint64_t* records = nullptr;   // one record block for the call's pass shape, or NULL: the workspace regions
@@ -869,6 +870,51 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         q.single_group = h->L.single_group;
     }
     return matvec_impl(h, Z, zkind, b, Out, (hipStream_t)stream, q);
+}
+
+dm_status dm_matvec_static(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream) {
+    int zkind = 0;
+    dm_status st = query_args(h, Z, z_dtype, b, Out, &zkind);
+    if (st != DM_OK) return st;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DM_ERR_DEVICE;
+    if (dev != h->device) return DM_ERR_ARG;   // the array of the handle's device must be current
+    // plan the call's memory inside the static array: query scratch, the
+    // record block of the pass shape, and (b = 1, l1 / TV) as many
+    // coordinates of the group buffer as fit
+    QueryMem q;
+    size_t at = al(query_scratch_bytes(h->n, h->d, h->metric, b));
+    size_t words = 0;
+    if (l1_pass_metric(h->metric)) {
+        const int v = variant_for(h, kind_index(h->is_int, zkind), log2_pad(b));
+        words = l1_shape(h->n, b, h->is_int, zkind, v).record_words;
+        if (b == 1) words = std::max(words, l1_single_shape(h->n, h->is_int, zkind, v).record_words);
+    } else if (lp_metric(h->metric)) {
+        words = lp_shape(h, b, zkind).record_words;
+    }
+    const size_t rec_at = at;
+    at += al(words * 8);
+    if (at > STATIC_SCRATCH_BYTES) return DM_ERR_ARG;   // beyond the array: use dm_matvec
+    char* base = nullptr;
+    if (static_scratch(&base) != hipSuccess) return DM_ERR_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    q.scratch = base;
+    if (words) {
+        q.records = (uint64_t*)(base + rec_at);
+        q.record_words = words;
+        // the array keeps the last call's records (any handle's): start from
+        // zero words, which carry no pass tag
+        DM_TRY(launch_fill_u32((uint32_t*)q.records, 0u, words * 2, s));
+    }
+    if (b == 1 && l1_pass_metric(h->metric)) {
+        const size_t per = (size_t)h->L.ld * (h->is_int ? 8 : 4);
+        const size_t g = (STATIC_SCRATCH_BYTES - at) / per;
+        if (g >= 1) {
+            q.single = base + at;
+            q.single_group = (int32_t)std::min<size_t>(g, (size_t)h->d);
+        }
+    }
+    return matvec_impl(h, Z, zkind, b, Out, s, q);
 }
 
 dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t variant) {

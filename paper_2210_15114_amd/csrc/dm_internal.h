@@ -89,6 +89,12 @@ hipError_t launch_rank_invert(const uint32_t* perm, int64_t ld, int64_t n, int32
 // with distinct handles and devices are safe.
 int persistent_grid(const void* fn, const void* fn2, int64_t ntiles);
 
+// The library's static device scratch (k_static.hip): STATIC_SCRATCH_BYTES
+// per device, for dm_matvec_static.  *ptr = its address on the current device
+// (looked up once per device).
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)32 << 20;
+hipError_t static_scratch(char** ptr);
+
 // ---- l1 query --------------------------------------------------------------
 // totals: T0[c] = sum_j z_jc, U[c] = sum_j w_j z_jc, |z_c|_1; with guards.
 struct TotalsOut {
