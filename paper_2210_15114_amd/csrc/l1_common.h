@@ -259,6 +259,7 @@ __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, c
                                                        P::cadd(s_part[2][t][c], s_part[3][t][c])));
                 }
                 hi = fin ? -1 : hi - take;
+                spins = 0;   // progress: the budget counts polls without progress
             } else if (++spins > LOOK_BACK_SPINS) {
                 if (lane == 0) atomicOr(status, (uint32_t)QF_STALL);
                 hi = -1;

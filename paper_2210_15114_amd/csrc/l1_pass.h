@@ -29,6 +29,10 @@
 // carries the prefixes between threads, waves and tiles as double-float
 // (hi, lo) FP32 pairs; inside a thread the short runs are plain FP32 relative
 // to that carry.  Integer data runs in wrapping int64, which is exact modulo
+// 2^64: only additions, subtractions and multiplications are used, so the
+// result is exact whenever |(A z)_i| < 2^63, which the guard
+// ||z||_1 sum_k range_k < 2^62 of the totals kernel ensures with a factor of
+// two to spare.
 //
 // This header holds the two pass kernels and their launch; it is compiled
 // once per data path (k_l1_f32.hip, k_l1_i32.hip, k_l1_i64.hip).

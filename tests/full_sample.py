@@ -47,28 +47,9 @@ def workload():
     return synth.workload3(N, D, B)
 
 
-def boundary_and_tie_rows(X):
-    """Scan-boundary points of coordinates 0 and d-1 and 16 rows of the longest
-    tie run of coordinate 0 (stable order, ties by ascending point index)."""
-    extra = []
-    for k in (0, X.shape[1] - 1):
-        o = np.argsort(X[:, k], kind="stable")
-        extra += [int(o[0]), int(o[-1])]
-    o = np.argsort(X[:, 0], kind="stable")
-    v = X[o, 0]
-    # runs of equal values in sorted order
-    starts = np.flatnonzero(np.concatenate([[True], v[1:] != v[:-1]]))
-    lens = np.diff(np.concatenate([starts, [v.size]]))
-    i = int(np.argmax(lens))
-    run = o[starts[i]:starts[i] + lens[i]]
-    extra += [int(r) for r in run[:16]]
-    return extra, int(lens[i])
-
-
 def sample_rows(X):
-    extra, tie_len = boundary_and_tie_rows(X)
-    rows = synth.subsample_rows(X.shape[0], M_ROWS, synth.seeds(3)["sub"], extra)
-    return rows, extra, tie_len
+    from oracle import sampling
+    return sampling.workload3_rows(X, M_ROWS)
 
 
 def rows_key(rows):
@@ -111,6 +92,18 @@ def cmd_oracle(a):
         print("%s: %d / %d rows (%.1f s per chunk)" % (a.metric, done, m, time.perf_counter() - t0), flush=True)
 
 
+SRCS = ("l1_pass.h", "l1_common.h", "k_l1.hip", "k_prep.hip", "k_sort.hip", "k_l2_mfma.hip", "k_l2.hip")
+
+
+def sources_hash():
+    """The kernel sources the sampled results come from (the benchmark reports
+    these figures only while the sources are unchanged)."""
+    h = hashlib.sha256()
+    for f in SRCS:
+        h.update(open(os.path.join(ROOT, "paper_2210_15114_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def fmt(e):
     return "spec %.3e  per_row %.3e  componentwise %.3e  max_abs %.3e" % (
         e["spec"], e["per_row"], e["componentwise"], e["max_abs"])
@@ -130,6 +123,7 @@ def cmd_errors(a):
              "# rows: %d uniform without replacement + %d boundary/tie rows (longest tie run of coordinate 0: %d)"
              % (M_ROWS, len(set(extra)), tie_len),
              "# GPU rows: %s" % os.path.basename(a.gpu),
+             "# sources_sha256_16: %s" % sources_hash(),
              "# command: python tests/full_sample.py errors --gpu %s --cache <dir>" % os.path.basename(a.gpu)]
     for metric, keys in (("l1", ("l1", "single")), ("l2sq", ("l2sq",))):
         path = cache_file(a.cache, metric, rows)
