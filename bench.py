@@ -334,7 +334,10 @@ def run_multi(args, dm, synth, np, torch, dev, stream):
     t0 = time.perf_counter()
     h = dm.prepare_multi(Xd)
     prep_ms = (time.perf_counter() - t0) * 1e3
-    outs = None
+    # tile variant of the coordinate-round launches, chosen by the library's
+    # tuner on these datasets (the winner's plan stays captured)
+    tv, tms, outs = h.tune(Zd, reps=3)
+    log("multi: tuned variant %d, ms per query %s" % (tv, ["%.2f" % t for t in tms]))
     for _ in range(max(1, args.warmup)):
         outs = h.matvec(Zd, outs)
     h.sync()
@@ -366,7 +369,8 @@ def run_multi(args, dm, synth, np, torch, dev, stream):
     res = {"datasets": len(specs), "b": b, "ms_per_query": round(ms, 3), "prep_ms": round(prep_ms, 1),
            "point_coords": pc, "point_coord_columns_per_s": pc * b / (ms * 1e-3),
            "model_GBps_effective": round(model / (ms * 1e-3) / 1e9, 1),
-           "spot_checked_datasets": checked, "float_componentwise_max": worst}
+           "spot_checked_datasets": checked, "float_componentwise_max": worst,
+           "tuned_variant": tv, "ms_per_query_by_variant": [round(t, 3) for t in tms]}
     h.free()
     return res
 
@@ -477,13 +481,15 @@ def main():
     avg_pass_ms = pass_ms / max(pass_n, 1)
     # run-to-run agreement of two identical queries (the chained scan adds a
     # timing-dependent set of predecessor records: not guaranteed bitwise)
-    iu = Out.view(torch.int32).to(torch.int64)
-    ju = Out2.view(torch.int32).to(torch.int64)
-    iu = torch.where(iu < 0, -(iu & 0x7fffffff), iu)      # monotone integer image of the floats
-    ju = torch.where(ju < 0, -(ju & 0x7fffffff), ju)
-    repro = {"max_ulps": int((iu - ju).abs().max().item()),
-             "identical_fraction": float((Out == Out2).float().mean().item())}
-    del iu, ju, Out2
+    # ulps are counted where |y| >= 2^-10 max|y| (near zero an ulp is
+    # meaningless); the largest difference is also given relative to max|y|
+    big = Out.abs() >= Out.abs().max() * 2.0 ** -10
+    ulp = torch.abs(torch.nextafter(Out, torch.full_like(Out, float("inf"))) - Out)
+    dif = (Out - Out2).abs()
+    repro = {"identical_fraction": float((Out == Out2).float().mean().item()),
+             "max_ulps_large": float((dif / ulp)[big].max().item()),
+             "max_diff_over_max_abs": float((dif.max() / Out.abs().max()).item())}
+    del big, ulp, dif, Out2
     log("batched: %.2f ms/step (wall %.2f ms), %.1f columns/s, pass %.3f ms x %d; run-to-run %s" %
         (ms_step, wall * 1e3 / args.steps, cols_s, avg_pass_ms, pass_n // prof_steps, repro))
 

@@ -305,6 +305,29 @@ dm_status dm_matvec_multi(dm_handle* h, const void* const* Z, int32_t b, void* c
 dm_status dm_multi_count(const dm_handle* h, int32_t* count);
 
 /*
+ * Tile tuning of the many-dataset query (the batching of the Appendix C lemma
+ * on products AB, taken over many point sets).  Each b has
+ * dm_multi_variant_count() tile variants of its coordinate-round launches
+ * (ranks per thread R, R / 2, and 2 R for b <= 8 or R / 4 for wider blocks),
+ * with identical results on integer datasets and results within the same
+ * bounds on float ones.  dm_tune_multi runs the caller's query (Z, Out as for
+ * dm_matvec_multi; Out receives A Z) once untimed and `reps` times timed with
+ * every variant's plan, keeps the fastest for later calls with this b (its
+ * plan stays captured) and stores it in *chosen; ms_per_query, if not NULL,
+ * receives dm_multi_variant_count() mean query times in milliseconds.  It
+ * synchronises `stream`; it allocates no device memory (every variant's plan
+ * fits the workspace's plan area).  dm_set_variant_multi fixes a variant for
+ * a b (host only), dm_get_variant_multi reports it.
+ * Errors: DM_ERR_ARG (NULL pointers, b outside 1..64, reps outside 1..4096,
+ * variant out of range), DM_ERR_STATE (single-dataset handle), DM_ERR_DEVICE.
+ */
+int32_t dm_multi_variant_count(void);
+dm_status dm_tune_multi(dm_handle* h, const void* const* Z, int32_t b, void* const* Out, int32_t reps, void* stream,
+                        int32_t* chosen, double* ms_per_query);
+dm_status dm_set_variant_multi(dm_handle* h, int32_t b, int32_t variant);
+dm_status dm_get_variant_multi(dm_handle* h, int32_t b, int32_t* variant);
+
+/*
  * Rank-k approximation A ~ U diag(lam) U^T by block Krylov iteration, using
  * only products with A (the query model of Section 1; Appendix C.1 cites
  * block Krylov methods for the top singular values, and Table 2 lists the

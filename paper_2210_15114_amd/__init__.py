@@ -99,6 +99,15 @@ def lib():
     L.dm_prepare_multi.restype = i32
     L.dm_matvec_multi.argtypes = [P, ctypes.POINTER(P), i32, ctypes.POINTER(P), P]
     L.dm_matvec_multi.restype = i32
+    L.dm_multi_variant_count.argtypes = []
+    L.dm_multi_variant_count.restype = i32
+    L.dm_tune_multi.argtypes = [P, ctypes.POINTER(P), i32, ctypes.POINTER(P), i32, P, ctypes.POINTER(i32),
+                                ctypes.POINTER(ctypes.c_double)]
+    L.dm_tune_multi.restype = i32
+    L.dm_set_variant_multi.argtypes = [P, i32, i32]
+    L.dm_set_variant_multi.restype = i32
+    L.dm_get_variant_multi.argtypes = [P, i32, ctypes.POINTER(i32)]
+    L.dm_get_variant_multi.restype = i32
     L.dm_multi_count.argtypes = [P, ctypes.POINTER(i32)]
     L.dm_multi_count.restype = i32
     L.dm_variant_count.argtypes = []
@@ -372,8 +381,7 @@ class MultiHandle:
         self.shapes = shapes          # [(n, d)]
         self.dtypes = dtypes          # dtype codes
 
-    def matvec(self, Zs, outs=None, stream=None):
-        """Outs[s] = A_s Zs[s] for every dataset (same b for all)."""
+    def _ptrs(self, Zs, outs):
         torch = _torch()
         if len(Zs) != len(self.shapes):
             raise ValueError("one Z per dataset")
@@ -392,8 +400,32 @@ class MultiHandle:
             zp[i] = _dev_ptr(Z, "Z").value
             op[i] = _dev_ptr(O, "out").value
         self._keep = (Zs, outs)       # the graph reads these pointers when it runs
+        return b, zp, op, outs
+
+    def matvec(self, Zs, outs=None, stream=None):
+        """Outs[s] = A_s Zs[s] for every dataset (same b for all)."""
+        b, zp, op, outs = self._ptrs(Zs, outs)
         _check(lib().dm_matvec_multi(self._ptr, zp, b, op, _stream_ptr(stream)), "dm_matvec_multi")
         return outs
+
+    def tune(self, Zs, outs=None, reps: int = 3, stream=None):
+        """Time every tile variant of the query on these right-hand sides and
+        keep the fastest; returns (variant, [ms per query per variant], outs)."""
+        b, zp, op, outs = self._ptrs(Zs, outs)
+        nv = lib().dm_multi_variant_count()
+        ch = ctypes.c_int32(0)
+        ms = (ctypes.c_double * nv)()
+        _check(lib().dm_tune_multi(self._ptr, zp, b, op, reps, _stream_ptr(stream), ctypes.byref(ch), ms),
+               "dm_tune_multi")
+        return ch.value, list(ms), outs
+
+    def set_variant(self, b: int, variant: int):
+        _check(lib().dm_set_variant_multi(self._ptr, b, variant), "dm_set_variant_multi")
+
+    def get_variant(self, b: int) -> int:
+        v = ctypes.c_int32(0)
+        _check(lib().dm_get_variant_multi(self._ptr, b, ctypes.byref(v)), "dm_get_variant_multi")
+        return v.value
 
     def sync(self):
         _check(lib().dm_sync(self._ptr), "dm_sync")

@@ -1253,6 +1253,7 @@ struct MultiPlan {
     uint64_t* tickets = nullptr;   // one per (round, kind)
     double* partials = nullptr;
     double* tot = nullptr;         // per dataset: T0 (b) and U (b)
+    int variant = 0;               // tile variant of the plan's pass launches
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -1284,6 +1285,7 @@ struct MultiState {
     uint32_t* d_blk = nullptr;   // dataset of every totals block
     int nblk = 0;
     MultiPlan plan;
+    int8_t variant[7] = {0, 0, 0, 0, 0, 0, 0};   // tile variant per log2 of the padded b (set or tuned)
     hipStream_t cap = nullptr;   // capture stream
     hipEvent_t done = nullptr;   // recorded after every graph launch
     bool launched = false;
@@ -1360,12 +1362,13 @@ dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSe
     M.tot = take((size_t)count * 2 * MAX_B * 8);
     M.partials = take((size_t)M.nblk * MAX_B * 3 * 8 + 8);
     // per (round, kind): the tile table and the record region of that
-    // round's launch; both depend on b through the tile size
-    for (int32_t b = 1; b <= MAX_B; ++b) {
+    // round's launch; both depend on b and the tile variant through the tile size
+    for (int32_t b = 1; b <= MAX_B; ++b)
+        for (int var = 0; var < MULTI_VARIANTS; ++var) {
         size_t bytes = 0;
         for (int k = 0; k < maxd; ++k)
             for (int kind = 0; kind < 2; ++kind) {
-                const int tr = multi_tile_ranks(b, kind == 1);
+                const int tr = multi_tile_ranks(b, kind == 1, var);
                 int64_t nt = 0;
                 for (auto& m : v)
                     if (m.is_int == (kind == 1) && m.d > k) nt += (m.n + tr - 1) / tr;
@@ -1373,7 +1376,7 @@ dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSe
                 bytes += al((size_t)nt * sizeof(MultiTile)) + al(multi_record_words(nt, b, kind == 1) * 8);
             }
         M.plan_bytes = std::max(M.plan_bytes, bytes);
-    }
+        }
     M.plan = take(M.plan_bytes);
     M.total = o;
     if (out) *out = std::move(v);
@@ -1381,14 +1384,16 @@ dm_status check_multi(const dm_dataset* sets, int32_t count, std::vector<MultiSe
     return DM_OK;
 }
 
-// Build the round tables, record regions and the captured graph for b.
-dm_status build_plan(dm_handle* h, int32_t b, bool vec) {
+// Build the round tables, record regions and the captured graph for b and
+// tile variant v.
+dm_status build_plan(dm_handle* h, int32_t b, bool vec, int v) {
     MultiState* m = h->multi;
     MultiPlan& p = m->plan;
     if (m->launched) DM_TRY(hipEventSynchronize(m->done));
     free_plan(p);
     p.b = b;
     p.vec = vec;
+    p.variant = v;
     p.rounds = m->maxd;
     const int nsets = (int)m->sets.size();
     // per-dataset totals storage and descriptors
@@ -1413,7 +1418,7 @@ dm_status build_plan(dm_handle* h, int32_t b, bool vec) {
     p.records.assign((size_t)p.rounds * 2, nullptr);
     for (int k = 0; k < p.rounds; ++k)
         for (int kind = 0; kind < 2; ++kind) {
-            const int tr = multi_tile_ranks(b, kind == 1);
+            const int tr = multi_tile_ranks(b, kind == 1, v);
             std::vector<MultiTile> t;
             for (int s : order) {
                 const MultiSet& ms = m->sets[s];
@@ -1435,7 +1440,7 @@ dm_status build_plan(dm_handle* h, int32_t b, bool vec) {
             at += al(words * 8);
             p.records[ix] = (uint64_t*)q;
             DM_TRY(launch_fill_u32((uint32_t*)q, 0u, words * 2, m->cap));
-            p.grids[ix] = multi_grid((int64_t)t.size(), b, kind == 1);
+            p.grids[ix] = multi_grid((int64_t)t.size(), b, kind == 1, v);
             DM_TRY(hipStreamSynchronize(m->cap));   // the host vector dies with this scope
         }
     // capture: descriptor upload, totals, every round
@@ -1448,7 +1453,7 @@ dm_status build_plan(dm_handle* h, int32_t b, bool vec) {
             const size_t ix = (size_t)k * 2 + kind;
             if (p.ntiles[ix] == 0) continue;
             e = launch_multi_pass(kind == 1, b, m->d_ds, p.tiles[ix], p.ntiles[ix], k, p.tickets + ix, p.records[ix],
-                                  p.grids[ix], p.vec, &h->ctl->status, m->cap);
+                                  p.grids[ix], p.vec, &h->ctl->status, v, m->cap);
         }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(m->cap, &g);
@@ -1667,11 +1672,13 @@ dm_status dm_matvec_multi(dm_handle* h, const void* const* Z, int32_t b, void* c
         if (zp < op + ob && op < zp + zb) return DM_ERR_ARG;
     }
     // 16-byte row accesses when every row of every dataset allows them; a
-    // plan captured for the other choice is rebuilt
+    // plan captured for the other choice (or another tile variant) is rebuilt
     bool vec = b % 4 == 0;
     for (int i = 0; i < nsets && vec; ++i) vec = ((uintptr_t)Z[i] % 16 == 0) && ((uintptr_t)Out[i] % 16 == 0);
+    const int v = m->variant[log2_pad(b)];
     dm_status st;
-    if ((m->plan.b != b || m->plan.vec != vec) && (st = build_plan(h, b, vec)) != DM_OK) return st;
+    if ((m->plan.b != b || m->plan.vec != vec || m->plan.variant != v) && (st = build_plan(h, b, vec, v)) != DM_OK)
+        return st;
     // refresh the pointer table only when it changes (the previous launch's
     // upload must have run before the pinned mirror is rewritten)
     bool same = true;
@@ -1688,6 +1695,72 @@ dm_status dm_matvec_multi(dm_handle* h, const void* const* Z, int32_t b, void* c
     DM_TRY(hipEventRecord(m->done, s));
     m->launched = true;
     h->last = s;
+    return DM_OK;
+}
+
+int32_t dm_multi_variant_count(void) { return MULTI_VARIANTS; }
+
+dm_status dm_set_variant_multi(dm_handle* h, int32_t b, int32_t variant) {
+    if (!h || b < 1 || b > MAX_B || variant < 0 || variant >= MULTI_VARIANTS) return DM_ERR_ARG;
+    if (!h->multi) return DM_ERR_STATE;
+    h->multi->variant[log2_pad(b)] = (int8_t)variant;
+    return DM_OK;
+}
+
+dm_status dm_get_variant_multi(dm_handle* h, int32_t b, int32_t* variant) {
+    if (!h || !variant || b < 1 || b > MAX_B) return DM_ERR_ARG;
+    if (!h->multi) return DM_ERR_STATE;
+    *variant = h->multi->variant[log2_pad(b)];
+    return DM_OK;
+}
+
+dm_status dm_tune_multi(dm_handle* h, const void* const* Z, int32_t b, void* const* Out, int32_t reps, void* stream,
+                        int32_t* chosen, double* ms_per_query) {
+    if (!h || !Z || !Out || b < 1 || b > MAX_B || reps < 1 || reps > 4096) return DM_ERR_ARG;
+    if (!h->multi) return DM_ERR_STATE;
+    MultiState* m = h->multi;
+    hipStream_t s = (hipStream_t)stream;
+    const int lg = log2_pad(b);
+    const int8_t keep = m->variant[lg];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best = 1e300;
+    int bestv = 0;
+    // every variant: one untimed query (which builds its plan), then reps
+    // timed graph launches on the caller's own right-hand sides
+    auto run = [&]() -> dm_status {
+        DM_TRY(hipEventCreate(&e0));
+        DM_TRY(hipEventCreate(&e1));
+        for (int v = 0; v < MULTI_VARIANTS; ++v) {
+            m->variant[lg] = (int8_t)v;
+            dm_status st = dm_matvec_multi(h, Z, b, Out, stream);
+            if (st != DM_OK) return st;
+            DM_TRY(hipEventRecord(e0, s));
+            for (int i = 0; i < reps; ++i)
+                if ((st = dm_matvec_multi(h, Z, b, Out, stream)) != DM_OK) return st;
+            DM_TRY(hipEventRecord(e1, s));
+            DM_TRY(hipEventSynchronize(e1));
+            float t = 0.0f;
+            DM_TRY(hipEventElapsedTime(&t, e0, e1));
+            const double per = (double)t / reps;
+            if (ms_per_query) ms_per_query[v] = per;
+            if (per < best) {
+                best = per;
+                bestv = v;
+            }
+        }
+        return DM_OK;
+    };
+    dm_status st = run();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != DM_OK) {
+        m->variant[lg] = keep;
+        return st;
+    }
+    m->variant[lg] = (int8_t)bestv;
+    // leave the winner's plan captured (and Out holding its result)
+    if ((st = dm_matvec_multi(h, Z, b, Out, stream)) != DM_OK) return st;
+    if (chosen) *chosen = bestv;
     return DM_OK;
 }
 

@@ -177,16 +177,19 @@ struct MultiTile {
     uint32_t ds;  // dataset
     uint32_t t;   // tile index inside the dataset's coordinate segment
 };
-int multi_tile_ranks(int32_t b, bool is_int);
+// tile variants of the multi-dataset pass (ranks per slot R, R / 2, and 2 R for
+// up to 8 columns or R / 4 beyond), chosen per handle and b by dm_tune_multi
+constexpr int MULTI_VARIANTS = 3;
+int multi_tile_ranks(int32_t b, bool is_int, int variant);
 size_t multi_record_words(int64_t ntiles, int32_t b, bool is_int);
-int multi_grid(int64_t ntiles, int32_t b, bool is_int);
+int multi_grid(int64_t ntiles, int32_t b, bool is_int, int variant);
 int multi_totals_rows();
 hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nblocks, int ndatasets, int32_t b,
                                double* partials, uint32_t* status, hipStream_t s);
 // vec: 16-byte row accesses; needs b % 4 == 0 and 16-byte aligned Z and Out of every dataset
 hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
                              int k, uint64_t* ticket, uint64_t* records, int grid, bool vec, uint32_t* status,
-                             hipStream_t s);
+                             int variant, hipStream_t s);
 
 // ---- block-Krylov low rank (k_lowrank.hip) ---------------------------------
 int lr_max_block();

@@ -289,8 +289,15 @@ __global__ __launch_bounds__(256, 2) void multi_pass_kernel(const MultiDs* __res
     }
 }
 
-// ranks per slot of the multi-dataset pass (register-resident tiles)
+// ranks per slot of the multi-dataset pass (register-resident tiles): the
+// default R, and the tile variants the tuner chooses from (V = 0: R, 1: R / 2,
+// 2: 2 R for blocks of up to 8 columns, R / 4 for wider ones)
 template <int BP, bool INT> constexpr int mr() { return INT ? (BP >= 16 ? 4 : 8) : (BP >= 32 ? 8 : 16); }
+template <int BP, bool INT, int V> constexpr int mrv() {
+    return V == 0 ? mr<BP, INT>()
+                  : V == 1 ? (mr<BP, INT>() / 2 > 0 ? mr<BP, INT>() / 2 : 1)
+                           : (BP <= 8 ? 2 * mr<BP, INT>() : (mr<BP, INT>() / 4 > 0 ? mr<BP, INT>() / 4 : 1));
+}
 template <int BP, int R> constexpr int moc() { return BP >= 4 ? (R >= 4 ? 4 : R) : R; }
 
 static int bpad2(int32_t b) {
@@ -299,21 +306,22 @@ static int bpad2(int32_t b) {
     return bp;
 }
 
-template <int BP, bool INT> static int mtile() { return Lay<BP>::NS * mr<BP, INT>(); }
+template <int BP, bool INT, int V> static int mtile() { return Lay<BP>::NS * mrv<BP, INT, V>(); }
 
-template <typename P, int BP, bool VEC>
+template <typename P, int BP, int V, bool VEC>
 static const void* kfn() {
     constexpr bool INT = !std::is_same<P, FloatPath>::value;
-    return (const void*)multi_pass_kernel<P, BP, mr<BP, INT>(), moc<BP, mr<BP, INT>()>(), VEC>;
+    constexpr int R = mrv<BP, INT, V>();
+    return (const void*)multi_pass_kernel<P, BP, R, moc<BP, R>(), VEC>;
 }
 
 // VEC: 16-byte row accesses (b % 4 == 0 and every Z and Out row 16-byte
 // aligned, checked by the caller for all datasets)
-template <typename P, int BP>
-static hipError_t launch_bp(const MultiDs* ds, const MultiTile* tiles, int64_t ntiles, int k, int32_t b,
-                            uint64_t* ctr, uint64_t* rec, int grid, bool vec, uint32_t* status, hipStream_t s) {
+template <typename P, int BP, int V>
+static hipError_t launch_bpv(const MultiDs* ds, const MultiTile* tiles, int64_t ntiles, int k, int32_t b,
+                             uint64_t* ctr, uint64_t* rec, int grid, bool vec, uint32_t* status, hipStream_t s) {
     constexpr bool INT = !std::is_same<P, FloatPath>::value;
-    constexpr int R = mr<BP, INT>();
+    constexpr int R = mrv<BP, INT, V>();
     constexpr int TILEW = 2 * 2 * P::WPV * BP;
     uint64_t* stat = rec + (size_t)ntiles * TILEW;
     if (vec)
@@ -323,21 +331,40 @@ static hipError_t launch_bp(const MultiDs* ds, const MultiTile* tiles, int64_t n
     return hipGetLastError();
 }
 
-template <typename P, int BP> static int grid2(int64_t ntiles) {
-    return persistent_grid(kfn<P, BP, false>(), kfn<P, BP, true>(), ntiles);
+template <typename P, int BP>
+static hipError_t launch_bp(const MultiDs* ds, const MultiTile* tiles, int64_t ntiles, int k, int32_t b,
+                            uint64_t* ctr, uint64_t* rec, int grid, bool vec, uint32_t* status, int v, hipStream_t s) {
+    switch (v) {
+    case 0: return launch_bpv<P, BP, 0>(ds, tiles, ntiles, k, b, ctr, rec, grid, vec, status, s);
+    case 1: return launch_bpv<P, BP, 1>(ds, tiles, ntiles, k, b, ctr, rec, grid, vec, status, s);
+    case 2: return launch_bpv<P, BP, 2>(ds, tiles, ntiles, k, b, ctr, rec, grid, vec, status, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename P, int BP> static int grid2(int64_t ntiles, int v) {
+    switch (v) {
+    case 0: return persistent_grid(kfn<P, BP, 0, false>(), kfn<P, BP, 0, true>(), ntiles);
+    case 1: return persistent_grid(kfn<P, BP, 1, false>(), kfn<P, BP, 1, true>(), ntiles);
+    default: return persistent_grid(kfn<P, BP, 2, false>(), kfn<P, BP, 2, true>(), ntiles);
+    }
+}
+
+template <int BP, bool INT> static int mtile_v(int v) {
+    return v == 0 ? mtile<BP, INT, 0>() : v == 1 ? mtile<BP, INT, 1>() : mtile<BP, INT, 2>();
 }
 
 }  // namespace
 
-int multi_tile_ranks(int32_t b, bool is_int) {
+int multi_tile_ranks(int32_t b, bool is_int, int v) {
     switch (bpad2(b)) {
-    case 1: return is_int ? mtile<1, true>() : mtile<1, false>();
-    case 2: return is_int ? mtile<2, true>() : mtile<2, false>();
-    case 4: return is_int ? mtile<4, true>() : mtile<4, false>();
-    case 8: return is_int ? mtile<8, true>() : mtile<8, false>();
-    case 16: return is_int ? mtile<16, true>() : mtile<16, false>();
-    case 32: return is_int ? mtile<32, true>() : mtile<32, false>();
-    default: return is_int ? mtile<64, true>() : mtile<64, false>();
+    case 1: return is_int ? mtile_v<1, true>(v) : mtile_v<1, false>(v);
+    case 2: return is_int ? mtile_v<2, true>(v) : mtile_v<2, false>(v);
+    case 4: return is_int ? mtile_v<4, true>(v) : mtile_v<4, false>(v);
+    case 8: return is_int ? mtile_v<8, true>(v) : mtile_v<8, false>(v);
+    case 16: return is_int ? mtile_v<16, true>(v) : mtile_v<16, false>(v);
+    case 32: return is_int ? mtile_v<32, true>(v) : mtile_v<32, false>(v);
+    default: return is_int ? mtile_v<64, true>(v) : mtile_v<64, false>(v);
     }
 }
 
@@ -348,15 +375,15 @@ size_t multi_record_words(int64_t ntiles, int32_t b, bool is_int) {
 
 // the smaller occupancy of the two row-access variants, so that a plan's grid
 // does not depend on which one it launches
-int multi_grid(int64_t ntiles, int32_t b, bool is_int) {
+int multi_grid(int64_t ntiles, int32_t b, bool is_int, int v) {
     switch (bpad2(b)) {
-    case 1: return is_int ? grid2<IntPath<int32_t>, 1>(ntiles) : grid2<FloatPath, 1>(ntiles);
-    case 2: return is_int ? grid2<IntPath<int32_t>, 2>(ntiles) : grid2<FloatPath, 2>(ntiles);
-    case 4: return is_int ? grid2<IntPath<int32_t>, 4>(ntiles) : grid2<FloatPath, 4>(ntiles);
-    case 8: return is_int ? grid2<IntPath<int32_t>, 8>(ntiles) : grid2<FloatPath, 8>(ntiles);
-    case 16: return is_int ? grid2<IntPath<int32_t>, 16>(ntiles) : grid2<FloatPath, 16>(ntiles);
-    case 32: return is_int ? grid2<IntPath<int32_t>, 32>(ntiles) : grid2<FloatPath, 32>(ntiles);
-    default: return is_int ? grid2<IntPath<int32_t>, 64>(ntiles) : grid2<FloatPath, 64>(ntiles);
+    case 1: return is_int ? grid2<IntPath<int32_t>, 1>(ntiles, v) : grid2<FloatPath, 1>(ntiles, v);
+    case 2: return is_int ? grid2<IntPath<int32_t>, 2>(ntiles, v) : grid2<FloatPath, 2>(ntiles, v);
+    case 4: return is_int ? grid2<IntPath<int32_t>, 4>(ntiles, v) : grid2<FloatPath, 4>(ntiles, v);
+    case 8: return is_int ? grid2<IntPath<int32_t>, 8>(ntiles, v) : grid2<FloatPath, 8>(ntiles, v);
+    case 16: return is_int ? grid2<IntPath<int32_t>, 16>(ntiles, v) : grid2<FloatPath, 16>(ntiles, v);
+    case 32: return is_int ? grid2<IntPath<int32_t>, 32>(ntiles, v) : grid2<FloatPath, 32>(ntiles, v);
+    default: return is_int ? grid2<IntPath<int32_t>, 64>(ntiles, v) : grid2<FloatPath, 64>(ntiles, v);
     }
 }
 
@@ -374,15 +401,16 @@ hipError_t launch_multi_totals(const MultiDs* ds, const uint32_t* blk_ds, int nb
 
 hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const MultiTile* tiles, int64_t ntiles,
                              int k, uint64_t* ticket, uint64_t* records, int grid, bool vec, uint32_t* status,
-                             hipStream_t s)
+                             int v, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     if (vec && b % 4 != 0) return hipErrorInvalidValue;
+    if (v < 0 || v >= MULTI_VARIANTS) return hipErrorInvalidValue;
     switch (bpad2(b)) {
 #define DM_MCASE(BP)                                                                                         \
     case BP:                                                                                                 \
-        return is_int ? launch_bp<IntPath<int32_t>, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, status, s) \
-                      : launch_bp<FloatPath, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, status, s);
+        return is_int ? launch_bp<IntPath<int32_t>, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, status, v, s) \
+                      : launch_bp<FloatPath, BP>(ds, tiles, ntiles, k, b, ticket, records, grid, vec, status, v, s);
         DM_MCASE(1) DM_MCASE(2) DM_MCASE(4) DM_MCASE(8) DM_MCASE(16) DM_MCASE(32) DM_MCASE(64)
 #undef DM_MCASE
     default: return hipErrorInvalidValue;

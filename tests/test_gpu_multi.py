@@ -92,3 +92,31 @@ def test_multi_rejects_wrong_use():
     z = (ctypes.c_void_p * 1)(1)
     o = (ctypes.c_void_p * 1)(2)
     assert dm.lib().dm_matvec_multi(single._ptr, z, 1, o, None) == dm.ERR_STATE
+
+
+@pytest.mark.parametrize("b", [1, 8, 40])
+def test_every_tile_variant_matches_the_oracle(b):
+    """Each tile variant of the many-dataset pass (set explicitly), on the
+    same datasets: integer sets bit-exact, float sets within the bounds; then
+    the tuner times them all and keeps one."""
+    Xs = _sets(1300 + b)
+    g = synth.rng(1310 + b)
+    Zs = [_rhs(X, b, g) for X in Xs]
+    h = dm.prepare_multi([dev(X) for X in Xs])
+    Zd = [dev(Z) for Z in Zs]
+    count = dm.lib().dm_multi_variant_count()
+    assert count >= 2
+    for v in range(count):
+        h.set_variant(b, v)
+        assert h.get_variant(b) == v
+        outs = h.matvec(Zd)
+        h.sync()
+        for X, Z, O in zip(Xs, Zs, outs):
+            _check(X, Z, O.cpu().numpy())
+    v, ms, outs = h.tune(Zd, reps=2)
+    h.sync()
+    assert 0 <= v < count and len(ms) == count and min(ms) > 0
+    assert h.get_variant(b) == v
+    for X, Z, O in zip(Xs, Zs, outs):
+        _check(X, Z, O.cpu().numpy())
+    h.free()
