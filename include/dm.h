@@ -180,8 +180,16 @@ dm_status dm_prepare_matrix(const void* X, int64_t n, int32_t d, int32_t metric,
  * Z: device n x b of `z_dtype` (DM_F32 for float data; DM_I32 or DM_I64 for
  * integer data).  Out: device n x b, float or int64.  Z and Out must not
  * overlap.  1 <= b <= 64.
- * Stream-ordered and asynchronous: it only enqueues kernels on `stream`, in
- * the handle's workspace; it neither allocates device memory nor waits.
+ * Stream-ordered and asynchronous: it only enqueues work on `stream`, in the
+ * handle's workspace; it neither allocates device memory nor waits.  The
+ * first call with a given (Z, Out, b, z_dtype) records the query's launches
+ * (totals and one pass per coordinate for l1) in a hipGraph on a private
+ * capture stream, and later calls with the same arguments replay it with one
+ * hipGraphLaunch; the handle keeps the 4 most recently used graphs (evicting
+ * one waits for the handle's last stream).  Replays read Z and write Out at
+ * the recorded addresses, so the contents may change between calls.  While
+ * profiling is on (dm_profile_enable), or with the environment variable
+ * DM_QUERY_GRAPH=0 at preparation, queries are launched eagerly instead.
  * Errors (synchronous): DM_ERR_ARG, DM_ERR_DTYPE, DM_ERR_DEVICE.
  * Errors (sticky, via dm_sync): DM_ERR_NONFINITE, DM_ERR_OVERFLOW.
  */

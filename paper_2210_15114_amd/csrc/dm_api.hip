@@ -252,6 +252,15 @@ struct dm_handle {
     double guard_scale = 0.0;   // sum over the coordinates of range^p
     bool symmetric = true;      // A = A^T (false for the divergences and a non-symmetric bilinear form)
     hipStream_t last = nullptr;
+    // Captured queries: dm_matvec records a query's launches once per
+    // (Z, Out, b, right-hand-side type) in a hipGraph on a private capture
+    // stream and replays it afterwards (least recently used of GRAPHS kept).
+    struct Graph { const void* Z; void* Out; int32_t b; int zkind; hipGraphExec_t exec; uint64_t used; };
+    static constexpr int GRAPHS = 4;
+    std::vector<Graph> graphs;
+    uint64_t graph_clock = 0;
+    hipStream_t cap = nullptr;
+    bool use_graphs = true;
     // tile variant of the l1 pass per (data path, log2 of the padded block
     // width); -1 until set, tuned or found in the tuning cache (then 0)
     int8_t variant[3][8];
@@ -272,9 +281,17 @@ namespace {
 
 void release_multi(MultiState* m);
 
+void drop_graphs(dm_handle* h) {
+    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
+
 void release(dm_handle* h) {
     if (!h) return;
     if (h->multi) release_multi(h->multi);
+    if (!h->graphs.empty() && h->last) (void)hipStreamSynchronize(h->last);
+    drop_graphs(h);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     for (auto& e : h->evs) {
         if (e.a) (void)hipEventDestroy(e.a);
         if (e.b) (void)hipEventDestroy(e.b);
@@ -571,6 +588,10 @@ static dm_status prepare_impl(const void* X, int64_t n, int32_t d, int32_t metri
     h->L = L;
     std::memset(h->variant, -1, sizeof h->variant);
     arch_name(dev, h->arch);
+    {   // DM_QUERY_GRAPH=0: launch every query eagerly instead of replaying graphs
+        const char* e = std::getenv("DM_QUERY_GRAPH");
+        h->use_graphs = !(e && e[0] == '0');
+    }
     auto fail = [&](dm_status e) {
         release(h);
         return e;
@@ -861,7 +882,7 @@ extern "C" {
 
 dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream) {
     int zkind = 0;
-    const dm_status st = query_args(h, Z, z_dtype, b, Out, &zkind);
+    dm_status st = query_args(h, Z, z_dtype, b, Out, &zkind);
     if (st != DM_OK) return st;
     QueryMem q;
     q.scratch = h->ws + h->L.qscratch;
@@ -869,7 +890,44 @@ dm_status dm_matvec(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, voi
         q.single = h->ws + h->L.single;
         q.single_group = h->L.single_group;
     }
-    return matvec_impl(h, Z, zkind, b, Out, (hipStream_t)stream, q);
+    hipStream_t s = (hipStream_t)stream;
+    // profiling brackets every launch with events: run those queries eagerly
+    if (!h->use_graphs || h->prof) return matvec_impl(h, Z, zkind, b, Out, s, q);
+    for (auto& g : h->graphs)
+        if (g.Z == Z && g.Out == Out && g.b == b && g.zkind == zkind) {
+            g.used = ++h->graph_clock;
+            DM_TRY(hipGraphLaunch(g.exec, s));
+            h->last = s;
+            return DM_OK;
+        }
+    // record the query's launches (nothing runs during the capture), then
+    // launch the graph on the caller's stream
+    if (!h->cap) DM_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    DM_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    st = matvec_impl(h, Z, zkind, b, Out, h->cap, q);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->cap, &graph);
+    if (st != DM_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != DM_OK ? st : from_hip(ec);
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return from_hip(ei);
+    if ((int)h->graphs.size() == dm_handle::GRAPHS) {
+        auto lru = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                    [](const dm_handle::Graph& a, const dm_handle::Graph& c) { return a.used < c.used; });
+        // a replay of the evicted graph may still be queued on some stream:
+        // wait for the handle's last stream before destroying it
+        if (h->last) DM_TRY(hipStreamSynchronize(h->last));
+        (void)hipGraphExecDestroy(lru->exec);
+        h->graphs.erase(lru);
+    }
+    h->graphs.push_back(dm_handle::Graph{Z, Out, b, zkind, exec, ++h->graph_clock});
+    DM_TRY(hipGraphLaunch(exec, s));
+    h->last = s;
+    return DM_OK;
 }
 
 dm_status dm_matvec_static(dm_handle* h, const void* Z, int32_t z_dtype, int32_t b, void* Out, void* stream) {
@@ -925,6 +983,7 @@ dm_status dm_set_variant(dm_handle* h, int32_t b, int32_t z_dtype, int32_t varia
     const dm_status st = zkind_of(h, z_dtype, &zkind);
     if (st != DM_OK) return st;
     h->variant[kind_index(h->is_int, zkind)][log2_pad(b)] = (int8_t)variant;
+    drop_graphs(h);   // captured queries hold the old variant's launches
     return DM_OK;
 }
 
@@ -1013,6 +1072,7 @@ dm_status dm_tune(dm_handle* h, int32_t b, int32_t z_dtype, int32_t reps, void* 
     if (Ot) (void)hipFree(Ot);
     if (st != DM_OK) return st;
     h->variant[kind][lg] = (int8_t)bestv;
+    drop_graphs(h);
     cache_store(h, kind, lg, bestv);
     if (chosen) *chosen = bestv;
     h->last = s;
