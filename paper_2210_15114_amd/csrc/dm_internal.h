@@ -281,6 +281,7 @@ hipError_t launch_maha_weights(const float* X, const double* centre, int64_t n, 
 
 // ---- l2 squared query ------------------------------------------------------
 size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b);
+size_t l2_mfma_scratch_bytes(int64_t n, int32_t d, int32_t b);
 hipError_t launch_l2sq(bool is_int, int zkind, const void* Xc, const void* nrm, int64_t n, int32_t d,
                        const void* Z, int32_t b, void* Out, void* scratch, const TotalsOut& tot,
                        double guard_scale, hipStream_t s);

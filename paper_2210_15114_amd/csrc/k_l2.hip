@@ -139,24 +139,31 @@ size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b) {
     const size_t nblk = (size_t)((n + VROWS - 1) / VROWS);
     const size_t vec = (nblk + 1) * (size_t)d * (size_t)b * 8 + 256;
     const size_t lin = sf_scratch_bytes(n, d, b, SF_LIN, 1);
-    return vec > lin ? vec : lin;
+    const size_t mf = l2_mfma_scratch_bytes(n, d, b);
+    const size_t m = vec > lin ? vec : lin;
+    return m > mf ? m : mf;
 }
 
-hipError_t launch_l2sq_mfma(const float* Xc, const double* nrm, int64_t n, int32_t d, const float* Z, int32_t b,
-                            float* Out, void* scratch, const TotalsOut& tot, hipStream_t s, bool* used);
+hipError_t launch_l2sq_mfma(int zkind, const float* Xc, const double* nrm, int64_t n, int32_t d, const float* Z,
+                            int32_t b, float* Out, void* scratch, const TotalsOut& tot, double guard_scale,
+                            hipStream_t s, bool* used);
 
 hipError_t launch_l2sq(bool is_int, int zkind, const void* Xc, const void* nrm, int64_t n, int32_t d,
                        const void* Z, int32_t b, void* Out, void* scratch, const TotalsOut& tot,
                        double guard_scale, hipStream_t s)
 {
+    hipError_t e;
+    if (!is_int) {
+        // the matrix-core form (it takes its totals itself)
+        bool used = false;
+        e = launch_l2sq_mfma(zkind, (const float*)Xc, (const double*)nrm, n, d, (const float*)Z, b, (float*)Out,
+                             scratch, tot, guard_scale, s, &used);
+        if (e != hipSuccess || used) return e;
+    }
     // S0 and R (the totals kernel with weights ||x_j||^2)
-    hipError_t e = launch_totals(is_int, zkind, Z, n, b, nrm, guard_scale, tot, s);
+    e = launch_totals(is_int, zkind, Z, n, b, nrm, guard_scale, tot, s);
     if (e != hipSuccess) return e;
     if (!is_int) {
-        bool used = false;
-        e = launch_l2sq_mfma((const float*)Xc, (const double*)nrm, n, d, (const float*)Z, b, (float*)Out, scratch,
-                             tot, s, &used);
-        if (e != hipSuccess || used) return e;
         // (A z)_i = <x_i, -2 X^T z> + ||x_i||^2 S0 + R: the linear sort-free form
         SfQuery q;
         q.X = Xc;

@@ -13,6 +13,10 @@
 // latency of each one, which made both kernels latency-bound (about half the
 // achievable bandwidth) when the three shared one accumulator.
 //
+// For d = 128, b = 64 and whole ranges of points the first kernel also adds
+// the rank-one totals S0 = sum_j z_j and R = sum_j ||x_j||^2 z_j (FP64) while
+// it reads Z, so Z is read twice per query (here and by no totals kernel).
+//
 // Shapes: d <= 128 and b >= 16 (other shapes take the vector path).
 //
 // MFMA v_mfma_f32_32x32x16_bf16 lane layout (wave of 64):
@@ -38,31 +42,27 @@ __device__ __forceinline__ void split(float x, __bf16& h, __bf16& l) {
 }
 
 // ---------------------------------------------------------------------------
-// V partials: workgroup g sums points [g*ROWS_PER_WG, ...) into its own d x b
-// FP64 partial.  Wave w owns k-tile (w % kt_n) for every c-tile and takes the
-// 16-point steps s with s % rsplit == w / kt_n; operands are loaded straight
-// into MFMA lane order (for a fixed t the 32 lanes of a half-wave read 32
-// consecutive floats of one row, so every load is coalesced), and the next
-// step's operands are loaded before the current step's products.
-// FAST: d = 128 and b = 64 (every wave one k-tile, both c-tiles, no checks)
-// for the whole steps of a workgroup; the general form checks every access.
+// V partials (general shapes): workgroup g sums points [g*ROWS_PER_WG, ...)
+// into its own d x b FP64 partial.  Wave w owns k-tile (w % kt_n) for every
+// c-tile and takes the 16-point steps s with s % rsplit == w / kt_n; operands
+// are loaded straight into MFMA lane order (for a fixed t the 32 lanes of a
+// half-wave read 32 consecutive floats of one row, so every load is
+// coalesced), two steps ahead of the products, and every access is checked.
 // ---------------------------------------------------------------------------
-template <bool FAST>
 __global__ __launch_bounds__(256) void xtz_mfma_kernel(const float* __restrict__ X, int64_t n, int32_t d,
                                                        const float* __restrict__ Z, int32_t b,
                                                        double* __restrict__ part)
 {
     __shared__ double s_red[4][2][16][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int kt_n = FAST ? 4 : (d + 31) / 32, ct_n = FAST ? 2 : (b + 31) / 32;
+    const int kt_n = (d + 31) / 32, ct_n = (b + 31) / 32;
     const int rsplit = kt_n >= 4 ? 1 : 4 / kt_n;
     const int kt = w % kt_n, rs = w / kt_n;
     const bool active = rs < rsplit;
     const int kcol = kt * 32 + lane % 32, jg = lane / 32;
     // FP32 accumulators per c-tile: the main product (hh) and the two
     // remainder products (hl, lh; 2^-8 of it), two independent chains; their
-    // FP64 sums live in LDS (s_red, one slot per wave), which keeps the
-    // registers of two waves per SIMD
+    // FP64 sums live in LDS (s_red, one slot per wave)
     f32x16 acc[2][2] = {};
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
@@ -74,18 +74,12 @@ __global__ __launch_bounds__(256) void xtz_mfma_kernel(const float* __restrict__
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int64_t row = j + 8 * jg + t;
-            if (FAST) {   // d = 128, b = 64 as constants: one base address, immediate offsets
-                xv[t] = X[row * MAXD + kcol];
+            const bool ok = row < j1;
+            xv[t] = (ok && kcol < d) ? X[row * d + kcol] : 0.0f;
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct) zv[ct][t] = Z[row * MAXB + ct * 32 + lane % 32];
-            } else {
-                const bool ok = row < j1;
-                xv[t] = (ok && kcol < d) ? X[row * d + kcol] : 0.0f;
-#pragma unroll
-                for (int ct = 0; ct < 2; ++ct) {
-                    const int c = ct * 32 + lane % 32;
-                    zv[ct][t] = (ok && ct < ct_n && c < b) ? Z[row * b + c] : 0.0f;
-                }
+            for (int ct = 0; ct < 2; ++ct) {
+                const int c = ct * 32 + lane % 32;
+                zv[ct][t] = (ok && ct < ct_n && c < b) ? Z[row * b + c] : 0.0f;
             }
         }
     };
@@ -101,7 +95,7 @@ __global__ __launch_bounds__(256) void xtz_mfma_kernel(const float* __restrict__
         }
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-            if (FAST || ct < ct_n) {
+            if (ct < ct_n) {
                 bf16x8 bh, bl;
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
@@ -176,12 +170,153 @@ __global__ __launch_bounds__(256) void xtz_mfma_kernel(const float* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// V partials and the totals for d = 128, b = 64 and whole ranges of points.
+// Every wave covers all four k-tiles and both c-tiles (eight independent
+// accumulator chains) for the 16-point steps s with s % 4 == w, so each row
+// of X and of Z is read once per query.  The FP32 accumulators are flushed
+// every 16 steps (256 points) into FP32 sums in LDS: a wave has four flushes
+// per range, whose three additions round far below the split products.  The
+// four waves' sums are added in FP64 in wave order.  The same loads feed S0
+// and R in FP64; the lanes l and l + 32 hold alternate groups of 8 points of
+// one column.  Partial layout per workgroup: V (d x b), then S0 (b), R (b).
+// ---------------------------------------------------------------------------
+constexpr int WIDE_ENT = MAXD * MAXB + 2 * MAXB;
+
+__global__ __launch_bounds__(256) void xtz_wide_kernel(const float* __restrict__ X, const float* __restrict__ Z,
+                                                       const double* __restrict__ nrm, double* __restrict__ part)
+{
+    constexpr int NT = 8;                          // tiles: kt * 2 + ct
+    __shared__ float s_sum[4][NT][16][64];         // per wave, FP32 sums of the flushes
+    __shared__ double s_tot[4][2][2][64];          // per wave: S0 | R, lane half, column
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int jg = lane >> 5, l32 = lane & 31;
+    f32x16 acc[NT] = {};
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s_sum[w][q][r][lane] = 0.0f;
+    double s0[2] = {0.0, 0.0}, r1[2] = {0.0, 0.0};
+    auto load = [&](int64_t j, float (&xv)[4][8], float (&zv)[2][8], double (&nv)[8]) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int64_t row = j + 8 * jg + t;
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) xv[kt][t] = X[row * MAXD + kt * 32 + l32];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) zv[ct][t] = Z[row * MAXB + ct * 32 + l32];
+            nv[t] = nrm[row];
+        }
+    };
+    auto products = [&](const float (&xv)[4][8], const float (&zv)[2][8], const double (&nv)[8]) {
+        bf16x8 ah[4], al[4], bh[2], bl[2];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            __bf16 h, l;
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) {
+                split(xv[kt][t], h, l);
+                ah[kt][t] = h;
+                al[kt][t] = l;
+            }
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                split(zv[ct][t], h, l);
+                bh[ct][t] = h;
+                bl[ct][t] = l;
+            }
+        }
+        // hh of all eight tiles, then hl, then lh: a tile's next product
+        // waits behind seven others
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[kt * 2 + ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kt], bh[ct], acc[kt * 2 + ct], 0, 0, 0);
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[kt * 2 + ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kt], bl[ct], acc[kt * 2 + ct], 0, 0, 0);
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[kt * 2 + ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kt], bh[ct], acc[kt * 2 + ct], 0, 0, 0);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                s0[ct] += (double)zv[ct][t];
+                r1[ct] = fma(nv[t], (double)zv[ct][t], r1[ct]);
+            }
+    };
+    // 4 x 16 steps of 16 points per wave, a flush after every 16; the next
+    // step's operands are loaded before the current step's products
+    const int64_t jw = (int64_t)blockIdx.x * ROWS_PER_WG + 16 * w;
+    float xa[4][8], za[2][8];
+    double na[8];
+    load(jw, xa, za, na);
+    for (int f = 0; f < 4; ++f) {
+        for (int u = 0; u < 16; ++u) {
+            const int st = f * 16 + u;
+            float xb[4][8], zb[2][8];
+            double nb[8];
+            if (st < 63) load(jw + (int64_t)(st + 1) * 64, xb, zb, nb);
+            products(xa, za, na);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+#pragma unroll
+                for (int kt = 0; kt < 4; ++kt) xa[kt][t] = xb[kt][t];
+                za[0][t] = zb[0][t];
+                za[1][t] = zb[1][t];
+                na[t] = nb[t];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                s_sum[w][q][r][lane] += acc[q][r];
+                acc[q][r] = 0.0f;
+            }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        s_tot[w][0][jg][ct * 32 + l32] = s0[ct];
+        s_tot[w][1][jg][ct * 32 + l32] = r1[ct];
+    }
+    __syncthreads();
+    double* pb = part + (size_t)blockIdx.x * WIDE_ENT;
+    // wave w writes k-tile w: the four waves' sums in wave order
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v += (double)s_sum[q][w * 2 + ct][r][lane];
+            const int k = w * 32 + (r / 4) * 8 + jg * 4 + (r % 4);
+            pb[(size_t)k * MAXB + ct * 32 + l32] = v;
+        }
+    if (tid < 2 * MAXB) {
+        const int q = tid / MAXB, c = tid % MAXB;
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v += s_tot[u][q][0][c] + s_tot[u][q][1][c];
+        pb[MAXD * MAXB + tid] = v;
+    }
+}
+
 // fixed-order sum of the partials: V[e] = sum_g part[g][e].  A block takes 32
 // consecutive entries; its 8 row groups each sum the partials g = q, q + 8, ...
 // in ascending order (32 lanes read 256 contiguous bytes per load), and the 8
 // group sums are added in group order.
+// Entries [chk0, chk1) are sums of Z (S0): a non-finite one means a
+// non-finite z, which raises the status flag.
 __global__ __launch_bounds__(256) void xtz_reduce_kernel(const double* __restrict__ part, int nblk, int ent,
-                                                         double* __restrict__ V)
+                                                         double* __restrict__ V, int chk0, int chk1,
+                                                         uint32_t* __restrict__ status)
 {
     __shared__ double s[8][32];
     const int el = threadIdx.x % 32, q = threadIdx.x / 32;
@@ -198,6 +333,7 @@ __global__ __launch_bounds__(256) void xtz_reduce_kernel(const double* __restric
 #pragma unroll
         for (int r = 0; r < 8; ++r) v += s[r][el];
         V[e] = v;
+        if (e >= chk0 && e < chk1 && !isfinite(v)) atomicOr(status, (uint32_t)QF_NONFINITE);
     }
 }
 
@@ -321,31 +457,46 @@ static void launch_apply(bool vec, unsigned grid, hipStream_t s, const float* X,
 
 size_t l2_mfma_partials(int64_t n) { return (size_t)((n + ROWS_PER_WG - 1) / ROWS_PER_WG); }
 
-hipError_t launch_l2sq_mfma(const float* Xc, const double* nrm, int64_t n, int32_t d, const float* Z, int32_t b,
-                            float* Out, void* scratch, const TotalsOut& tot, hipStream_t s, bool* used)
+size_t l2_mfma_scratch_bytes(int64_t n, int32_t d, int32_t b) {
+    return (l2_mfma_partials(n) + 1) * ((size_t)d * b + 2 * (size_t)b) * 8 + 256;
+}
+
+hipError_t launch_l2sq_mfma(int zkind, const float* Xc, const double* nrm, int64_t n, int32_t d, const float* Z,
+                            int32_t b, float* Out, void* scratch, const TotalsOut& tot, double guard_scale,
+                            hipStream_t s, bool* used)
 {
     *used = false;
-    if (d > MAXD || b < 16 || b > MAXB) return hipSuccess;
+    if (n < 1 || d > MAXD || b < 16 || b > MAXB) return hipSuccess;
     const int nblk = (int)l2_mfma_partials(n);
-    const int ent = d * b;
+    // d = 128, b = 64 and whole ranges of points: the totals come with X^T Z
+    const bool wide = d == MAXD && b == MAXB && n % ROWS_PER_WG == 0;
+    const int ent = wide ? WIDE_ENT : d * b;
     double* part = (double*)scratch;
     double* V = part + (size_t)nblk * ent;
-    // the branch-free form needs d = 128, b = 64 and whole workgroup ranges
-    // (the last range is whole when n is a multiple of the range)
-    if (d == MAXD && b == MAXB && n % ROWS_PER_WG == 0)
-        xtz_mfma_kernel<true><<<nblk, 256, 0, s>>>(Xc, n, d, Z, b, part);
-    else
-        xtz_mfma_kernel<false><<<nblk, 256, 0, s>>>(Xc, n, d, Z, b, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    xtz_reduce_kernel<<<(ent + 31) / 32, 256, 0, s>>>(part, nblk, ent, V);
+    const double* S0;
+    const double* Rr;
+    hipError_t e;
+    if (wide) {
+        xtz_wide_kernel<<<nblk, 256, 0, s>>>(Xc, Z, nrm, part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        xtz_reduce_kernel<<<(ent + 31) / 32, 256, 0, s>>>(part, nblk, ent, V, d * b, d * b + b, tot.status);
+        S0 = V + (size_t)d * b;
+        Rr = V + (size_t)d * b + b;
+    } else {
+        // S0 and R from the totals kernel (weights ||x_j||^2)
+        if ((e = launch_totals(false, zkind, Z, n, b, nrm, guard_scale, tot, s)) != hipSuccess) return e;
+        xtz_mfma_kernel<<<nblk, 256, 0, s>>>(Xc, n, d, Z, b, part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        xtz_reduce_kernel<<<(ent + 31) / 32, 256, 0, s>>>(part, nblk, ent, V, 0, 0, tot.status);
+        S0 = (const double*)tot.T0;
+        Rr = (const double*)tot.U;
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // six workgroups of four waves per compute unit (measured best of 4, 6, 8)
     const int64_t blocks = (n + 127) / 128;
-    const unsigned grid = (unsigned)(blocks < 256 * 8 ? blocks : 256 * 8);
+    const unsigned grid = (unsigned)(blocks < 256 * 6 ? blocks : 256 * 6);
     const bool vec = (d % 8 == 0) && ((uintptr_t)Xc % 16 == 0);
     const int ks = (d + 15) / 16;
-    const double* S0 = (const double*)tot.T0;
-    const double* Rr = (const double*)tot.U;
     if (ks <= 1) launch_apply<1>(vec, grid, s, Xc, n, d, V, b, nrm, S0, Rr, Out);
     else if (ks <= 2) launch_apply<2>(vec, grid, s, Xc, n, d, V, b, nrm, S0, Rr, Out);
     else if (ks <= 4) launch_apply<4>(vec, grid, s, Xc, n, d, V, b, nrm, S0, Rr, Out);

@@ -32,9 +32,11 @@ def _mscale(X32, Z32):
 
 
 # matrix-core shapes: d <= 32 (4 waves split the points), 33..64 (2), 65..96
-# (one wave idle), 97..128; b up to 32 (one column tile) and beyond
+# (one wave idle), 97..128; b up to 32 (one column tile) and beyond; d = 128,
+# b = 64 with n a multiple of 4096 takes the kernel that also forms the totals
 @pytest.mark.parametrize("n,d,b", [(1, 3, 1), (2048, 16, 1), (3001, 7, 4), (5000, 64, 16), (4099, 128, 64),
-                                   (3000, 20, 24), (257, 33, 17), (4500, 96, 40), (9001, 128, 33)])
+                                   (3000, 20, 24), (257, 33, 17), (4500, 96, 40), (9001, 128, 33),
+                                   (4096, 128, 64), (8192, 128, 64)])
 def test_float(n, d, b):
     g = synth.rng(700 + n + b)
     X = g.standard_normal((n, d), dtype=np.float32)
@@ -83,3 +85,30 @@ def test_nonfinite_rhs_flagged(b):
     Z[333, b - 1] = 0.0
     h.matvec(dev(Z))
     h.sync()
+
+
+@pytest.mark.parametrize("case", ["inf", "nan", "both_infs"])
+def test_nonfinite_rhs_flagged_fused_totals(case):
+    # d = 128, b = 64, n = 4096: the totals come from the X^T Z kernel, and a
+    # non-finite z shows as a non-finite column sum (+inf and -inf give NaN)
+    g = synth.rng(860)
+    n, d, b = 4096, 128, 64
+    X = g.standard_normal((n, d)).astype(np.float32)
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    Z0 = Z.copy()
+    if case == "inf":
+        Z[4000, 7] = np.inf
+    elif case == "nan":
+        Z[17, 63] = np.nan
+    else:
+        Z[5, 30] = np.inf
+        Z[4095, 30] = -np.inf
+    h = dm.prepare(dev(X), L2SQ)
+    h.matvec(dev(Z))
+    with pytest.raises(dm.DMError) as ei:
+        h.sync()
+    assert ei.value.status == dm.ERR_NONFINITE
+    Y = h.matvec(dev(Z0))
+    h.sync()
+    e, _ = float_errors(X, Z0, Y.cpu().numpy(), L2SQ)
+    assert e["spec"] <= 1e-6
