@@ -397,9 +397,12 @@ __device__ __forceinline__ void l2_apply_block(const float* __restrict__ X, int6
         for (int ct = 0; ct < CT; ++ct) {
             const int c = ct * 32 + lane % 32;
             // the two remainder products are 2^-8 of the main one: their sum
-            // in FP32 adds an error below that of the split itself
+            // in FP32 adds an error below that of the split itself; Out is
+            // written once and not read here, so its stores bypass the caches'
+            // retention (the next query's X^T Z then finds no dirty lines)
             const float p = (acc[ct][1][r] + acc[ct][2][r]) + acc[ct][0][r];
-            if (!CHECK || c < b) Out[i * b + c] = (float)(nrm[i] * S0[c] + R[c] - 2.0 * (double)p);
+            if (!CHECK || c < b)
+                __builtin_nontemporal_store((float)(nrm[i] * S0[c] + R[c] - 2.0 * (double)p), &Out[i * b + c]);
         }
     }
 }
