@@ -24,6 +24,9 @@ Z = n x 64 right-hand sides N(0, 1) in FP32 (seeded, synthetic).
 * single_vector_mixture: the plain single-vector method at n = 2^20, d = 64
   (32-component Gaussian mixture): 100 timed queries, median / p10 / p90, for
   l1 and l2 squared, with errors against the oracle.
+* precision_stress: points 10^4 + U[0,1) (n = 2^20, d = 16) with z ~ N(0,1)
+  and z = 1 + 10^-3 N(0,1): l1, p = 3 and l2 squared errors against the oracle
+  on sampled and scan-boundary rows.
 * roofline: algorithmic bytes of one coordinate pass, 12 n b + 8 n (perm and
   sorted values read once, the Z rows gathered once, the Out rows read and
   written once), over the pass kernel's mean device time from HIP events on
@@ -222,6 +225,46 @@ def run_single_mixture(args, dm, synth, np, torch, dev, stream):
     return res
 
 
+def run_precision_stress(args, dm, synth, np, torch, dev, stream):
+    """Points far from the origin: n = 2^20, d = 16, X = 10^4 + U[0,1) FP32,
+    and right-hand sides N(0, 1) or the Perron-like 1 + 10^-3 N(0, 1); one
+    query each of l1 (b = 64 and b = 1), odd p = 3 and l2 squared (b = 64),
+    errors against the FP64 oracle on 48 sampled rows plus the scan
+    boundaries (ranks 0 and n - 1 of the first and last coordinate)."""
+    import oracle
+    from oracle import metrics
+    n, d = 1 << 20, 16
+    X = (1.0e4 + synth.rng(4242).random((n, d))).astype(np.float32)
+    X64 = X.astype(np.float64)
+    extra = []
+    for k in (0, d - 1):
+        o = np.argsort(X[:, k], kind="stable")
+        extra += [int(o[0]), int(o[-1])]
+    rows = synth.subsample_rows(n, 48, 4243, extra=extra)
+    Xd = torch.from_numpy(X).to(dev)
+    res = {"workload": "n=2^20, d=16, X = 1e4 + U[0,1) FP32", "rows": int(rows.size)}
+    cases = (("l1", dm.L1, oracle.L1, (("positive", 64), ("normal", 64), ("positive", 1))),
+             ("l3", dm.L3, oracle.L3, (("positive", 64),)),
+             ("l2sq", dm.L2SQ, oracle.L2SQ, (("positive", 64), ("normal", 64))))
+    for name, metric, ometric, zs in cases:
+        h = dm.prepare(Xd, metric)
+        for zk, b in zs:
+            Z = synth.rhs_positive(n, b, 4244 + b) if zk == "positive" else synth.rhs_normal(n, b, 4245 + b)
+            Zd = torch.from_numpy(Z if b > 1 else Z[:, 0].copy()).to(dev)
+            y = h.matvec(Zd)
+            h.sync()
+            Y = y.cpu().numpy().astype(np.float64).reshape(n, b)
+            Z64 = Z.astype(np.float64)
+            o, rn, ad = oracle.matvec(X64, Z64, ometric, rows)
+            frob = metrics.frob_l2sq(X64) if name == "l2sq" else metrics.frob_from_rows(rn, n)
+            e = metrics.errors(Y[rows], o, rn, ad, Z64, frob)
+            key = "%s_b%d_z_%s" % (name, b, zk)
+            res[key] = {"spec": e["spec"], "per_row": e["per_row"]}
+            log("precision stress %s: spec %.2e per-row %.2e" % (key, e["spec"], e["per_row"]))
+        h.free()
+    return res
+
+
 def run_approx_l2(args, dm, synth, np, torch, dev, stream):
     """Approximate l2 products at n = 2^20, d = 64 (32-component mixture), k =
     256 embedding rows: embedding, preparation of the embedded points, one
@@ -416,6 +459,7 @@ def main():
     ap.add_argument("--no-lowrank", action="store_true", help="skip the block-Krylov low-rank leg")
     ap.add_argument("--no-mixture", action="store_true", help="skip the single-vector mixture leg")
     ap.add_argument("--no-approx-l2", action="store_true", help="skip the approximate l2 leg")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-stress leg")
     ap.add_argument("--no-sortfree", action="store_true", help="skip the sort-free family leg")
     ap.add_argument("--multi-count", type=int, default=512)
     ap.add_argument("--dump-rows", default="", help="write the results on the 16 384-row sample to this .npz")
@@ -605,6 +649,9 @@ def main():
     mixture = None
     if not args.no_mixture:
         mixture = run_single_mixture(args, dm, synth, np, torch, dev, stream)
+    precision = None
+    if not args.no_precision:
+        precision = run_precision_stress(args, dm, synth, np, torch, dev, stream)
 
     # ---- approximate l2 through the l1 path ----
     approx = None
@@ -701,6 +748,7 @@ def main():
         "multi": multi,
         "lowrank": lowrank,
         "single_vector_mixture": mixture,
+        "precision_stress": precision,
         "approx_l2": approx,
         "sortfree": sortfree,
         "errors": errors,
