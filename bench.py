@@ -30,7 +30,8 @@ Z = n x 64 right-hand sides N(0, 1) in FP32 (seeded, synthetic).
 * roofline: algorithmic bytes of one coordinate pass, 12 n b + 8 n (perm and
   sorted values read once, the Z rows gathered once, the Out rows read and
   written once), over the pass kernel's mean device time from HIP events on
-  the query stream, against the 8 TB/s HBM peak.
+  the query stream, against the 8 TB/s HBM peak; beside it the rates of a
+  plain copy and of the pass's random row accesses alone (dm_gather_probe).
 * cpu_baseline: the FP64 CPU oracle (explicit rows of A, O(n^2 d)) on a
   bounded sample of rows of the same workload, extrapolated to whole columns.
 
@@ -503,6 +504,26 @@ def main():
     del buf
     log("copy probe %.0f GB/s" % copy_gbps)
 
+    # ---- achievable rate of the pass's random row accesses: Out[p] += Z[p]
+    # over a random permutation p (the gather and read-modify-write of one
+    # pass without its scan), 4n + 12nb bytes per probe ----
+    gather_gbps = None
+    if b in (4, 8, 16, 32, 64):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2210)
+        permd = torch.randperm(n, device=dev, generator=gen).to(torch.int32)
+        Ob = torch.zeros_like(Zd)
+        for _ in range(2):
+            dm.gather_probe(permd, Zd, Ob)
+        e0.record()
+        for _ in range(reps):
+            dm.gather_probe(permd, Zd, Ob)
+        e1.record()
+        torch.cuda.synchronize()
+        gather_gbps = (4.0 * n + 12.0 * n * b) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del permd, Ob
+        log("random-row probe %.0f GB/s" % gather_gbps)
+
     # ---- preparation (Algorithm 1), timed once ----
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -571,6 +592,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "achievable_GBps": round(copy_gbps, 1), "frac_of_achievable": round(achieved / copy_gbps, 4),
+                "random_row_probe_GBps": round(gather_gbps, 1) if gather_gbps else None,
+                "frac_of_random_row_probe": round(achieved / gather_gbps, 4) if gather_gbps else None,
                 "measured_GBps": round(traffic / (avg_pass_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "kernel": pass_kernel_name(vb, b), "variant": vb, "bytes_per_launch": bytes_pass,
                 "avg_launch_ms": round(avg_pass_ms, 4), "launches": pass_n}
@@ -741,6 +764,7 @@ def main():
         "batched_vs_single": round(cols_s / single["columns_per_s"], 2) if single else None,
         "hbm_frac": roofline["frac"],
         "copy_probe_GBps": round(copy_gbps, 1),
+        "random_row_probe_GBps": round(gather_gbps, 1) if gather_gbps else None,
         "prep_ms": round(prep_ms, 1),
         "totals_ms_per_step": round(tot_ms / prof_steps, 4),
         "run_to_run": repro,

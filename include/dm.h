@@ -406,6 +406,18 @@ dm_status dm_profile_read(dm_handle* h, int32_t kernel_class, double* total_ms, 
  */
 dm_status dm_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
 
+/*
+ * Random-row probe: Out[perm[r]] += Z[perm[r]] for r = 0 .. n-1, with rows of
+ * b FP32 values; the gather and read-modify-write of one coordinate pass of
+ * Algorithm 2 in the fused form (the prefix sums left out), used to measure
+ * the rate of the pass's random row accesses.  perm: device, n uint32 point
+ * indices (a permutation gives the pass's pattern; entries >= n are skipped,
+ * repeated entries race).  Z, Out: device n x b FP32 row-major, 16-byte
+ * aligned, not overlapping.  b: a power of two, 4..64.  Stream-ordered.
+ * Errors: DM_ERR_ARG, DM_ERR_DEVICE.
+ */
+dm_status dm_gather_probe(const uint32_t* perm, const float* Z, float* Out, int64_t n, int32_t b, void* stream);
+
 /* Release a handle (and its workspace if the library allocated it).  NULL is a no-op. */
 void dm_free(dm_handle* h);
 

@@ -93,6 +93,8 @@ def lib():
     L.dm_profile_read.restype = i32
     L.dm_copy_probe.argtypes = [P, P, sz, P]
     L.dm_copy_probe.restype = i32
+    L.dm_gather_probe.argtypes = [P, P, P, i64, i32, P]
+    L.dm_gather_probe.restype = i32
     L.dm_workspace_size_multi.argtypes = [ctypes.POINTER(Dataset), i32, ctypes.POINTER(sz)]
     L.dm_workspace_size_multi.restype = i32
     L.dm_prepare_multi.argtypes = [ctypes.POINTER(Dataset), i32, P, sz, P, ctypes.POINTER(P)]
@@ -162,6 +164,17 @@ def copy_probe(dst, src, stream=None):
         raise ValueError("size mismatch")
     _check(lib().dm_copy_probe(_dev_ptr(dst, "dst"), _dev_ptr(src, "src"), nbytes, _stream_ptr(stream)),
            "dm_copy_probe")
+
+
+def gather_probe(perm, Z, Out, stream=None):
+    """Out[perm[r]] += Z[perm[r]] for every r (perm: int32 device tensor of
+    point indices; Z, Out: n x b float32 device tensors): the random-row
+    accesses of a coordinate pass without its scan."""
+    n, b = Z.shape
+    if tuple(Out.shape) != (n, b) or perm.numel() != n:
+        raise ValueError("shape mismatch")
+    _check(lib().dm_gather_probe(_dev_ptr(perm, "perm"), _dev_ptr(Z, "Z"), _dev_ptr(Out, "Out"), n, b,
+                                 _stream_ptr(stream)), "dm_gather_probe")
 
 
 def _torch():

@@ -1280,6 +1280,18 @@ dm_status dm_copy_probe(void* dst, const void* src, size_t bytes, void* stream) 
     return DM_OK;
 }
 
+dm_status dm_gather_probe(const uint32_t* perm, const float* Z, float* Out, int64_t n, int32_t b, void* stream) {
+    if (!perm || !Z || !Out || n < 1 || n > (int64_t)UINT32_MAX) return DM_ERR_ARG;
+    if (b < 4 || b > 64 || (b & (b - 1)) != 0) return DM_ERR_ARG;
+    if (((uintptr_t)Z | (uintptr_t)Out) % 16 != 0 || (uintptr_t)perm % 4 != 0) return DM_ERR_ARG;
+    const char* z = (const char*)Z;
+    const char* o = (const char*)Out;
+    const size_t bytes = (size_t)n * b * 4;
+    if (o < z + bytes && z < o + bytes) return DM_ERR_ARG;
+    DM_TRY(launch_gather_probe(perm, Z, Out, n, b, (hipStream_t)stream));
+    return DM_OK;
+}
+
 void dm_free(dm_handle* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->last);

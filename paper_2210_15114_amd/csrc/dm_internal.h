@@ -70,6 +70,8 @@ hipError_t launch_centre(const uint32_t* kmin, const uint32_t* kmax, int32_t d, 
 hipError_t launch_add_centre(float* xs, int64_t n, int32_t d, int64_t pitch, const float* centre, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_gather_probe(const uint32_t* perm, const float* Z, float* Out, int64_t n, int32_t b,
+                               hipStream_t s);
 
 // ---- segmented radix sort (LSD, 4 passes of 8 bits) -----------------------
 hipError_t launch_sort_count(const uint32_t* keys, uint32_t* counts, const SegTables& t, int shift,

@@ -219,6 +219,40 @@ __global__ __launch_bounds__(256) void copy_probe_kernel(uint4* __restrict__ dst
     if (i < n16) dst[i] = src[i];
 }
 
+// random-row probe: Out[perm[r]] += Z[perm[r]] for every rank r, rows of b
+// FP32 values (b a power of two, 4..64) read and written with one 16-byte
+// access per lane, GP ranks per row slot in flight; the gather and
+// read-modify-write of a coordinate pass without its scan.  Indices >= n are
+// skipped.
+constexpr int GP = 8;
+__global__ __launch_bounds__(256) void gather_probe_kernel(const uint32_t* __restrict__ perm,
+                                                           const float* __restrict__ Z, float* __restrict__ Out,
+                                                           int64_t n, int32_t b)
+{
+    const int lpr = b >> 2, slots = 256 / lpr;
+    const int slot = threadIdx.x / lpr, col = (threadIdx.x % lpr) * 4;
+    const int64_t r0 = ((int64_t)blockIdx.x * slots + slot) * GP;
+    uint32_t p[GP];
+    float4 g[GP], o[GP];
+#pragma unroll
+    for (int i = 0; i < GP; ++i) p[i] = r0 + i < n ? perm[r0 + i] : 0xffffffffu;
+#pragma unroll
+    for (int i = 0; i < GP; ++i)
+        if (p[i] < n) g[i] = *reinterpret_cast<const float4*>(Z + (size_t)p[i] * b + col);
+#pragma unroll
+    for (int i = 0; i < GP; ++i)
+        if (p[i] < n) o[i] = *reinterpret_cast<const float4*>(Out + (size_t)p[i] * b + col);
+#pragma unroll
+    for (int i = 0; i < GP; ++i)
+        if (p[i] < n) {
+            o[i].x += g[i].x;
+            o[i].y += g[i].y;
+            o[i].z += g[i].z;
+            o[i].w += g[i].w;
+            *reinterpret_cast<float4*>(Out + (size_t)p[i] * b + col) = o[i];
+        }
+}
+
 // p[i] *= s
 __global__ __launch_bounds__(256) void scale_f32_kernel(float* __restrict__ p, size_t count, float s)
 {
@@ -246,6 +280,16 @@ hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream
         const size_t cnt = n16 - at < CHUNK ? n16 - at : CHUNK;
         copy_probe_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>((uint4*)dst + at, (const uint4*)src + at, cnt);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_probe(const uint32_t* perm, const float* Z, float* Out, int64_t n, int32_t b,
+                               hipStream_t s)
+{
+    const int64_t per = (int64_t)(256 / (b / 4)) * GP;   // ranks per workgroup
+    const int64_t grid = (n + per - 1) / per;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    gather_probe_kernel<<<(unsigned)grid, 256, 0, s>>>(perm, Z, Out, n, b);
     return hipGetLastError();
 }
 

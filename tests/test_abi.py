@@ -159,6 +159,17 @@ def test_copy_probe_argument_errors_before_device(L):
     assert L.dm_copy_probe(None, B, 32, None) == dm.ERR_ARG
 
 
+def test_gather_probe_argument_errors_before_device(L):
+    P, Z, O = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000)
+    assert L.dm_gather_probe(P, Z, O, 0, 64, None) == dm.ERR_ARG                       # n
+    assert L.dm_gather_probe(P, Z, O, 100, 48, None) == dm.ERR_ARG                     # b not a power of two
+    assert L.dm_gather_probe(P, Z, O, 100, 2, None) == dm.ERR_ARG                      # b < 4
+    assert L.dm_gather_probe(P, Z, O, 100, 128, None) == dm.ERR_ARG                    # b > 64
+    assert L.dm_gather_probe(P, ctypes.c_void_p(0x100008), O, 100, 64, None) == dm.ERR_ARG   # misaligned
+    assert L.dm_gather_probe(P, Z, ctypes.c_void_p(0x100100), 100, 64, None) == dm.ERR_ARG   # overlap
+    assert L.dm_gather_probe(None, Z, O, 100, 64, None) == dm.ERR_ARG
+
+
 def test_variant_count(L):
     assert L.dm_variant_count() == 4
 

@@ -59,3 +59,23 @@ def test_queries_at_growing_b_allocate_nothing(metric, kind):
     after = _free()
     h.free()
     assert abs(before - after) <= SLACK, (before, after)
+
+
+@pytest.mark.parametrize("n,b", [(1000, 64), (4097, 4), (777, 16)])
+def test_gather_probe_adds_each_row_once(n, b):
+    # perm is a permutation except for a few entries >= n, which are skipped
+    import torch
+    g = synth.rng(900 + n)
+    perm = g.permutation(n).astype(np.int64)
+    skipped = perm[[0, n // 2, n - 1]].copy()
+    perm[[0, n // 2, n - 1]] = n + np.array([0, 7, 1 << 20])
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    O0 = g.standard_normal((n, b)).astype(np.float32)
+    Pd = torch.from_numpy(perm.astype(np.int32)).cuda()
+    Zd = torch.from_numpy(Z).cuda()
+    Od = torch.from_numpy(O0).cuda()
+    dm.gather_probe(Pd, Zd, Od)
+    torch.cuda.synchronize()
+    want = O0 + Z
+    want[skipped] = O0[skipped]
+    assert np.array_equal(Od.cpu().numpy(), want)

@@ -112,3 +112,17 @@ def test_nonfinite_rhs_flagged_fused_totals(case):
     h.sync()
     e, _ = float_errors(X, Z0, Y.cpu().numpy(), L2SQ)
     assert e["spec"] <= 1e-6
+
+
+@pytest.mark.parametrize("n,d,b", [(8192, 128, 64), (4099, 96, 40), (3001, 7, 4)])
+def test_float_query_is_bitwise_reproducible(n, d, b):
+    # every sum of the l2-squared query has a fixed order (no look-back chain)
+    g = synth.rng(870 + n)
+    X = g.standard_normal((n, d), dtype=np.float32)
+    Z = g.standard_normal((n, b), dtype=np.float32)
+    h = dm.prepare(dev(X), L2SQ)
+    Zd = dev(Z)
+    Y1 = h.matvec(Zd).cpu().numpy()
+    Y2 = h.matvec(Zd).cpu().numpy()
+    h.sync()
+    assert np.array_equal(Y1, Y2)
