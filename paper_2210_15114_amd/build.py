@@ -36,9 +36,20 @@ CFLAGS = [
 ]
 
 
+# Per-file code generation options.  The sort-free FP64 matrix-core kernels
+# keep their accumulators in ordinary VGPRs: with the default choice the
+# compiler copied the accumulators between VGPRs and AGPRs around every
+# product step (v_accvgpr_read/write), which took the b = 64 moments kernels
+# from about 0.17 to 0.26 ms.  (The same option made the low-rank update
+# kernel several times slower, so it applies to this file only.)
+FILE_FLAGS = {
+    "k_sortfree.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + CFLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))

@@ -456,7 +456,8 @@ __device__ __forceinline__ void load4(const XT* p, double (&v)[4]) {
 // so tile t of the coordinates holds k = k0 + 4 i + t at tile row i and tile u
 // of the columns holds c = 4 n + u at tile column n.  Needs d % 4 == 0 and
 // b % 4 == 0.
-template <typename XT>
+constexpr int SF_MOM_DEPTH = 4;   // row steps in flight per wave
+template <typename XT, int P>
 __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X, const double* __restrict__ centre,
                                                        const float* __restrict__ Z, int64_t n, int32_t d, int32_t b,
                                                        int64_t rows_per_wave, double* __restrict__ part)
@@ -479,46 +480,53 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
         for (int u = 0; u < 4; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
     const int64_t r0 = xw * rows_per_wave;
     const int64_t r1 = r0 + rows_per_wave < n ? r0 + rows_per_wave : n;
-    // raw values of one row step; the next step's are loaded before this
-    // step's products
-    XT xn[4] = {XT(0), XT(0), XT(0), XT(0)};
-    float zn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    auto fetch = [&](int64_t j) {
+    // raw values of P row steps in flight: slot p holds step s with s % P == p;
+    // a slot is refilled with the step P ahead right after it is consumed
+    XT xn[P][4];
+    float zn[P][4];
+    auto fetch = [&](int64_t j, XT (&xv)[4], float (&zv)[4]) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) { xn[t] = XT(0); zn[t] = 0.0f; }
+        for (int t = 0; t < 4; ++t) { xv[t] = XT(0); zv[t] = 0.0f; }
         if (j < r1) {
             if (kin) {
                 if constexpr (sizeof(XT) == 4) {
                     const Vec<XT, 4> q = *reinterpret_cast<const Vec<XT, 4>*>(X + j * d + kq);
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) xn[t] = q.v[t];
+                    for (int t = 0; t < 4; ++t) xv[t] = q.v[t];
                 } else {
                     const Vec<XT, 2> q0 = *reinterpret_cast<const Vec<XT, 2>*>(X + j * d + kq);
                     const Vec<XT, 2> q1 = *reinterpret_cast<const Vec<XT, 2>*>(X + j * d + kq + 2);
-                    xn[0] = q0.v[0]; xn[1] = q0.v[1]; xn[2] = q1.v[0]; xn[3] = q1.v[1];
+                    xv[0] = q0.v[0]; xv[1] = q0.v[1]; xv[2] = q1.v[0]; xv[3] = q1.v[1];
                 }
             }
             if (cin) {
                 const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(Z + j * b + cq);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) zn[t] = q.v[t];
+                for (int t = 0; t < 4; ++t) zv[t] = q.v[t];
             }
         }
     };
-    fetch(r0 + g);
-    for (int64_t j0 = r0; j0 < r1; j0 += 4) {   // the same trip count on every lane
-        const int64_t j = j0 + g;
-        double a[4], z[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            a[t] = (j < r1 && kin) ? (CEN ? (double)xn[t] - cen[t] : (double)xn[t]) : 0.0;
-            z[t] = (double)zn[t];
+    for (int p = 0; p < P; ++p) fetch(r0 + 4 * p + g, xn[p], zn[p]);
+    for (int64_t js = r0; js < r1; js += 4 * P) {   // the same trip count on every lane
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int64_t j0 = js + 4 * p;
+            if (j0 >= r1) break;
+            const int64_t j = j0 + g;
+            double a[4], z[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = (j < r1 && kin) ? (CEN ? (double)xn[p][t] - cen[t] : (double)xn[p][t]) : 0.0;
+                z[t] = (double)zn[p][t];
+            }
+            if (j0 + 4 * P < r1) fetch(j + 4 * P, xn[p], zn[p]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], z[u], acc[t][u], 0, 0, 0);
         }
-        if (j0 + 4 < r1) fetch(j + 4);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], z[u], acc[t][u], 0, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -538,9 +546,13 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
 // loads are issued before the current chunk's products), and step s of the
 // chunk multiplies the A column g = coordinate k0 + 4g + s.  V (d x b FP64) is
 // staged once per workgroup in dynamic LDS when it fits (LDS_V), else read
-// through the caches; each V operand serves all NTL tiles.
+// through the caches; each V operand serves all NTL tiles.  PIPE: the
+// (group, chunk) pairs of a wave form one loop, so the loads run ahead across
+// group boundaries too (0.30 -> 0.23 ms at n = 2^20, d = 64, b = 64; the
+// per-group loop left the first chunk's points and the epilogue's weights
+// waiting on memory in every group).
 constexpr int NTL = 1;   // 2 or 4 tiles per step measured slower (fewer waves per SIMD) than 1
-template <int CT, bool LDS_V>
+template <int CT, bool LDS_V, bool PIPE>
 __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X, const double* __restrict__ centre,
                                                      int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
                                                      const double* __restrict__ V, const double* __restrict__ a,
@@ -583,6 +595,92 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
                 if (kq + s < d) xv[s] = X[ia * d + kq + s];
         }
     };
+    if constexpr (PIPE) {
+        // one flat loop over the wave's (group, chunk) pairs: the next pair's
+        // points and centres are loaded before the current pair's products,
+        // also across a group boundary, and a group's weights a_i when the
+        // group starts, so neither waits at the group's ends
+        const int nch = (d + 15) / 16;
+        int64_t grp = wave;
+        int kc = 0;
+        float xn[4];
+        double cn[4];
+        auto load_centre = [&](int k0, double (&c)[4]) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + 4 * g + s;
+                c[s] = (centre && k < d) ? centre[k] : 0.0;
+            }
+        };
+        if (grp < ngroup) {
+            load_chunk(grp * 16 + m, 0, xn);
+            load_centre(0, cn);
+        }
+        d4v acc[CT];
+        double aw[4];
+        while (grp < ngroup) {
+            const int64_t i0 = grp * 16;
+            if (kc == 0) {
+#pragma unroll
+                for (int u = 0; u < CT; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = i0 + 4 * r + g;
+                    aw[r] = (a && i < n) ? a[i] : 0.0;
+                }
+            }
+            float xv[4];
+            double cv[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                xv[s] = xn[s];
+                cv[s] = cn[s];
+            }
+            int kc2 = kc + 1;
+            int64_t grp2 = grp;
+            if (kc2 == nch) {
+                kc2 = 0;
+                grp2 += nwaves;
+            }
+            if (grp2 < ngroup) {
+                load_chunk(grp2 * 16 + m, 16 * kc2, xn);
+                load_centre(16 * kc2, cn);
+            }
+            const int kq = 16 * kc + 4 * g;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = kq + s;
+                const bool kin = k < d;
+                double vb[CT];
+#pragma unroll
+                for (int u = 0; u < CT; ++u) {
+                    const int c = 16 * u + m;
+                    vb[u] = (kin && c < b) ? Vs[(size_t)k * b + c] : 0.0;
+                }
+                const double xa = kin ? (double)xv[s] - cv[s] : 0.0;   // zero for points past n
+#pragma unroll
+                for (int u = 0; u < CT; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, vb[u], acc[u], 0, 0, 0);
+            }
+            if (kc == nch - 1) {
+#pragma unroll
+                for (int u = 0; u < CT; ++u) {
+                    const int c = 16 * u + m;
+                    if (c >= b) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t i = i0 + 4 * r + g;
+                        if (i >= n) continue;
+                        double v = acc[u][r] + uu[u];
+                        if (a) v = fma(aw[r], t0[u], v);
+                        Out[i * b + c] = (float)v;
+                    }
+                }
+            }
+            kc = kc2;
+            grp = grp2;
+        }
+        return;
+    }
     for (int64_t grp = wave; grp < ngroup; grp += nwaves) {
         const int64_t i0 = grp * 16 * NTL;
         d4v acc[NTL][CT];
@@ -652,6 +750,103 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
                     Out[i * b + c] = (float)v;
                 }
             }
+    }
+}
+
+// The same product for d <= 64 with V in registers: lane (m, g) keeps the
+// 4 x 4 x CT values V[16 kc + 4 g + s][16 u + m] that its B operands take in
+// every group, loaded once per wave, and the centres of its coordinates; the
+// next group's points are loaded before the current group's products.  No LDS,
+// and the products are taken in the same order as in sf_apply_mfma, so the
+// results are the same bit for bit.
+template <int CT>
+__global__ __launch_bounds__(256) void sf_apply_vreg(const float* __restrict__ X, const double* __restrict__ centre,
+                                                     int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
+                                                     const double* __restrict__ V, const double* __restrict__ a,
+                                                     const double* __restrict__ U, float* __restrict__ Out)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int64_t ngroup = (n + 15) / 16;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + w, nwaves = (int64_t)gridDim.x * 4;
+    double vr[4][4][CT], cz[4][4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = 16 * kc + 4 * g + s;
+            cz[kc][s] = (centre && k < d) ? centre[k] : 0.0;
+#pragma unroll
+            for (int u = 0; u < CT; ++u) {
+                const int c = 16 * u + m;
+                vr[kc][s][u] = (k < d && c < b) ? V[(size_t)k * b + c] : 0.0;
+            }
+        }
+    double t0[CT], uu[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+        const int c = 16 * u + m;
+        t0[u] = c < b ? T0[c] : 0.0;
+        uu[u] = (U && c < b) ? U[c] : 0.0;
+    }
+    const bool vec = d % 4 == 0;
+    // coordinates 16 kc + 4g .. +3 of point i, zero outside the data
+    auto load = [&](int64_t i, float (&xv)[4][4]) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            const int kq = 16 * kc + 4 * g;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) xv[kc][s] = 0.0f;
+            if (i >= n) continue;
+            if (vec) {
+                if (kq < d) {
+                    const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(X + i * d + kq);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) xv[kc][s] = q.v[s];
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    if (kq + s < d) xv[kc][s] = X[i * d + kq + s];
+            }
+        }
+    };
+    float xg[4][4];
+    if (wave < ngroup) load(wave * 16 + m, xg);
+    for (int64_t grp = wave; grp < ngroup; grp += nwaves) {
+        const int64_t i0 = grp * 16;
+        float xv[4][4];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) xv[kc][s] = xg[kc][s];
+        if (grp + nwaves < ngroup) load((grp + nwaves) * 16 + m, xg);
+        d4v acc[CT];
+#pragma unroll
+        for (int u = 0; u < CT; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bool kin = 16 * kc + 4 * g + s < d;
+                const double xa = kin ? (double)xv[kc][s] - cz[kc][s] : 0.0;
+#pragma unroll
+                for (int u = 0; u < CT; ++u)
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, vr[kc][s][u], acc[u], 0, 0, 0);
+            }
+#pragma unroll
+        for (int u = 0; u < CT; ++u) {
+            const int c = 16 * u + m;
+            if (c >= b) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + 4 * r + g;
+                if (i >= n) continue;
+                double v = acc[u][r] + uu[u];
+                if (a) v = fma(a[i], t0[u], v);
+                Out[i * b + c] = (float)v;
+            }
+        }
     }
 }
 
@@ -1198,10 +1393,10 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
         const int64_t rpw = ((q.n + waves - 1) / waves + 3) / 4 * 4;
         dim3 grid((unsigned)(waves / 4), (unsigned)((q.d + 63) / 64));
         if (form == SF_LOG)
-            sf_moments_mfma<double><<<grid, 256, 0, s>>>(q.LX, nullptr, (const float*)q.Z, q.n, q.d, q.b, rpw,
+            sf_moments_mfma<double, SF_MOM_DEPTH><<<grid, 256, 0, s>>>(q.LX, nullptr, (const float*)q.Z, q.n, q.d, q.b, rpw,
                                                          (double*)part);
         else
-            sf_moments_mfma<float><<<grid, 256, 0, s>>>((const float*)q.X, (const double*)q.centre,
+            sf_moments_mfma<float, SF_MOM_DEPTH><<<grid, 256, 0, s>>>((const float*)q.X, (const double*)q.centre,
                                                         (const float*)q.Z, q.n, q.d, q.b, rpw, (double*)part);
         e = hipGetLastError();
         nblk = waves;
@@ -1236,9 +1431,9 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
 #define SF_APPLY_MFMA(CT)                                                                                           \
     do {                                                                                                            \
         if (lds)                                                                                                    \
-            sf_apply_mfma<CT, true><<<gb, 512, shm, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, q.U, O);              \
+            sf_apply_mfma<CT, true, true><<<gb, 512, shm, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, q.U, O);        \
         else                                                                                                        \
-            sf_apply_mfma<CT, false><<<2 * gb, 256, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, q.U, O);           \
+            sf_apply_mfma<CT, false, true><<<2 * gb, 256, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, q.U, O);     \
     } while (0)
         switch ((q.b + 15) / 16) {
         case 1: SF_APPLY_MFMA(1); break;
