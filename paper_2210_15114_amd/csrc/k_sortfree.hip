@@ -570,10 +570,14 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
     const int64_t ngroup = (n + 16 * NTL - 1) / (16 * NTL);
     const int64_t wave = (int64_t)blockIdx.x * wpb + w, nwaves = (int64_t)gridDim.x * wpb;
     const bool vec = d % 4 == 0;
+    // column of tile u at tile column m: 16 u + m, or with PIPE CT m + u, so
+    // that a lane's CT results of a row are adjacent columns (one 16-byte
+    // store per row at CT = 4)
+    auto colof = [&](int u) { return PIPE ? CT * m + u : 16 * u + m; };
     double t0[CT], uu[CT];
 #pragma unroll
     for (int u = 0; u < CT; ++u) {
-        const int c = 16 * u + m;
+        const int c = colof(u);
         t0[u] = c < b ? T0[c] : 0.0;
         uu[u] = (U && c < b) ? U[c] : 0.0;
     }
@@ -596,6 +600,8 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
         }
     };
     if constexpr (PIPE) {
+        // 16-byte rows of Out: b a multiple of 4 and Out 16-byte aligned
+        const bool vec4 = b % 4 == 0 && (uintptr_t)Out % 16 == 0;
         // one flat loop over the wave's (group, chunk) pairs: the next pair's
         // points and centres are loaded before the current pair's products,
         // also across a group boundary, and a group's weights a_i when the
@@ -654,7 +660,7 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
                 double vb[CT];
 #pragma unroll
                 for (int u = 0; u < CT; ++u) {
-                    const int c = 16 * u + m;
+                    const int c = colof(u);
                     vb[u] = (kin && c < b) ? Vs[(size_t)k * b + c] : 0.0;
                 }
                 const double xa = kin ? (double)xv[s] - cv[s] : 0.0;   // zero for points past n
@@ -663,16 +669,23 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
             }
             if (kc == nch - 1) {
 #pragma unroll
-                for (int u = 0; u < CT; ++u) {
-                    const int c = 16 * u + m;
-                    if (c >= b) continue;
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = i0 + 4 * r + g;
+                    if (i >= n) continue;
+                    float o[CT];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t i = i0 + 4 * r + g;
-                        if (i >= n) continue;
+                    for (int u = 0; u < CT; ++u) {
                         double v = acc[u][r] + uu[u];
                         if (a) v = fma(aw[r], t0[u], v);
-                        Out[i * b + c] = (float)v;
+                        o[u] = (float)v;
+                    }
+                    if (CT == 4 && vec4) {
+                        if (CT * m < b)
+                            *reinterpret_cast<float4*>(Out + i * b + CT * m) = make_float4(o[0], o[1], o[2], o[3]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < CT; ++u)
+                            if (colof(u) < b) Out[i * b + colof(u)] = o[u];
                     }
                 }
             }
