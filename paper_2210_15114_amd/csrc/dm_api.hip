@@ -771,7 +771,11 @@ dm_status matvec_impl(dm_handle* h, const void* Z, int zkind, int32_t b, void* O
             DM_TRY(launch_lp_pass(h->is_int, zkind, pw, b, a, s));
         }
     } else if (sf_metric(h->metric)) {
-        {
+        // the single-moment forms on matrix cores sum z and w z inside their
+        // moments kernel; the others take the totals kernel first
+        const int form = sf_form(h->metric);
+        const bool fuse = sf_fuses_totals(form, h->is_int, h->d, b, Z);
+        if (!fuse) {
             ProfScope ps(h, DM_K_TOTALS, s);
             DM_TRY(launch_totals(h->is_int, zkind, Z, h->n, b, h->ws + h->L.rowsum, h->guard_scale, tot, s));
         }
@@ -803,6 +807,7 @@ dm_status matvec_impl(dm_handle* h, const void* Z, int zkind, int32_t b, void* O
             q.W = W;
             q.a = weights;
             q.U = (const double*)tot.U;
+            if (fuse) q.wu = weights;
             break;
         case DM_BILINEAR:   // x_i^T M sum_j z_j x_j (Algorithms 8 and 9)
             q.W = W;
@@ -811,8 +816,9 @@ dm_status matvec_impl(dm_handle* h, const void* Z, int zkind, int32_t b, void* O
         default:
             break;
         }
+        if (fuse) q.status = &h->ctl->status;
         ProfScope ps(h, DM_K_SORTFREE, s);
-        DM_TRY(launch_sf_query(sf_form(h->metric), metric_power(h->metric), h->is_int, zkind, q, rest, s));
+        DM_TRY(launch_sf_query(form, metric_power(h->metric), h->is_int, zkind, q, rest, s));
     } else if (l1_pass_metric(h->metric)) {
         {
             ProfScope ps(h, DM_K_TOTALS, s);

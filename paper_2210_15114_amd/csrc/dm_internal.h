@@ -269,7 +269,16 @@ struct SfQuery {
     const double* W;        // d x d applied to the moments, or NULL
     double alpha;           // scale of the moments when W is NULL
     void* Out;              // n x b (float | int64)
+    // Totals formed by the query itself (when sf_fuses_totals holds): the
+    // moments kernel also sums z and w z from its loads; T0 and U above are
+    // then ignored, and a non-finite z raises QF_NONFINITE in *status.
+    uint32_t* status = nullptr;   // NULL: T0 (and U) are given
+    const double* wu = nullptr;   // n weights w of U = sum_j w_j z_j, or NULL (no U)
 };
+// whether launch_sf_query forms the totals itself for this shape (the
+// single-moment forms on matrix cores: float data, b > 32, d and b multiples
+// of 4, Z 16-byte aligned)
+bool sf_fuses_totals(int form, bool is_int, int32_t d, int32_t b, const void* Z);
 int sf_moment_count(int form, int p);
 size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p);
 hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuery& q, void* scratch, hipStream_t s);

@@ -457,10 +457,13 @@ __device__ __forceinline__ void load4(const XT* p, double (&v)[4]) {
 // of the columns holds c = 4 n + u at tile column n.  Needs d % 4 == 0 and
 // b % 4 == 0.
 constexpr int SF_MOM_DEPTH = 4;   // row steps in flight per wave
-template <typename XT, int P>
+// TOT: the waves of the first coordinate block also sum z and w z (FP64)
+// over their rows into tpart[wave][0 | 1][c] (the totals of the query).
+template <typename XT, int P, bool TOT>
 __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X, const double* __restrict__ centre,
                                                        const float* __restrict__ Z, int64_t n, int32_t d, int32_t b,
-                                                       int64_t rows_per_wave, double* __restrict__ part)
+                                                       int64_t rows_per_wave, double* __restrict__ part,
+                                                       const double* __restrict__ wu, double* __restrict__ tpart)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
@@ -484,10 +487,15 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
     // a slot is refilled with the step P ahead right after it is consumed
     XT xn[P][4];
     float zn[P][4];
-    auto fetch = [&](int64_t j, XT (&xv)[4], float (&zv)[4]) {
+    double wn[P];
+    const bool tw = TOT && blockIdx.y == 0;
+    double t0a[4] = {0.0, 0.0, 0.0, 0.0}, ua[4] = {0.0, 0.0, 0.0, 0.0};
+    auto fetch = [&](int64_t j, XT (&xv)[4], float (&zv)[4], double& wv) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) { xv[t] = XT(0); zv[t] = 0.0f; }
+        wv = 0.0;
         if (j < r1) {
+            if (tw && wu) wv = wu[j];
             if (kin) {
                 if constexpr (sizeof(XT) == 4) {
                     const Vec<XT, 4> q = *reinterpret_cast<const Vec<XT, 4>*>(X + j * d + kq);
@@ -507,7 +515,7 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
         }
     };
 #pragma unroll
-    for (int p = 0; p < P; ++p) fetch(r0 + 4 * p + g, xn[p], zn[p]);
+    for (int p = 0; p < P; ++p) fetch(r0 + 4 * p + g, xn[p], zn[p], wn[p]);
     for (int64_t js = r0; js < r1; js += 4 * P) {   // the same trip count on every lane
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -520,12 +528,39 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
                 a[t] = (j < r1 && kin) ? (CEN ? (double)xn[p][t] - cen[t] : (double)xn[p][t]) : 0.0;
                 z[t] = (double)zn[p][t];
             }
-            if (j0 + 4 * P < r1) fetch(j + 4 * P, xn[p], zn[p]);
+            if (tw) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    t0a[u] += z[u];
+                    ua[u] = fma(wn[p], z[u], ua[u]);
+                }
+            }
+            if (j0 + 4 * P < r1) fetch(j + 4 * P, xn[p], zn[p], wn[p]);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], z[u], acc[t][u], 0, 0, 0);
+        }
+    }
+    if (tw) {
+        // the four row lanes g of a column group, added in a fixed xor order
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            t0a[u] += __shfl_xor(t0a[u], 16);
+            ua[u] += __shfl_xor(ua[u], 16);
+            t0a[u] += __shfl_xor(t0a[u], 32);
+            ua[u] += __shfl_xor(ua[u], 32);
+        }
+        if (g == 0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = cq + u;
+                if (c < b) {
+                    tpart[((size_t)xw * 2) * b + c] = t0a[u];
+                    tpart[((size_t)xw * 2 + 1) * b + c] = ua[u];
+                }
+            }
         }
     }
 #pragma unroll
@@ -764,6 +799,14 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
                 }
             }
     }
+}
+
+// a non-finite column sum of z means a non-finite z (finite FP32 values
+// cannot overflow an FP64 sum)
+__global__ void sf_check_finite(const double* __restrict__ T0, int32_t b, uint32_t* __restrict__ status)
+{
+    const int c = threadIdx.x;
+    if (c < b && !isfinite(T0[c])) atomicOr(status, (uint32_t)QF_NONFINITE);
 }
 
 // The same product for d <= 64 with V in registers: lane (m, g) keeps the
@@ -1375,7 +1418,13 @@ size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p) {
     const int nt = sf_moment_count(form, p);
     const int64_t nblk = partial_count(n, d, b, form, nt);
     const size_t cnt = (size_t)nt * d * b;
-    return ((size_t)nblk + 2 + SF_SLICES) * cnt * 8;   // row-range partials, the moments, the mixed moments, slices
+    // row-range partials, the moments, the mixed moments, slices; then the
+    // totals' partials and the totals
+    return ((size_t)nblk + 2 + SF_SLICES) * cnt * 8 + ((size_t)nblk + 1) * 2 * (size_t)b * 8;
+}
+
+bool sf_fuses_totals(int form, bool is_int, int32_t d, int32_t b, const void* Z) {
+    return !is_int && mfma_moments_fit(form, d, b) && (uintptr_t)Z % 16 == 0;
 }
 
 hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuery& q, void* scratch, hipStream_t s)
@@ -1388,6 +1437,8 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     char* G = part + (size_t)nblk_max * cnt * 8;
     char* V = G + cnt * 8;
     char* SL = V + cnt * 8;
+    double* tpart = (double*)(SL + (size_t)SF_SLICES * cnt * 8);
+    double* GT = tpart + (size_t)nblk_max * 2 * q.b;
     if (form == SF_EVEN) {
         switch (p) {
         case 2: return even_query<2>(is_int, zkind, q, part, G, SL, s);
@@ -1401,18 +1452,36 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     const int64_t per_t = (int64_t)q.d * q.b;
     // KL and cross entropy: moments of the logarithms kept since preparation
     hipError_t e;
+    const bool fuse = q.status != nullptr;
+    if (fuse && !sf_fuses_totals(form, is_int, q.d, q.b, q.Z)) return hipErrorInvalidValue;
+    const double* T0q = (const double*)q.T0;
+    const double* Uq = q.U;
     if (mfma_moments_fit(form, q.d, q.b) && (uintptr_t)q.Z % 16 == 0) {
         const int64_t waves = mfma_row_waves(q.n, q.d);
         const int64_t rpw = ((q.n + waves - 1) / waves + 3) / 4 * 4;
         dim3 grid((unsigned)(waves / 4), (unsigned)((q.d + 63) / 64));
-        if (form == SF_LOG)
-            sf_moments_mfma<double, SF_MOM_DEPTH><<<grid, 256, 0, s>>>(q.LX, nullptr, (const float*)q.Z, q.n, q.d, q.b, rpw,
-                                                         (double*)part);
-        else
-            sf_moments_mfma<float, SF_MOM_DEPTH><<<grid, 256, 0, s>>>((const float*)q.X, (const double*)q.centre,
-                                                        (const float*)q.Z, q.n, q.d, q.b, rpw, (double*)part);
+#define SF_MOMENTS(XT, XP, CP, TOT)                                                                               \
+    sf_moments_mfma<XT, SF_MOM_DEPTH, TOT><<<grid, 256, 0, s>>>(XP, CP, (const float*)q.Z, q.n, q.d, q.b, rpw,    \
+                                                                 (double*)part, q.wu, tpart)
+        if (form == SF_LOG) {
+            if (fuse) SF_MOMENTS(double, q.LX, nullptr, true);
+            else SF_MOMENTS(double, q.LX, nullptr, false);
+        } else {
+            if (fuse) SF_MOMENTS(float, (const float*)q.X, (const double*)q.centre, true);
+            else SF_MOMENTS(float, (const float*)q.X, (const double*)q.centre, false);
+        }
+#undef SF_MOMENTS
         e = hipGetLastError();
         nblk = waves;
+        if (e == hipSuccess && fuse) {
+            // sum z and sum w z over the waves (fixed order), then the finiteness check
+            if ((e = reduce_launch<double>(tpart, waves, 2 * (int64_t)q.b, 1, 0, 1.0, GT, SL, s)) != hipSuccess)
+                return e;
+            sf_check_finite<<<1, 64, 0, s>>>(GT, q.b, q.status);
+            e = hipGetLastError();
+            T0q = GT;
+            Uq = q.wu ? GT + q.b : nullptr;
+        }
     } else {
         e = (form == SF_LOG)
                 ? moments_t<double, float, double, 1>(q.b, q.LX, nullptr, q.Z, q.n, q.d, part, &nblk, s)
@@ -1435,7 +1504,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
         if (blocks > 1024) blocks = 1024;
         const unsigned gb = (unsigned)blocks;
         const float* Xf = (const float*)q.X;
-        const double* T0 = (const double*)q.T0;
+        const double* T0 = T0q;
         const double* Vd = (const double*)Gv;
         float* O = (float*)q.Out;
         const size_t vbytes = (size_t)q.d * q.b * 8;
@@ -1444,9 +1513,9 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
 #define SF_APPLY_MFMA(CT)                                                                                           \
     do {                                                                                                            \
         if (lds)                                                                                                    \
-            sf_apply_mfma<CT, true, true><<<gb, 512, shm, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, q.U, O);        \
+            sf_apply_mfma<CT, true, true><<<gb, 512, shm, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O);         \
         else                                                                                                        \
-            sf_apply_mfma<CT, false, true><<<2 * gb, 256, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, q.U, O);     \
+            sf_apply_mfma<CT, false, true><<<2 * gb, 256, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O);      \
     } while (0)
         switch ((q.b + 15) / 16) {
         case 1: SF_APPLY_MFMA(1); break;
@@ -1457,7 +1526,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
 #undef SF_APPLY_MFMA
         return hipGetLastError();
     }
-    return apply_t<float, double, float, 1, false>(q.X, cen, q.n, q.d, q.b, q.T0, Gv, q.a, q.U, q.Out, s);
+    return apply_t<float, double, float, 1, false>(q.X, cen, q.n, q.d, q.b, T0q, Gv, q.a, Uq, q.Out, s);
 }
 
 hipError_t launch_kl_weights(const float* X, int64_t n, int32_t d, double* negH, double* LX, uint32_t* flags,

@@ -425,3 +425,44 @@ def test_full_size_wide_blocks_sampled_rows():
         _check_float(X, Z, Y.cpu().numpy(), metric, scale, M=Mm, rows=rows, p=p)
         h.free()
         del Y
+
+
+# ---------------------------------------------------------------------------
+# a non-finite right-hand side raises DM_ERR_NONFINITE on every path: the
+# totals kernel, and the single-moment forms on matrix cores, which sum z
+# inside their moments kernel and check the column sums
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("metric,b,d", [(oracle.KL, 64, 8), (oracle.MAHA2, 64, 12), (oracle.BILINEAR, 48, 16),
+                                        (oracle.CE, 64, 4), (oracle.L4, 64, 5), (oracle.KL, 1, 8)])
+@pytest.mark.parametrize("case", ["inf", "nan", "both_infs"])
+def test_nonfinite_rhs_flagged(metric, b, d, case):
+    g = synth.rng(9990 + b + d)
+    n = 3001
+    M = None
+    if metric in (oracle.KL, oracle.CE):
+        X = synth.simplex_points(n, d, 9991 + d)
+    else:
+        X = (g.standard_normal((n, d)) + 2.0).astype(np.float32)
+        if metric in (oracle.MAHA2, oracle.BILINEAR):
+            M = synth.square_matrix(d, 9992 + d, "spd" if metric == oracle.MAHA2 else "general")
+    Z = g.standard_normal((n, b)).astype(np.float32)
+    Zbad = Z.copy()
+    if case == "inf":
+        Zbad[1234, b - 1] = np.inf
+    elif case == "nan":
+        Zbad[0, 0] = np.nan
+    else:
+        Zbad[7, b // 2] = np.inf
+        Zbad[n - 1, b // 2] = -np.inf
+    h = dm.prepare(dev(X), metric, M=M)
+    h.matvec(dev(Zbad if b > 1 else Zbad[:, 0].copy()))
+    with pytest.raises(dm.DMError) as ei:
+        h.sync()
+    assert ei.value.status == dm.ERR_NONFINITE
+    Y = h.matvec(dev(Z if b > 1 else Z[:, 0].copy()))
+    h.sync()
+    Y = Y.cpu().numpy()
+    h.free()
+    assert np.all(np.isfinite(Y))
+    Yref = _query(X, Z if b > 1 else Z[:, 0].copy(), metric, M=M)
+    assert np.array_equal(Y, Yref)
