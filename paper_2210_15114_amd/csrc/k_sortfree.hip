@@ -448,7 +448,7 @@ __device__ __forceinline__ void load4(const XT* p, double (&v)[4]) {
     }
 }
 
-// part[wave][k][c] = sum over the wave's rows j of phi(x_jk) z_jc (phi: the
+// part[wg][k][c] = sum over the workgroup's rows j of phi(x_jk) z_jc (phi: the
 // centred coordinate, or the stored logarithm).  A wave owns 64 coordinates
 // (workgroup column blockIdx.y) and 64 columns: 4 x 4 tiles of 16 x 16.  Each
 // step takes 4 rows; lane (m, g) = (l % 16, l / 16) loads coordinates
@@ -563,15 +563,44 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
             }
         }
     }
+    // the workgroup's four waves (disjoint row ranges, the same coordinates)
+    // add their sums in LDS in a fixed order, (w0 + w2) + (w1 + w3), and
+    // wave 0 writes one partial per workgroup
+    __shared__ d4v s_acc[2][4][4][64];
+    if (w >= 2) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) s_acc[w - 2][t][u][lane] = acc[t][u];
+    }
+    __syncthreads();
+    if (w < 2) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int k = k0 + 4 * (4 * r + g) + t, c = 4 * m + u;
-                if (k < d && c < b) part[((size_t)xw * d + k) * b + c] = acc[t][u][r];
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[t][u] += s_acc[w][t][u][lane];
+    }
+    __syncthreads();
+    if (w == 1) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s_acc[0][t][u][lane] = acc[t][u];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const d4v v = acc[t][u] + s_acc[0][t][u][lane];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = k0 + 4 * (4 * r + g) + t, c = 4 * m + u;
+                    if (k < d && c < b) part[((size_t)blockIdx.x * d + k) * b + c] = v[r];
+                }
             }
+    }
 }
 
 // Out[i][c] = sum_k x~_ik V[k][c] + a_i T0_c + U_c on matrix cores.  A wave
@@ -1472,7 +1501,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
         }
 #undef SF_MOMENTS
         e = hipGetLastError();
-        nblk = waves;
+        nblk = waves / 4;   // one partial per workgroup
         if (e == hipSuccess && fuse) {
             // sum z and sum w z over the waves (fixed order), then the finiteness check
             if ((e = reduce_launch<double>(tpart, waves, 2 * (int64_t)q.b, 1, 0, 1.0, GT, SL, s)) != hipSuccess)
