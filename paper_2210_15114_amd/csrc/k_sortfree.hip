@@ -604,19 +604,19 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
 }
 
 // Out[i][c] = sum_k x~_ik V[k][c] + a_i T0_c + U_c on matrix cores.  A wave
-// takes NTL tiles of 16 points at a time and every column (CT tiles of 16);
-// per chunk of 16 coordinates lane (m, g) loads coordinates k0 + 4g .. +3 of
-// point m of each tile (one 16-byte load when d % 4 == 0; the next chunk's
-// loads are issued before the current chunk's products), and step s of the
-// chunk multiplies the A column g = coordinate k0 + 4g + s.  V (d x b FP64) is
-// staged once per workgroup in dynamic LDS when it fits (LDS_V), else read
-// through the caches; each V operand serves all NTL tiles.  PIPE: the
-// (group, chunk) pairs of a wave form one loop, so the loads run ahead across
-// group boundaries too (0.30 -> 0.23 ms at n = 2^20, d = 64, b = 64; the
-// per-group loop left the first chunk's points and the epilogue's weights
-// waiting on memory in every group).
-constexpr int NTL = 1;   // 2 or 4 tiles per step measured slower (fewer waves per SIMD) than 1
-template <int CT, bool LDS_V, bool PIPE>
+// takes groups of 16 points and every column (CT tiles of 16); per chunk of
+// 16 coordinates lane (m, g) loads coordinates k0 + 4g .. +3 of point m (one
+// 16-byte load when d % 4 == 0), and step s of the chunk multiplies the A
+// column g = coordinate k0 + 4g + s.  The (group, chunk) pairs of a wave form
+// one loop, so the next pair's loads are issued before the current pair's
+// products also across group boundaries, and a group's weights a_i when the
+// group starts (0.30 -> 0.23 ms at n = 2^20, d = 64, b = 64 against a loop per
+// group, which left the first chunk's points and the epilogue's weights
+// waiting on memory in every group).  V (d x b FP64) is staged once per
+// workgroup in dynamic LDS when it fits (LDS_V), else read through the caches.
+// One 16-point group per wave: 2 or 4 groups at a time measured slower (fewer
+// waves per SIMD).
+template <int CT, bool LDS_V>
 __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X, const double* __restrict__ centre,
                                                      int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
                                                      const double* __restrict__ V, const double* __restrict__ a,
@@ -631,13 +631,13 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
         __syncthreads();
     }
     const double* Vs = LDS_V ? sV : V;
-    const int64_t ngroup = (n + 16 * NTL - 1) / (16 * NTL);
+    const int64_t ngroup = (n + 15) / 16;
     const int64_t wave = (int64_t)blockIdx.x * wpb + w, nwaves = (int64_t)gridDim.x * wpb;
     const bool vec = d % 4 == 0;
-    // column of tile u at tile column m: 16 u + m, or with PIPE CT m + u, so
-    // that a lane's CT results of a row are adjacent columns (one 16-byte
-    // store per row at CT = 4)
-    auto colof = [&](int u) { return PIPE ? CT * m + u : 16 * u + m; };
+    // column of tile u at tile column m: CT m + u, so that a lane's CT
+    // results of a row are adjacent columns (one 16-byte store per row at
+    // CT = 4)
+    auto colof = [&](int u) { return CT * m + u; };
     double t0[CT], uu[CT];
 #pragma unroll
     for (int u = 0; u < CT; ++u) {
@@ -663,170 +663,97 @@ __global__ __launch_bounds__(512) void sf_apply_mfma(const float* __restrict__ X
                 if (kq + s < d) xv[s] = X[ia * d + kq + s];
         }
     };
-    if constexpr (PIPE) {
-        // 16-byte rows of Out: b a multiple of 4 and Out 16-byte aligned
-        const bool vec4 = b % 4 == 0 && (uintptr_t)Out % 16 == 0;
-        // one flat loop over the wave's (group, chunk) pairs: the next pair's
-        // points and centres are loaded before the current pair's products,
-        // also across a group boundary, and a group's weights a_i when the
-        // group starts, so neither waits at the group's ends
-        const int nch = (d + 15) / 16;
-        int64_t grp = wave;
-        int kc = 0;
-        float xn[4];
-        double cn[4];
-        auto load_centre = [&](int k0, double (&c)[4]) {
+    // 16-byte rows of Out: b a multiple of 4 and Out 16-byte aligned
+    const bool vec4 = b % 4 == 0 && (uintptr_t)Out % 16 == 0;
+    // one flat loop over the wave's (group, chunk) pairs: the next pair's
+    // points and centres are loaded before the current pair's products,
+    // also across a group boundary, and a group's weights a_i when the
+    // group starts, so neither waits at the group's ends
+    const int nch = (d + 15) / 16;
+    int64_t grp = wave;
+    int kc = 0;
+    float xn[4];
+    double cn[4];
+    auto load_centre = [&](int k0, double (&c)[4]) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = k0 + 4 * g + s;
-                c[s] = (centre && k < d) ? centre[k] : 0.0;
-            }
-        };
-        if (grp < ngroup) {
-            load_chunk(grp * 16 + m, 0, xn);
-            load_centre(0, cn);
+        for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * g + s;
+            c[s] = (centre && k < d) ? centre[k] : 0.0;
         }
-        d4v acc[CT];
-        double aw[4];
-        while (grp < ngroup) {
-            const int64_t i0 = grp * 16;
-            if (kc == 0) {
-#pragma unroll
-                for (int u = 0; u < CT; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t i = i0 + 4 * r + g;
-                    aw[r] = (a && i < n) ? a[i] : 0.0;
-                }
-            }
-            float xv[4];
-            double cv[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                xv[s] = xn[s];
-                cv[s] = cn[s];
-            }
-            int kc2 = kc + 1;
-            int64_t grp2 = grp;
-            if (kc2 == nch) {
-                kc2 = 0;
-                grp2 += nwaves;
-            }
-            if (grp2 < ngroup) {
-                load_chunk(grp2 * 16 + m, 16 * kc2, xn);
-                load_centre(16 * kc2, cn);
-            }
-            const int kq = 16 * kc + 4 * g;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = kq + s;
-                const bool kin = k < d;
-                double vb[CT];
-#pragma unroll
-                for (int u = 0; u < CT; ++u) {
-                    const int c = colof(u);
-                    vb[u] = (kin && c < b) ? Vs[(size_t)k * b + c] : 0.0;
-                }
-                const double xa = kin ? (double)xv[s] - cv[s] : 0.0;   // zero for points past n
-#pragma unroll
-                for (int u = 0; u < CT; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, vb[u], acc[u], 0, 0, 0);
-            }
-            if (kc == nch - 1) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t i = i0 + 4 * r + g;
-                    if (i >= n) continue;
-                    float o[CT];
-#pragma unroll
-                    for (int u = 0; u < CT; ++u) {
-                        double v = acc[u][r] + uu[u];
-                        if (a) v = fma(aw[r], t0[u], v);
-                        o[u] = (float)v;
-                    }
-                    if (CT == 4 && vec4) {
-                        if (CT * m < b)
-                            *reinterpret_cast<float4*>(Out + i * b + CT * m) = make_float4(o[0], o[1], o[2], o[3]);
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < CT; ++u)
-                            if (colof(u) < b) Out[i * b + colof(u)] = o[u];
-                    }
-                }
-            }
-            kc = kc2;
-            grp = grp2;
-        }
-        return;
+    };
+    if (grp < ngroup) {
+        load_chunk(grp * 16 + m, 0, xn);
+        load_centre(0, cn);
     }
-    for (int64_t grp = wave; grp < ngroup; grp += nwaves) {
-        const int64_t i0 = grp * 16 * NTL;
-        d4v acc[NTL][CT];
+    d4v acc[CT];
+    double aw[4];
+    while (grp < ngroup) {
+        const int64_t i0 = grp * 16;
+        if (kc == 0) {
 #pragma unroll
-        for (int q = 0; q < NTL; ++q)
+            for (int u = 0; u < CT; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int u = 0; u < CT; ++u) acc[q][u] = d4v{0.0, 0.0, 0.0, 0.0};
-        float xn[NTL][4];
-        double cn[4];   // centres of the lane's 4 coordinates of the chunk, fetched with X
-        auto load_centre = [&](int k0) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = k0 + 4 * g + s;
-                cn[s] = (centre && k < d) ? centre[k] : 0.0;
-            }
-        };
-#pragma unroll
-        for (int q = 0; q < NTL; ++q) load_chunk(i0 + 16 * q + m, 0, xn[q]);
-        load_centre(0);
-        for (int k0 = 0; k0 < d; k0 += 16) {
-            float xv[NTL][4];
-            double cv[4];
-#pragma unroll
-            for (int q = 0; q < NTL; ++q)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) xv[q][s] = xn[q][s];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) cv[s] = cn[s];
-            if (k0 + 16 < d) {
-#pragma unroll
-                for (int q = 0; q < NTL; ++q) load_chunk(i0 + 16 * q + m, k0 + 16, xn[q]);
-                load_centre(k0 + 16);
-            }
-            const int kq = k0 + 4 * g;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = kq + s;
-                const bool kin = k < d;
-                const double ck = cv[s];
-                double vb[CT];
-#pragma unroll
-                for (int u = 0; u < CT; ++u) {
-                    const int c = 16 * u + m;
-                    vb[u] = (kin && c < b) ? Vs[(size_t)k * b + c] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < NTL; ++q) {
-                    const double xa = kin ? (double)xv[q][s] - ck : 0.0;   // zero for points past n
-#pragma unroll
-                    for (int u = 0; u < CT; ++u)
-                        acc[q][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, vb[u], acc[q][u], 0, 0, 0);
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + 4 * r + g;
+                aw[r] = (a && i < n) ? a[i] : 0.0;
             }
         }
+        float xv[4];
+        double cv[4];
 #pragma unroll
-        for (int q = 0; q < NTL; ++q)
+        for (int s = 0; s < 4; ++s) {
+            xv[s] = xn[s];
+            cv[s] = cn[s];
+        }
+        int kc2 = kc + 1;
+        int64_t grp2 = grp;
+        if (kc2 == nch) {
+            kc2 = 0;
+            grp2 += nwaves;
+        }
+        if (grp2 < ngroup) {
+            load_chunk(grp2 * 16 + m, 16 * kc2, xn);
+            load_centre(16 * kc2, cn);
+        }
+        const int kq = 16 * kc + 4 * g;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kq + s;
+            const bool kin = k < d;
+            double vb[CT];
 #pragma unroll
             for (int u = 0; u < CT; ++u) {
-                const int c = 16 * u + m;
-                if (c >= b) continue;
+                const int c = colof(u);
+                vb[u] = (kin && c < b) ? Vs[(size_t)k * b + c] : 0.0;
+            }
+            const double xa = kin ? (double)xv[s] - cv[s] : 0.0;   // zero for points past n
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t i = i0 + 16 * q + 4 * r + g;
-                    if (i >= n) continue;
-                    double v = acc[q][u][r] + uu[u];
-                    if (a) v = fma(a[i], t0[u], v);
-                    Out[i * b + c] = (float)v;
+            for (int u = 0; u < CT; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, vb[u], acc[u], 0, 0, 0);
+        }
+        if (kc == nch - 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + 4 * r + g;
+                if (i >= n) continue;
+                float o[CT];
+#pragma unroll
+                for (int u = 0; u < CT; ++u) {
+                    double v = acc[u][r] + uu[u];
+                    if (a) v = fma(aw[r], t0[u], v);
+                    o[u] = (float)v;
+                }
+                if (CT == 4 && vec4) {
+                    if (CT * m < b)
+                        *reinterpret_cast<float4*>(Out + i * b + CT * m) = make_float4(o[0], o[1], o[2], o[3]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < CT; ++u)
+                        if (colof(u) < b) Out[i * b + colof(u)] = o[u];
                 }
             }
+        }
+        kc = kc2;
+        grp = grp2;
     }
 }
 
@@ -1528,7 +1455,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     }
     const double* cen = form == SF_LOG ? nullptr : (const double*)q.centre;
     if (q.b >= 4) {   // matrix cores: 16 points x every column per wave (masked past b)
-        const int64_t groups = (q.n + 16 * NTL - 1) / (16 * NTL);
+        const int64_t groups = (q.n + 15) / 16;
         int64_t blocks = (groups + 7) / 8;
         if (blocks > 1024) blocks = 1024;
         const unsigned gb = (unsigned)blocks;
@@ -1542,9 +1469,9 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
 #define SF_APPLY_MFMA(CT)                                                                                           \
     do {                                                                                                            \
         if (lds)                                                                                                    \
-            sf_apply_mfma<CT, true, true><<<gb, 512, shm, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O);         \
+            sf_apply_mfma<CT, true><<<gb, 512, shm, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O);         \
         else                                                                                                        \
-            sf_apply_mfma<CT, false, true><<<2 * gb, 256, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O);      \
+            sf_apply_mfma<CT, false><<<2 * gb, 256, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O);      \
     } while (0)
         switch ((q.b + 15) / 16) {
         case 1: SF_APPLY_MFMA(1); break;
