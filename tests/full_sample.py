@@ -124,6 +124,9 @@ def cmd_errors(a):
              % (M_ROWS, len(set(extra)), tie_len),
              "# GPU rows: %s" % os.path.basename(a.gpu),
              "# sources_sha256_16: %s" % sources_hash(),
+             "# GPU rows written by: python bench.py --dump-rows %s" % os.path.basename(a.gpu),
+             "# oracle rows computed by: python tests/full_sample.py oracle --metric l1 --cache <dir>"
+             " (and --metric l2sq), on the host",
              "# command: python tests/full_sample.py errors --gpu %s --cache <dir>" % os.path.basename(a.gpu)]
     for metric, keys in (("l1", ("l1", "single")), ("l2sq", ("l2sq",))):
         path = cache_file(a.cache, metric, rows)
