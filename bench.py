@@ -40,7 +40,6 @@ Prints exactly one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -60,10 +59,10 @@ def log(*a):
 
 
 def src_hash(paths):
-    h = hashlib.sha256()
-    for p in paths:
-        h.update(open(p, "rb").read())
-    return h.hexdigest()[:16]
+    """Hash of the kernel code (comments and whitespace runs ignored) that the
+    stored counter and error figures were taken with."""
+    from paper_2210_15114_amd.build import code_hash
+    return code_hash(paths)
 
 
 def read_traffic(variant):

@@ -5,17 +5,18 @@
 // split into a BF16 high part and a BF16 remainder, x = xh + xl; products
 // use xh*yh + xh*yl + xl*yh, which keeps each term to about 2^-16 relative
 // (the dropped xl*yl and the remainders of the splits are of that order).
-// Accumulation is FP32 inside the matrix cores, flushed into FP64 every 256
-// points in the first contraction; the rank-one terms and the final
-// combination are FP64.  The three products of a split go to three
-// independent accumulators (hh, hl, lh), added only when they leave the
-// matrix cores: a chain of dependent matrix-core products waits out the full
-// latency of each one, which made both kernels latency-bound (about half the
-// achievable bandwidth) when the three shared one accumulator.
+// Accumulation is FP32 inside the matrix cores, flushed every 256 points in
+// the first contraction (into FP32 sums of at most four flushes, then FP64,
+// or straight into FP64 for the general shapes); the rank-one terms and the
+// final combination are FP64.  No matrix-core product waits on the one
+// before it: the split products go to separate accumulators or are
+// interleaved with other tiles' products, since a chain of dependent
+// products waits out the full latency of each one (with one accumulator per
+// tile both kernels ran at about half the achievable bandwidth).
 //
-// For d = 128, b = 64 and whole ranges of points the first kernel also adds
-// the rank-one totals S0 = sum_j z_j and R = sum_j ||x_j||^2 z_j (FP64) while
-// it reads Z, so Z is read twice per query (here and by no totals kernel).
+// For d = 128, b = 64 and whole ranges of points the first kernel also forms
+// the rank-one totals S0 = sum_j z_j and R = sum_j ||x_j||^2 z_j (FP64) from
+// its own loads of Z, so a query reads Z once.
 //
 // Shapes: d <= 128 and b >= 16 (other shapes take the vector path).
 //

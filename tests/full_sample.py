@@ -96,12 +96,10 @@ SRCS = ("l1_pass.h", "l1_common.h", "k_l1.hip", "k_prep.hip", "k_sort.hip", "k_l
 
 
 def sources_hash():
-    """The kernel sources the sampled results come from (the benchmark reports
-    these figures only while the sources are unchanged)."""
-    h = hashlib.sha256()
-    for f in SRCS:
-        h.update(open(os.path.join(ROOT, "paper_2210_15114_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
+    """The kernel code the sampled results come from (comments ignored; the
+    benchmark reports these figures only while the code is unchanged)."""
+    from paper_2210_15114_amd.build import code_hash
+    return code_hash([os.path.join(ROOT, "paper_2210_15114_amd", "csrc", f) for f in SRCS])
 
 
 def fmt(e):
