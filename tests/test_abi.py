@@ -180,3 +180,15 @@ def test_int_bound_guard(L):
     assert not dm.int_bound_ok(2.0 ** 31, 2.0 ** 31)          # 2^62 is not below 2^62
     assert not dm.int_bound_ok(float("nan"), 1.0)
     assert not dm.int_bound_ok(-1.0, 1.0)
+
+
+def test_code_hash_ignores_comments_only(tmp_path):
+    # the stored counter and error figures name the kernel code by this hash
+    from paper_2210_15114_amd.build import code_hash
+    a = tmp_path / "a.hip"
+    a.write_text("int f(int x) {\n    return x + 1;   // one more\n}\n")
+    h0 = code_hash([str(a)])
+    a.write_text("/* header */\nint f(int x)\n{\n  return x + 1;\n}\n// trailing\n")
+    assert code_hash([str(a)]) == h0
+    a.write_text("int f(int x) {\n    return x + 2;\n}\n")
+    assert code_hash([str(a)]) != h0
