@@ -137,11 +137,12 @@ __global__ __launch_bounds__(256) void l2_apply_vec(const typename L2T<INT>::X* 
 
 size_t l2_scratch_bytes(int64_t n, int32_t d, int32_t b) {
     const size_t nblk = (size_t)((n + VROWS - 1) / VROWS);
+    // the integer path's partials; then, for float data, the matrix-core
+    // form (d <= 128, 16 <= b <= 64) or else the linear sort-free form
     const size_t vec = (nblk + 1) * (size_t)d * (size_t)b * 8 + 256;
-    const size_t lin = sf_scratch_bytes(n, d, b, SF_LIN, 1);
-    const size_t mf = l2_mfma_scratch_bytes(n, d, b);
-    const size_t m = vec > lin ? vec : lin;
-    return m > mf ? m : mf;
+    const bool mfma = d <= 128 && b >= 16 && b <= 64;
+    const size_t fl = mfma ? l2_mfma_scratch_bytes(n, d, b) : sf_scratch_bytes(n, d, b, SF_LIN, 1);
+    return vec > fl ? vec : fl;
 }
 
 hipError_t launch_l2sq_mfma(int zkind, const float* Xc, const double* nrm, int64_t n, int32_t d, const float* Z,

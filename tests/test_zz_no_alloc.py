@@ -78,6 +78,26 @@ def test_static_l2sq_and_odd_p():
         assert e1["spec"] <= 1e-6 and e2["spec"] <= 1e-6, (e1, e2)
 
 
+def test_static_fixed_order_paths_are_bitwise_equal():
+    """Queries whose every sum has a fixed order give the same bits through
+    either entry point: l2 squared at d = 128, b = 64 (the X^T Z kernel that
+    also forms the totals), and the KL divergence on matrix cores (totals
+    summed inside the moments kernel); the second call of each is smaller."""
+    for metric, shapes in ((L2SQ, ((8192, 128, 64), (4096, 128, 64))),
+                           (oracle.KL, ((3001, 8, 64), (1000, 8, 48)))):
+        for n, d, b in shapes:
+            g = synth.rng(9400 + n + b)
+            if metric == oracle.KL:
+                X = synth.simplex_points(n, d, 9401 + n)
+            else:
+                X = g.standard_normal((n, d)).astype(np.float32)
+            Z = g.standard_normal((n, b)).astype(np.float32)
+            h = dm.prepare(dev(X), metric)
+            y1, y2 = _both(h, Z)
+            h.free()
+            assert np.array_equal(y1, y2), (metric, n, d, b)
+
+
 def test_static_refuses_shapes_beyond_the_array():
     """n = 2^23 points at b = 64: the pass's look-back records alone (two
     records of 64 double-float pairs per 512-rank tile) exceed 32 MiB."""
