@@ -8,10 +8,15 @@
 // for a standard Gaussian g is beta ||x||_2).  X' is then prepared and
 // queried with the l1 path unchanged.
 //
-// A tiled product: a workgroup forms 64 rows x 64 columns of X' from LDS
-// tiles of X (64 rows) and G (64 rows), 32 coordinates at a time; each
-// thread owns 4 x 4 outputs, accumulated in FP64 and rounded once to FP32.
-// The work is one-time preparation, bound by writing X' (n k 4 bytes).
+// A tiled product on the FP64 matrix cores (v_mfma_f64_16x16x4f64): a
+// workgroup forms 64 rows x 64 columns of X' from LDS tiles of X (64 rows)
+// and G (64 rows), 32 coordinates at a time; wave w owns rows 16w .. +15 and
+// the four 16-column tiles.  The products are exact FP64 fused operations, the
+// sums FP64, rounded once to FP32.  The work is one-time preparation.
+//
+// Lane layout (checked on the GPU with a probe): A (16 x 4): lane l holds
+// A[l % 16][l / 16]; B (4 x 16): lane l holds B[l / 16][l % 16]; D (16 x 16):
+// lane l, element r holds D[4r + l / 16][l % 16].
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,6 +31,8 @@ constexpr int ER = 64;   // rows of X' per workgroup
 constexpr int EC = 64;   // columns of X' per workgroup
 constexpr int EK = 32;   // coordinates per LDS step
 
+typedef double d4v __attribute__((ext_vector_type(4)));
+
 template <typename XT>
 __global__ __launch_bounds__(256) void embed_kernel(const XT* __restrict__ X, int64_t n, int32_t d,
                                                     const double* __restrict__ G, int32_t k, double scale,
@@ -33,15 +40,13 @@ __global__ __launch_bounds__(256) void embed_kernel(const XT* __restrict__ X, in
 {
     __shared__ double sX[ER][EK + 1];
     __shared__ double sG[EC][EK + 1];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m = lane & 15, g = lane >> 4;
     const int64_t r0 = (int64_t)blockIdx.x * ER;
     const int c0 = blockIdx.y * EC;
-    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;   // this thread's 4 x 4 outputs
-    double acc[4][4];
+    d4v acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int u = 0; u < 4; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
     for (int j0 = 0; j0 < d; j0 += EK) {
         for (int e = tid; e < ER * EK; e += 256) {
             const int r = e / EK, j = e % EK;
@@ -53,29 +58,24 @@ __global__ __launch_bounds__(256) void embed_kernel(const XT* __restrict__ X, in
             sG[c][j] = (c0 + c < k && j0 + j < d) ? G[(int64_t)(c0 + c) * d + j0 + j] : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int j = 0; j < EK; ++j) {
-            double a[4], g[4];
+        // coordinates j0 + 4 kk + g: A[m][g] = X[16w + m][..], B[g][m] = G[16u + m][..]
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = sX[tr + i][j];
-                g[i] = sG[tc + i][j];
-            }
+        for (int kk = 0; kk < EK / 4; ++kk) {
+            const double a = sX[16 * w + m][4 * kk + g];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) acc[i][t] = fma(a[i], g[t], acc[i][t]);
+            for (int u = 0; u < 4; ++u)
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sG[16 * u + m][4 * kk + g], acc[u], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t row = r0 + tr + i;
+    for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + 16 * w + 4 * r + g;
         if (row >= n) continue;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int c = c0 + tc + t;
-            if (c < k) Xout[row * k + c] = (float)(scale * acc[i][t]);
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + 16 * u + m;
+            if (c < k) Xout[row * k + c] = (float)(scale * acc[u][r]);
         }
     }
 }
