@@ -273,13 +273,24 @@ __device__ __forceinline__ void look_back_wg(const uint64_t* __restrict__ rec, c
 // load / store CPL consecutive columns of one row.  VEC: one 16-byte access
 // per lane; the caller guarantees b % 4 == 0 and 16-byte aligned rows, so a
 // lane with col0 < b owns four whole columns.
-template <int CPL, bool VEC, typename E>
+// NT marks the load non-temporal (streaming cache policy) for rows that are
+// read once per pass; the value read is the same.  The elements of the
+// loaded vector are copied out as plain words before the bit casts: this
+// clang's __builtin_bit_cast applied to an ext_vector_type element (t.y)
+// reads the vector's first element, whatever the index.
+typedef uint32_t u32x4_nt __attribute__((ext_vector_type(4)));
+template <int CPL, bool VEC, bool NT = false, typename E>
 __device__ __forceinline__ void load_row(const E* __restrict__ row, int col0, int b, bool valid, E (&v)[CPL]) {
     if constexpr (VEC && CPL == 4 && sizeof(E) == 4) {
         if (valid && col0 < b) {
-            const auto t = *reinterpret_cast<const uint4*>(row + col0);
-            v[0] = __builtin_bit_cast(E, t.x); v[1] = __builtin_bit_cast(E, t.y);
-            v[2] = __builtin_bit_cast(E, t.z); v[3] = __builtin_bit_cast(E, t.w);
+            u32x4_nt t;
+            if constexpr (NT)
+                t = __builtin_nontemporal_load(reinterpret_cast<const u32x4_nt*>(row + col0));
+            else
+                t = *reinterpret_cast<const u32x4_nt*>(row + col0);
+            const uint32_t w[4] = {t[0], t[1], t[2], t[3]};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = __builtin_bit_cast(E, w[j]);
         } else {
 #pragma unroll
             for (int j = 0; j < CPL; ++j) v[j] = E(0);

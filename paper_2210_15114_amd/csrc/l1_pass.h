@@ -332,7 +332,8 @@ __global__ __launch_bounds__(256, 2) void l1_pass_keep_kernel(
                 x[i] = valid ? xs[r0 + i] : typename P::X(0);
             }
 #pragma unroll
-            for (int i = 0; i < R; ++i) load_row<CPL, VEC>(Z + (size_t)p[i] * b, col0, b, r0 + i < n, g[i]);
+            // every Z row of the tile is read here once: streaming loads
+            for (int i = 0; i < R; ++i) load_row<CPL, VEC, true>(Z + (size_t)p[i] * b, col0, b, r0 + i < n, g[i]);
 #pragma unroll
             for (int j = 0; j < CPL; ++j) {
                 L a0 = P::lzero(), a1 = P::lzero();
