@@ -198,14 +198,16 @@ __global__ __launch_bounds__(256) void xtz_wide_kernel(const float* __restrict__
 #pragma unroll
         for (int r = 0; r < 16; ++r) s_sum[w][q][r][lane] = 0.0f;
     double s0[2] = {0.0, 0.0}, r1[2] = {0.0, 0.0};
+    // X and Z are streamed once per query here: non-temporal loads (the
+    // apply reads X again, but 4nd bytes do not stay cached between the two)
     auto load = [&](int64_t j, float (&xv)[4][8], float (&zv)[2][8], double (&nv)[8]) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int64_t row = j + 8 * jg + t;
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt) xv[kt][t] = X[row * MAXD + kt * 32 + l32];
+            for (int kt = 0; kt < 4; ++kt) xv[kt][t] = __builtin_nontemporal_load(&X[row * MAXD + kt * 32 + l32]);
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct) zv[ct][t] = Z[row * MAXB + ct * 32 + l32];
+            for (int ct = 0; ct < 2; ++ct) zv[ct][t] = __builtin_nontemporal_load(&Z[row * MAXB + ct * 32 + l32]);
             nv[t] = nrm[row];
         }
     };
