@@ -61,6 +61,29 @@ struct alignas(sizeof(T) * V) Vec {
     T v[V];
 };
 
+// a Vec loaded with a non-temporal (streaming) load; the elements are copied
+// out of the vector by value
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> load_vec_nt(const T* p) {
+    Vec<T, V> r;
+    if constexpr (V == 1) {
+        r.v[0] = __builtin_nontemporal_load(p);
+    } else {
+        typedef T tv __attribute__((ext_vector_type(V)));
+        const tv t = __builtin_nontemporal_load(reinterpret_cast<const tv*>(p));
+#pragma unroll
+        for (int i = 0; i < V; ++i) r.v[i] = t[i];
+    }
+    return r;
+}
+// X rows of the narrow moments: FP64 rows (the logarithms of KL and cross
+// entropy) stream faster with non-temporal loads, FP32 rows did not
+template <typename XT, int V>
+__device__ __forceinline__ Vec<XT, V> load_x_narrow(const XT* p) {
+    if constexpr (sizeof(XT) == 8) return load_vec_nt<XT, V>(p);
+    else return *reinterpret_cast<const Vec<XT, V>*>(p);
+}
+
 // a coordinate value less its centre (none: the value itself)
 template <typename XT, typename ACC>
 __device__ __forceinline__ ACC feature(XT x, const ACC* centre, int k) {
@@ -392,7 +415,7 @@ __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ 
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int64_t row = r + (int64_t)u * R;
-                xv[u] = *reinterpret_cast<const Vec<XT, V>*>(X + row * d + k);
+                xv[u] = load_x_narrow<XT, V>(X + row * d + k);
                 load_z(row, zv[u]);
             }
 #pragma unroll
@@ -401,7 +424,7 @@ __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ 
         for (; r < re; r += R) {
             ZT zv[BW];
             load_z(r, zv);
-            step(*reinterpret_cast<const Vec<XT, V>*>(X + r * d + k), zv);
+            step(load_x_narrow<XT, V>(X + r * d + k), zv);
         }
     }
 #pragma unroll
