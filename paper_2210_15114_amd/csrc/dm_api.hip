@@ -1110,7 +1110,7 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     const size_t o_basis = take(nb * (iters + 1) * sizeof(double));
     const size_t o_zf = take(nb * sizeof(float));
     const size_t o_yf = take(nb * sizeof(float));
-    const size_t o_part = take(lr_gram_scratch_doubles(n, B, B) * sizeof(double));
+    const size_t o_part = take(lr_gram_scratch_doubles(n, B, B, iters) * sizeof(double));
     const size_t o_T = take((size_t)K * K * sizeof(double));
     const size_t o_V = take((size_t)K * K * sizeof(double));
     const size_t o_T2 = take((size_t)K * K * sizeof(double));
@@ -1157,20 +1157,16 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
             // coefficients Q_i^T (A Q_{j-1}) are exactly the Rayleigh-Ritz
             // blocks T[i][j-1], so they are written straight into T (rows
             // i B .. of column block j - 1, leading dimension K).
-            for (int i = 0; i < j; ++i) {
-                double* Tij = T + (size_t)i * B * K + (size_t)(j - 1) * B;
-                DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, Tij, K, 1.0, s));
-            }
+            if (j > 0) DM_TRY(lr_gram_blocks(Qb(0), nb, j, B, Y, B, n, part, T + (size_t)(j - 1) * B, K, 1.0, s));
             if (j == iters) break;
             if (j > 0) {
                 DM_TRY(lr_update_blocks(Y, B, Qb(0), nb, j, B, T + (size_t)(j - 1) * B, K, -1.0, 1.0, n, s));
-                for (int i = 0; i < j; ++i)
-                    DM_TRY(lr_gram(Qb(i), B, Y, B, n, part, C + (size_t)i * B * B, B, 1.0, s));
+                DM_TRY(lr_gram_blocks(Qb(0), nb, j, B, Y, B, n, part, C, B, 1.0, s));
                 DM_TRY(lr_update_blocks(Y, B, Qb(0), nb, j, B, C, B, -1.0, 1.0, n, s));
             }
             // Cholesky QR, twice
             for (int pass = 0; pass < 2; ++pass) {
-                DM_TRY(lr_gram(Y, B, Y, B, n, part, G, B, 1.0, s));
+                DM_TRY(lr_gram_blocks(Y, 0, 1, B, Y, B, n, part, G, B, 1.0, s));
                 DM_TRY(lr_cholinv(G, B, rel, X, status, s));
                 DM_TRY(lr_update_rows(Y, B, Y, B, X, B, 1.0, 0.0, n, s));
             }

@@ -196,10 +196,13 @@ hipError_t launch_multi_pass(bool is_int, int32_t b, const MultiDs* ds, const Mu
 // ---- block-Krylov low rank (k_lowrank.hip) ---------------------------------
 int lr_max_block();
 int lr_max_basis();
-size_t lr_gram_scratch_doubles(int64_t n, int ma, int mb);
-// out[p * ldo + q] = scale * sum_r A[r][p] B[r][q]; part: lr_gram_scratch_doubles doubles
-hipError_t lr_gram(const double* A, int ma, const double* B, int mb, int64_t n, double* part, double* out,
-                   int ldo, double scale, hipStream_t s);
+// scratch of lr_gram_blocks for up to nq_max blocks per call
+size_t lr_gram_scratch_doubles(int64_t n, int ma, int mb, int nq_max);
+// out[(i ma + p) * ldo + q] = scale * sum_r Q_i[r][p] Y[r][q] for i < nq, with
+// Q_i = Q + i qstride (n x ma) and Y n x mb (Y may be Q when nq = 1);
+// part: lr_gram_scratch_doubles doubles
+hipError_t lr_gram_blocks(const double* Q, size_t qstride, int nq, int ma, const double* Y, int mb, int64_t n,
+                          double* part, double* out, int ldo, double scale, hipStream_t s);
 // Y = beta Y + alpha Q C; Y n x mb, Q n x ma, C ma x ldc (Y may be Q when beta is 0)
 hipError_t lr_update_rows(double* Y, int mb, const double* Q, int ma, const double* C, int ldc, double alpha,
                           double beta, int64_t n, hipStream_t s);

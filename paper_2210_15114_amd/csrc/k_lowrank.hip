@@ -5,9 +5,10 @@
 // The products with A run through the l1 / l2-squared query; everything
 // here works on tall, skinny FP64 blocks (n x m with m <= 64) and on the
 // small projected matrix T = Q^T A Q:
-//   * lr_gram_partial / lr_reduce - C = A^T B of two n x m blocks, split over
-//     rows into fixed per-block partial sums and reduced in a fixed order
-//     (bit-reproducible run to run);
+//   * lr_gram_mfma / lr_reduce - C_i = Q_i^T Y for several n x m blocks Q_i
+//     against one block Y in one call, on FP64 matrix cores, split over rows
+//     into fixed partial sums and reduced in a fixed order (bit-reproducible
+//     run to run);
 //   * lr_update   - Y = beta Y + alpha sum_i Q_i C_i, row by row on FP64 matrix
 //     cores (block Gram-Schmidt updates, Y R^-1 of Cholesky QR, U = Q V);
 //   * lr_chol     - the orthonormalising factor of Cholesky QR for a small
@@ -28,127 +29,117 @@ namespace {
 
 constexpr int GT = 64;     // rows per LDS tile
 constexpr int MAXM = 64;   // widest block
-constexpr int64_t LR_ROWS_PER_BLK = 1024;   // rows per partial Gram product
 
 // ---------------------------------------------------------------------------
-// C_part[blk] = sum over the block's rows r of A[r][p] * B[r][q]
-// A: n x ma, B: n x mb, row-major.  Tiles of GT rows are contiguous in
-// memory and are read flat (coalesced), one tile ahead into registers while
-// the current tile is multiplied out of LDS.  Each thread owns a 4 x 4 block
-// of (p, q) entries and a share of the rows of each tile; row shares are
-// added in a fixed order at the end.
+// part[blk][i][p][q] = sum over the rows r of range blk of Q_i[r][p] * Y[r][q]
+// for the nq blocks Q_i = Q + i qstride (n x ma, row-major) against one
+// n x mb block Y, on FP64 matrix cores.  One wave per (range, i): operands
+// are loaded straight into the v_mfma_f64_16x16x4f64 lane layout (A lane l
+// holds A[l % 16][l / 16], here Q_i[r + l / 16][16 pt + l % 16]; B lane l
+// holds B[l / 16][l % 16], here Y[r + l / 16][16 qt + l % 16]; D lane l,
+// element e holds D[4e + l / 16][l % 16]), four rows per product and 16 rows
+// per step, so a row of Q_i and of Y is read once by the wave.  Workgroup
+// ids go round-robin over the 8 XCDs; ids are decoded so that the nq waves of
+// one range sit on the same XCD and start together, and Y's rows are read
+// from HBM about once per call and then from that XCD's L2.  The sum over a
+// range runs in row order, so the partials, and the fixed-order reduction
+// after them, are the same run to run.
 // ---------------------------------------------------------------------------
-constexpr int TPT = GT * MAXM / 256;   // tile doubles per thread
+typedef double d4v __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void lr_gram_partial(const double* __restrict__ A, int ma,
-                                                       const double* __restrict__ B, int mb, int64_t n,
-                                                       int64_t rows_per_blk, double* __restrict__ part)
+constexpr int GRAM_PARTS = 4096;   // (range, i) waves per call, at most
+constexpr int GRAM_STEP = 16;      // rows per step (four products)
+
+__global__ __launch_bounds__(64) void lr_gram_mfma(const double* __restrict__ Q, size_t qstride, int nq, int ma,
+                                                   const double* __restrict__ Y, int mb, int64_t n, int64_t rw,
+                                                   int64_t nblk, double* __restrict__ part)
 {
-    __shared__ double sA[GT][MAXM + 4];
-    __shared__ double sB[GT][MAXM + 4];
-    const int tid = threadIdx.x;
-    const int pa = (ma + 3) / 4, pb = (mb + 3) / 4, ne = pa * pb;
-    int groups = 256 / ne;
-    if (groups > 8) groups = 8;
-    if (groups < 1) groups = 1;
-    const int e = tid % ne, g = tid / ne;
-    const bool active = tid < ne * groups;
-    const int p0 = (e / pb) * 4, q0 = (e % pb) * 4;
-    // columns ma.. and mb.. up to the next multiple of 4 are read as zeros
-    for (int i = tid; i < GT * (MAXM + 4); i += 256) {
-        (&sA[0][0])[i] = 0.0;
-        (&sB[0][0])[i] = 0.0;
-    }
-    double acc[4][4];
+    const int id = blockIdx.x;
+    const int xcd = id & 7;
+    const int slot = id >> 3;
+    const int i = slot % nq;
+    const int64_t blk = (int64_t)(slot / nq) * 8 + xcd;
+    if (blk >= nblk) return;   // the whole wave
+    const int lane = threadIdx.x, m = lane & 15, g = lane >> 4;
+    const double* __restrict__ A = Q + (size_t)i * qstride;
+    const int pt_n = (ma + 15) / 16, qt_n = (mb + 15) / 16;
+    d4v acc[MAXM / 16][MAXM / 16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int pt = 0; pt < MAXM / 16; ++pt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    const int64_t rb = (int64_t)blockIdx.x * rows_per_blk;
-    const int64_t re = rb + rows_per_blk < n ? rb + rows_per_blk : n;
-    double ra[TPT], rbv[TPT];
-    auto fetch = [&](int64_t r0) {
-        const int nr = (int)(re - r0 < GT ? re - r0 : GT);
-        const double* a0 = A + r0 * ma;
-        const double* b0 = B + r0 * mb;
-        const int na = nr * ma, nb = nr * mb;
+        for (int qt = 0; qt < MAXM / 16; ++qt) acc[pt][qt] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int64_t r0 = blk * rw;
+    const int64_t r1 = r0 + rw < n ? r0 + rw : n;
+    for (int64_t r = r0; r < r1; r += GRAM_STEP) {
+        double a[GRAM_STEP / 4][MAXM / 16], y[GRAM_STEP / 4][MAXM / 16];
 #pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            const int i = tid + 256 * k;
-            ra[k] = i < na ? a0[i] : 0.0;
-            rbv[k] = i < nb ? b0[i] : 0.0;
-        }
-    };
-    if (rb < re) fetch(rb);
-    for (int64_t r0 = rb; r0 < re; r0 += GT) {
-        const int nr = (int)(re - r0 < GT ? re - r0 : GT);
-        __syncthreads();   // the previous tile is no longer read
+        for (int u = 0; u < GRAM_STEP / 4; ++u) {
+            const int64_t row = r + 4 * u + g;
+            const bool rv = row < r1;
 #pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            const int i = tid + 256 * k;
-            if (i < nr * ma) sA[i / ma][i % ma] = ra[k];
-            if (i < nr * mb) sB[i / mb][i % mb] = rbv[k];
-        }
-        __syncthreads();
-        if (r0 + GT < re) fetch(r0 + GT);
-        if (active) {
-            for (int r = g; r < nr; r += groups) {
-                double a[4], bq[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    a[i] = sA[r][p0 + i];
-                    bq[i] = sB[r][q0 + i];
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bq[j], acc[i][j]);
+            for (int t = 0; t < MAXM / 16; ++t) {
+                const int c = 16 * t + m;
+                a[u][t] = (t < pt_n && rv && c < ma) ? A[row * ma + c] : 0.0;
+                y[u][t] = (t < qt_n && rv && c < mb) ? Y[row * mb + c] : 0.0;
             }
         }
+#pragma unroll
+        for (int u = 0; u < GRAM_STEP / 4; ++u)
+#pragma unroll
+            for (int pt = 0; pt < MAXM / 16; ++pt)
+#pragma unroll
+                for (int qt = 0; qt < MAXM / 16; ++qt)
+                    if (pt < pt_n && qt < qt_n)   // the same on every lane
+                        acc[pt][qt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][pt], y[u][qt], acc[pt][qt], 0, 0, 0);
     }
-    __syncthreads();
-    // add the row shares in group order
-    double* red = &sA[0][0];   // GT * (MAXM + 4) >= 256 * 16 doubles
-    if (active) {
+    double* out = part + ((size_t)blk * nq + i) * ma * mb;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+    for (int pt = 0; pt < MAXM / 16; ++pt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) red[(g * ne + e) * 16 + i * 4 + j] = acc[i][j];
-    }
-    __syncthreads();
-    if (active && g == 0) {
-        for (int gg = 1; gg < groups; ++gg)
+        for (int qt = 0; qt < MAXM / 16; ++qt) {
+            if (pt >= pt_n || qt >= qt_n) continue;
+            const int q = 16 * qt + m;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += red[(gg * ne + e) * 16 + i * 4 + j];
-        double* out = part + (size_t)blockIdx.x * ma * mb;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (p0 + i < ma && q0 + j < mb) out[(p0 + i) * mb + (q0 + j)] = acc[i][j];
-    }
+            for (int e = 0; e < 4; ++e) {
+                const int p = 16 * pt + 4 * e + g;
+                if (p < ma && q < mb) out[p * mb + q] = acc[pt][qt][e];
+            }
+        }
 }
 
-// out[p * ldo + q] = scale * sum_blk part[blk][p][q].  A workgroup owns 32
-// entries; its 8 thread groups add blocks g, g + 8, g + 16, ... in order and
-// the 8 group sums are then added in group order (a fixed order).
+// out[p * ldo + q] = scale * sum_blk part[blk][p][q].  A workgroup owns
+// RED_E entries; its RED_G thread groups add blocks g, g + RED_G, ... in
+// order (four loads in flight), and the group sums are then added in group
+// order, so the order is fixed.
+constexpr int RED_E = 4, RED_G = 64;
+
 __global__ __launch_bounds__(256) void lr_reduce(const double* __restrict__ part, int nblk, int ma, int mb,
                                                  double* __restrict__ out, int ldo, double scale)
 {
-    __shared__ double red[8][32];
-    const int t = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const int e = blockIdx.x * 32 + t;
+    __shared__ double red[RED_G][RED_E];
+    const int t = threadIdx.x % RED_E, g = threadIdx.x / RED_E;
+    const int e = blockIdx.x * RED_E + t;
     const int cnt = ma * mb;
     double s = 0.0;
-    if (e < cnt)
-        for (int k = g; k < nblk; k += 8) s += part[(size_t)k * cnt + e];
+    if (e < cnt) {
+        int k = g;
+        for (; k + 3 * RED_G < nblk; k += 4 * RED_G) {
+            const double v0 = part[(size_t)k * cnt + e];
+            const double v1 = part[(size_t)(k + RED_G) * cnt + e];
+            const double v2 = part[(size_t)(k + 2 * RED_G) * cnt + e];
+            const double v3 = part[(size_t)(k + 3 * RED_G) * cnt + e];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; k < nblk; k += RED_G) s += part[(size_t)k * cnt + e];
+    }
     red[g][t] = s;
     __syncthreads();
     if (g == 0 && e < cnt) {
         double v = red[0][t];
-        for (int gg = 1; gg < 8; ++gg) v += red[gg][t];
+        for (int gg = 1; gg < RED_G; ++gg) v += red[gg][t];
         out[(size_t)(e / mb) * ldo + (e % mb)] = scale * v;
     }
 }
@@ -166,8 +157,6 @@ __global__ __launch_bounds__(256) void lr_reduce(const double* __restrict__ part
 // (in-place right multiplication).  One call with nq blocks moves Y once,
 // where nq single-block calls would move it nq times.
 // ---------------------------------------------------------------------------
-typedef double d4v __attribute__((ext_vector_type(4)));
-
 __global__ __launch_bounds__(256) void lr_update(double* Y, int mb, const double* Q, size_t qstride, int nq, int ma,
                                                  const double* __restrict__ C, int ldc, double alpha, double beta,
                                                  int64_t n)
@@ -476,20 +465,38 @@ __global__ __launch_bounds__(1024) void lr_select(const double* __restrict__ w, 
 int lr_max_block() { return MAXM; }
 int lr_max_basis() { return JMAX; }
 
-size_t lr_gram_scratch_doubles(int64_t n, int ma, int mb) {
-    const int64_t nblk = (n + LR_ROWS_PER_BLK - 1) / LR_ROWS_PER_BLK;
-    return (size_t)nblk * ma * mb;
+// rows per range of lr_gram_blocks: at most GRAM_PARTS (range, block) waves,
+// at least 64 rows each, a multiple of the step
+static int64_t gram_rows(int64_t n, int nq) {
+    const int64_t per = GRAM_PARTS / nq > 0 ? GRAM_PARTS / nq : 1;
+    int64_t rw = (n + per - 1) / per;
+    if (rw < 64) rw = 64;
+    return (rw + GRAM_STEP - 1) / GRAM_STEP * GRAM_STEP;
 }
 
-hipError_t lr_gram(const double* A, int ma, const double* B, int mb, int64_t n, double* part, double* out,
-                   int ldo, double scale, hipStream_t s)
+size_t lr_gram_scratch_doubles(int64_t n, int ma, int mb, int nq_max) {
+    size_t most = 0;
+    for (int nq = 1; nq <= nq_max; ++nq) {
+        const int64_t rw = gram_rows(n, nq);
+        const size_t c = (size_t)((n + rw - 1) / rw) * nq;
+        if (c > most) most = c;
+    }
+    return most * ma * mb;
+}
+
+hipError_t lr_gram_blocks(const double* Q, size_t qstride, int nq, int ma, const double* Y, int mb, int64_t n,
+                          double* part, double* out, int ldo, double scale, hipStream_t s)
 {
-    if (ma < 1 || mb < 1 || ma > MAXM || mb > MAXM || n < 1) return hipErrorInvalidValue;
-    const int64_t nblk = (n + LR_ROWS_PER_BLK - 1) / LR_ROWS_PER_BLK;
-    lr_gram_partial<<<(unsigned)nblk, 256, 0, s>>>(A, ma, B, mb, n, LR_ROWS_PER_BLK, part);
+    if (ma < 1 || mb < 1 || ma > MAXM || mb > MAXM || n < 1 || nq < 1) return hipErrorInvalidValue;
+    const int64_t rw = gram_rows(n, nq);
+    const int64_t nblk = (n + rw - 1) / rw;
+    const int64_t grid = (nblk + 7) / 8 * 8 * nq;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    lr_gram_mfma<<<(unsigned)grid, 64, 0, s>>>(Q, qstride, nq, ma, Y, mb, n, rw, nblk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    lr_reduce<<<(ma * mb + 31) / 32, 256, 0, s>>>(part, (int)nblk, ma, mb, out, ldo, scale);
+    const int cnt = nq * ma * mb;
+    lr_reduce<<<(cnt + RED_E - 1) / RED_E, 256, 0, s>>>(part, (int)nblk, nq * ma, mb, out, ldo, scale);
     return hipGetLastError();
 }
 
