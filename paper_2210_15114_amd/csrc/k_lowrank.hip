@@ -157,6 +157,7 @@ __global__ __launch_bounds__(256) void lr_reduce(const double* __restrict__ part
 // (in-place right multiplication).  One call with nq blocks moves Y once,
 // where nq single-block calls would move it nq times.
 // ---------------------------------------------------------------------------
+template <int QPT>
 __global__ __launch_bounds__(256) void lr_update(double* Y, int mb, const double* Q, size_t qstride, int nq, int ma,
                                                  const double* __restrict__ C, int ldc, double alpha, double beta,
                                                  int64_t n)
@@ -168,41 +169,69 @@ __global__ __launch_bounds__(256) void lr_update(double* Y, int mb, const double
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m = lane & 15, g = lane >> 4;
     const int ct_n = (mb + 15) / 16;
-    for (int64_t r0 = (int64_t)blockIdx.x * GT; r0 < n; r0 += (int64_t)gridDim.x * GT) {   // uniform
+    // The workgroup's (tile, block) steps in order: tiles blockIdx.x,
+    // + gridDim.x, ..., and for each tile the blocks i = 0 .. nq - 1.  The
+    // next step's Q rows (QPT doubles per thread, QPT >= GT ma / 256) are
+    // loaded into registers while the current step multiplies out of LDS.
+    // alpha C_i is staged from L2 at each step, or once when nq = 1.
+    const int64_t ntile = (n + GT - 1) / GT;
+    const int64_t mine = (int64_t)blockIdx.x < ntile ? (ntile - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+    const int64_t steps = mine * nq;
+    double rq[QPT];
+    auto fetch = [&](int64_t it) {
+        const int64_t r0 = ((int64_t)blockIdx.x + (it / nq) * gridDim.x) * GT;
+        const int i = (int)(it % nq);
         const int nr = (int)(n - r0 < GT ? n - r0 : GT);
-        d4v acc[MAXM / 16];
+        const double* q0 = Q + (size_t)i * qstride + r0 * ma;
 #pragma unroll
-        for (int u = 0; u < MAXM / 16; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
-        for (int i = 0; i < nq; ++i) {
-            __syncthreads();   // the previous block's tiles are no longer read
-            const double* q0 = Q + (size_t)i * qstride + r0 * ma;
-            for (int e = tid; e < GT * ma; e += 256) sQ[(e / ma) * lq + (e % ma)] = e < nr * ma ? q0[e] : 0.0;
-            for (int e = tid; e < ma * mb; e += 256)
-                sC[e] = alpha * C[(size_t)(i * ma + e / mb) * ldc + (e % mb)];
-            __syncthreads();
-            for (int k0 = 0; k0 < ma; k0 += 4) {
-                const int kk = k0 + g;
-                const double av = kk < ma ? sQ[(16 * w + m) * lq + kk] : 0.0;
+        for (int k = 0; k < QPT; ++k) {
+            const int e = tid + 256 * k;
+            rq[k] = e < nr * ma ? q0[e] : 0.0;
+        }
+    };
+    d4v acc[MAXM / 16];
+    if (steps > 0) fetch(0);
+    for (int64_t it = 0; it < steps; ++it) {   // uniform
+        const int i = (int)(it % nq);
+        const int64_t r0 = ((int64_t)blockIdx.x + (it / nq) * gridDim.x) * GT;
+        if (i == 0) {
 #pragma unroll
-                for (int u = 0; u < MAXM / 16; ++u) {
-                    if (u < ct_n) {   // the same on every lane
-                        const int c = 16 * u + m;
-                        const double bv = (kk < ma && c < mb) ? sC[kk * mb + c] : 0.0;
-                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
-                    }
+            for (int u = 0; u < MAXM / 16; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
+        }
+        __syncthreads();   // the previous step's tiles are no longer read
+#pragma unroll
+        for (int k = 0; k < QPT; ++k) {
+            const int e = tid + 256 * k;
+            if (e < GT * ma) sQ[(e / ma) * lq + (e % ma)] = rq[k];
+        }
+        if (nq > 1 || it == 0)
+            for (int e = tid; e < ma * mb; e += 256) sC[e] = alpha * C[(size_t)(i * ma + e / mb) * ldc + (e % mb)];
+        __syncthreads();
+        if (it + 1 < steps) fetch(it + 1);
+        for (int k0 = 0; k0 < ma; k0 += 4) {
+            const int kk = k0 + g;
+            const double av = kk < ma ? sQ[(16 * w + m) * lq + kk] : 0.0;
+#pragma unroll
+            for (int u = 0; u < MAXM / 16; ++u) {
+                if (u < ct_n) {   // the same on every lane
+                    const int c = 16 * u + m;
+                    const double bv = (kk < ma && c < mb) ? sC[kk * mb + c] : 0.0;
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
                 }
             }
         }
+        if (i == nq - 1) {
 #pragma unroll
-        for (int u = 0; u < MAXM / 16; ++u) {
-            const int c = 16 * u + m;
-            if (u >= ct_n || c >= mb) continue;
+            for (int u = 0; u < MAXM / 16; ++u) {
+                const int c = 16 * u + m;
+                if (u >= ct_n || c >= mb) continue;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = r0 + 16 * w + 4 * r + g;
-                if (row >= n) continue;
-                double* y = Y + row * mb + c;
-                *y = beta == 0.0 ? acc[u][r] : fma(beta, *y, acc[u][r]);
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = r0 + 16 * w + 4 * r + g;
+                    if (row >= n) continue;
+                    double* y = Y + row * mb + c;
+                    *y = beta == 0.0 ? acc[u][r] : fma(beta, *y, acc[u][r]);
+                }
             }
         }
     }
@@ -507,7 +536,11 @@ hipError_t lr_update_blocks(double* Y, int mb, const double* Q, size_t qstride, 
     const size_t lds = ((size_t)GT * (ma + 1) + (size_t)ma * mb) * sizeof(double);
     int64_t blocks = (n + GT - 1) / GT;
     if (blocks > 2048) blocks = 2048;
-    lr_update<<<(unsigned)blocks, 256, lds, s>>>(Y, mb, Q, qstride, nq, ma, C, ldc, alpha, beta, n);
+    // registers for the prefetched Q rows: 10 per thread up to 40 columns
+    if (GT * ma <= 256 * 10)
+        lr_update<10><<<(unsigned)blocks, 256, lds, s>>>(Y, mb, Q, qstride, nq, ma, C, ldc, alpha, beta, n);
+    else
+        lr_update<GT * MAXM / 256><<<(unsigned)blocks, 256, lds, s>>>(Y, mb, Q, qstride, nq, ma, C, ldc, alpha, beta, n);
     return hipGetLastError();
 }
 
