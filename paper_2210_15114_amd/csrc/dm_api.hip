@@ -1141,16 +1141,22 @@ dm_status dm_lowrank(dm_handle* h, int32_t rank, int32_t block, int32_t iters, c
     // relative accuracy 1e-10
     const double rel = 1e-20;
 
+    // The products run on the FP32 copy split into a block of 32k columns and
+    // the rest (B = 40: 32 + 8), queried one after the other: a 128-byte row
+    // fills one cache line and a 32-byte row sits inside one, where every
+    // 160-byte row of the 40-column block spans two 128-byte lines.
+    const int B1 = B > 32 && B % 32 != 0 ? B / 32 * 32 : B;
     int sw_used = 0;
     auto run = [&]() -> dm_status {
         const double* Qprev = Omega;
         for (int j = 0; j <= iters; ++j) {
             // Y = A Q_{j-1} (A Omega for j = 0), through the FP32 query
             double* Y = Qb(j);
-            DM_TRY(lr_cvt(Qprev, Zf, nb, s));
-            const dm_status ms = dm_matvec(h, Zf, DM_F32, B, Yf, s);
+            DM_TRY(lr_cvt(Qprev, Zf, n, B, B1, s));
+            dm_status ms = dm_matvec(h, Zf, DM_F32, B1, Yf, s);
+            if (ms == DM_OK && B1 < B) ms = dm_matvec(h, Zf + (size_t)n * B1, DM_F32, B - B1, Yf + (size_t)n * B1, s);
             if (ms != DM_OK) return ms;
-            DM_TRY(lr_cvt(Yf, Y, nb, s));
+            DM_TRY(lr_cvt(Yf, Y, n, B, B1, s));
             // Block classical Gram-Schmidt against Q_0 .. Q_{j-1}, twice: every
             // coefficient block Q_i^T Y first, then one update
             // Y -= sum_i Q_i C_i that moves Y once.  The first pass's

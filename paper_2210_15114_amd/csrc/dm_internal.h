@@ -212,8 +212,10 @@ hipError_t lr_update_blocks(double* Y, int mb, const double* Q, size_t qstride, 
                             int ldc, double alpha, double beta, int64_t n, hipStream_t s);
 hipError_t lr_cholinv(const double* G, int m, double rel, double* X, uint32_t* status, hipStream_t s);
 hipError_t lr_symm(double* T, int m, int bw, hipStream_t s);
-hipError_t lr_cvt(const double* a, float* b, size_t n, hipStream_t s);
-hipError_t lr_cvt(const float* a, double* b, size_t n, hipStream_t s);
+// FP64 n x B block a <-> FP32 copy b held as two row-major arrays, columns
+// 0 .. B1 - 1 (rows x B1) followed by columns B1 .. B - 1 (rows x (B - B1))
+hipError_t lr_cvt(const double* a, float* b, int64_t rows, int B, int B1, hipStream_t s);
+hipError_t lr_cvt(const float* b, double* a, int64_t rows, int B, int B1, hipStream_t s);
 // eigen-decomposition of the symmetric m x m T (destroyed; T2 is a second
 // m x m buffer): eigenvalues w (m) and eigenvectors as the rows of V (m x m);
 // *sweeps = sweeps used (host value); synchronises s once per sweep

@@ -329,13 +329,28 @@ __global__ __launch_bounds__(256) void lr_symmetrize(double* __restrict__ T, int
     }
 }
 
-__global__ __launch_bounds__(256) void lr_cvt_f64_f32(const double* __restrict__ a, float* __restrict__ b, size_t n)
-{
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) b[i] = (float)a[i];
+// The FP32 copy of an n x B FP64 block is kept as two row-major arrays, the
+// first B1 columns (n x B1) and then the other B - B1 (n x (B - B1)), so that
+// each can be queried with rows that fill whole cache lines (B1 = B: one
+// array).  Element (r, c) of the block sits at split_index in the copy.
+__device__ __forceinline__ size_t split_index(size_t i, int64_t rows, int B, int B1) {
+    const size_t r = i / (size_t)B;
+    const int c = (int)(i - r * (size_t)B);
+    return c < B1 ? r * (size_t)B1 + c : (size_t)rows * B1 + r * (size_t)(B - B1) + (c - B1);
 }
-__global__ __launch_bounds__(256) void lr_cvt_f32_f64(const float* __restrict__ a, double* __restrict__ b, size_t n)
+__global__ __launch_bounds__(256) void lr_cvt_f64_f32(const double* __restrict__ a, float* __restrict__ b,
+                                                      int64_t rows, int B, int B1)
 {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) b[i] = (double)a[i];
+    const size_t n = (size_t)rows * B;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        b[split_index(i, rows, B, B1)] = (float)a[i];
+}
+__global__ __launch_bounds__(256) void lr_cvt_f32_f64(const float* __restrict__ b, double* __restrict__ a,
+                                                      int64_t rows, int B, int B1)
+{
+    const size_t n = (size_t)rows * B;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        a[i] = (double)b[split_index(i, rows, B, B1)];
 }
 
 // ---------------------------------------------------------------------------
@@ -563,18 +578,18 @@ hipError_t lr_symm(double* T, int m, int bw, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t lr_cvt(const double* a, float* b, size_t n, hipStream_t s)
+hipError_t lr_cvt(const double* a, float* b, int64_t rows, int B, int B1, hipStream_t s)
 {
-    size_t blocks = (n + 255) / 256;
+    size_t blocks = ((size_t)rows * B + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    lr_cvt_f64_f32<<<(unsigned)blocks, 256, 0, s>>>(a, b, n);
+    lr_cvt_f64_f32<<<(unsigned)blocks, 256, 0, s>>>(a, b, rows, B, B1);
     return hipGetLastError();
 }
-hipError_t lr_cvt(const float* a, double* b, size_t n, hipStream_t s)
+hipError_t lr_cvt(const float* b, double* a, int64_t rows, int B, int B1, hipStream_t s)
 {
-    size_t blocks = (n + 255) / 256;
+    size_t blocks = ((size_t)rows * B + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    lr_cvt_f32_f64<<<(unsigned)blocks, 256, 0, s>>>(a, b, n);
+    lr_cvt_f32_f64<<<(unsigned)blocks, 256, 0, s>>>(b, a, rows, B, B1);
     return hipGetLastError();
 }
 
