@@ -69,6 +69,28 @@ def test_exact_low_rank_matrix_is_recovered():
     assert rel <= 1e-5
 
 
+@pytest.mark.parametrize("block", [33, 36, 48, 64])
+def test_blocks_that_split_into_two_queries(block):
+    # a block above 32 columns that is not a multiple of 32 runs each product
+    # as a query of its first 32 columns and one of the rest (33: 32 + 1,
+    # 36: 32 + 4, 48: 32 + 16; 64 is one query); the rank-5 matrix of l2
+    # squared on d = 3 coordinates must come back exactly whatever the split
+    g = synth.rng(5353 + block)
+    n, d = 3000, 3
+    X = g.standard_normal((n, d)).astype(np.float32)
+    omega = g.standard_normal((n, block))
+    h = dm.prepare(dev(X), L2SQ)
+    U, lam, _ = h.lowrank(5, dev(omega), 1)
+    U, lam = U.cpu().numpy(), lam.cpu().numpy()
+    h.free()
+    A = oracle.explicit(X, L2SQ)
+    rel = olr.approx_error(A, U, lam) / np.linalg.norm(A)
+    orth = float(np.abs(U.T @ U - np.eye(5)).max())
+    print("block", block, "relative error", rel, "orth", orth)
+    assert rel <= 1e-5
+    assert orth <= 1e-10
+
+
 def test_lowrank_rejects_bad_arguments():
     X = synth.rng(1).standard_normal((500, 2)).astype(np.float32)
     h = dm.prepare(dev(X), L1)
