@@ -449,7 +449,7 @@ __global__ __launch_bounds__(256) void sf_moments_narrow(const XT* __restrict__ 
     }
 }
 
-// ---- FP64 matrix cores for the single-moment forms (b > 32) ----------------
+// ---- FP64 matrix cores for the single-moment forms (b >= 4) ----------------
 // v_mfma_f64_16x16x4f64 lane layout on gfx950 (checked on the GPU with a
 // probe): A (16 x 4): lane l holds A[l % 16][l / 16]; B (4 x 16): lane l holds
 // B[l / 16][l % 16]; D (16 x 16): lane l, element r holds D[4r + l / 16][l % 16].
@@ -473,16 +473,19 @@ __device__ __forceinline__ void load4(const XT* p, double (&v)[4]) {
 
 // part[wg][k][c] = sum over the workgroup's rows j of phi(x_jk) z_jc (phi: the
 // centred coordinate, or the stored logarithm).  A wave owns 64 coordinates
-// (workgroup column blockIdx.y) and 64 columns: 4 x 4 tiles of 16 x 16.  Each
-// step takes 4 rows; lane (m, g) = (l % 16, l / 16) loads coordinates
-// k0 + 4m .. +3 and columns 4m .. +3 of row j + g with one 16-byte load each,
-// so tile t of the coordinates holds k = k0 + 4 i + t at tile row i and tile u
-// of the columns holds c = 4 n + u at tile column n.  Needs d % 4 == 0 and
-// b % 4 == 0.
+// (workgroup column blockIdx.y) and 16 CU columns: 4 x CU tiles of 16 x 16.
+// Each step takes 4 rows; lane (m, g) = (l % 16, l / 16) loads coordinates
+// k0 + 4m .. +3 of row j + g with one 16-byte load and columns CU m .. +CU-1
+// of the same row with one load of 4 CU bytes, so tile t of the coordinates
+// holds k = k0 + 4 i + t at tile row i and tile u of the columns holds
+// c = CU n + u at tile column n.  CU = 4 serves b <= 64, 2 b <= 32 and 1
+// b <= 16 (a step of CU = 1 reads 4 whole rows of Z for b = 16 in one
+// coalesced load and takes 4 products instead of the 16 of CU = 4).  Needs
+// d % 4 == 0, b % CU == 0 and Z rows aligned to 4 CU bytes.
 constexpr int SF_MOM_DEPTH = 4;   // row steps in flight per wave
 // TOT: the waves of the first coordinate block also sum z and w z (FP64)
 // over their rows into tpart[wave][0 | 1][c] (the totals of the query).
-template <typename XT, int P, bool TOT>
+template <typename XT, int P, bool TOT, int CU>
 __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X, const double* __restrict__ centre,
                                                        const float* __restrict__ Z, int64_t n, int32_t d, int32_t b,
                                                        int64_t rows_per_wave, double* __restrict__ part,
@@ -492,30 +495,34 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
     const int m = lane & 15, g = lane >> 4;
     const int64_t xw = (int64_t)blockIdx.x * 4 + w;
     const int k0 = blockIdx.y * 64;
-    const int kq = k0 + 4 * m, cq = 4 * m;
+    const int kq = k0 + 4 * m, cq = CU * m;
     const bool kin = kq < d, cin = cq < b;
     // centres apply to FP32 coordinates only (the stored logarithms have none)
     constexpr bool CEN = sizeof(XT) == 4;
     double cen[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) cen[t] = (CEN && centre && kin) ? centre[kq + t] : 0.0;
-    d4v acc[4][4];
+    d4v acc[4][CU];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
+        for (int u = 0; u < CU; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
     const int64_t r0 = xw * rows_per_wave;
     const int64_t r1 = r0 + rows_per_wave < n ? r0 + rows_per_wave : n;
     // raw values of P row steps in flight: slot p holds step s with s % P == p;
     // a slot is refilled with the step P ahead right after it is consumed
     XT xn[P][4];
-    float zn[P][4];
+    float zn[P][CU];
     double wn[P];
     const bool tw = TOT && blockIdx.y == 0;
-    double t0a[4] = {0.0, 0.0, 0.0, 0.0}, ua[4] = {0.0, 0.0, 0.0, 0.0};
-    auto fetch = [&](int64_t j, XT (&xv)[4], float (&zv)[4], double& wv) {
+    double t0a[CU], ua[CU];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) { xv[t] = XT(0); zv[t] = 0.0f; }
+    for (int u = 0; u < CU; ++u) { t0a[u] = 0.0; ua[u] = 0.0; }
+    auto fetch = [&](int64_t j, XT (&xv)[4], float (&zv)[CU], double& wv) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) xv[t] = XT(0);
+#pragma unroll
+        for (int u = 0; u < CU; ++u) zv[u] = 0.0f;
         wv = 0.0;
         if (j < r1) {
             if (tw && wu) wv = wu[j];
@@ -531,9 +538,9 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
                 }
             }
             if (cin) {
-                const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(Z + j * b + cq);
+                const Vec<float, CU> q = *reinterpret_cast<const Vec<float, CU>*>(Z + j * b + cq);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) zv[t] = q.v[t];
+                for (int u = 0; u < CU; ++u) zv[u] = q.v[u];
             }
         }
     };
@@ -545,15 +552,15 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
             const int64_t j0 = js + 4 * p;
             if (j0 >= r1) break;
             const int64_t j = j0 + g;
-            double a[4], z[4];
+            double a[4], z[CU];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < 4; ++t)
                 a[t] = (j < r1 && kin) ? (CEN ? (double)xn[p][t] - cen[t] : (double)xn[p][t]) : 0.0;
-                z[t] = (double)zn[p][t];
-            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u) z[u] = (double)zn[p][u];
             if (tw) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < CU; ++u) {
                     t0a[u] += z[u];
                     ua[u] = fma(wn[p], z[u], ua[u]);
                 }
@@ -562,14 +569,14 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < CU; ++u)
                     acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], z[u], acc[t][u], 0, 0, 0);
         }
     }
     if (tw) {
         // the four row lanes g of a column group, added in a fixed xor order
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < CU; ++u) {
             t0a[u] += __shfl_xor(t0a[u], 16);
             ua[u] += __shfl_xor(ua[u], 16);
             t0a[u] += __shfl_xor(t0a[u], 32);
@@ -577,7 +584,7 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
         }
         if (g == 0) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < CU; ++u) {
                 const int c = cq + u;
                 if (c < b) {
                     tpart[((size_t)xw * 2) * b + c] = t0a[u];
@@ -589,37 +596,37 @@ __global__ __launch_bounds__(256) void sf_moments_mfma(const XT* __restrict__ X,
     // the workgroup's four waves (disjoint row ranges, the same coordinates)
     // add their sums in LDS in a fixed order, (w0 + w2) + (w1 + w3), and
     // wave 0 writes one partial per workgroup
-    __shared__ d4v s_acc[2][4][4][64];
+    __shared__ d4v s_acc[2][4][CU][64];
     if (w >= 2) {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) s_acc[w - 2][t][u][lane] = acc[t][u];
+            for (int u = 0; u < CU; ++u) s_acc[w - 2][t][u][lane] = acc[t][u];
     }
     __syncthreads();
     if (w < 2) {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[t][u] += s_acc[w][t][u][lane];
+            for (int u = 0; u < CU; ++u) acc[t][u] += s_acc[w][t][u][lane];
     }
     __syncthreads();
     if (w == 1) {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) s_acc[0][t][u][lane] = acc[t][u];
+            for (int u = 0; u < CU; ++u) s_acc[0][t][u][lane] = acc[t][u];
     }
     __syncthreads();
     if (w == 0) {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < CU; ++u) {
                 const d4v v = acc[t][u] + s_acc[0][t][u][lane];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int k = k0 + 4 * (4 * r + g) + t, c = 4 * m + u;
+                    const int k = k0 + 4 * (4 * r + g) + t, c = CU * m + u;
                     if (k < d && c < b) part[((size_t)blockIdx.x * d + k) * b + c] = v[r];
                 }
             }
@@ -788,100 +795,120 @@ __global__ void sf_check_finite(const double* __restrict__ T0, int32_t b, uint32
     if (c < b && !isfinite(T0[c])) atomicOr(status, (uint32_t)QF_NONFINITE);
 }
 
-// The same product for d <= 64 with V in registers: lane (m, g) keeps the
-// 4 x 4 x CT values V[16 kc + 4 g + s][16 u + m] that its B operands take in
-// every group, loaded once per wave, and the centres of its coordinates; the
-// next group's points are loaded before the current group's products.  No LDS,
-// and the products are taken in the same order as in sf_apply_mfma, so the
-// results are the same bit for bit.
-template <int CT>
-__global__ __launch_bounds__(256) void sf_apply_vreg(const float* __restrict__ X, const double* __restrict__ centre,
-                                                     int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
-                                                     const double* __restrict__ V, const double* __restrict__ a,
-                                                     const double* __restrict__ U, float* __restrict__ Out)
+// The same product for d <= 16 NCH, d % 4 == 0, with a whole 16-point group
+// in flight: a wave loads every coordinate of its next group (NCH 16-byte
+// loads per lane) and the group's weights a_i before it multiplies the current
+// group, so the 4 NCH product steps of a group cover the memory latency rather
+// than the 4 steps of one 16-coordinate chunk.  V and the centres are staged
+// once per workgroup in dynamic LDS, zero-padded to 16 NCH rows of 16 CT
+// columns, so the product steps read them without bounds tests.  The products
+// are taken in the same order as in sf_apply_mfma, so the results are the
+// same bit for bit.
+template <int CT, int NCH>
+__global__ __launch_bounds__(512, 2) void sf_apply_mfma_grp(const float* __restrict__ X, const double* __restrict__ centre,
+                                                         int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
+                                                         const double* __restrict__ V, const double* __restrict__ a,
+                                                         const double* __restrict__ U, float* __restrict__ Out)
 {
+    constexpr int KP = 16 * NCH, BP = 16 * CT;   // padded rows and columns of V
+    extern __shared__ double sV[];               // V (KP x BP), then KP centres
+    double* const sC = sV + KP * BP;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
+    const int wpb = blockDim.x >> 6;
+    for (int e = threadIdx.x; e < KP * BP; e += blockDim.x) {
+        const int k = e / BP, c = e % BP;
+        sV[e] = (k < d && c < b) ? V[(size_t)k * b + c] : 0.0;
+    }
+    for (int e = threadIdx.x; e < KP; e += blockDim.x) sC[e] = (centre && e < d) ? centre[e] : 0.0;
+    __syncthreads();
     const int64_t ngroup = (n + 15) / 16;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + w, nwaves = (int64_t)gridDim.x * 4;
-    double vr[4][4][CT], cz[4][4];
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int k = 16 * kc + 4 * g + s;
-            cz[kc][s] = (centre && k < d) ? centre[k] : 0.0;
-#pragma unroll
-            for (int u = 0; u < CT; ++u) {
-                const int c = 16 * u + m;
-                vr[kc][s][u] = (k < d && c < b) ? V[(size_t)k * b + c] : 0.0;
-            }
-        }
+    const int64_t wave = (int64_t)blockIdx.x * wpb + w, nwaves = (int64_t)gridDim.x * wpb;
     double t0[CT], uu[CT];
 #pragma unroll
     for (int u = 0; u < CT; ++u) {
-        const int c = 16 * u + m;
+        const int c = CT * m + u;
         t0[u] = c < b ? T0[c] : 0.0;
         uu[u] = (U && c < b) ? U[c] : 0.0;
     }
-    const bool vec = d % 4 == 0;
-    // coordinates 16 kc + 4g .. +3 of point i, zero outside the data
-    auto load = [&](int64_t i, float (&xv)[4][4]) {
+    // coordinates 16 kc + 4g .. +3 of point grp 16 + m and the weights of the
+    // group's rows 4r + g, zero outside the data
+    auto load_group = [&](int64_t grp, float (&xg)[NCH][4], double (&ag)[4]) {
+        const int64_t ia = grp * 16 + m;
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
+        for (int kc = 0; kc < NCH; ++kc) {
             const int kq = 16 * kc + 4 * g;
+            Vec<float, 4> q;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) xv[kc][s] = 0.0f;
-            if (i >= n) continue;
-            if (vec) {
-                if (kq < d) {
-                    const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(X + i * d + kq);
+            for (int s = 0; s < 4; ++s) q.v[s] = 0.0f;
+            if (ia < n && kq < d) q = *reinterpret_cast<const Vec<float, 4>*>(X + ia * d + kq);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) xv[kc][s] = q.v[s];
-                }
-            } else {
+            for (int s = 0; s < 4; ++s) xg[kc][s] = q.v[s];
+        }
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    if (kq + s < d) xv[kc][s] = X[i * d + kq + s];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = grp * 16 + 4 * r + g;
+            ag[r] = (a && i < n) ? a[i] : 0.0;
         }
     };
-    float xg[4][4];
-    if (wave < ngroup) load(wave * 16 + m, xg);
-    for (int64_t grp = wave; grp < ngroup; grp += nwaves) {
+    const bool vec4 = b % 4 == 0 && (uintptr_t)Out % 16 == 0;
+    float xn[NCH][4];
+    double an[4];
+    int64_t grp = wave;
+    if (grp < ngroup) load_group(grp, xn, an);
+    while (grp < ngroup) {
         const int64_t i0 = grp * 16;
-        float xv[4][4];
+        float xv[NCH][4];
+        double aw[4];
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc)
+        for (int kc = 0; kc < NCH; ++kc)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) xv[kc][s] = xg[kc][s];
-        if (grp + nwaves < ngroup) load((grp + nwaves) * 16 + m, xg);
+            for (int s = 0; s < 4; ++s) xv[kc][s] = xn[kc][s];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) aw[r] = an[r];
+        const int64_t grp2 = grp + nwaves;
+        if (grp2 < ngroup) load_group(grp2, xn, an);
+        // the lane's V offset, hidden from the optimiser per group so that V
+        // is read from LDS at each step instead of being held in registers
+        // across the loop (4 NCH CT values per lane)
+        int vo = (4 * g) * BP + CT * m;
+        asm volatile("" : "+v"(vo));
         d4v acc[CT];
 #pragma unroll
         for (int u = 0; u < CT; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc)
+        for (int kc = 0; kc < NCH; ++kc)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const bool kin = 16 * kc + 4 * g + s < d;
-                const double xa = kin ? (double)xv[kc][s] - cz[kc][s] : 0.0;
+                // rows past d: x, the centre and V are zero (so is the product)
+                const int k = 16 * kc + 4 * g + s;
+                double vb[CT];
+#pragma unroll
+                for (int u = 0; u < CT; ++u) vb[u] = sV[vo + (16 * kc + s) * BP + u];
+                const double xa = (double)xv[kc][s] - sC[k];
+#pragma unroll
+                for (int u = 0; u < CT; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, vb[u], acc[u], 0, 0, 0);
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + 4 * r + g;
+            if (i >= n) continue;
+            float o[CT];
+#pragma unroll
+            for (int u = 0; u < CT; ++u) {
+                double v = acc[u][r] + uu[u];
+                if (a) v = fma(aw[r], t0[u], v);
+                o[u] = (float)v;
+            }
+            if (CT == 4 && vec4) {
+                if (CT * m < b) *reinterpret_cast<float4*>(Out + i * b + CT * m) = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
 #pragma unroll
                 for (int u = 0; u < CT; ++u)
-                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, vr[kc][s][u], acc[u], 0, 0, 0);
-            }
-#pragma unroll
-        for (int u = 0; u < CT; ++u) {
-            const int c = 16 * u + m;
-            if (c >= b) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + 4 * r + g;
-                if (i >= n) continue;
-                double v = acc[u][r] + uu[u];
-                if (a) v = fma(a[i], t0[u], v);
-                Out[i * b + c] = (float)v;
+                    if (CT * m + u < b) Out[i * b + CT * m + u] = o[u];
             }
         }
+        grp = grp2;
     }
 }
 
@@ -1303,10 +1330,21 @@ hipError_t reduce_launch(const void* part, int64_t nblk, int64_t per_t, int nt, 
     return hipGetLastError();
 }
 
-// The matrix-core moments serve the single-moment forms at b > 32 with d and b
-// multiples of 4 (16-byte loads of X and Z; Z must also be 16-byte aligned).
+// Columns per lane of the matrix-core moments for a block of b columns: 1 for
+// 4 <= b <= 16, 2 for even b <= 32, 4 for b % 4 == 0 (0: not served).
+int mfma_moment_cu(int32_t b) {
+    if (b < 4) return 0;
+    if (b <= 16) return 1;
+    if (b <= 32) return b % 2 == 0 ? 2 : 0;
+    return b % 4 == 0 ? 4 : 0;
+}
+// The matrix-core moments serve the single-moment forms at d % 4 == 0 (16-byte
+// loads of X) and the b above; Z must also be aligned to 4 CU bytes.
 bool mfma_moments_fit(int form, int32_t d, int32_t b) {
-    return form != SF_EVEN && pad_bw(b) == 64 && d % 4 == 0 && b % 4 == 0;
+    return form != SF_EVEN && d % 4 == 0 && mfma_moment_cu(b) > 0;
+}
+bool mfma_moments_aligned(const void* Z, int32_t b) {
+    return (uintptr_t)Z % (4 * (uintptr_t)mfma_moment_cu(b)) == 0;
 }
 // even p (float data) on matrix cores: b > 32 and b % 4 == 0 (16-byte loads of Z)
 bool even_mfma_fit(int32_t b) { return pad_bw(b) == 64 && b % 4 == 0; }
@@ -1403,7 +1441,7 @@ size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p) {
 }
 
 bool sf_fuses_totals(int form, bool is_int, int32_t d, int32_t b, const void* Z) {
-    return !is_int && mfma_moments_fit(form, d, b) && (uintptr_t)Z % 16 == 0;
+    return !is_int && mfma_moments_fit(form, d, b) && mfma_moments_aligned(Z, b);
 }
 
 hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuery& q, void* scratch, hipStream_t s)
@@ -1435,13 +1473,20 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     if (fuse && !sf_fuses_totals(form, is_int, q.d, q.b, q.Z)) return hipErrorInvalidValue;
     const double* T0q = (const double*)q.T0;
     const double* Uq = q.U;
-    if (mfma_moments_fit(form, q.d, q.b) && (uintptr_t)q.Z % 16 == 0) {
+    if (mfma_moments_fit(form, q.d, q.b) && mfma_moments_aligned(q.Z, q.b)) {
+        const int cu = mfma_moment_cu(q.b);
         const int64_t waves = mfma_row_waves(q.n, q.d);
         const int64_t rpw = ((q.n + waves - 1) / waves + 3) / 4 * 4;
         dim3 grid((unsigned)(waves / 4), (unsigned)((q.d + 63) / 64));
-#define SF_MOMENTS(XT, XP, CP, TOT)                                                                               \
-    sf_moments_mfma<XT, SF_MOM_DEPTH, TOT><<<grid, 256, 0, s>>>(XP, CP, (const float*)q.Z, q.n, q.d, q.b, rpw,    \
-                                                                 (double*)part, q.wu, tpart)
+#define SF_MOMENTS_CU(XT, XP, CP, TOT, CU)                                                                         \
+    sf_moments_mfma<XT, SF_MOM_DEPTH, TOT, CU><<<grid, 256, 0, s>>>(XP, CP, (const float*)q.Z, q.n, q.d, q.b, rpw, \
+                                                                     (double*)part, q.wu, tpart)
+#define SF_MOMENTS(XT, XP, CP, TOT)                                                                                \
+    do {                                                                                                           \
+        if (cu == 1) SF_MOMENTS_CU(XT, XP, CP, TOT, 1);                                                            \
+        else if (cu == 2) SF_MOMENTS_CU(XT, XP, CP, TOT, 2);                                                       \
+        else SF_MOMENTS_CU(XT, XP, CP, TOT, 4);                                                                    \
+    } while (0)
         if (form == SF_LOG) {
             if (fuse) SF_MOMENTS(double, q.LX, nullptr, true);
             else SF_MOMENTS(double, q.LX, nullptr, false);
@@ -1450,6 +1495,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
             else SF_MOMENTS(float, (const float*)q.X, (const double*)q.centre, false);
         }
 #undef SF_MOMENTS
+#undef SF_MOMENTS_CU
         e = hipGetLastError();
         nblk = waves / 4;   // one partial per workgroup
         if (e == hipSuccess && fuse) {
@@ -1489,9 +1535,21 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
         const size_t vbytes = (size_t)q.d * q.b * 8;
         const bool lds = vbytes <= 65536;
         const size_t shm = lds ? vbytes : 0;
+        // whole groups in flight where d allows (V and the centres in LDS)
+        const bool grp = q.d % 4 == 0 && q.d <= 64;
+#define SF_APPLY_GRP(CT, NCH)                                                                                         \
+    sf_apply_mfma_grp<CT, NCH><<<gb, 512, (size_t)16 * (NCH) * (16 * (CT) + 1) * 8, s>>>(Xf, cen, q.n, q.d, q.b, T0, \
+                                                                                       Vd, q.a, Uq, O)
 #define SF_APPLY_MFMA(CT)                                                                                           \
     do {                                                                                                            \
-        if (lds)                                                                                                    \
+        if (grp) {                                                                                                  \
+            switch ((q.d + 15) / 16) {                                                                              \
+            case 1: SF_APPLY_GRP(CT, 1); break;                                                                     \
+            case 2: SF_APPLY_GRP(CT, 2); break;                                                                     \
+            case 3: SF_APPLY_GRP(CT, 3); break;                                                                     \
+            default: SF_APPLY_GRP(CT, 4); break;                                                                    \
+            }                                                                                                       \
+        } else if (lds)                                                                                             \
             sf_apply_mfma<CT, true><<<gb, 512, shm, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O);         \
         else                                                                                                        \
             sf_apply_mfma<CT, false><<<2 * gb, 256, 0, s>>>(Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O);      \
@@ -1503,6 +1561,7 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
         default: SF_APPLY_MFMA(4); break;
         }
 #undef SF_APPLY_MFMA
+#undef SF_APPLY_GRP
         return hipGetLastError();
     }
     return apply_t<float, double, float, 1, false>(q.X, cen, q.n, q.d, q.b, T0q, Gv, q.a, Uq, q.Out, s);

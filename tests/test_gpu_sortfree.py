@@ -319,12 +319,17 @@ def test_many_coordinates():
 
 
 # ---------------------------------------------------------------------------
-# the matrix-core kernels of the single-moment forms: moments at b > 32 with d,
-# b multiples of 4 and an aligned Z; the point pass at b >= 16
+# the matrix-core kernels of the single-moment forms: moments at d % 4 == 0
+# with one column per lane for 4 <= b <= 16, two for even b <= 32 and four for
+# b % 4 == 0 (others take the vector moments); the point pass at b >= 4
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("metric,b,n,d", [(oracle.KL, 20, 3001, 12), (oracle.MAHA2, 33, 2501, 37),
                                           (oracle.BILINEAR, 48, 4099, 64), (oracle.CE, 64, 2049, 70),
-                                          (oracle.MAHA2, 64, 4099, 132), (oracle.KL, 40, 2053, 8)])
+                                          (oracle.MAHA2, 64, 4099, 132), (oracle.KL, 40, 2053, 8),
+                                          (oracle.KL, 16, 3001, 64), (oracle.MAHA2, 4, 2501, 36),
+                                          (oracle.BILINEAR, 13, 4099, 20), (oracle.CE, 30, 2049, 68),
+                                          (oracle.MAHA2, 32, 4099, 132), (oracle.BILINEAR, 9, 1031, 8),
+                                          (oracle.KL, 25, 2053, 16)])
 def test_matrix_core_shapes(metric, b, n, d):
     g = synth.rng(9970 + b + d)
     M = None
@@ -433,7 +438,8 @@ def test_full_size_wide_blocks_sampled_rows():
 # inside their moments kernel and check the column sums
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("metric,b,d", [(oracle.KL, 64, 8), (oracle.MAHA2, 64, 12), (oracle.BILINEAR, 48, 16),
-                                        (oracle.CE, 64, 4), (oracle.L4, 64, 5), (oracle.KL, 1, 8)])
+                                        (oracle.CE, 64, 4), (oracle.L4, 64, 5), (oracle.KL, 1, 8),
+                                        (oracle.KL, 16, 8), (oracle.MAHA2, 6, 12), (oracle.CE, 26, 4)])
 @pytest.mark.parametrize("case", ["inf", "nan", "both_infs"])
 def test_nonfinite_rhs_flagged(metric, b, d, case):
     g = synth.rng(9990 + b + d)
