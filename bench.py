@@ -320,8 +320,8 @@ def run_sortfree(args, dm, synth, np, torch, dev, stream):
     """The sort-free family (Appendix A) on n = 2^20 points, d = 64: l_4^4 and
     l_6^6 on the 32-component mixture, KL divergence and cross entropy on
     Dirichlet(1) probability vectors, the squared Mahalanobis distance and the
-    bilinear form with a seeded SPD matrix.  Single vector (b = 1) and a block
-    of b = 64; 3 warm-up and 10 timed queries each (median).  Reported per
+    bilinear form with a seeded SPD matrix.  Single vector (b = 1) and blocks
+    of b = 16 and b = 64; 3 warm-up and 10 timed queries each (median).  Reported per
     query: time, the algorithmic HBM bytes (moments read X, or its FP64
     logarithms for KL and cross entropy, plus Z; the point pass reads X and
     writes Out; the totals read Z) and their rate, and the FP64 operation
@@ -336,7 +336,7 @@ def run_sortfree(args, dm, synth, np, torch, dev, stream):
     cases = (("l4", dm.L4, Xm, None, 4), ("l6", dm.L6, Xm, None, 6), ("kl", dm.KL, P, None, 1),
              ("ce", dm.CE, P, None, 1), ("maha2", dm.MAHA2, Xm, M, 1), ("bilinear", dm.BILINEAR, Xm, M, 1))
     res = {"n": n, "d": d}
-    for b in (1, 64):
+    for b in (1, 16, 64):
         Z = synth.rhs_normal(n, b, synth.seeds(2)["Z"] + 20 + b, np.float32)
         Zd = torch.from_numpy(Z).to(dev)
         out = torch.empty((n, b), dtype=torch.float32, device=dev)

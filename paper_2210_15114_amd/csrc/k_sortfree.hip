@@ -915,11 +915,12 @@ __global__ __launch_bounds__(512, 2) void sf_apply_mfma_grp(const float* __restr
 // Even-p moments on matrix cores: part[blk][t][k][c] = sum over the
 // workgroup's rows j of x~_jk^(t+1) z_jc, t = 0 .. NT-1.  A workgroup owns a
 // row range and 64 coordinates; wave w owns the 16 coordinates
-// k0 + 16w .. +15 (tile row m is coordinate k0 + 16w + m) and all 64 columns
-// (tile u holds column 4n + u at tile column n, from one 16-byte load of Z
-// per lane and step); the powers of x~ are formed once per lane and feed NT
-// products.  Needs b % 4 == 0 and a 16-byte aligned Z.
-template <int NT>
+// k0 + 16w .. +15 (tile row m is coordinate k0 + 16w + m) and 16 CU columns
+// (tile u holds column CU n + u at tile column n, from one load of CU values
+// of Z per lane and step; CU as in sf_moments_mfma); the powers of x~ are
+// formed once per lane and feed NT CU products.  Needs b % CU == 0 and Z rows
+// aligned to 4 CU bytes.
+template <int NT, int CU>
 __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restrict__ X,
                                                             const double* __restrict__ centre,
                                                             const float* __restrict__ Z, int64_t n, int32_t d,
@@ -929,43 +930,43 @@ __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restr
     const int m = lane & 15, g = lane >> 4;
     const int kt0 = blockIdx.y * 64 + 16 * w;   // the wave's first coordinate
     const int k = kt0 + m;
-    const bool kin = k < d, cin = 4 * m < b;
+    const bool kin = k < d, cin = CU * m < b;
     const double ck = kin ? centre[k] : 0.0;
-    d4v acc[NT][4];
+    d4v acc[NT][CU];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
+        for (int u = 0; u < CU; ++u) acc[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
     // two 4-row steps per iteration; the next iteration's raw values are
     // loaded before this iteration's products
-    float xn[2], zn[2][4];
+    float xn[2], zn[2][CU];
     auto fetch = [&](int64_t j0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t j = j0 + 4 * h + g;
             xn[h] = 0.0f;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) zn[h][u] = 0.0f;
+            for (int u = 0; u < CU; ++u) zn[h][u] = 0.0f;
             if (j < r1) {
                 if (kin) xn[h] = X[j * d + k];
                 if (cin) {
-                    const Vec<float, 4> q = *reinterpret_cast<const Vec<float, 4>*>(Z + j * b + 4 * m);
+                    const Vec<float, CU> q = *reinterpret_cast<const Vec<float, CU>*>(Z + j * b + CU * m);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) zn[h][u] = q.v[u];
+                    for (int u = 0; u < CU; ++u) zn[h][u] = q.v[u];
                 }
             }
         }
     };
     fetch(r0);
     for (int64_t j0 = r0; j0 < r1; j0 += 8) {   // the same trip count on every lane
-        double x[2], z[2][4];
+        double x[2], z[2][CU];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             x[h] = (double)xn[h];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) z[h][u] = (double)zn[h][u];
+            for (int u = 0; u < CU; ++u) z[h][u] = (double)zn[h][u];
         }
         if (j0 + 8 < r1) fetch(j0 + 8);
 #pragma unroll
@@ -975,7 +976,7 @@ __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restr
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < CU; ++u)
                     acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xt, z[h][u], acc[t][u], 0, 0, 0);
                 xt *= xh;
             }
@@ -984,10 +985,10 @@ __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restr
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < CU; ++u)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int kk = kt0 + 4 * r + g, c = 4 * m + u;
+                const int kk = kt0 + 4 * r + g, c = CU * m + u;
                 if (kk < d && c < b) part[(((size_t)blockIdx.x * NT + t) * d + kk) * b + c] = acc[t][u][r];
             }
 }
@@ -1346,8 +1347,10 @@ bool mfma_moments_fit(int form, int32_t d, int32_t b) {
 bool mfma_moments_aligned(const void* Z, int32_t b) {
     return (uintptr_t)Z % (4 * (uintptr_t)mfma_moment_cu(b)) == 0;
 }
-// even p (float data) on matrix cores: b > 32 and b % 4 == 0 (16-byte loads of Z)
-bool even_mfma_fit(int32_t b) { return pad_bw(b) == 64 && b % 4 == 0; }
+// even p (float data) on matrix cores: the b of mfma_moment_cu from b = 8 (Z
+// aligned to 4 CU bytes); at b = 4 the vector moments measured faster (l6
+// 0.50 against 0.54 ms per query at n = 2^20, d = 64)
+bool even_mfma_fit(int32_t b) { return b >= 8 && mfma_moment_cu(b) > 0; }
 // row ranges of the even-p matrix-core moments: about 2048 workgroups
 int64_t even_mfma_blocks(int64_t n, int32_t d) {
     const int64_t ky = (d + 63) / 64;
@@ -1371,13 +1374,19 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
     hipError_t e;
     const int64_t per_t = (int64_t)q.d * q.b;
     if (!is_int) {
-        if (even_mfma_fit(q.b) && (uintptr_t)q.Z % 16 == 0) {
+        if (even_mfma_fit(q.b) && mfma_moments_aligned(q.Z, q.b)) {
             const int64_t blk = even_mfma_blocks(q.n, q.d);
             const int64_t rpb = ((q.n + blk - 1) / blk + 3) / 4 * 4;
             const int64_t nb = (q.n + rpb - 1) / rpb;
             dim3 grid((unsigned)nb, (unsigned)((q.d + 63) / 64));
-            sf_moments_even_mfma<P><<<grid, 256, 0, s>>>((const float*)q.X, (const double*)q.centre,
-                                                         (const float*)q.Z, q.n, q.d, q.b, rpb, (double*)part);
+            const float* Xf = (const float*)q.X;
+            const double* cen = (const double*)q.centre;
+            const float* Zf = (const float*)q.Z;
+            switch (mfma_moment_cu(q.b)) {
+            case 1: sf_moments_even_mfma<P, 1><<<grid, 256, 0, s>>>(Xf, cen, Zf, q.n, q.d, q.b, rpb, (double*)part); break;
+            case 2: sf_moments_even_mfma<P, 2><<<grid, 256, 0, s>>>(Xf, cen, Zf, q.n, q.d, q.b, rpb, (double*)part); break;
+            default: sf_moments_even_mfma<P, 4><<<grid, 256, 0, s>>>(Xf, cen, Zf, q.n, q.d, q.b, rpb, (double*)part); break;
+            }
             e = hipGetLastError();
             nblk = nb;
         } else {
@@ -1385,7 +1394,10 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
         }
         if (e != hipSuccess) return e;
         if ((e = reduce_launch<double>(part, nblk, per_t, P, P, 1.0, G, SL, s)) != hipSuccess) return e;
-        if (q.b >= 16) {   // matrix cores for the point pass
+        // matrix cores for the point pass from b = 8: a 16-column tile costs
+        // the same at any b <= 16, the vector pass grows with b (the two meet
+        // near b = 6 at n = 2^20, d = 64)
+        if (q.b >= 8) {
             int64_t blocks = (q.n + 127) / 128;
             if (blocks > 1024) blocks = 1024;
             const unsigned gb = (unsigned)blocks;

@@ -362,7 +362,9 @@ def test_matrix_core_moments_with_unaligned_z():
 
 
 @pytest.mark.parametrize("p,b,n,d,aligned", [(4, 40, 3001, 70, True), (6, 48, 2053, 9, True),
-                                              (4, 64, 3001, 33, False), (6, 20, 4099, 64, True)])
+                                              (4, 64, 3001, 33, False), (6, 20, 4099, 64, True),
+                                              (4, 16, 2501, 40, False), (6, 30, 3001, 12, False),
+                                              (4, 6, 3001, 70, True), (6, 13, 2049, 66, True)])
 def test_even_p_matrix_core_shapes(p, b, n, d, aligned):
     import torch
     g = synth.rng(9990 + p + b + d)
