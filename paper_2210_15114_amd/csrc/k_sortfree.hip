@@ -801,18 +801,21 @@ __global__ void sf_check_finite(const double* __restrict__ T0, int32_t b, uint32
 // group, so the 4 NCH product steps of a group cover the memory latency rather
 // than the 4 steps of one 16-coordinate chunk.  V and the centres are staged
 // once per workgroup in dynamic LDS, zero-padded to 16 NCH rows of 16 CT
-// columns, so the product steps read them without bounds tests.  The products
+// columns, so the product steps read them without bounds tests, and so are the
+// column totals T0 and U of the epilogue (registers kept for 4 waves per SIMD).  The products
 // are taken in the same order as in sf_apply_mfma, so the results are the
 // same bit for bit.
 template <int CT, int NCH>
-__global__ __launch_bounds__(512, 2) void sf_apply_mfma_grp(const float* __restrict__ X, const double* __restrict__ centre,
+__global__ __launch_bounds__(512, 4) void sf_apply_mfma_grp(const float* __restrict__ X, const double* __restrict__ centre,
                                                          int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
                                                          const double* __restrict__ V, const double* __restrict__ a,
                                                          const double* __restrict__ U, float* __restrict__ Out)
 {
     constexpr int KP = 16 * NCH, BP = 16 * CT;   // padded rows and columns of V
-    extern __shared__ double sV[];               // V (KP x BP), then KP centres
+    extern __shared__ double sV[];               // V (KP x BP), KP centres, BP T0, BP U
     double* const sC = sV + KP * BP;
+    double* const sT = sC + KP;
+    double* const sU = sT + BP;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
     const int wpb = blockDim.x >> 6;
@@ -821,16 +824,13 @@ __global__ __launch_bounds__(512, 2) void sf_apply_mfma_grp(const float* __restr
         sV[e] = (k < d && c < b) ? V[(size_t)k * b + c] : 0.0;
     }
     for (int e = threadIdx.x; e < KP; e += blockDim.x) sC[e] = (centre && e < d) ? centre[e] : 0.0;
+    for (int e = threadIdx.x; e < BP; e += blockDim.x) {
+        sT[e] = e < b ? T0[e] : 0.0;
+        sU[e] = (U && e < b) ? U[e] : 0.0;
+    }
     __syncthreads();
     const int64_t ngroup = (n + 15) / 16;
     const int64_t wave = (int64_t)blockIdx.x * wpb + w, nwaves = (int64_t)gridDim.x * wpb;
-    double t0[CT], uu[CT];
-#pragma unroll
-    for (int u = 0; u < CT; ++u) {
-        const int c = CT * m + u;
-        t0[u] = c < b ? T0[c] : 0.0;
-        uu[u] = (U && c < b) ? U[c] : 0.0;
-    }
     // coordinates 16 kc + 4g .. +3 of point grp 16 + m and the weights of the
     // group's rows 4r + g, zero outside the data
     auto load_group = [&](int64_t grp, float (&xg)[NCH][4], double (&ag)[4]) {
@@ -896,8 +896,8 @@ __global__ __launch_bounds__(512, 2) void sf_apply_mfma_grp(const float* __restr
             float o[CT];
 #pragma unroll
             for (int u = 0; u < CT; ++u) {
-                double v = acc[u][r] + uu[u];
-                if (a) v = fma(aw[r], t0[u], v);
+                double v = acc[u][r] + sU[CT * m + u];
+                if (a) v = fma(aw[r], sT[CT * m + u], v);
                 o[u] = (float)v;
             }
             if (CT == 4 && vec4) {
@@ -1550,8 +1550,8 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
         // whole groups in flight where d allows (V and the centres in LDS)
         const bool grp = q.d % 4 == 0 && q.d <= 64;
 #define SF_APPLY_GRP(CT, NCH)                                                                                         \
-    sf_apply_mfma_grp<CT, NCH><<<gb, 512, (size_t)16 * (NCH) * (16 * (CT) + 1) * 8, s>>>(Xf, cen, q.n, q.d, q.b, T0, \
-                                                                                       Vd, q.a, Uq, O)
+    sf_apply_mfma_grp<CT, NCH><<<gb, 512, ((size_t)16 * (NCH) * (16 * (CT) + 1) + 32 * (CT)) * 8, s>>>(          \
+        Xf, cen, q.n, q.d, q.b, T0, Vd, q.a, Uq, O)
 #define SF_APPLY_MFMA(CT)                                                                                           \
     do {                                                                                                            \
         if (grp) {                                                                                                  \
