@@ -281,8 +281,9 @@ struct SfQuery {
     const double* wu = nullptr;   // n weights w of U = sum_j w_j z_j, or NULL (no U)
 };
 // whether launch_sf_query forms the totals itself for this shape (the
-// single-moment forms on matrix cores: float data, d % 4 == 0, and 4 <= b <= 16,
-// or even b <= 32 with Z 8-byte aligned, or b % 4 == 0 with Z 16-byte aligned)
+// matrix-core moments of float data: 4 <= b <= 16, or even b <= 32 with Z
+// 8-byte aligned, or b % 4 == 0 with Z 16-byte aligned; the single-moment
+// forms need d % 4 == 0, even p needs b >= 8)
 bool sf_fuses_totals(int form, bool is_int, int32_t d, int32_t b, const void* Z);
 int sf_moment_count(int form, int p);
 size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p);

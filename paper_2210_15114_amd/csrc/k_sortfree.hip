@@ -919,12 +919,15 @@ __global__ __launch_bounds__(512, 4) void sf_apply_mfma_grp(const float* __restr
 // (tile u holds column CU n + u at tile column n, from one load of CU values
 // of Z per lane and step; CU as in sf_moments_mfma); the powers of x~ are
 // formed once per lane and feed NT CU products.  Needs b % CU == 0 and Z rows
-// aligned to 4 CU bytes.
-template <int NT, int CU>
+// aligned to 4 CU bytes.  TOT: wave 0 of the first coordinate block also sums
+// z over the workgroup's rows into tpart[blk][c] (FP64; every wave of a
+// workgroup loads the same Z values).
+template <int NT, int CU, bool TOT>
 __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restrict__ X,
                                                             const double* __restrict__ centre,
                                                             const float* __restrict__ Z, int64_t n, int32_t d,
-                                                            int32_t b, int64_t rows_per_blk, double* __restrict__ part)
+                                                            int32_t b, int64_t rows_per_blk, double* __restrict__ part,
+                                                            double* __restrict__ tpart)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
@@ -942,6 +945,10 @@ __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restr
     // two 4-row steps per iteration; the next iteration's raw values are
     // loaded before this iteration's products
     float xn[2], zn[2][CU];
+    const bool tw = TOT && blockIdx.y == 0 && w == 0;
+    double t0a[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) t0a[u] = 0.0;
     auto fetch = [&](int64_t j0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -968,6 +975,12 @@ __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restr
 #pragma unroll
             for (int u = 0; u < CU; ++u) z[h][u] = (double)zn[h][u];
         }
+        if (tw) {   // rows past the range hold z = 0
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < CU; ++u) t0a[u] += z[h][u];
+        }
         if (j0 + 8 < r1) fetch(j0 + 8);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -980,6 +993,16 @@ __global__ __launch_bounds__(256) void sf_moments_even_mfma(const float* __restr
                     acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xt, z[h][u], acc[t][u], 0, 0, 0);
                 xt *= xh;
             }
+        }
+    }
+    if (tw) {
+        // the four row lanes g of a column group, added in a fixed xor order
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            t0a[u] += __shfl_xor(t0a[u], 16);
+            t0a[u] += __shfl_xor(t0a[u], 32);
+            const int c = CU * m + u;
+            if (g == 0 && c < b) tpart[(size_t)blockIdx.x * b + c] = t0a[u];
         }
     }
 #pragma unroll
@@ -1368,12 +1391,17 @@ int64_t mfma_row_waves(int64_t n, int32_t d) {
     return w < 4 ? 4 : (w + 3) / 4 * 4;
 }
 template <int P>
-hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char* G, char* SL, hipStream_t s)
+hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char* G, char* SL, double* tpart,
+                      double* GT, hipStream_t s)
 {
     int64_t nblk = 0;
     hipError_t e;
     const int64_t per_t = (int64_t)q.d * q.b;
+    // fused totals: the matrix-core moments also sum z (T0 of the query)
+    const bool fuse = q.status != nullptr;
+    const double* T0q = (const double*)q.T0;
     if (!is_int) {
+        if (fuse && !(even_mfma_fit(q.b) && mfma_moments_aligned(q.Z, q.b))) return hipErrorInvalidValue;
         if (even_mfma_fit(q.b) && mfma_moments_aligned(q.Z, q.b)) {
             const int64_t blk = even_mfma_blocks(q.n, q.d);
             const int64_t rpb = ((q.n + blk - 1) / blk + 3) / 4 * 4;
@@ -1382,13 +1410,27 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
             const float* Xf = (const float*)q.X;
             const double* cen = (const double*)q.centre;
             const float* Zf = (const float*)q.Z;
-            switch (mfma_moment_cu(q.b)) {
-            case 1: sf_moments_even_mfma<P, 1><<<grid, 256, 0, s>>>(Xf, cen, Zf, q.n, q.d, q.b, rpb, (double*)part); break;
-            case 2: sf_moments_even_mfma<P, 2><<<grid, 256, 0, s>>>(Xf, cen, Zf, q.n, q.d, q.b, rpb, (double*)part); break;
-            default: sf_moments_even_mfma<P, 4><<<grid, 256, 0, s>>>(Xf, cen, Zf, q.n, q.d, q.b, rpb, (double*)part); break;
+#define SF_EVEN_MOM(CU, TOT)                                                                                        \
+    sf_moments_even_mfma<P, CU, TOT><<<grid, 256, 0, s>>>(Xf, cen, Zf, q.n, q.d, q.b, rpb, (double*)part, tpart)
+            switch (mfma_moment_cu(q.b) * 2 + (fuse ? 1 : 0)) {
+            case 2: SF_EVEN_MOM(1, false); break;
+            case 3: SF_EVEN_MOM(1, true); break;
+            case 4: SF_EVEN_MOM(2, false); break;
+            case 5: SF_EVEN_MOM(2, true); break;
+            case 9: SF_EVEN_MOM(4, true); break;
+            default: SF_EVEN_MOM(4, false); break;
             }
+#undef SF_EVEN_MOM
             e = hipGetLastError();
             nblk = nb;
+            if (e == hipSuccess && fuse) {
+                // sum z over the row blocks (fixed order), then the finiteness check
+                if ((e = reduce_launch<double>(tpart, nb, (int64_t)q.b, 1, 0, 1.0, GT, SL, s)) != hipSuccess)
+                    return e;
+                sf_check_finite<<<1, 64, 0, s>>>(GT, q.b, q.status);
+                e = hipGetLastError();
+                T0q = GT;
+            }
         } else {
             e = moments_t<float, float, double, P>(q.b, q.X, q.centre, q.Z, q.n, q.d, part, &nblk, s);
         }
@@ -1403,7 +1445,7 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
             const unsigned gb = (unsigned)blocks;
             const float* Xf = (const float*)q.X;
             const double* cen = (const double*)q.centre;
-            const double* T0 = (const double*)q.T0;
+            const double* T0 = T0q;
             const double* Gd = (const double*)G;
             float* O = (float*)q.Out;
             switch ((q.b + 15) / 16) {
@@ -1414,7 +1456,7 @@ hipError_t even_query(bool is_int, int zkind, const SfQuery& q, char* part, char
             }
             return hipGetLastError();
         }
-        return apply_t<float, double, float, P, true>(q.X, q.centre, q.n, q.d, q.b, q.T0, G, nullptr, nullptr, q.Out,
+        return apply_t<float, double, float, P, true>(q.X, q.centre, q.n, q.d, q.b, T0q, G, nullptr, nullptr, q.Out,
                                                       s);
     }
     if (zkind == IN_I32)
@@ -1453,6 +1495,7 @@ size_t sf_scratch_bytes(int64_t n, int32_t d, int32_t b, int form, int p) {
 }
 
 bool sf_fuses_totals(int form, bool is_int, int32_t d, int32_t b, const void* Z) {
+    if (form == SF_EVEN) return !is_int && even_mfma_fit(b) && mfma_moments_aligned(Z, b);
     return !is_int && mfma_moments_fit(form, d, b) && mfma_moments_aligned(Z, b);
 }
 
@@ -1470,9 +1513,9 @@ hipError_t launch_sf_query(int form, int p, bool is_int, int zkind, const SfQuer
     double* GT = tpart + (size_t)nblk_max * 2 * q.b;
     if (form == SF_EVEN) {
         switch (p) {
-        case 2: return even_query<2>(is_int, zkind, q, part, G, SL, s);
-        case 4: return even_query<4>(is_int, zkind, q, part, G, SL, s);
-        case 6: return even_query<6>(is_int, zkind, q, part, G, SL, s);
+        case 2: return even_query<2>(is_int, zkind, q, part, G, SL, tpart, GT, s);
+        case 4: return even_query<4>(is_int, zkind, q, part, G, SL, tpart, GT, s);
+        case 6: return even_query<6>(is_int, zkind, q, part, G, SL, tpart, GT, s);
         default: return hipErrorInvalidValue;
         }
     }
