@@ -802,14 +802,15 @@ __global__ void sf_check_finite(const double* __restrict__ T0, int32_t b, uint32
 // than the 4 steps of one 16-coordinate chunk.  V and the centres are staged
 // once per workgroup in dynamic LDS, zero-padded to 16 NCH rows of 16 CT
 // columns, so the product steps read them without bounds tests, and so are the
-// column totals T0 and U of the epilogue (registers kept for 4 waves per SIMD).  The products
-// are taken in the same order as in sf_apply_mfma, so the results are the
-// same bit for bit.
+// column totals T0 and U of the epilogue (which keeps the kernel within the
+// registers of 4 waves per SIMD).  The products are taken in the same order as
+// in sf_apply_mfma, so the results are the same bit for bit.
 template <int CT, int NCH>
-__global__ __launch_bounds__(512, 4) void sf_apply_mfma_grp(const float* __restrict__ X, const double* __restrict__ centre,
-                                                         int64_t n, int32_t d, int32_t b, const double* __restrict__ T0,
-                                                         const double* __restrict__ V, const double* __restrict__ a,
-                                                         const double* __restrict__ U, float* __restrict__ Out)
+__global__ __launch_bounds__(512, 4) void sf_apply_mfma_grp(const float* __restrict__ X,
+                                                            const double* __restrict__ centre, int64_t n, int32_t d,
+                                                            int32_t b, const double* __restrict__ T0,
+                                                            const double* __restrict__ V, const double* __restrict__ a,
+                                                            const double* __restrict__ U, float* __restrict__ Out)
 {
     constexpr int KP = 16 * NCH, BP = 16 * CT;   // padded rows and columns of V
     extern __shared__ double sV[];               // V (KP x BP), KP centres, BP T0, BP U
@@ -880,7 +881,8 @@ __global__ __launch_bounds__(512, 4) void sf_apply_mfma_grp(const float* __restr
         for (int kc = 0; kc < NCH; ++kc)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                // rows past d: x, the centre and V are zero (so is the product)
+                // coordinates past d: x, the centre and V are zero (so is the
+                // product); points past n only feed output rows that are not stored
                 const int k = 16 * kc + 4 * g + s;
                 double vb[CT];
 #pragma unroll
