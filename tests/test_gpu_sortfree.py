@@ -345,15 +345,19 @@ def test_matrix_core_shapes(metric, b, n, d):
     _check_float(X, Z, Y, metric, scale, M=M)
 
 
-def test_matrix_core_moments_with_unaligned_z():
+@pytest.mark.parametrize("b", [64, 30, 16])
+def test_matrix_core_moments_with_unaligned_z(b):
+    """Z 4 bytes past a 16-byte boundary: b = 64 (four columns per lane) and
+    b = 30 (two) need 16- and 8-byte rows and take the vector moments, b = 16
+    (one column per lane) stays on matrix cores."""
     import torch
-    n, d, b = 3001, 16, 64
+    n, d = 3001, 16
     X = synth.simplex_points(n, d, 9980)
     Z = synth.rhs_normal(n, b, 9981)
     flat = torch.empty(n * b + 1, dtype=torch.float32, device="cuda")
     Zd = flat[1:].view(n, b)                     # 4 bytes past a 16-byte boundary
     Zd.copy_(torch.from_numpy(Z))
-    assert Zd.data_ptr() % 16 != 0
+    assert Zd.data_ptr() % 16 != 0 and Zd.data_ptr() % 8 != 0
     h = dm.prepare(dev(X), oracle.KL)
     Y = h.matvec(Zd)
     h.sync()
@@ -441,7 +445,8 @@ def test_full_size_wide_blocks_sampled_rows():
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("metric,b,d", [(oracle.KL, 64, 8), (oracle.MAHA2, 64, 12), (oracle.BILINEAR, 48, 16),
                                         (oracle.CE, 64, 4), (oracle.L4, 64, 5), (oracle.KL, 1, 8),
-                                        (oracle.KL, 16, 8), (oracle.MAHA2, 6, 12), (oracle.CE, 26, 4)])
+                                        (oracle.KL, 16, 8), (oracle.MAHA2, 6, 12), (oracle.CE, 26, 4),
+                                        (oracle.L6, 8, 5), (oracle.L4, 20, 7)])
 @pytest.mark.parametrize("case", ["inf", "nan", "both_infs"])
 def test_nonfinite_rhs_flagged(metric, b, d, case):
     g = synth.rng(9990 + b + d)
