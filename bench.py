@@ -377,6 +377,51 @@ def run_sortfree(args, dm, synth, np, torch, dev, stream):
     return res
 
 
+def run_oddp_tv(args, dm, torch, dev, stream, Xd, Zd):
+    """Odd p (l_3^3 and l_5^5, the p+1 chained prefix sums of each coordinate
+    pass) and total variation (the l1 query halved) on the batched workload's
+    points and right-hand sides.  Per metric: preparation once, one warm-up
+    and 3 timed queries (mean), then one query with the library's events
+    around every coordinate pass for its average device time.  The pass of
+    odd p moves the bytes of the l1 pass (perm and sorted values, Z rows read,
+    Out rows read and written: 12nb + 8n - 4nb/d per pass averaged over the d
+    passes), so its rate is given against the same HBM peak."""
+    n, d = Xd.shape
+    b = Zd.shape[1]
+    Out = torch.empty((n, b), dtype=torch.float32, device=dev)
+    bytes_pass = 12.0 * n * b + 8.0 * n - 4.0 * n * b / d
+    res = {"n": n, "d": d, "b": b, "bytes_per_pass": bytes_pass}
+    for name, metric in (("l3", dm.L3), ("l5", dm.L5), ("tv", dm.TV)):
+        h = dm.prepare(Xd, metric)
+        h.reserve(b)
+        h.matvec(Zd, out=Out)
+        h.sync()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record(stream)
+        for _ in range(reps):
+            h.matvec(Zd, out=Out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        h.sync()
+        ms = e0.elapsed_time(e1) / reps
+        h.profile(True)
+        h.matvec(Zd, out=Out)
+        h.sync()
+        pass_ms, pass_n = h.profile_read(dm.K_L1_PASS)
+        h.profile(False)
+        h.free()
+        avg = pass_ms / max(pass_n, 1)
+        ach = bytes_pass / (avg * 1e-3) / 1e9
+        res[name] = {"ms_per_query": round(ms, 3), "columns_per_s": round(b / (ms * 1e-3), 1),
+                     "avg_pass_ms": round(avg, 4), "pass_GBps": round(ach, 1),
+                     "pass_frac_of_hbm_peak": round(ach / HBM_PEAK_GBPS, 4)}
+        log("%s: %.2f ms/query, pass %.4f ms (%.0f GB/s)" % (name, ms, avg, ach))
+    del Out
+    return res
+
+
 def pass_kernel_name(variant, b):
     """Kernel of a float l1 pass variant: 0/1 the keep kernel, 2/3 the
     re-gathering kernel; odd variants halve the ranks per slot."""
@@ -466,6 +511,7 @@ def main():
     ap.add_argument("--no-approx-l2", action="store_true", help="skip the approximate l2 leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-stress leg")
     ap.add_argument("--no-sortfree", action="store_true", help="skip the sort-free family leg")
+    ap.add_argument("--no-oddp", action="store_true", help="skip the odd-p and total-variation leg")
     ap.add_argument("--multi-count", type=int, default=512)
     ap.add_argument("--dump-rows", default="", help="write the results on the 16 384-row sample to this .npz")
     args = ap.parse_args()
@@ -685,6 +731,11 @@ def main():
     if not args.no_approx_l2:
         approx = run_approx_l2(args, dm, synth, np, torch, dev, stream)
 
+    # ---- odd p and total variation on the batched workload ----
+    oddp = None
+    if not args.no_oddp:
+        oddp = run_oddp_tv(args, dm, torch, dev, stream, Xd, Zd)
+
     # ---- the sort-free family ----
     sortfree = None
     if not args.no_sortfree:
@@ -778,6 +829,7 @@ def main():
         "single_vector_mixture": mixture,
         "precision_stress": precision,
         "approx_l2": approx,
+        "oddp_tv": oddp,
         "sortfree": sortfree,
         "errors": errors,
         "errors_16k_rows": errors_16k,

@@ -172,7 +172,9 @@ __device__ __forceinline__ typename P::O lp_horner(typename P::O h, typename P::
 // ---------------------------------------------------------------------------
 // the pass of one coordinate for odd p (NM = p + 1 running sums)
 // ---------------------------------------------------------------------------
-template <typename P, int BP, int NM, int R>
+// VEC: 16-byte accesses to the Z and Out rows (b % 4 == 0, 16-byte aligned
+// rows), as in the l1 pass; the same values either way.
+template <typename P, int BP, int NM, int R, bool VEC>
 __global__ __launch_bounds__(256, 2) void lp_pass_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void lp_pass_kernel(
             x[i] = valid ? xs[r0 + i] : typename P::X(0);
         }
 #pragma unroll
-        for (int i = 0; i < R; ++i) load_row<CPL, false>(Z + (size_t)pr[i] * b, col0, b, r0 + i < n, g[i]);
+        for (int i = 0; i < R; ++i) load_row<CPL, VEC>(Z + (size_t)pr[i] * b, col0, b, r0 + i < n, g[i]);
 
         // thread sums of z x^t, then the wave's exclusive prefix over slots
         L e[NM][CPL];
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(256, 2) void lp_pass_kernel(
         for (int i = 0; i < R; ++i) {
             typename P::O o[CPL];
             if (!first) {
-                load_row<CPL, false>(Out + (size_t)pr[i] * b, col0, b, r0 + i < n, o);
+                load_row<CPL, VEC>(Out + (size_t)pr[i] * b, col0, b, r0 + i < n, o);
             } else {
 #pragma unroll
                 for (int j = 0; j < CPL; ++j) o[j] = col0 + j < b ? lp_u<P>(U[col0 + j]) : typename P::O(0);
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(256, 2) void lp_pass_kernel(
                 for (int t = 1; t < NM; ++t) h = lp_horner<P>(h, x[i], lp_coef(PW, t), D[t][j], l[t][j]);
                 res[j] = P::oadd(o[j], h);
             }
-            if (r0 + i < n) store_row<CPL, false>(Out + (size_t)pr[i] * b, col0, b, res);
+            if (r0 + i < n) store_row<CPL, VEC>(Out + (size_t)pr[i] * b, col0, b, res);
         }
         if (tid == 0) s_ticket = atomicAdd((unsigned long long*)ticket_ctr, 1ull);
         __syncthreads();
@@ -356,12 +358,19 @@ hipError_t lp_launch_bp(const LpPassArgs& a, int32_t b, hipStream_t s) {
     const int64_t ntiles = (a.n + TILE - 1) / TILE;
     if ((size_t)ntiles * (2 * (size_t)NM * P::WPV * BP + 1) > a.record_words) return hipErrorInvalidValue;
     uint64_t* stat = a.records + (size_t)ntiles * 2 * NM * P::WPV * BP;
-    const int64_t grid = persistent_grid((const void*)lp_pass_kernel<P, BP, NM, R>,
-                                         (const void*)lp_pass_kernel<P, BP, NM, R>, ntiles);
-    lp_pass_kernel<P, BP, NM, R><<<(unsigned)grid, 256, 0, s>>>(
-        a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,
-        (const typename P::T*)a.T0, (const typename P::T*)a.Mk, a.mstride, (const typename P::T*)a.U, a.first,
-        &a.chain->ticket[a.cls], ntiles, a.records, stat, a.status);
+    // one grid for both row-access forms (the ticket count of a pass is
+    // ntiles + grid, so every pass of a shape must launch the same grid)
+    const int64_t grid = persistent_grid((const void*)lp_pass_kernel<P, BP, NM, R, false>,
+                                         (const void*)lp_pass_kernel<P, BP, NM, R, true>, ntiles);
+    const bool vec = (b % 4 == 0) && ((uintptr_t)a.Z % 16 == 0) && ((uintptr_t)a.Out % 16 == 0);
+#define LP_PASS(V)                                                                                                  \
+    lp_pass_kernel<P, BP, NM, R, V><<<(unsigned)grid, 256, 0, s>>>(                                                  \
+        a.perm, (const typename P::X*)a.xs, a.n, (const typename P::Z*)a.Z, (typename P::O*)a.Out, b,               \
+        (const typename P::T*)a.T0, (const typename P::T*)a.Mk, a.mstride, (const typename P::T*)a.U, a.first,        \
+        &a.chain->ticket[a.cls], ntiles, a.records, stat, a.status)
+    if (vec) LP_PASS(true);
+    else LP_PASS(false);
+#undef LP_PASS
     return hipGetLastError();
 }
 
