@@ -173,9 +173,12 @@ __device__ __forceinline__ typename P::O lp_horner(typename P::O h, typename P::
 // the pass of one coordinate for odd p (NM = p + 1 running sums)
 // ---------------------------------------------------------------------------
 // VEC: 16-byte accesses to the Z and Out rows (b % 4 == 0, 16-byte aligned
-// rows), as in the l1 pass; the same values either way.
+// rows), as in the l1 pass; the same values either way.  p = 3 is held to
+// three waves per SIMD (168 registers, one spilled): the pass waits on
+// memory and the look-back, and the third wave took it from 3.01 to 2.81 ms
+// at n = 2^22, d = 128, b = 64; p = 5 would spill a dozen and keeps two.
 template <typename P, int BP, int NM, int R, bool VEC>
-__global__ __launch_bounds__(256, 2) void lp_pass_kernel(
+__global__ __launch_bounds__(256, NM <= 4 ? 3 : 2) void lp_pass_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
     const typename P::Z* __restrict__ Z, typename P::O* __restrict__ Out, int32_t b,
     const typename P::T* __restrict__ T0, const typename P::T* __restrict__ Mk, int64_t mstride,
