@@ -176,7 +176,8 @@ __device__ __forceinline__ typename P::O lp_horner(typename P::O h, typename P::
 // rows), as in the l1 pass; the same values either way.  p = 3 is held to
 // three waves per SIMD (168 registers, one spilled): the pass waits on
 // memory and the look-back, and the third wave took it from 3.01 to 2.81 ms
-// at n = 2^22, d = 128, b = 64; p = 5 would spill a dozen and keeps two.
+// at n = 2^22, d = 128, b = 64; p = 5 would spill a dozen registers (its pass
+// then took 9.90 ms against 8.66 ms) and keeps two.
 template <typename P, int BP, int NM, int R, bool VEC>
 __global__ __launch_bounds__(256, NM <= 4 ? 3 : 2) void lp_pass_kernel(
     const uint32_t* __restrict__ perm, const typename P::X* __restrict__ xs, int64_t n,
